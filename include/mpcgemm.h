@@ -1,0 +1,173 @@
+/*
+ * mpcgemm.h - arbitrary-precision complex matrix multiplication C := A B on
+ * AMD Instinct MI355X (gfx950) by the Ozaki scheme, 4M and 3M forms.
+ *
+ * The operation is eq. (1) of the paper (C := AB, A in C^{m x k}, B in
+ * C^{k x n}), each entry being the sum of eq. (2) over complex products.
+ * Each multi-precision matrix is split error-free into short signed-digit
+ * slice matrices (the splitting idea of Algorithm 2), every slice-pair product
+ * is formed exactly on the matrix cores, and the products are combined in an
+ * exact multi-limb fixed-point accumulator (instead of the L-bit floating-point
+ * accumulation of Algorithm 2) and rounded once to nearest-even.  The complex
+ * product is assembled either from four real products (eq. 5, "4M") or from
+ * three (eq. 6, "3M"); with exact slice products both give identical bits.
+ *
+ * NUMBER FORMAT (one real component of a matrix; column-major, leading
+ * dimension ld >= rows):
+ *   sign[c*ld + r]  uint8: 0 = +, 1 = -.
+ *   exp [c*ld + r]  int32: value = (-1)^sign * M * 2^(exp - 64*L), where
+ *                   L = ceil(prec_bits / 64) and M is the L-limb significand;
+ *                   exp == MPCG_EXP_ZERO (INT32_MIN) marks an exact zero
+ *                   (sign and limbs are then ignored).  Nonzero inputs need
+ *                   |exp| <= 2^30.
+ *   mant[l*limb_stride + c*ld + r]  uint64: limb l of M, limb 0 least
+ *                   significant.  A nonzero entry has the top bit of limb L-1
+ *                   set (significand in [1/2, 1), the MPFR convention of the
+ *                   paper's F_bM, Section II).  Only the top prec_bits bits are
+ *                   read; the lower bits of limb 0 are ignored on input and
+ *                   written as zero on output.
+ *   limb_stride >= ld*cols; 0 means exactly ld*cols.
+ * Outputs: each component of each entry of C is the exact value rounded to
+ * prec_bits, round to nearest, ties to even.  An exact zero is written as
+ * sign 0, exp MPCG_EXP_ZERO, limbs 0.
+ *
+ * MEMORY AND STREAMS: every matrix pointer is a DEVICE pointer owned by the
+ * caller; the library never frees or retains it.  Work is issued on the
+ * stream set by mpcg_set_stream (default: the null stream) and is
+ * asynchronous, except that each multiplication synchronizes that stream once,
+ * after its exponent scan, to size the slice planes (the number of slices
+ * depends on the exponent spread of the data).  C must not overlap A or B.
+ *
+ * ERRORS: functions return MPCG_OK (0) or a negative code.  Argument errors
+ * are detected on the host before any device work is issued.  The text of the
+ * last error of the calling thread is returned by mpcg_last_error().
+ */
+#ifndef MPCGEMM_H
+#define MPCGEMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPCG_EXP_ZERO INT32_MIN
+#define MPCG_MIN_PREC 2
+#define MPCG_MAX_PREC 4096
+
+enum {
+    MPCG_OK = 0,
+    MPCG_EINVAL = -1,      /* bad dimension, leading dimension, precision, enum, NULL, aliasing */
+    MPCG_ENOMEM = -2,      /* workspace too small / allocation failed */
+    MPCG_ERANGE = -3,      /* input exponent outside [-2^30, 2^30] or output exponent overflow */
+    MPCG_EHIP = -4,        /* HIP runtime error (text in mpcg_last_error) */
+    MPCG_EUNSUPPORTED = -5,/* valid request this build cannot serve */
+    MPCG_EDOMAIN = -6      /* nonzero input whose significand top bit is clear */
+};
+
+typedef struct {
+    uint8_t *sign;
+    int32_t *exp;
+    uint64_t *mant;
+    int64_t limb_stride;
+} mpcg_part;
+
+typedef struct {
+    mpcg_part re, im;
+} mpcg_cmat;
+
+typedef enum { MPCG_4M = 0, MPCG_3M = 1 } mpcg_mode;
+typedef enum { MPCG_EXACT = 0, MPCG_TRUNCATED = 1 } mpcg_scheme;
+typedef enum { MPCG_SLICE_INT8 = 0, MPCG_SLICE_FP64 = 1 } mpcg_slice;
+
+/*
+ * mp_cgemm - C := A B (eq. 1), A m x k (lda), B k x n (ldb), C m x n (ldc).
+ *   mode   MPCG_4M: eq. (5), four real slice products per slice pair.
+ *          MPCG_3M: eq. (6), three; (Re A + Im A) and (Re B + Im B) are formed
+ *          exactly in fixed point, so no accuracy is lost.
+ *   scheme MPCG_EXACT: every slice pair is kept; the result is the exact sum
+ *          rounded once (bit-identical for 4M/3M and for both slice types).
+ *          MPCG_TRUNCATED: slice pairs (s, t) with s + t above a cutoff are
+ *          dropped (the triangular product loop of Algorithm 2); every
+ *          component then satisfies
+ *            |C~ - C*| <= 2^-(prec_bits-4) * sum_k |a_ik|_max |b_kj|_max,
+ *          with C* the exact product and |z|_max = max(|Re z|, |Im z|).
+ *   Slices are signed 7-bit integers on INT8 matrix cores.
+ * Quick returns: m == 0 or n == 0 does nothing; k == 0 writes +0 to C.
+ * Returns MPCG_OK, MPCG_EINVAL, MPCG_ENOMEM, MPCG_ERANGE (input exponents),
+ * MPCG_EHIP.  Output exponent overflow and non-normalized inputs are reported
+ * by mpcg_stream_status.
+ */
+int mp_cgemm(int m, int n, int k, const mpcg_cmat *A, int lda, const mpcg_cmat *B, int ldb,
+             mpcg_cmat *C, int ldc, int prec_bits, int mode, int scheme);
+
+/* Options for mp_cgemm_ex (NULL = defaults, all fields 0). */
+typedef struct {
+    int slice_type;       /* MPCG_SLICE_INT8 (default) or MPCG_SLICE_FP64: FP64 slices of
+                             floor((53 - ceil(log2 k)) / 2) bits on FP64 matrix cores, the
+                             slice width rule of Algorithm 2 */
+    int cutoff_override;  /* truncated scheme: > 0 keeps pairs with s + t <= cutoff_override
+                             (no error bound is then promised); 0 = derived cutoff */
+    int ksplit_override;  /* > 0: number of contraction chunks; 0 = planner's choice */
+    int block_override;   /* > 0: slices per register block in the INT8 slice GEMM (4, 6 or 8) */
+} mpcg_options;
+
+/* Plan and timing report of one multiplication. */
+typedef struct {
+    int S_A, S_B;         /* slices per operand (A side, B side) */
+    int w;                /* bits per slice digit */
+    int cutoff;           /* highest kept diagonal s + t */
+    int nprod;            /* real slice products per slice pair: 4 (4M) or 3 (3M) */
+    int ksplit;           /* contraction chunks */
+    int block;            /* slices per register block (INT8) */
+    int reserved;
+    long long pairs;      /* kept slice pairs (s, t) */
+    double algo_ops;      /* 2*m*n*k*pairs*nprod: slice-product operations */
+    double bound_bits;    /* truncated: error bound exponent (error <= 2^-bound_bits * sum|a||b|) */
+} mpcg_info;
+
+/* mp_cgemm with options; info (may be NULL) receives the plan. */
+int mp_cgemm_ex(int m, int n, int k, const mpcg_cmat *A, int lda, const mpcg_cmat *B, int ldb,
+                mpcg_cmat *C, int ldc, int prec_bits, int mode, int scheme,
+                const mpcg_options *opt, mpcg_info *info);
+
+/* Issue subsequent work on this HIP stream (hipStream_t as void*; NULL = null stream). */
+int mpcg_set_stream(void *hip_stream);
+
+/*
+ * Use caller-owned device memory as workspace (NULL/0 = library-owned,
+ * grown on demand with hipMalloc).  A multiplication whose plan needs more
+ * than `bytes` fails with MPCG_ENOMEM.
+ */
+int mpcg_set_workspace(void *dev_ptr, size_t bytes);
+
+/*
+ * Workspace bytes needed for a multiplication whose operands have row/column
+ * exponent spreads of at most max_spread (E_i - min exponent of the row),
+ * e.g. 2R for exponents drawn from [-R, R].
+ */
+size_t mpcg_workspace_size(int m, int n, int k, int prec_bits, int mode, int scheme,
+                           const mpcg_options *opt, int max_spread);
+
+/*
+ * Synchronize `hip_stream` and return (and clear) the device status of the
+ * work issued so far: MPCG_OK, MPCG_ERANGE (an output exponent overflowed
+ * int32; that entry was written as zero) or MPCG_EDOMAIN (a nonzero input had
+ * its significand top bit clear).
+ */
+int mpcg_stream_status(void *hip_stream);
+
+/* Text of the calling thread's last error ("" if none). */
+const char *mpcg_last_error(void);
+
+/* Device kernel time of the last multiplication, per stage, in microseconds
+ * (scan, split, slice GEMM, round), measured with HIP events when enabled. */
+int mpcg_enable_timing(int on);
+int mpcg_last_timing(float us[4]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPCGEMM_H */

@@ -1,0 +1,251 @@
+"""Arbitrary-precision complex GEMM (Ozaki scheme, 4M/3M) on MI355X.
+
+Thin ctypes binding over ``libmpcgemm.so``: the functions below carry the C
+names of ``include/mpcgemm.h`` and only marshal arguments.  PyTorch supplies
+device memory and the current stream; every step of the multiplication runs
+in the library's HIP kernels.  There is no CPU fallback: importing this
+package fails if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpcgemm.so")
+
+MPCG_OK = 0
+MPCG_EINVAL = -1
+MPCG_ENOMEM = -2
+MPCG_ERANGE = -3
+MPCG_EHIP = -4
+MPCG_EUNSUPPORTED = -5
+MPCG_EDOMAIN = -6
+
+MPCG_4M = 0
+MPCG_3M = 1
+MPCG_EXACT = 0
+MPCG_TRUNCATED = 1
+MPCG_SLICE_INT8 = 0
+MPCG_SLICE_FP64 = 1
+
+EXP_ZERO = np.iinfo(np.int32).min
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+
+class mpcg_part(ctypes.Structure):
+    _fields_ = [("sign", ctypes.c_void_p), ("exp", ctypes.c_void_p), ("mant", ctypes.c_void_p),
+                ("limb_stride", ctypes.c_int64)]
+
+
+class mpcg_cmat(ctypes.Structure):
+    _fields_ = [("re", mpcg_part), ("im", mpcg_part)]
+
+
+class mpcg_options(ctypes.Structure):
+    _fields_ = [("slice_type", ctypes.c_int), ("cutoff_override", ctypes.c_int),
+                ("ksplit_override", ctypes.c_int), ("block_override", ctypes.c_int)]
+
+
+class mpcg_info(ctypes.Structure):
+    _fields_ = [("S_A", ctypes.c_int), ("S_B", ctypes.c_int), ("w", ctypes.c_int), ("cutoff", ctypes.c_int),
+                ("nprod", ctypes.c_int), ("ksplit", ctypes.c_int), ("block", ctypes.c_int),
+                ("reserved", ctypes.c_int), ("pairs", ctypes.c_longlong), ("algo_ops", ctypes.c_double),
+                ("bound_bits", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+_P = ctypes.POINTER
+_i = ctypes.c_int
+_vp = ctypes.c_void_p
+_lib.mp_cgemm.argtypes = [_i, _i, _i, _P(mpcg_cmat), _i, _P(mpcg_cmat), _i, _P(mpcg_cmat), _i, _i, _i, _i]
+_lib.mp_cgemm.restype = _i
+_lib.mp_cgemm_ex.argtypes = [_i, _i, _i, _P(mpcg_cmat), _i, _P(mpcg_cmat), _i, _P(mpcg_cmat), _i, _i, _i, _i,
+                             _P(mpcg_options), _P(mpcg_info)]
+_lib.mp_cgemm_ex.restype = _i
+_lib.mpcg_set_stream.argtypes = [_vp]
+_lib.mpcg_set_stream.restype = _i
+_lib.mpcg_set_workspace.argtypes = [_vp, ctypes.c_size_t]
+_lib.mpcg_set_workspace.restype = _i
+_lib.mpcg_workspace_size.argtypes = [_i, _i, _i, _i, _i, _i, _P(mpcg_options), _i]
+_lib.mpcg_workspace_size.restype = ctypes.c_size_t
+_lib.mpcg_stream_status.argtypes = [_vp]
+_lib.mpcg_stream_status.restype = _i
+_lib.mpcg_last_error.argtypes = []
+_lib.mpcg_last_error.restype = ctypes.c_char_p
+_lib.mpcg_enable_timing.argtypes = [_i]
+_lib.mpcg_enable_timing.restype = _i
+_lib.mpcg_last_timing.argtypes = [_P(ctypes.c_float)]
+_lib.mpcg_last_timing.restype = _i
+
+EXPORTS = ["mp_cgemm", "mp_cgemm_ex", "mpcg_set_stream", "mpcg_set_workspace", "mpcg_workspace_size",
+           "mpcg_stream_status", "mpcg_last_error", "mpcg_enable_timing", "mpcg_last_timing"]
+
+
+class MPCGError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mpcgemm error {code}: {msg}")
+        self.code = code
+
+
+def mpcg_last_error() -> str:
+    return (_lib.mpcg_last_error() or b"").decode()
+
+
+def _check(code: int) -> int:
+    if code != MPCG_OK:
+        raise MPCGError(code, mpcg_last_error())
+    return code
+
+
+# ---------------------------------------------------------------------------
+# Device matrices: torch tensors used as plain device memory.
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class DevicePart:
+    sign: "object"  # torch.uint8 [cols, ld]
+    exp: "object"   # torch.int32 [cols, ld]
+    mant: "object"  # torch.int64 [L, cols, ld] (uint64 bit patterns)
+
+    def struct(self) -> mpcg_part:
+        return mpcg_part(self.sign.data_ptr(), self.exp.data_ptr(), self.mant.data_ptr(),
+                         self.mant.shape[1] * self.mant.shape[2])
+
+
+@dataclasses.dataclass
+class DeviceCMat:
+    rows: int
+    cols: int
+    ld: int
+    L: int
+    re: DevicePart
+    im: DevicePart
+
+    def struct(self) -> mpcg_cmat:
+        return mpcg_cmat(self.re.struct(), self.im.struct())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def device_empty(rows: int, cols: int, prec_bits: int, ld: int | None = None, device="cuda") -> DeviceCMat:
+    torch = _torch()
+    ld = rows if ld is None else ld
+    L = (prec_bits + 63) // 64
+
+    def part():
+        return DevicePart(torch.zeros((cols, ld), dtype=torch.uint8, device=device),
+                          torch.full((cols, ld), EXP_ZERO, dtype=torch.int32, device=device),
+                          torch.zeros((L, cols, ld), dtype=torch.int64, device=device))
+    return DeviceCMat(rows, cols, ld, L, part(), part())
+
+
+def to_device(host, device="cuda") -> DeviceCMat:
+    """Upload a host matrix (objects with .re/.im parts holding sign/exp/mant numpy arrays)."""
+    torch = _torch()
+
+    def part(p):
+        return DevicePart(torch.from_numpy(np.ascontiguousarray(p.sign)).to(device),
+                          torch.from_numpy(np.ascontiguousarray(p.exp)).to(device),
+                          torch.from_numpy(np.ascontiguousarray(p.mant).view(np.int64)).to(device))
+    return DeviceCMat(host.rows, host.cols, host.ld, host.L, part(host.re), part(host.im))
+
+
+def to_numpy(dev: DeviceCMat):
+    """Download: returns dict of numpy arrays {re: (sign, exp, mant), im: (...)} (mant as uint64)."""
+    out = {}
+    for name in ("re", "im"):
+        p = getattr(dev, name)
+        out[name] = (p.sign.cpu().numpy(), p.exp.cpu().numpy(), p.mant.cpu().numpy().view(np.uint64))
+    return out
+
+
+def current_stream_handle():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+# C entry points (same names as the header).
+# ---------------------------------------------------------------------------
+def mpcg_set_stream(stream=None) -> int:
+    """Bind the library to a HIP stream (default: torch's current stream)."""
+    if stream is None:
+        stream = current_stream_handle()
+    elif not isinstance(stream, ctypes.c_void_p):
+        stream = ctypes.c_void_p(int(stream))
+    return _check(_lib.mpcg_set_stream(stream))
+
+
+def mpcg_set_workspace(ptr: int | None, nbytes: int) -> int:
+    return _check(_lib.mpcg_set_workspace(ctypes.c_void_p(ptr) if ptr else None, nbytes))
+
+
+def mpcg_workspace_size(m, n, k, prec_bits, mode=MPCG_3M, scheme=MPCG_EXACT, options=None,
+                        max_spread=0) -> int:
+    opt = ctypes.byref(options) if options is not None else None
+    return int(_lib.mpcg_workspace_size(m, n, k, prec_bits, mode, scheme, opt, max_spread))
+
+
+def mpcg_stream_status(stream=None) -> int:
+    if stream is None:
+        stream = current_stream_handle()
+    return int(_lib.mpcg_stream_status(stream))
+
+
+def mpcg_enable_timing(on: bool = True) -> int:
+    return _check(_lib.mpcg_enable_timing(1 if on else 0))
+
+
+def mpcg_last_timing():
+    us = (ctypes.c_float * 4)()
+    _check(_lib.mpcg_last_timing(us))
+    return list(us)
+
+
+def mp_cgemm_raw(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, mode, scheme) -> int:
+    """Direct call with ctypes structs/pointers (or None); returns the status code unchanged."""
+    return int(_lib.mp_cgemm(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, mode, scheme))
+
+
+def mp_cgemm_ex_raw(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, mode, scheme, options=None, info=None) -> int:
+    return int(_lib.mp_cgemm_ex(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, mode, scheme, options, info))
+
+
+def mp_cgemm(m, n, k, A: DeviceCMat, lda, B: DeviceCMat, ldb, C: DeviceCMat, ldc, prec_bits,
+             mode=MPCG_3M, scheme=MPCG_EXACT) -> int:
+    a, b, c = A.struct(), B.struct(), C.struct()
+    return _check(_lib.mp_cgemm(m, n, k, ctypes.byref(a), lda, ctypes.byref(b), ldb, ctypes.byref(c), ldc,
+                                prec_bits, mode, scheme))
+
+
+def mp_cgemm_ex(m, n, k, A: DeviceCMat, lda, B: DeviceCMat, ldb, C: DeviceCMat, ldc, prec_bits,
+                mode=MPCG_3M, scheme=MPCG_EXACT, slice_type=MPCG_SLICE_INT8, cutoff_override=0,
+                ksplit_override=0, block_override=0) -> dict:
+    a, b, c = A.struct(), B.struct(), C.struct()
+    opt = mpcg_options(slice_type, cutoff_override, ksplit_override, block_override)
+    info = mpcg_info()
+    _check(_lib.mp_cgemm_ex(m, n, k, ctypes.byref(a), lda, ctypes.byref(b), ldb, ctypes.byref(c), ldc,
+                            prec_bits, mode, scheme, ctypes.byref(opt), ctypes.byref(info)))
+    return info.as_dict()
+
+
+def matmul(A: DeviceCMat, B: DeviceCMat, prec_bits: int, mode=MPCG_3M, scheme=MPCG_EXACT,
+           slice_type=MPCG_SLICE_INT8, **kw):
+    """Convenience: allocate C and run mp_cgemm_ex on torch's current stream. Returns (C, info)."""
+    C = device_empty(A.rows, B.cols, prec_bits, device=A.re.sign.device)
+    mpcg_set_stream()
+    info = mp_cgemm_ex(A.rows, B.cols, A.cols, A, A.ld, B, B.ld, C, C.ld, prec_bits, mode, scheme,
+                       slice_type=slice_type, **kw)
+    return C, info

@@ -1,0 +1,134 @@
+// Internal declarations shared by the host planner and the device kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpcg {
+
+constexpr int32_t EXP_ZERO = INT32_MIN;
+constexpr int32_t EXP_LIMIT = 1 << 30;  // |exp| of a nonzero input
+
+// Device status bits (OR-ed into a word in the workspace).
+constexpr int ST_IN_RANGE = 1;   // input exponent outside [-2^30, 2^30]
+constexpr int ST_DENORM = 2;     // nonzero input with clear top significand bit
+constexpr int ST_OUT_RANGE = 4;  // output exponent does not fit int32
+
+// One real component of a column-major matrix (read side).
+struct DPart {
+  const uint8_t* sign;
+  const int32_t* exp;
+  const uint64_t* mant;
+  int64_t ls;  // limb stride (elements)
+};
+
+// One real component (write side).
+struct DOutPart {
+  uint8_t* sign;
+  int32_t* exp;
+  uint64_t* mant;
+  int64_t ls;
+};
+
+// A real component viewed as an R x K operand: element (r, kk) at r*rs + kk*ks.
+// For A (m x k, column-major) R = m, rs = 1, ks = lda; for B (k x n) R = n,
+// rs = ldb, ks = 1 (B is read transposed, one "row" per output column).
+struct DOperand {
+  DPart re, im;
+  int R, K;
+  int64_t rs, ks;
+};
+
+// Per-row (A) or per-column (B) exponent statistics, filled by the scan.
+struct RowStat {
+  int32_t emax;   // largest exponent of any nonzero Re/Im component (INT32_MIN: all zero)
+  int32_t emin;   // smallest such exponent
+  int32_t ehat;   // min over the row of max(e_re, e_im) of nonzero entries
+  int32_t pad;
+};
+
+// Whole-operand summary (device side, read back once by the host).
+struct ScanSummary {
+  int32_t spread;     // max over nonzero rows of emax - emin
+  int32_t hat;        // max over nonzero rows of emax - ehat
+  int32_t nonzero;    // number of rows with a nonzero entry
+  int32_t status;     // ST_* bits from the scan
+};
+
+// ----------------------------------------------------------------------------
+// Launchers (all asynchronous on `stream`).
+// ----------------------------------------------------------------------------
+
+// Exponent scan of one operand: stats[R], summary.  `stats` and `summary` are
+// initialised by the launcher's own fill kernel.
+hipError_t launch_scan(const DOperand& op, RowStat* stats, ScanSummary* summary, hipStream_t stream);
+
+// Digit planes of one operand.
+//   nops       planes per slice index: 2 (Re, Im), 3 (Re, Im, Re+Im) or
+//              3 with the third plane = -Im (neg_im_plane).
+//   S          digits needed for exactness (frame size); Sp >= S planes are written
+//              (planes s >= S are zero).
+//   w          digit width in bits.
+//   G          per-row scale exponents (int32 [Rpad]); digits represent
+//              |x| / 2^G[r] = sum_s d_s 2^(-w(s+1)).
+//   out        INT8: int8 planes [nops][Sp][Rpad/16][Kpad/64][64][16];
+//              FP64: double planes [nops][Sp][Rpad/16][Kpad/4][64].
+enum class Third { NONE = 0, SUM = 1, NEG_IM = 2 };
+hipError_t launch_split_i8(const DOperand& op, int prec, int L, int S, int Sp, Third third,
+                           const int32_t* G, int Rpad, int Kpad, int8_t* out, int* status,
+                           hipStream_t stream);
+hipError_t launch_split_f64(const DOperand& op, int prec, int L, int S, int Sp, int w, Third third,
+                            const int32_t* G, int Rpad, int Kpad, double* out, int* status,
+                            hipStream_t stream);
+
+// Scale exponents G[r] = emax + x (0 for all-zero rows), r < Rpad.
+hipError_t launch_scales(const RowStat* stats, int R, int Rpad, int x, int32_t* G, hipStream_t stream);
+
+// Slice GEMM + combination + carry chain (INT8 digits).
+struct GemmArgs {
+  const int8_t* X;   // A-side planes
+  const int8_t* Y;   // B-side planes
+  int mt, nt;        // 16-row tiles of A, 16-column tiles of B
+  int kblocks;       // Kpad / 64 (INT8) or Kpad / 4 (FP64)
+  int ksplit;        // contraction chunks
+  int SAp, SBp;      // padded slice counts (multiples of the block)
+  int Dmax;          // highest emitted diagonal
+  int mode3m;        // 1: planes are (Re, Im, Re+Im) on both sides; 0: A (Re, Im), B (Re, Im, -Im)
+  void* digits;      // [ksplit][tiles][Dmax+1][64][8] digit type
+  int64_t* top;      // [ksplit][tiles][64][8]
+  int32_t* lnz;      // [ksplit][tiles][64][8]
+};
+hipError_t launch_gemm_i8(const GemmArgs& a, int block, hipStream_t stream);
+
+struct GemmF64Args {
+  const double* X;
+  const double* Y;
+  int mt, nt, kblocks, ksplit, SA, SB, Dmax, mode3m, w;
+  uint32_t* digits;
+  int64_t* top;
+  int32_t* lnz;
+};
+hipError_t launch_gemm_f64(const GemmF64Args& a, hipStream_t stream);
+
+// Merge chunk streams (if ksplit > 1), round to prec, write C.
+struct RoundArgs {
+  const void* digits;  // uint8 (w = 7) or uint32 (w > 8) digits
+  int digit_bytes;     // 1 or 4
+  int f64_layout;      // 1: element (i, j) of a 16x16 tile sits in lane j + 16*(i%4), slot i/4
+                       //    (fp64 matrix-core output order); 0: lane j + 16*(i/4), slot i%4
+  const int64_t* top;
+  const int32_t* lnz;
+  int ksplit, mt, nt, Dmax, w;
+  const int32_t* G;  // [m]
+  const int32_t* H;  // [n]
+  int m, n, prec, L;
+  DOutPart cre, cim;
+  int64_t ldc;
+  int* status;
+};
+hipError_t launch_round(const RoundArgs& a, hipStream_t stream);
+
+// C := +0 everywhere.
+hipError_t launch_zero(DOutPart cre, DOutPart cim, int m, int n, int64_t ldc, int L, hipStream_t stream);
+
+}  // namespace mpcg

@@ -1,0 +1,244 @@
+// Exact accumulation tail and the single rounding.
+//
+// For every output component the slice GEMM leaves an exact integer
+//     X = T * 2^(w*nd) + sum_{d=0}^{Dmax} n_d * 2^(w*(Dmax-d)),   0 <= n_d < 2^w,
+// (T the signed final carry, nd = Dmax + 1) whose value is
+// X * 2^(G_i + H_j - w(Dmax + 2)).  Algorithm 2 adds its slice products into an
+// L-bit floating-point accumulator; here the sum is already exact, and this
+// kernel rounds it once to prec_bits, to nearest with ties to even.
+//
+// If the contraction was cut into chunks, their streams are first added
+// digit by digit with a carry (the sum is written back into chunk 0's digits).
+//
+// For negative X the magnitude is formed digit-wise without materialising it:
+// with z = the lowest nonzero digit index (largest d),
+//     |X| digits = 2^w - 1 - n_d above z,  2^w - n_z at z,  0 below z,
+// and top part -T - 1 (or -T when all digits are zero).
+// Sticky information needs only the position of the lowest set bit of X,
+// which is the same for X and |X|.
+#include "mpcg_internal.h"
+
+namespace mpcg {
+
+namespace {
+
+template <typename DIG>
+struct Stream {
+  const DIG* base;  // digit d of this element: base[d * 512]
+  int Dmax, w;
+  int neg;
+  int z;        // lowest nonzero digit index (largest d), -1 if none
+  uint64_t U;   // magnitude of the top part
+  __device__ inline uint64_t n(int d) const { return (uint64_t)base[(size_t)d * 512]; }
+  __device__ inline uint64_t m(int d) const {  // magnitude digit
+    if (!neg) return n(d);
+    if (z < 0 || d > z) return 0;
+    const uint64_t full = 1ull << w;
+    return d == z ? full - n(d) : full - 1 - n(d);
+  }
+  // bits [pos, pos + 64) of |X|; bit 0 = lowest bit of digit Dmax
+  __device__ uint64_t field(int64_t pos) const {
+    const int64_t nbits = (int64_t)w * (Dmax + 1);
+    uint64_t r = 0;
+    const int64_t lo = pos < 0 ? 0 : pos;
+    const int64_t hi = pos + 64;  // exclusive
+    if (lo < nbits) {
+      const int64_t q0 = lo / w;
+      const int64_t q1 = min((hi - 1) / w, (int64_t)Dmax);
+      for (int64_t q = q0; q <= q1; ++q) {
+        const uint64_t v = m(Dmax - (int)q);
+        const int64_t sh = (int64_t)w * q - pos;
+        if (sh >= 0) {
+          if (sh < 64) r |= v << sh;
+        } else if (-sh < 64) {
+          r |= v >> (-sh);
+        }
+      }
+    }
+    if (hi > nbits && U) {
+      const int64_t sh = nbits - pos;
+      if (sh >= 0) {
+        if (sh < 64) r |= U << sh;
+      } else if (-sh < 64) {
+        r |= U >> (-sh);
+      }
+    }
+    return r;
+  }
+  __device__ inline int bit(int64_t pos) const {
+    if (pos < 0) return 0;
+    const int64_t nbits = (int64_t)w * (Dmax + 1);
+    if (pos >= nbits) {
+      const int64_t s = pos - nbits;
+      return s < 64 ? (int)((U >> s) & 1) : 0;
+    }
+    const int64_t q = pos / w;
+    return (int)((m(Dmax - (int)q) >> (pos - q * w)) & 1);
+  }
+};
+
+template <typename DIG>
+__global__ __launch_bounds__(256) void round_kernel(RoundArgs a) {
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (int64_t)a.m * a.n * 2;
+  if (gid >= total) return;
+  const int i = (int)(gid % a.m);
+  const int64_t rest = gid / a.m;
+  const int j = (int)(rest % a.n);
+  const int comp = (int)(rest / a.n);
+
+  const int ti = i >> 4, tj = j >> 4;
+  const int ii = i & 15, jj = j & 15;
+  const int lane = a.f64_layout ? jj + 16 * (ii & 3) : jj + 16 * (ii >> 2);
+  const int slot = comp * 4 + (a.f64_layout ? (ii >> 2) : (ii & 3));
+  const int tiles = a.mt * a.nt;
+  const int tile = tj * a.mt + ti;
+  const int nd = a.Dmax + 1;
+  const int w = a.w;
+
+  DIG* digits = reinterpret_cast<DIG*>(const_cast<void*>(a.digits));
+  DIG* d0 = digits + ((size_t)tile * nd * 64 + lane) * 8 + slot;
+  const size_t tb0 = ((size_t)tile * 64 + lane) * 8 + slot;
+
+  int64_t T;
+  int z;
+  if (a.ksplit == 1) {
+    T = a.top[tb0];
+    z = a.lnz[tb0];
+  } else {
+    // add the chunk streams exactly, least significant digit first
+    const uint64_t dmask = (1ull << w) - 1;
+    const size_t sstride = (size_t)tiles * nd * 64 * 8;
+    int64_t c = 0;
+    z = -1;
+    for (int d = a.Dmax; d >= 0; --d) {
+      int64_t s = c;
+      for (int q = 0; q < a.ksplit; ++q) s += (int64_t)d0[q * sstride + (size_t)d * 512];
+      const uint64_t nd_ = (uint64_t)s & dmask;
+      c = s >> w;
+      d0[(size_t)d * 512] = (DIG)nd_;
+      if (nd_ && z < 0) z = d;
+    }
+    T = c;
+    for (int q = 0; q < a.ksplit; ++q) T += a.top[(size_t)q * tiles * 64 * 8 + tb0];
+  }
+
+  DOutPart out = comp ? a.cim : a.cre;
+  const int64_t o = (int64_t)j * a.ldc + i;
+  const int L = a.L, p = a.prec;
+
+  if (T == 0 && z < 0) {  // exact zero -> +0
+    out.sign[o] = 0;
+    out.exp[o] = EXP_ZERO;
+    for (int l = 0; l < L; ++l) out.mant[(int64_t)l * out.ls + o] = 0;
+    return;
+  }
+
+  Stream<DIG> st;
+  st.base = d0;
+  st.Dmax = a.Dmax;
+  st.w = w;
+  st.neg = T < 0;
+  st.z = z;
+  if (!st.neg)
+    st.U = (uint64_t)T;
+  else
+    st.U = (z < 0) ? (uint64_t)(-T) : (uint64_t)(-T - 1);
+
+  const int64_t nbits = (int64_t)w * nd;
+  // leading bit of |X|
+  int64_t lead;
+  if (st.U) {
+    lead = nbits + 63 - __builtin_clzll(st.U);
+  } else {
+    lead = -1;
+    for (int d = 0; d <= a.Dmax; ++d) {
+      const uint64_t v = st.m(d);
+      if (v) {
+        lead = (int64_t)w * (a.Dmax - d) + 63 - __builtin_clzll(v);
+        break;
+      }
+    }
+  }
+  // lowest set bit of X (= of |X|)
+  int64_t lowset;
+  if (z >= 0)
+    lowset = (int64_t)w * (a.Dmax - z) + __builtin_ctzll(st.n(z));
+  else
+    lowset = nbits + __builtin_ctzll((uint64_t)T);
+
+  const int64_t low = lead - p + 1;  // lowest kept bit of |X|
+  int round_up = 0;
+  if (low > 0) {
+    const int rbit = st.bit(low - 1);
+    const int sticky = lowset < low - 1;
+    const int lsb = st.bit(low);
+    round_up = rbit && (sticky || lsb);
+  }
+  // significand limbs, least significant first, with the rounding increment
+  const int64_t off = lead + 1 - 64ll * L;
+  const int keep_from = 64 * L - p;  // 0..63
+  uint64_t carry = round_up ? (1ull << keep_from) : 0;
+  int64_t e_out = lead + 1 + (int64_t)a.G[i] + (int64_t)a.H[j] - (int64_t)w * (a.Dmax + 2);
+  uint64_t limbs_hi = 0;
+  bool overflow = false;
+  // first pass decides nothing further; write limbs as we go
+  for (int l = 0; l < L; ++l) {
+    uint64_t f = st.field(off + 64ll * l);
+    if (l == 0 && keep_from) f &= ~((1ull << keep_from) - 1ull);
+    const uint64_t s = f + carry;
+    carry = (s < f) ? 1 : 0;
+    limbs_hi = s;
+    if (l < L - 1) out.mant[(int64_t)l * out.ls + o] = s;
+  }
+  if (carry) {  // significand overflowed to 2^p: 2^(p-1) with exponent + 1
+    overflow = true;
+    limbs_hi = 1ull << 63;
+    e_out += 1;
+  }
+  (void)overflow;
+  if (e_out > INT32_MAX || e_out <= (int64_t)INT32_MIN) {
+    atomicOr(a.status, ST_OUT_RANGE);
+    out.sign[o] = 0;
+    out.exp[o] = EXP_ZERO;
+    for (int l = 0; l < L; ++l) out.mant[(int64_t)l * out.ls + o] = 0;
+    return;
+  }
+  out.mant[(int64_t)(L - 1) * out.ls + o] = limbs_hi;
+  out.sign[o] = (uint8_t)st.neg;
+  out.exp[o] = (int32_t)e_out;
+}
+
+__global__ void zero_kernel(DOutPart cre, DOutPart cim, int m, int n, int64_t ldc, int L) {
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (int64_t)m * n * 2;
+  if (gid >= total) return;
+  const int i = (int)(gid % m);
+  const int64_t rest = gid / m;
+  const int j = (int)(rest % n);
+  DOutPart out = (rest / n) ? cim : cre;
+  const int64_t o = (int64_t)j * ldc + i;
+  out.sign[o] = 0;
+  out.exp[o] = EXP_ZERO;
+  for (int l = 0; l < L; ++l) out.mant[(int64_t)l * out.ls + o] = 0;
+}
+
+}  // namespace
+
+hipError_t launch_round(const RoundArgs& a, hipStream_t stream) {
+  const int64_t total = (int64_t)a.m * a.n * 2;
+  const int blocks = (int)((total + 255) / 256);
+  if (a.digit_bytes == 1)
+    round_kernel<uint8_t><<<dim3(blocks), dim3(256), 0, stream>>>(a);
+  else
+    round_kernel<uint32_t><<<dim3(blocks), dim3(256), 0, stream>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(DOutPart cre, DOutPart cim, int m, int n, int64_t ldc, int L, hipStream_t stream) {
+  const int64_t total = (int64_t)m * n * 2;
+  zero_kernel<<<dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream>>>(cre, cim, m, n, ldc, L);
+  return hipGetLastError();
+}
+
+}  // namespace mpcg

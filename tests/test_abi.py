@@ -1,0 +1,133 @@
+"""C-ABI library: loads, exports every declared symbol, and validates
+arguments on the host before any device work (no GPU needed)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mpcgemm.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\**\s*([a-z_0-9]+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_expected_entry_points():
+    names = _declared_functions()
+    for must in ("mp_cgemm", "mp_cgemm_ex", "mpcg_set_stream", "mpcg_set_workspace",
+                 "mpcg_workspace_size", "mpcg_stream_status", "mpcg_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2307_06072_amd as mp
+    lib = ctypes.CDLL(mp.LIB_PATH)
+    missing = [n for n in _declared_functions() if not hasattr(lib, n)]
+    assert not missing, f"not exported: {missing}"
+
+
+def test_binding_has_same_names():
+    import paper_2307_06072_amd as mp
+    for n in _declared_functions():
+        assert hasattr(mp, n), n
+
+
+# ---------------------------------------------------------------------------
+# validation runs on the host, before any HIP call
+# ---------------------------------------------------------------------------
+def _fake_cmat(base: int):
+    import paper_2307_06072_amd as mp
+    # distinct fake device addresses, far apart; never dereferenced on the host
+    def part(off):
+        return mp.mpcg_part(base + off, base + off + (1 << 24), base + off + (2 << 24), 0)
+    return mp.mpcg_cmat(part(0), part(3 << 24))
+
+
+def _call(m=4, n=4, k=4, lda=4, ldb=4, ldc=4, p=256, mode=1, scheme=0, A=None, B=None, C=None, opt=None):
+    import paper_2307_06072_amd as mp
+    A = _fake_cmat(1 << 40) if A is None else A
+    B = _fake_cmat(2 << 40) if B is None else B
+    C = _fake_cmat(3 << 40) if C is None else C
+    pa = ctypes.byref(A) if A is not False else None
+    pb = ctypes.byref(B) if B is not False else None
+    pc = ctypes.byref(C) if C is not False else None
+    if opt is not None:
+        return mp.mp_cgemm_ex_raw(m, n, k, pa, lda, pb, ldb, pc, ldc, p, mode, scheme, ctypes.byref(opt), None)
+    return mp.mp_cgemm_raw(m, n, k, pa, lda, pb, ldb, pc, ldc, p, mode, scheme)
+
+
+@pytest.mark.parametrize("kw", [dict(m=-1), dict(n=-2), dict(k=-3), dict(lda=3), dict(ldb=3), dict(ldc=2),
+                                dict(p=1), dict(p=4097), dict(mode=2), dict(scheme=5), dict(A=False),
+                                dict(B=False), dict(C=False)])
+def test_invalid_arguments(kw):
+    import paper_2307_06072_amd as mp
+    assert _call(**kw) == mp.MPCG_EINVAL
+    assert mp.mpcg_last_error() != ""
+
+
+def test_null_component_pointer():
+    import paper_2307_06072_amd as mp
+    A = _fake_cmat(1 << 40)
+    A.im.mant = None
+    assert _call(A=A) == mp.MPCG_EINVAL
+    assert "NULL" in mp.mpcg_last_error()
+
+
+def test_limb_stride_too_small():
+    import paper_2307_06072_amd as mp
+    B = _fake_cmat(2 << 40)
+    B.re.limb_stride = 15  # ld*cols = 16
+    assert _call(B=B) == mp.MPCG_EINVAL
+
+
+def test_output_aliasing_input_rejected():
+    import paper_2307_06072_amd as mp
+    A = _fake_cmat(1 << 40)
+    C = _fake_cmat(3 << 40)
+    C.im.exp = A.re.exp + 8  # overlaps A's exponent array
+    assert _call(A=A, C=C) == mp.MPCG_EINVAL
+    assert "overlap" in mp.mpcg_last_error()
+
+
+def test_bad_options_rejected():
+    import paper_2307_06072_amd as mp
+    assert _call(opt=mp.mpcg_options(7, 0, 0, 0)) == mp.MPCG_EINVAL
+    assert _call(opt=mp.mpcg_options(0, -1, 0, 0)) == mp.MPCG_EINVAL
+
+
+def test_quick_return_empty_output():
+    # m == 0 or n == 0: nothing to do, even with NULL matrices
+    assert _call(m=0, A=False, B=False, C=False) == 0
+    assert _call(n=0, A=False, B=False, C=False) == 0
+
+
+def test_workspace_size_planning():
+    import paper_2307_06072_amd as mp
+    s1 = mp.mpcg_workspace_size(512, 512, 512, 512, mp.MPCG_3M, mp.MPCG_EXACT, None, 16)
+    s2 = mp.mpcg_workspace_size(512, 512, 512, 512, mp.MPCG_3M, mp.MPCG_TRUNCATED, None, 16)
+    s3 = mp.mpcg_workspace_size(512, 512, 512, 1024, mp.MPCG_3M, mp.MPCG_EXACT, None, 16)
+    assert 0 < s2 < s1 < s3
+    assert mp.mpcg_workspace_size(0, 5, 5, 256) == 0
+
+
+def test_injected_hip_failure_is_reported():
+    """MPCG_FAULT_INJECT=hip makes the first HIP call fail: the status is MPCG_EHIP."""
+    code = (
+        "import ctypes, sys\n"
+        f"sys.path.insert(0, {ROOT!r})\n"
+        "from tests.test_abi import _call\n"
+        "import paper_2307_06072_amd as mp\n"
+        "rc = _call(k=0)\n"
+        "print(rc, mp.mpcg_last_error())\n"
+        "sys.exit(0 if rc == mp.MPCG_EHIP else 1)\n")
+    env = dict(os.environ, MPCG_FAULT_INJECT="hip", HIP_VISIBLE_DEVICES="")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr

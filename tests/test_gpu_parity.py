@@ -1,0 +1,130 @@
+"""Device path vs the CPU oracle, bit for bit (exact scheme) on seeded inputs.
+
+Every call goes through the C-ABI (libmpcgemm.so) via the thin binding.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from mpgen import EXP_ZERO, random_cmat, workload_inputs
+from tests.gpu_util import mismatches, run_device
+
+pytestmark = pytest.mark.gpu
+
+M4, M3 = 0, 1
+EXACT, TRUNC = 0, 1
+I8, F64 = 0, 1
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _check_exact(A, B, p, mode, slice_type=I8, **kw):
+    m, n = A.rows, B.cols
+    _say(f"case m={m} n={n} k={A.cols} p={p} mode={mode} slice={slice_type} {kw}")
+    C, info = run_device(A, B, p, mode, EXACT, slice_type, **kw)
+    R = oracle.cgemm(A, B, p)
+    bad, first = mismatches(C, R, m, n)
+    assert bad == 0, f"{bad} mismatching components, first {first}, info {info}"
+    return info
+
+
+@pytest.mark.parametrize("mode", [M4, M3])
+@pytest.mark.parametrize("slice_type", [I8, F64])
+def test_small_square_exact(mode, slice_type):
+    # 64 x 64 x 64 at 256 bits, exponents in [-4, 4]
+    m, n, k, p, A, B = workload_inputs("cgemm64_p256")
+    info = _check_exact(A, B, p, mode, slice_type)
+    assert info["nprod"] == (3 if mode == M3 else 4)
+
+
+@pytest.mark.parametrize("mode", [M4, M3])
+@pytest.mark.parametrize("slice_type", [I8, F64])
+@pytest.mark.parametrize("shape", [(37, 45, 71), (1, 1, 1), (16, 48, 130), (50, 3, 200)])
+def test_ragged_exact(mode, slice_type, shape):
+    m, n, k = shape
+    p = 130
+    A = random_cmat(11, 0, m, k, p, 10, zero_frac=0.15)
+    B = random_cmat(11, 1, k, n, p, 10, zero_frac=0.15)
+    _check_exact(A, B, p, mode, slice_type)
+
+
+@pytest.mark.parametrize("block", [4, 6, 8])
+@pytest.mark.parametrize("ksplit", [1, 2, 3])
+def test_tiling_independent(block, ksplit):
+    """Register-block size and contraction chunks never change the bits."""
+    m, n, k, p = 40, 36, 300, 200
+    A = random_cmat(5, 0, m, k, p, 6)
+    B = random_cmat(5, 1, k, n, p, 6)
+    _check_exact(A, B, p, M3, I8, block_override=block, ksplit_override=ksplit)
+    _check_exact(A, B, p, M4, I8, block_override=block, ksplit_override=ksplit)
+
+
+@pytest.mark.parametrize("p", [2, 3, 53, 64, 65, 127, 512, 1024])
+def test_precisions(p):
+    A = random_cmat(p, 0, 20, 33, p, 5)
+    B = random_cmat(p, 1, 33, 18, p, 5)
+    _check_exact(A, B, p, M3)
+    _check_exact(A, B, p, M4)
+
+
+def test_wide_exponent_spread():
+    p = 96
+    A = random_cmat(21, 0, 24, 40, p, 70)
+    B = random_cmat(21, 1, 40, 24, p, 70)
+    _check_exact(A, B, p, M3)
+    _check_exact(A, B, p, M4, F64)
+
+
+def test_all_zero_and_k_zero():
+    p = 64
+    A = random_cmat(3, 0, 8, 8, p, 2, zero_frac=1.0)
+    B = random_cmat(3, 1, 8, 8, p, 2)
+    C, _ = run_device(A, B, p, M3, EXACT)
+    assert (C.re.exp[:8, :8] == EXP_ZERO).all() and (C.im.exp[:8, :8] == EXP_ZERO).all()
+
+
+def test_cancellation_to_zero():
+    """Terms that cancel exactly: full cancellation gives +0, partial cancellation stays exact."""
+    p = 64
+    for k in (2, 10):
+        A = random_cmat(8, 0, 6, k, p, 3)
+        B = random_cmat(8, 1, k, 6, p, 3)
+        # column 1 of A is minus column 0, row 1 of B equals row 0: those terms cancel
+        for part in (A.re, A.im):
+            part.exp[1] = part.exp[0]
+            part.mant[:, 1] = part.mant[:, 0]
+            part.sign[1] = part.sign[0] ^ 1
+        for part in (B.re, B.im):
+            part.exp[:, 1] = part.exp[:, 0]
+            part.mant[:, :, 1] = part.mant[:, :, 0]
+            part.sign[:, 1] = part.sign[:, 0]
+        _check_exact(A, B, p, M3)
+        _check_exact(A, B, p, M4)
+        if k == 2:
+            C, _ = run_device(A, B, p, M3, EXACT)
+            assert (C.re.exp[:6, :6] == EXP_ZERO).all() and (C.im.exp[:6, :6] == EXP_ZERO).all()
+
+
+def test_config_512_p512_sampled():
+    """512 x 512 x 512 at 512 bits: every output checked on a sample, all 4 forms."""
+    m, n, k, p, A, B = workload_inputs("cgemm512_p512")
+    rng = np.random.default_rng(2)
+    rows = np.concatenate([rng.integers(0, m, 600), [0, m - 1, 0, m - 1]])
+    cols = np.concatenate([rng.integers(0, n, 600), [0, 0, n - 1, n - 1]])
+    s, e, mm = oracle.cgemm_entries(A, B, rows, cols, p)
+    for mode, st in [(M3, I8), (M4, I8), (M4, F64)]:
+        _say(f"config512 mode={mode} slice={st}")
+        C, info = run_device(A, B, p, mode, EXACT, st)
+        for t, (i, j) in enumerate(zip(rows, cols)):
+            for comp, part in enumerate((C.re, C.im)):
+                assert part.exp[j, i] == e[t, comp], (mode, st, i, j, comp)
+                if e[t, comp] != EXP_ZERO:
+                    assert part.sign[j, i] == s[t, comp]
+                    assert np.array_equal(part.mant[:, j, i], mm[t, comp])
