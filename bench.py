@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Benchmark of the Ozaki-scheme multi-precision complex GEMM on one MI355X.
+
+Default workload: C = AB with m = n = k = 2048 at 1024-bit precision,
+exponents uniform on [-32, 32] (INT8 slices, 3M form, exact scheme).  A step
+is one whole mp_cgemm call (exponent scan, split, slice GEMM, rounding) with
+the inputs already resident in HBM.  Prints ONE JSON line on stdout; progress
+goes to stderr.
+
+Also reported in "extra": the 512^3 / 512-bit family (FP64-slice 4M vs
+INT8-slice 4M vs INT8-slice 3M, exact and truncated) with the INT8-3M over
+FP64-4M speedup, and the truncated scheme on the default workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MP complex GEMM 8mnk/s at 256/1024-bit; INT8-3M vs FP64-4M Ozaki speedup"
+PEAK_INT8_TOPS = 5000.0   # MI355X dense INT8 matrix peak, TOP/s
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 matrix peak, TFLOP/s
+PEAK_HBM_GBS = 8000.0     # MI355X HBM3E, GB/s
+
+
+def log(msg: str) -> None:
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def _mode(s):
+    import paper_2307_06072_amd as mp
+    return {"3M": mp.MPCG_3M, "4M": mp.MPCG_4M}[s]
+
+
+def _scheme(s):
+    import paper_2307_06072_amd as mp
+    return {"exact": mp.MPCG_EXACT, "truncated": mp.MPCG_TRUNCATED}[s]
+
+
+def _slice(s):
+    import paper_2307_06072_amd as mp
+    return {"int8": mp.MPCG_SLICE_INT8, "fp64": mp.MPCG_SLICE_FP64}[s]
+
+
+def time_calls(dA, dB, dC, m, n, k, p, mode, scheme, slice_type, steps, warmup):
+    """Warm up, then time `steps` whole calls; returns (seconds, info, avg stage us)."""
+    import torch
+    import paper_2307_06072_amd as mp
+    mp.mpcg_set_stream()
+    info = None
+    for _ in range(warmup):
+        info = mp.mp_cgemm_ex(m, n, k, dA, dA.ld, dB, dB.ld, dC, dC.ld, p, mode, scheme, slice_type=slice_type)
+    torch.cuda.synchronize()
+    mp.mpcg_enable_timing(True)
+    mp.mpcg_timing_report()  # start a fresh collection
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        info = mp.mp_cgemm_ex(m, n, k, dA, dA.ld, dB, dB.ld, dC, dC.ld, p, mode, scheme, slice_type=slice_type)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    us_sum, ncalls = mp.mpcg_timing_report()
+    mp.mpcg_enable_timing(False)
+    st = mp.mpcg_stream_status()
+    if st != 0:
+        raise RuntimeError(f"device status {st}: {mp.mpcg_last_error()}")
+    avg = [u / max(1, ncalls) for u in us_sum]
+    return t1 - t0, info, avg
+
+
+def stage_bytes(m, n, k, p, info, mode3m, slice_fp64):
+    """Algorithmic HBM bytes of the split and round stages (per call)."""
+    L = (p + 63) // 64
+    esz = 8 if slice_fp64 else 1
+    ent_in = 2 * (8 * L + 5)  # Re + Im: limbs, exponent, sign
+    nops_a = 3 if mode3m else 2
+    nops_b = 3
+    split = (m * k + k * n) * ent_in + (m * k * nops_a * info["S_A"] + k * n * nops_b * info["S_B"]) * esz
+    nd = info["cutoff"] + 1
+    dig = 4 if slice_fp64 else 1
+    rnd = m * n * 2 * (nd * dig * info["ksplit"] + 12) + m * n * ent_in
+    return split, rnd
+
+
+def traffic_record(kernel_src: str):
+    """HBM traffic of the slice GEMM from committed rocprofv3 counters, if they
+    were taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "gemm_i8_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(kernel_src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(A, B, m, n, k, p, target_s):
+    """The oracle on a bounded sample of output entries, all host threads."""
+    import numpy as np
+    import oracle
+    threads = oracle.default_threads()
+    rng = np.random.default_rng(12345)
+    probe = max(threads, 8)
+    rows = rng.integers(0, m, probe)
+    cols = rng.integers(0, n, probe)
+    t0 = time.perf_counter()
+    oracle.cgemm_entries(A, B, rows, cols, p, nthreads=threads)
+    per = (time.perf_counter() - t0) / probe
+    nent = int(max(threads, min(m * n, target_s / max(per, 1e-9))))
+    rows = rng.integers(0, m, nent)
+    cols = rng.integers(0, n, nent)
+    log(f"cpu baseline: oracle on {nent} entries with {threads} threads")
+    t0 = time.perf_counter()
+    oracle.cgemm_entries(A, B, rows, cols, p, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": 8.0 * k * nent / dt, "unit": "8mnk/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nent} random output entries (both components) of the {m}x{n}x{k} product, "
+                      f"{dt:.1f} s wall on {threads} threads; value = 8*k*entries/s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cgemm2048_p1024")
+    ap.add_argument("--mode", default="3M", choices=["3M", "4M"])
+    ap.add_argument("--scheme", default="exact", choices=["exact", "truncated"])
+    ap.add_argument("--slice", default="int8", choices=["int8", "fp64"])
+    ap.add_argument("--no-extras", action="store_true", help="skip the comparison family")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures one GPU only; --gpus must be 1 "
+              "(the product shards by output blocks without any exchange, see the design notes)",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2307_06072_amd as mp
+    from mpgen import workload_inputs
+
+    torch.cuda.set_device(0)
+    log(f"generating {args.workload}")
+    m, n, k, p, A, B = workload_inputs(args.workload)
+    dA, dB = mp.to_device(A), mp.to_device(B)
+    dC = mp.device_empty(m, n, p)
+    torch.cuda.synchronize()
+    mode, scheme, sl = _mode(args.mode), _scheme(args.scheme), _slice(args.slice)
+    log(f"timing {args.steps} steps after {args.warmup} warmup ({args.slice} {args.mode} {args.scheme})")
+    dt, info, stages = time_calls(dA, dB, dC, m, n, k, p, mode, scheme, sl, args.steps, args.warmup)
+    ms = 1000.0 * dt / args.steps
+    value = 8.0 * m * n * k * args.steps / dt
+    log(f"{ms:.3f} ms/step, {value:.4e} 8mnk/s; stages us {['%.1f' % s for s in stages]}")
+
+    gemm_us = stages[2]
+    if args.slice == "int8":
+        achieved = info["algo_ops"] / (gemm_us * 1e-6) / 1e12
+        peak, unit = PEAK_INT8_TOPS, "TOP/s"
+    else:
+        achieved = info["algo_ops"] / (gemm_us * 1e-6) / 1e12
+        peak, unit = PEAK_FP64_TFLOPS, "TFLOP/s"
+    src = os.path.join(ROOT, "paper_2307_06072_amd", "csrc", "gemm_i8.hip")
+    roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
+            "traffic": traffic_record(src) if args.slice == "int8" else None,
+            "kernel": "gemm_i8_kernel (slice-pair GEMM + carry chain)" if args.slice == "int8"
+            else "gemm_f64_kernel", "algo_ops_per_launch": info["algo_ops"], "avg_launch_us": gemm_us}
+    split_b, round_b = stage_bytes(m, n, k, p, info, args.mode == "3M", args.slice == "fp64")
+    stage_report = {
+        "scan_us": stages[0], "split_us": stages[1], "gemm_us": stages[2], "round_us": stages[3],
+        "split_GBps": split_b / (stages[1] * 1e-6) / 1e9 if stages[1] > 0 else None,
+        "round_GBps": round_b / (stages[3] * 1e-6) / 1e9 if stages[3] > 0 else None,
+        "hbm_peak_GBps": PEAK_HBM_GBS,
+        "note": "split/scan include the scan read-back synchronisation; bytes are algorithmic",
+    }
+
+    extra = {}
+    if not args.no_extras:
+        log("comparison family 512^3 at 512 bits")
+        m2, n2, k2, p2, A2, B2 = workload_inputs("cgemm512_p512")
+        dA2, dB2 = mp.to_device(A2), mp.to_device(B2)
+        dC2 = mp.device_empty(m2, n2, p2)
+        fam = {}
+        for sl2, md2, sc2 in [("fp64", "4M", "exact"), ("int8", "4M", "exact"), ("int8", "3M", "exact"),
+                              ("fp64", "4M", "truncated"), ("int8", "4M", "truncated"),
+                              ("int8", "3M", "truncated")]:
+            dt2, info2, st2 = time_calls(dA2, dB2, dC2, m2, n2, k2, p2, _mode(md2), _scheme(sc2), _slice(sl2),
+                                         steps=5, warmup=1)
+            key = f"{sl2}_{md2}_{sc2}"
+            peak2 = PEAK_FP64_TFLOPS if sl2 == "fp64" else PEAK_INT8_TOPS
+            fam[key] = {"ms_per_call": 1000 * dt2 / 5, "8mnk_per_s": 8.0 * m2 * n2 * k2 * 5 / dt2,
+                        "gemm_us": st2[2], "gemm_frac_of_peak": info2["algo_ops"] / (st2[2] * 1e-6) / 1e12 / peak2,
+                        "S_A": info2["S_A"], "cutoff": info2["cutoff"], "pairs": info2["pairs"]}
+            log(f"  {key}: {fam[key]['ms_per_call']:.3f} ms")
+        fam["speedup_int8_3m_over_fp64_4m_exact"] = fam["fp64_4M_exact"]["ms_per_call"] / fam["int8_3M_exact"]["ms_per_call"]
+        fam["speedup_int8_3m_over_fp64_4m_truncated"] = (fam["fp64_4M_truncated"]["ms_per_call"] /
+                                                         fam["int8_3M_truncated"]["ms_per_call"])
+        extra["cgemm512_p512"] = fam
+        del dA2, dB2, dC2
+        if args.workload == "cgemm2048_p1024" and args.scheme == "exact":
+            log("default workload, truncated scheme")
+            dtt, infot, stt = time_calls(dA, dB, dC, m, n, k, p, mode, _scheme("truncated"), sl, steps=2, warmup=1)
+            extra["cgemm2048_p1024_truncated"] = {"ms_per_call": 1000 * dtt / 2, "8mnk_per_s": 8.0 * m * n * k * 2 / dtt,
+                                                  "cutoff": infot["cutoff"], "pairs": infot["pairs"],
+                                                  "gemm_frac_of_peak": infot["algo_ops"] / (stt[2] * 1e-6) / 1e12 / PEAK_INT8_TOPS}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(A, B, m, n, k, p, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "8mnk/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "i8" if args.slice == "int8" else "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload} {args.slice.upper()}-{args.mode} {args.scheme}", "m": m, "n": n,
+                   "k": k, "prec_bits": p, "mode": args.mode, "scheme": args.scheme, "slice": args.slice,
+                   "S_A": info["S_A"], "S_B": info["S_B"], "cutoff": info["cutoff"], "pairs": info["pairs"],
+                   "ksplit": info["ksplit"], "block": info["block"]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "stages": stage_report,
+        "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -166,6 +166,11 @@ const char *mpcg_last_error(void);
 int mpcg_enable_timing(int on);
 int mpcg_last_timing(float us[4]);
 
+/* Sum of the per-stage kernel times (us) over every multiplication issued
+ * since timing was enabled or since the previous report, and their number;
+ * synchronizes with the last recorded event and starts a new collection. */
+int mpcg_timing_report(float us_sum[4], int *ncalls);
+
 #ifdef __cplusplus
 }
 #endif

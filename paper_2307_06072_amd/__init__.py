@@ -86,9 +86,12 @@ _lib.mpcg_enable_timing.argtypes = [_i]
 _lib.mpcg_enable_timing.restype = _i
 _lib.mpcg_last_timing.argtypes = [_P(ctypes.c_float)]
 _lib.mpcg_last_timing.restype = _i
+_lib.mpcg_timing_report.argtypes = [_P(ctypes.c_float), _P(ctypes.c_int)]
+_lib.mpcg_timing_report.restype = _i
 
 EXPORTS = ["mp_cgemm", "mp_cgemm_ex", "mpcg_set_stream", "mpcg_set_workspace", "mpcg_workspace_size",
-           "mpcg_stream_status", "mpcg_last_error", "mpcg_enable_timing", "mpcg_last_timing"]
+           "mpcg_stream_status", "mpcg_last_error", "mpcg_enable_timing", "mpcg_last_timing",
+           "mpcg_timing_report"]
 
 
 class MPCGError(RuntimeError):
@@ -212,6 +215,14 @@ def mpcg_last_timing():
     us = (ctypes.c_float * 4)()
     _check(_lib.mpcg_last_timing(us))
     return list(us)
+
+
+def mpcg_timing_report():
+    """(per-stage microseconds summed over the recorded calls, number of calls)."""
+    us = (ctypes.c_float * 4)()
+    n = ctypes.c_int(0)
+    _check(_lib.mpcg_timing_report(us, ctypes.byref(n)))
+    return list(us), n.value
 
 
 def mp_cgemm_raw(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, mode, scheme) -> int:

@@ -11,6 +11,8 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <array>
+#include <vector>
 
 #include "../../include/mpcgemm.h"
 #include "mpcg_internal.h"
@@ -35,8 +37,11 @@ int* g_status = nullptr;  // persistent device status word
 ScanSummary* g_host_summary = nullptr;  // pinned
 int g_fault_inject = -1;  // test hook: MPCG_FAULT_INJECT=hip makes HIP calls fail
 
+// per-call stage events: [call][boundary], boundaries = start, after scan,
+// after split, after slice GEMM, after round
 bool g_timing = false;
-hipEvent_t g_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+std::vector<std::array<hipEvent_t, 5>> g_ev;
+int g_ncalls = 0;          // calls recorded since the last report
 bool g_timing_valid = false;
 
 int set_err(int code, const char* fmt, ...) {
@@ -259,8 +264,15 @@ int ensure_workspace(size_t bytes, void** ptr) {
 
 int record(int idx) {
   if (!g_timing) return MPCG_OK;
-  if (!g_ev[idx]) HIP_TRY(hipEventCreate(&g_ev[idx]));
-  HIP_TRY(hipEventRecord(g_ev[idx], g_stream));
+  if (idx == 0) {
+    if (g_ncalls == (int)g_ev.size()) {
+      std::array<hipEvent_t, 5> ev{};
+      for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+      g_ev.push_back(ev);
+    }
+    ++g_ncalls;
+  }
+  HIP_TRY(hipEventRecord(g_ev[g_ncalls - 1][idx], g_stream));
   return MPCG_OK;
 }
 
@@ -482,13 +494,40 @@ int mpcg_enable_timing(int on) {
 int mpcg_last_timing(float us[4]) {
   std::lock_guard<std::mutex> lock(g_mu);
   if (!us) return set_err(MPCG_EINVAL, "NULL output");
-  if (!g_timing_valid) return set_err(MPCG_EINVAL, "no timed multiplication");
-  HIP_TRY(hipEventSynchronize(g_ev[4]));
+  if (!g_timing_valid || g_ncalls == 0) return set_err(MPCG_EINVAL, "no timed multiplication");
+  const auto& ev = g_ev[g_ncalls - 1];
+  HIP_TRY(hipEventSynchronize(ev[4]));
   for (int s = 0; s < 4; ++s) {
     float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, g_ev[s], g_ev[s + 1]));
+    HIP_TRY(hipEventElapsedTime(&ms, ev[s], ev[s + 1]));
     us[s] = ms * 1000.f;
   }
+  return MPCG_OK;
+}
+
+int mpcg_timing_report(float us_sum[4], int* ncalls) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  if (!us_sum || !ncalls) return set_err(MPCG_EINVAL, "NULL output");
+  for (int s = 0; s < 4; ++s) us_sum[s] = 0.f;
+  *ncalls = 0;
+  if (g_ncalls == 0) return MPCG_OK;
+  HIP_TRY(hipEventSynchronize(g_ev[g_ncalls - 1][4]));
+  int done = 0;
+  for (int c = 0; c < g_ncalls; ++c) {
+    float st[4];
+    bool ok = true;
+    for (int s = 0; s < 4 && ok; ++s) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, g_ev[c][s], g_ev[c][s + 1]) != hipSuccess) ok = false;
+      st[s] = ms * 1000.f;
+    }
+    if (!ok) continue;  // a call that returned early (zero result) recorded fewer events
+    for (int s = 0; s < 4; ++s) us_sum[s] += st[s];
+    ++done;
+  }
+  *ncalls = done;
+  g_ncalls = 0;
+  g_timing_valid = false;
   return MPCG_OK;
 }
 
