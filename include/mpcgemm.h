@@ -110,7 +110,8 @@ typedef struct {
     int cutoff_override;  /* truncated scheme: > 0 keeps pairs with s + t <= cutoff_override
                              (no error bound is then promised); 0 = derived cutoff */
     int ksplit_override;  /* > 0: number of contraction chunks; 0 = planner's choice */
-    int block_override;   /* > 0: slices per register block in the INT8 slice GEMM (4, 6 or 8) */
+    int block_override;   /* > 0: band width of the INT8 slice GEMM, the number of consecutive
+                             anti-diagonals s + t a wavefront accumulates at once (8, 12 or 16) */
 } mpcg_options;
 
 /* Plan and timing report of one multiplication. */
@@ -120,7 +121,7 @@ typedef struct {
     int cutoff;           /* highest kept diagonal s + t */
     int nprod;            /* real slice products per slice pair: 4 (4M) or 3 (3M) */
     int ksplit;           /* contraction chunks */
-    int block;            /* slices per register block (INT8) */
+    int block;            /* band width of the INT8 slice GEMM (2 for FP64: pair block) */
     int reserved;
     long long pairs;      /* kept slice pairs (s, t) */
     double algo_ops;      /* 2*m*n*k*pairs*nprod: slice-product operations */

@@ -91,14 +91,15 @@ struct GemmArgs {
   int mt, nt;        // 16-row tiles of A, 16-column tiles of B
   int kblocks;       // Kpad / 64 (INT8) or Kpad / 4 (FP64)
   int ksplit;        // contraction chunks
-  int SAp, SBp;      // padded slice counts (multiples of the block)
+  int SAp, SBp;      // slice counts of the A and B planes
   int Dmax;          // highest emitted diagonal
   int mode3m;        // 1: planes are (Re, Im, Re+Im) on both sides; 0: A (Re, Im), B (Re, Im, -Im)
   void* digits;      // [ksplit][tiles][Dmax+1][64][8] digit type
   int64_t* top;      // [ksplit][tiles][64][8]
   int32_t* lnz;      // [ksplit][tiles][64][8]
+  const int8_t* zero;  // 1 KB of zeros: stands in for fragments outside the operand
 };
-hipError_t launch_gemm_i8(const GemmArgs& a, int block, hipStream_t stream);
+hipError_t launch_gemm_i8(const GemmArgs& a, int band, hipStream_t stream);
 
 struct GemmF64Args {
   const double* X;
@@ -127,6 +128,9 @@ struct RoundArgs {
   int* status;
 };
 hipError_t launch_round(const RoundArgs& a, hipStream_t stream);
+
+// bytes[0 .. n) := 0 (a kernel, so that the call stays capturable).
+hipError_t launch_fill_zero(void* p, size_t n, hipStream_t stream);
 
 // C := +0 everywhere.
 hipError_t launch_zero(DOutPart cre, DOutPart cim, int m, int n, int64_t ldc, int L, hipStream_t stream);

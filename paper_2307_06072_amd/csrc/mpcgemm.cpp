@@ -115,7 +115,7 @@ struct Plan {
   int nopsA, nopsB;
   long long pairs;
   double algo_ops, bound_bits;
-  size_t off_G, off_H, off_X, off_Y, off_dig, off_top, off_lnz, total;
+  size_t off_G, off_H, off_X, off_Y, off_dig, off_top, off_lnz, off_zero, total;
 };
 
 int plan_slices(Plan& P, int spreadA, int spreadB, int hatA, int hatB, const mpcg_options* opt) {
@@ -164,11 +164,12 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
   P.nopsB = 3;
   const int groups = (P.mpad / 32) * (P.npad / 32);
   if (!P.f64) {
-    P.block = (opt && opt->block_override) ? opt->block_override : 4;
-    if (P.block != 4 && P.block != 6 && P.block != 8)
-      return set_err(MPCG_EINVAL, "block_override must be 4, 6 or 8");
-    P.SAp = (int)round_up(P.SA, P.block);
-    P.SBp = (int)round_up(P.SB, P.block);
+    // band width: diagonals accumulated together by one wavefront
+    P.block = (opt && opt->block_override) ? opt->block_override : 16;
+    if (P.block != 8 && P.block != 12 && P.block != 16)
+      return set_err(MPCG_EINVAL, "block_override (band width) must be 8, 12 or 16");
+    P.SAp = P.SA;
+    P.SBp = P.SB;
     P.kblocks = P.kpad / 64;
     // int32 accumulators: terms per diagonal * 64*64 must stay below 2^31
     const long long terms_per_k = (long long)(P.mode3m ? 1 : 2) * std::min(P.SA, P.SB);
@@ -213,6 +214,7 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
   P.off_dig = o; o = align256(o + (size_t)P.ksplit * tiles * nd * 512 * dig_bytes);
   P.off_top = o; o = align256(o + (size_t)P.ksplit * tiles * 512 * 8);
   P.off_lnz = o; o = align256(o + (size_t)P.ksplit * tiles * 512 * 4);
+  P.off_zero = o; o = align256(o + 1024);
   P.total = o;
   return MPCG_OK;
 }
@@ -401,6 +403,8 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
     ga.mt = P.mt; ga.nt = P.nt; ga.kblocks = P.kblocks; ga.ksplit = P.ksplit;
     ga.SAp = P.SAp; ga.SBp = P.SBp; ga.Dmax = P.Dmax; ga.mode3m = P.mode3m;
     ga.digits = base + P.off_dig; ga.top = top; ga.lnz = lnz;
+    ga.zero = reinterpret_cast<const int8_t*>(base + P.off_zero);
+    HIP_TRY(launch_fill_zero(base + P.off_zero, 1024, g_stream));
     HIP_TRY(launch_gemm_i8(ga, P.block, g_stream));
   } else {
     GemmF64Args ga{};

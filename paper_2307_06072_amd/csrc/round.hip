@@ -223,7 +223,18 @@ __global__ void zero_kernel(DOutPart cre, DOutPart cim, int m, int n, int64_t ld
   for (int l = 0; l < L; ++l) out.mant[(int64_t)l * out.ls + o] = 0;
 }
 
+__global__ void fill_zero_kernel(uint32_t* p, size_t n32) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n32) p[i] = 0;
+}
+
 }  // namespace
+
+hipError_t launch_fill_zero(void* p, size_t n, hipStream_t stream) {
+  const size_t n32 = (n + 3) / 4;  // caller allocations are 256-byte aligned and rounded
+  fill_zero_kernel<<<dim3((unsigned)((n32 + 255) / 256)), dim3(256), 0, stream>>>(static_cast<uint32_t*>(p), n32);
+  return hipGetLastError();
+}
 
 hipError_t launch_round(const RoundArgs& a, hipStream_t stream) {
   const int64_t total = (int64_t)a.m * a.n * 2;

@@ -55,10 +55,10 @@ def test_ragged_exact(mode, slice_type, shape):
     _check_exact(A, B, p, mode, slice_type)
 
 
-@pytest.mark.parametrize("block", [4, 6, 8])
+@pytest.mark.parametrize("block", [8, 12, 16])
 @pytest.mark.parametrize("ksplit", [1, 2, 3])
 def test_tiling_independent(block, ksplit):
-    """Register-block size and contraction chunks never change the bits."""
+    """Band width and contraction chunks never change the bits."""
     m, n, k, p = 40, 36, 300, 200
     A = random_cmat(5, 0, m, k, p, 6)
     B = random_cmat(5, 1, k, n, p, 6)
