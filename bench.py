@@ -140,6 +140,8 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true", help="skip the comparison family")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -154,6 +156,15 @@ def main() -> int:
     from mpgen import workload_inputs
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        n = args.copy_probe // 4
+        src = torch.ones(n, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 3}))
+        return 0
     log(f"generating {args.workload}")
     m, n, k, p, A, B = workload_inputs(args.workload)
     dA, dB = mp.to_device(A), mp.to_device(B)

@@ -12,24 +12,37 @@
 // Work of one wavefront: a 16 x 16 output tile (v_mfma_i32_16x16x64_i8) and a
 // contraction chunk.  The diagonals are processed in bands of W consecutive
 // diagonals [d0, d0 + W), least significant band first, with one int32
-// accumulator per diagonal (and per real product).  Inside a band and a 64-wide
-// k-block the wave walks s upward; the B fragments Y_t with s + t in the band
-// form a sliding window of W registers (a ring: slot t mod W), so each step
-// loads one A fragment X_s and one new B fragment Y_{d0-s} and issues W MFMAs
-// (every pair (s, t) of the band exactly once).  Loads run PF steps ahead of
-// their use through a small register queue.
+// accumulator per diagonal (and per real product).  A band is worked in units
+// (band, pass, 64-wide k-block); inside a unit the wave walks s upward and the
+// B fragments Y_t with s + t in the band form a sliding window of W registers
+// (a ring: the fragment loaded at step v enters slot v mod W), so each step
+// needs one A fragment X_s and one new B fragment Y_{d0-s} and issues W MFMAs
+// (every pair (s, t) of the band exactly once).  A unit starts with W steps
+// that only fill the ring and has an even number of steps (it may end with
+// one step on zero fragments).
+//
+// Operand fragments (16 rows x 64 k, 16 bytes per lane) stream from the digit
+// planes into a workgroup-shared queue in LDS by direct global->LDS loads
+// (16 bytes per lane: one fragment per instruction).  A queue entry holds the
+// fragments of two consecutive steps for the workgroup's 2 x 2 tiles; each
+// fragment is loaded once and read by the two wavefronts that need it.  The
+// four wavefronts walk the (band, pass, k-block, step pair) sequence in
+// lockstep, each issuing a quarter of the loads QS - 2 entries ahead; one
+// barrier per entry publishes the loads, and every wavefront reads its
+// fragments from LDS two entries ahead of their use.  This keeps about 2 QS
+// steps of loads in flight without spending registers on them.  Fragments outside the operand are read from a zero block, so no
+// load is conditional.
 //
 // When a band is complete its W diagonals are combined into Re and Im
-// (4M, eq. 5: the accumulators already hold Re and Im, the B side supplying
+// (4M, eq. 5: the accumulators hold Re and Im directly, the B side supplying
 // -Im B; 3M, eq. 6: T1, T2, T3 with Re = T1 - T2, Im = T3 - T1 - T2) and pushed,
 // least significant first, through a per-element int64 carry chain that emits
 // one normalised base-2^7 digit per diagonal; the final carry is the signed top
 // of the exact result.
 //
-// Operand fragments (16 rows x 64 k, 16 bytes per lane) are read straight
-// from the digit planes of the split kernel.  Workgroups are 2 x 2 tiles; their
-// order is XCD-aware so that the workgroups resident on one XCD cover a compact
-// block of the output and share operand panels in that XCD's L2.
+// Workgroups are 2 x 2 tiles; their order is XCD-aware so that the workgroups
+// resident on one XCD cover a compact block of the output and share operand
+// panels in that XCD's L2.
 #include "mpcg_internal.h"
 
 namespace mpcg {
@@ -37,12 +50,21 @@ namespace mpcg {
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void;
 
 __device__ inline v4i mfma(v4i a, v4i b, v4i c) {
   return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
 }
 
-__device__ inline v4i ld(const int8_t* p) { return *reinterpret_cast<const v4i*>(p); }
+// s_waitcnt constraining only the vector-memory counter (gfx9 encoding: vmcnt
+// in bits 3:0 and 15:14; expcnt bits 6:4 and lgkmcnt bits 11:8 left at their
+// maxima).  The compiler does not relate direct-to-LDS loads to later LDS
+// reads, so the queue states its own waits.
+template <int N>
+__device__ inline void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
 
 // Workgroup -> (contraction chunk, 2x2 tile group).  Blocks are dispatched to
 // the 8 XCDs round-robin; consecutive blocks of one XCD get consecutive
@@ -62,93 +84,272 @@ __device__ inline void map_block(int b, int nblk, int gm, int gn, int& split, in
   gj = in / rows_here;
 }
 
-// One pass over a band: A plane xa, B plane y0 into accumulator Q0 and, when
-// TWO, B plane y1 into accumulator Q1 (both sharing the A fragment).
-//
-// Step u = s - s_lo loads the new fragment B_{d0-s} into ring slot u mod W;
-// slot r then holds the B fragment of diagonal d0 + ((u - r) mod W), so every
-// register index is static inside the W-step unrolled body.  Pairs whose t
-// falls outside [0, SB) meet a zero fragment: they are issued but add nothing,
-// which keeps the MFMA stream free of branches (branches there would force the
-// compiler to wait for every outstanding load before each MFMA).
-template <int W, int PF, bool TWO, int Q0, int Q1, int NACC>
-__device__ __forceinline__ void band_pass(v4i (&acc)[NACC][W], const int8_t* xa_base, const int8_t* y0_base,
-                                          const int8_t* y1_base, const int8_t* zp, size_t xplane, size_t yplane,
-                                          int d0, int s_lo, int s_hi, int SB, int kb0, int kb1) {
-  static_assert(W % PF == 0, "look-ahead depth must divide the band width");
-  // fragments outside the operand (t < 0, t >= SB, s > s_hi) are read from a
-  // zero block: every load is unconditional, only its address is selected
-#define MPCG_YA(base, t) (((t) >= 0 && (t) < SB) ? (base) + (size_t)(t) * yplane + ko : zp)
-#define MPCG_XA(s) (((s) <= s_hi) ? xa_base + (size_t)(s) * xplane + ko : zp)
-#pragma unroll 1
-  for (int kb = kb0; kb < kb1; ++kb) {
-    const size_t ko = (size_t)kb * 1024;
-    // window before the first step: t = d0 - s_lo + q, q = 1..W-1, in slot W - q
-    v4i ring0[W], ring1[TWO ? W : 1];
+// Band geometry: diagonals [d0, d0 + W) and the s range holding its pairs.
+struct Band {
+  int d0, s_lo, s_hi;
+  __device__ inline void set(int band, int W, int Dmax, int SA, int SB) {
+    d0 = Dmax + 1 - W * (band + 1);
+    s_lo = max(0, d0 - (SB - 1));
+    s_hi = min(SA - 1, d0 + W - 1);
+  }
+};
+
+// Compile-time shape of the fragment queue.  An entry holds two consecutive
+// steps; per step: the A fragment X_s of the workgroup's two row tiles and the
+// B fragments Y_{d0-s} of its two column tiles for each B plane.
+template <int W, bool M3>
+struct Q {
+  static constexpr int NB = M3 ? 1 : 2;     // B planes per step
+  static constexpr int E = 2 + 2 * NB;      // fragments per step
+  static constexpr int ENT = 2 * E;         // fragments per entry
+  static constexpr int PW = ENT / 4;        // loads each wavefront issues per entry
+  static constexpr int QS = M3 ? 16 : 12;   // entries in the queue
+  static constexpr int VM = (QS - 3) * PW;  // own loads still allowed in flight when the next entry must have landed
+  static constexpr int NPASS = M3 ? 3 : 2;
+  static constexpr int NACC = M3 ? 3 : 2;
+  static constexpr int CH = W / 2;          // entries per chunk (W steps: one turn of the ring)
+};
+
+// Steps of a unit (band, pass, k-block): s from s_lo - W (the first W steps
+// only fill the ring) on, padded with steps on zero fragments to a multiple of
+// 4 steps, i.e. an even number of entries.
+__device__ inline int unit_entries(const Band& g, int W) {
+  const int n = g.s_hi - (g.s_lo - W) + 1;
+  return ((n + 3) & ~3) >> 1;
+}
+
+// This wavefront's share of the loads, walking the (band, pass, k-block,
+// entry) sequence.  Load i of an entry is fragment f = wv * PW + i: the A
+// fragment of row tile c or a B fragment of column tile c, of step h of the
+// entry.  Within a unit its source moves by a constant stride per entry and is
+// valid on a precomputed range of entries (outside it the zero block is read),
+// so an entry costs a few scalar instructions per load.
+template <int W, bool M3>
+struct Producer {
+  using G = Q<W, M3>;
+  static constexpr int PW = G::PW;
+  const int8_t* zp;
+  size_t xplane, yplane;
+  int SA, SB, Dmax, nbands, kb0, kb1;
+  // per load (static index i)
+  const int8_t* tb[PW];  // lane-offset base of the tile's planes
+  int isa[PW], hh[PW], sel[PW], foff[PW];
+  // walk state
+  int band, pass, kb, e, ne;
+  Band g;
+  bool done;
+  int64_t off[PW], dlt[PW];
+  int elo[PW], ehi[PW];
+
+  __device__ inline void share(int wv, const int8_t* X0, const int8_t* X1, const int8_t* Y0, const int8_t* Y1) {
 #pragma unroll
-    for (int q = 1; q < W; ++q) {
-      const int t = d0 - s_lo + q;
-      ring0[W - q] = ld(MPCG_YA(y0_base, t));
-      if (TWO) ring1[W - q] = ld(MPCG_YA(y1_base, t));
+    for (int i = 0; i < PW; ++i) {
+      const int f = wv * PW + i;
+      const int h = f >= G::E ? 1 : 0, x = f - h * G::E;
+      const int a = x < 2 ? 1 : 0;
+      const int c = a ? x : ((x - 2) & 1);
+      tb[i] = a ? (c ? X1 : X0) : (c ? Y1 : Y0);
+      isa[i] = a;
+      hh[i] = h;
+      sel[i] = a ? 0 : ((x - 2) >> 1);
+      foff[i] = f * 1024;
     }
-    // look-ahead queue: the operands of step u sit in slot u mod PF
-    v4i qa[PF], qb0[PF], qb1[TWO ? PF : 1];
-#pragma unroll
-    for (int v = 0; v < PF; ++v) {
-      const int s = s_lo + v, t = s <= s_hi ? d0 - s : -1;
-      qa[v] = ld(MPCG_XA(s));
-      qb0[v] = ld(MPCG_YA(y0_base, t));
-      if (TWO) qb1[v] = ld(MPCG_YA(y1_base, t));
+  }
+
+  // set source offsets, strides and valid entry ranges for the unit (band, pass, kb)
+  __device__ inline void unit_begin() {
+    ne = unit_entries(g, W);
+    e = 0;
+    const int s0 = g.s_lo - W;
+    int pa, pb0, pb1;
+    if (M3) {
+      pa = pass; pb0 = pass; pb1 = 0;
+    } else {  // Re A with (Re B, Im B); Im A with (-Im B, Re B)
+      pa = pass; pb0 = pass == 0 ? 0 : 2; pb1 = pass == 0 ? 1 : 0;
     }
-    for (int s0 = s_lo; s0 <= s_hi; s0 += W) {
+    const int64_t ko = (int64_t)kb * 1024;
 #pragma unroll
-      for (int u = 0; u < W; ++u) {
-        const int s = s0 + u;
-        if (s > s_hi) break;
-        const v4i xa = qa[u % PF];
-        ring0[u] = qb0[u % PF];
-        if (TWO) ring1[u] = qb1[u % PF];
-        {  // refill the queue slot with step s + PF
-          const int sn = s + PF, tn = sn <= s_hi ? d0 - sn : -1;
-          qa[u % PF] = ld(MPCG_XA(sn));
-          qb0[u % PF] = ld(MPCG_YA(y0_base, tn));
-          if (TWO) qb1[u % PF] = ld(MPCG_YA(y1_base, tn));
-        }
-#pragma unroll
-        for (int r = 0; r < W; ++r) {
-          const int j = (u - r + W) % W;  // diagonal d0 + j
-          acc[Q0][j] = mfma(xa, ring0[r], acc[Q0][j]);
-          if (TWO) acc[Q1][j] = mfma(xa, ring1[r], acc[Q1][j]);
-        }
+    for (int i = 0; i < PW; ++i) {
+      const int h = hh[i];
+      // step of entry e: s = s0 + 2 e + h; valid while s <= s_hi and (A) s >= s_lo, (B) 0 <= d0 - s < SB
+      const int top = (g.s_hi - s0 - h) >> 1;  // last entry with s <= s_hi (floor)
+      if (isa[i]) {
+        off[i] = ((int64_t)pa * SA + s0 + h) * (int64_t)xplane + ko;
+        dlt[i] = 2 * (int64_t)xplane;
+        elo[i] = (g.s_lo - s0 - h + 1) >> 1;  // first entry with s >= s_lo (ceil)
+        ehi[i] = top;
+      } else {
+        const int pl = sel[i] ? pb1 : pb0;
+        const int t0 = g.d0 - s0 - h;  // t of entry 0
+        off[i] = ((int64_t)pl * SB + t0) * (int64_t)yplane + ko;
+        dlt[i] = -2 * (int64_t)yplane;
+        elo[i] = (t0 - (SB - 1) + 1) >> 1;  // first entry with t <= SB - 1 (ceil)
+        ehi[i] = min(top, t0 >> 1);         // last entry with t >= 0
       }
     }
   }
-#undef MPCG_YA
-#undef MPCG_XA
-}
+  __device__ inline void start() {
+    band = 0;
+    pass = 0;
+    kb = kb0;
+    g.set(0, W, Dmax, SA, SB);
+    done = false;
+    unit_begin();
+  }
+  __device__ inline void next_unit() {
+    if (++kb >= kb1) {
+      kb = kb0;
+      if (++pass >= G::NPASS) {
+        pass = 0;
+        if (++band >= nbands) {
+          done = true;
+          return;
+        }
+        g.set(band, W, Dmax, SA, SB);
+      }
+    }
+    unit_begin();
+  }
+  __device__ inline void advance() {
+#pragma unroll
+    for (int i = 0; i < PW; ++i) off[i] += dlt[i];
+    if (++e >= ne && !done) next_unit();
+  }
+  // issue this wavefront's loads of the current entry into the entry at `dst`
+  __device__ inline void issue(int8_t* dst) const {
+#pragma unroll
+    for (int i = 0; i < PW; ++i) {
+      const bool ok = !done && e >= elo[i] && e <= ehi[i];
+      const int8_t* src = ok ? (const int8_t*)((uintptr_t)tb[i] + (uintptr_t)off[i]) : zp;
+      __builtin_amdgcn_global_load_lds(src, (lds_void*)(dst + foff[i]), 16, 0, 0);
+    }
+  }
+};
+
+template <int W, bool M3>
+struct Consumer {
+  using G = Q<W, M3>;
+  static_assert(W % 4 == 0, "a ring turn is an even number of entries");
+  static constexpr int NB = G::NB, E = G::E, QS = G::QS, NACC = G::NACC;
+  int8_t* q;  // the workgroup's queue: QS entries of ENT KB
+  int lane, wi, wj;
+  int slot;   // queue entry of the current step pair
+  // fragments of the current entry (parity p) and of the next one (parity 1 - p)
+  v4i abuf[2][2], bbuf[2][2][NB];
+  v4i ring0[W], ring1[M3 ? 1 : W];
+
+  template <int P>
+  __device__ inline void read(int sl) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int8_t* base = q + (sl * G::ENT + h * E) * 1024 + lane * 16;
+      abuf[P][h] = *reinterpret_cast<const v4i*>(base + wi * 1024);
+#pragma unroll
+      for (int p = 0; p < NB; ++p) bbuf[P][h][p] = *reinterpret_cast<const v4i*>(base + (2 + 2 * p + wj) * 1024);
+    }
+  }
+
+  // One entry: ring steps V = 2C and 2C + 1 (V mod W static).  The entry two
+  // back has been used by every wavefront (they all passed the previous
+  // barrier), so its queue slot is refilled first; once this wavefront's loads
+  // of the next entry have landed, the barrier makes everybody's loads of it
+  // visible, and it is read into the other register buffer.
+  template <int C, bool MF, int Q0, int Q1>
+  __device__ inline void entry(v4i (&acc)[NACC][W], Producer<W, M3>& P) {
+    constexpr int PAR = C & 1;
+    const int back2 = slot >= 2 ? slot - 2 : slot + QS - 2;
+    P.issue(q + back2 * G::ENT * 1024);
+    P.advance();
+    wait_vmcnt<G::VM>();
+    __builtin_amdgcn_s_barrier();
+    read<1 - PAR>(slot + 1 == QS ? 0 : slot + 1);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      constexpr int V0 = 2 * C;
+      const int V = V0 + h;
+      ring0[V % W] = bbuf[PAR][h][0];
+      if (!M3) ring1[V % W] = bbuf[PAR][h][NB - 1];
+      if (MF) {
+#pragma unroll
+        for (int r = 0; r < W; ++r) {
+          const int j = (V - r + W) % W;  // slot r holds the B fragment of diagonal d0 + j
+          acc[Q0][j] = mfma(abuf[PAR][h], ring0[r], acc[Q0][j]);
+          if (!M3) acc[Q1][j] = mfma(abuf[PAR][h], ring1[r], acc[Q1][j]);
+        }
+      }
+    }
+    slot = slot + 1 == QS ? 0 : slot + 1;
+  }
+
+  template <int C, bool MF, int Q0, int Q1>
+  __device__ inline void chunk(v4i (&acc)[NACC][W], Producer<W, M3>& P, int left) {
+    if constexpr (C < G::CH) {
+      if (MF && left <= C) return;
+      entry<C, MF, Q0, Q1>(acc, P);
+      chunk<C + 1, MF, Q0, Q1>(acc, P, left);
+    }
+  }
+
+  // One unit: a chunk of ring-filling entries, then chunks with MFMAs.
+  template <int Q0, int Q1>
+  __device__ inline void unit(v4i (&acc)[NACC][W], Producer<W, M3>& P, const Band& g) {
+    const int ne = unit_entries(g, W);
+    chunk<0, false, Q0, Q1>(acc, P, G::CH);
+    for (int e0 = G::CH; e0 < ne; e0 += G::CH) chunk<0, true, Q0, Q1>(acc, P, ne - e0);
+  }
+};
 
 template <int W, bool M3>
 __global__ __launch_bounds__(256) void gemm_i8_kernel(GemmArgs a) {
-  constexpr int NACC = M3 ? 3 : 2;
-  constexpr int PF = W >= 16 ? 8 : 4;  // steps of load look-ahead
+  using G = Q<W, M3>;
+  using C = Consumer<W, M3>;
+  constexpr int NACC = G::NACC;
+  extern __shared__ __attribute__((aligned(1024))) int8_t lds_queue[];
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
   int split, gi, gj;
   map_block(blockIdx.x, gridDim.x, a.mt >> 1, a.nt >> 1, split, gi, gj);
-  const int ti = 2 * gi + (wv & 1);
-  const int tj = 2 * gj + (wv >> 1);
+  const int wi = wv & 1, wj = wv >> 1;
+  const int ti = 2 * gi + wi;
+  const int tj = 2 * gj + wj;
   const int tile = tj * a.mt + ti;
   const int kbps = (a.kblocks + a.ksplit - 1) / a.ksplit;
   const int kb0 = split * kbps;
   const int kb1 = min(a.kblocks, kb0 + kbps);
 
-  const size_t xplane = (size_t)a.mt * a.kblocks * 1024;  // bytes per (op, s) plane
-  const size_t yplane = (size_t)a.nt * a.kblocks * 1024;
-  const int8_t* Xb = a.X + (size_t)ti * a.kblocks * 1024 + lane * 16;
-  const int8_t* Yb = a.Y + (size_t)tj * a.kblocks * 1024 + lane * 16;
-  const int SA = a.SAp, SB = a.SBp;
-  const int8_t* zp = a.zero + lane * 16;
+  Producer<W, M3> P;
+  P.xplane = (size_t)a.mt * a.kblocks * 1024;  // bytes per (op, s) plane
+  P.yplane = (size_t)a.nt * a.kblocks * 1024;
+  P.zp = a.zero + lane * 16;
+  P.SA = a.SAp;
+  P.SB = a.SBp;
+  P.Dmax = a.Dmax;
+  P.nbands = (a.Dmax + W) / W;
+  P.kb0 = kb0;
+  P.kb1 = kb1;
+  {
+    const int8_t* X0 = a.X + (size_t)(2 * gi) * a.kblocks * 1024 + lane * 16;  // row tiles 2gi, 2gi+1
+    const int8_t* Y0 = a.Y + (size_t)(2 * gj) * a.kblocks * 1024 + lane * 16;  // column tiles 2gj, 2gj+1
+    P.share(wv, X0, X0 + (size_t)a.kblocks * 1024, Y0, Y0 + (size_t)a.kblocks * 1024);
+  }
+  P.start();
+
+  C c;
+  c.q = lds_queue;
+  c.lane = lane;
+  c.wi = wi;
+  c.wj = wj;
+  c.slot = 0;
+  // fill entries 0 .. QS-3, then read entry 0
+#pragma unroll 1
+  for (int i = 0; i < G::QS - 2; ++i) {
+    P.issue(c.q + i * G::ENT * 1024);
+    P.advance();
+  }
+  wait_vmcnt<G::VM>();
+  __builtin_amdgcn_s_barrier();
+  c.template read<0>(0);
 
   int64_t cre[4], cim[4];
   int32_t lre[4], lim[4];
@@ -160,37 +361,33 @@ __global__ __launch_bounds__(256) void gemm_i8_kernel(GemmArgs a) {
   const int nd = a.Dmax + 1;
   uint64_t* dig = reinterpret_cast<uint64_t*>(a.digits) + ((size_t)(split * a.mt * a.nt + tile) * nd) * 64 + lane;
 
-  const int nbands = (a.Dmax + W) / W;
 #pragma unroll 1
-  for (int band = 0; band < nbands; ++band) {
-    const int d0 = a.Dmax + 1 - W * (band + 1);  // band covers diagonals [d0, d0 + W)
+  for (int band = 0; band < P.nbands; ++band) {
+    Band g;
+    g.set(band, W, a.Dmax, a.SAp, a.SBp);
     v4i acc[NACC][W];
 #pragma unroll
     for (int p = 0; p < NACC; ++p)
 #pragma unroll
       for (int j = 0; j < W; ++j) acc[p][j] = v4i{0, 0, 0, 0};
 
-    const int s_lo = max(0, d0 - (SB - 1)), s_hi = min(SA - 1, d0 + W - 1);
-    if (s_lo <= s_hi) {
-      const int8_t* X0 = Xb;
-      const int8_t* X1 = Xb + (size_t)SA * xplane;
-      const int8_t* Y0 = Yb;
-      const int8_t* Y1 = Yb + (size_t)SB * yplane;
-      const int8_t* Y2 = Yb + (size_t)2 * SB * yplane;
-      if constexpr (M3) {  // T1 = Re Re, T2 = Im Im, T3 = (Re+Im)(Re+Im)
-        const int8_t* X2 = Xb + (size_t)2 * SA * xplane;
-        band_pass<W, PF, false, 0, 0>(acc, X0, Y0, Y0, zp, xplane, yplane, d0, s_lo, s_hi, SB, kb0, kb1);
-        band_pass<W, PF, false, 1, 1>(acc, X1, Y1, Y1, zp, xplane, yplane, d0, s_lo, s_hi, SB, kb0, kb1);
-        band_pass<W, PF, false, 2, 2>(acc, X2, Y2, Y2, zp, xplane, yplane, d0, s_lo, s_hi, SB, kb0, kb1);
-      } else {  // Re += ReA ReB + ImA (-ImB),  Im += ReA ImB + ImA ReB
-        band_pass<W, PF, true, 0, 1>(acc, X0, Y0, Y1, zp, xplane, yplane, d0, s_lo, s_hi, SB, kb0, kb1);
-        band_pass<W, PF, true, 0, 1>(acc, X1, Y2, Y0, zp, xplane, yplane, d0, s_lo, s_hi, SB, kb0, kb1);
-      }
+    if constexpr (M3) {  // T1 = Re Re, T2 = Im Im, T3 = (Re+Im)(Re+Im)
+#pragma unroll 1
+      for (int kb = kb0; kb < kb1; ++kb) c.template unit<0, 0>(acc, P, g);
+#pragma unroll 1
+      for (int kb = kb0; kb < kb1; ++kb) c.template unit<1, 1>(acc, P, g);
+#pragma unroll 1
+      for (int kb = kb0; kb < kb1; ++kb) c.template unit<2, 2>(acc, P, g);
+    } else {  // Re += ReA ReB + ImA (-ImB),  Im += ReA ImB + ImA ReB
+#pragma unroll 1
+      for (int pass = 0; pass < 2; ++pass)
+#pragma unroll 1
+        for (int kb = kb0; kb < kb1; ++kb) c.template unit<0, 1>(acc, P, g);
     }
     // the band is complete: emit its diagonals least significant first
 #pragma unroll
     for (int j = W - 1; j >= 0; --j) {
-      const int d = d0 + j;
+      const int d = g.d0 + j;
       if (d >= 0) {
         uint64_t packed = 0;
 #pragma unroll
@@ -218,6 +415,8 @@ __global__ __launch_bounds__(256) void gemm_i8_kernel(GemmArgs a) {
       }
     }
   }
+  // the producer ran past the end of the stream (zero-block loads): drain them
+  wait_vmcnt<0>();
 
   const size_t ob = ((size_t)(split * a.mt * a.nt + tile) * 64 + lane) * 8;
 #pragma unroll
@@ -229,14 +428,21 @@ __global__ __launch_bounds__(256) void gemm_i8_kernel(GemmArgs a) {
   }
 }
 
+template <int W, bool M3>
+hipError_t launch_wm(const GemmArgs& a, hipStream_t stream) {
+  using G = Q<W, M3>;
+  const int blocks = (a.mt / 2) * (a.nt / 2) * a.ksplit;
+  const size_t lds = (size_t)G::QS * G::ENT * 1024;
+  hipError_t e = hipFuncSetAttribute((const void*)gemm_i8_kernel<W, M3>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  gemm_i8_kernel<W, M3><<<dim3(blocks), dim3(256), lds, stream>>>(a);
+  return hipGetLastError();
+}
+
 template <int W>
 hipError_t launch_w(const GemmArgs& a, hipStream_t stream) {
-  const int blocks = (a.mt / 2) * (a.nt / 2) * a.ksplit;
-  if (a.mode3m)
-    gemm_i8_kernel<W, true><<<dim3(blocks), dim3(256), 0, stream>>>(a);
-  else
-    gemm_i8_kernel<W, false><<<dim3(blocks), dim3(256), 0, stream>>>(a);
-  return hipGetLastError();
+  return a.mode3m ? launch_wm<W, true>(a, stream) : launch_wm<W, false>(a, stream);
 }
 
 }  // namespace
