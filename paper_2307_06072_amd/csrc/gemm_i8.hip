@@ -18,13 +18,13 @@
 // (a ring: the fragment loaded at step v enters slot v mod W), so each step
 // needs one A fragment X_s and one new B fragment Y_{d0-s} and issues W MFMAs
 // (every pair (s, t) of the band exactly once).  A unit starts with W steps
-// that only fill the ring and has an even number of steps (it may end with
-// one step on zero fragments).
+// that only fill the ring and is padded with steps on zero fragments to an
+// even number of queue entries.
 //
 // Operand fragments (16 rows x 64 k, 16 bytes per lane) stream from the digit
 // planes into a workgroup-shared queue in LDS by direct global->LDS loads
 // (16 bytes per lane: one fragment per instruction).  A queue entry holds the
-// fragments of two consecutive steps for the workgroup's 2 x 2 tiles; each
+// fragments of NS consecutive steps for the workgroup's 2 x 2 tiles; each
 // fragment is loaded once and read by the two wavefronts that need it.  The
 // four wavefronts walk the (band, pass, k-block, step pair) sequence in
 // lockstep, each issuing a quarter of the loads QS - 2 entries ahead; one
@@ -84,6 +84,10 @@ __device__ inline void map_block(int b, int nblk, int gm, int gn, int& split, in
   gj = in / rows_here;
 }
 
+// floor and ceiling of a / b for b > 0 and any sign of a
+__device__ inline int fdiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+__device__ inline int cdiv(int a, int b) { return -fdiv(-a, b); }
+
 // Band geometry: diagonals [d0, d0 + W) and the s range holding its pairs.
 struct Band {
   int d0, s_lo, s_hi;
@@ -99,23 +103,27 @@ struct Band {
 // B fragments Y_{d0-s} of its two column tiles for each B plane.
 template <int W, bool M3>
 struct Q {
+  static constexpr int NS = (W % 8 == 0) ? 4 : 2;  // steps per entry (a ring turn is an even number of entries)
   static constexpr int NB = M3 ? 1 : 2;     // B planes per step
   static constexpr int E = 2 + 2 * NB;      // fragments per step
-  static constexpr int ENT = 2 * E;         // fragments per entry
+  static constexpr int ENT = NS * E;        // fragments per entry
   static constexpr int PW = ENT / 4;        // loads each wavefront issues per entry
-  static constexpr int QS = M3 ? 16 : 12;   // entries in the queue
+  static constexpr int QS = 128 / ENT;      // entries in the queue (128 KB of LDS)
   static constexpr int VM = (QS - 3) * PW;  // own loads still allowed in flight when the next entry must have landed
   static constexpr int NPASS = M3 ? 3 : 2;
   static constexpr int NACC = M3 ? 3 : 2;
-  static constexpr int CH = W / 2;          // entries per chunk (W steps: one turn of the ring)
+  static constexpr int CH = W / NS;         // entries per chunk (W steps: one turn of the ring)
+  static_assert(CH % 2 == 0, "entries alternate between two register buffers");
+  static_assert(VM < 64, "vmcnt range");
 };
 
 // Steps of a unit (band, pass, k-block): s from s_lo - W (the first W steps
-// only fill the ring) on, padded with steps on zero fragments to a multiple of
-// 4 steps, i.e. an even number of entries.
-__device__ inline int unit_entries(const Band& g, int W) {
+// only fill the ring) on, padded with steps on zero fragments to an even
+// number of entries of NS steps.
+__device__ inline int unit_entries(const Band& g, int W, int NS) {
   const int n = g.s_hi - (g.s_lo - W) + 1;
-  return ((n + 3) & ~3) >> 1;
+  const int per = 2 * NS;
+  return (n + per - 1) / per * 2;
 }
 
 // This wavefront's share of the loads, walking the (band, pass, k-block,
@@ -145,7 +153,7 @@ struct Producer {
 #pragma unroll
     for (int i = 0; i < PW; ++i) {
       const int f = wv * PW + i;
-      const int h = f >= G::E ? 1 : 0, x = f - h * G::E;
+      const int h = f / G::E, x = f - h * G::E;
       const int a = x < 2 ? 1 : 0;
       const int c = a ? x : ((x - 2) & 1);
       tb[i] = a ? (c ? X1 : X0) : (c ? Y1 : Y0);
@@ -158,7 +166,7 @@ struct Producer {
 
   // set source offsets, strides and valid entry ranges for the unit (band, pass, kb)
   __device__ inline void unit_begin() {
-    ne = unit_entries(g, W);
+    ne = unit_entries(g, W, G::NS);
     e = 0;
     const int s0 = g.s_lo - W;
     int pa, pb0, pb1;
@@ -171,20 +179,22 @@ struct Producer {
 #pragma unroll
     for (int i = 0; i < PW; ++i) {
       const int h = hh[i];
-      // step of entry e: s = s0 + 2 e + h; valid while s <= s_hi and (A) s >= s_lo, (B) 0 <= d0 - s < SB
-      const int top = (g.s_hi - s0 - h) >> 1;  // last entry with s <= s_hi (floor)
+      // step of entry e: s = s0 + NS e + h; valid while s <= s_hi and (A) s >= s_lo, (B) 0 <= d0 - s < SB
+      // (all quantities below are >= 0 except where noted, so / and % floor)
+      constexpr int NS = G::NS;
+      const int top = fdiv(g.s_hi - s0 - h, NS);  // last entry with s <= s_hi
       if (isa[i]) {
         off[i] = ((int64_t)pa * SA + s0 + h) * (int64_t)xplane + ko;
-        dlt[i] = 2 * (int64_t)xplane;
-        elo[i] = (g.s_lo - s0 - h + 1) >> 1;  // first entry with s >= s_lo (ceil)
+        dlt[i] = NS * (int64_t)xplane;
+        elo[i] = cdiv(g.s_lo - s0 - h, NS);  // first entry with s >= s_lo
         ehi[i] = top;
       } else {
         const int pl = sel[i] ? pb1 : pb0;
         const int t0 = g.d0 - s0 - h;  // t of entry 0
         off[i] = ((int64_t)pl * SB + t0) * (int64_t)yplane + ko;
-        dlt[i] = -2 * (int64_t)yplane;
-        elo[i] = (t0 - (SB - 1) + 1) >> 1;  // first entry with t <= SB - 1 (ceil)
-        ehi[i] = min(top, t0 >> 1);         // last entry with t >= 0
+        dlt[i] = -NS * (int64_t)yplane;
+        elo[i] = cdiv(t0 - (SB - 1), NS);  // first entry with t <= SB - 1
+        ehi[i] = min(top, fdiv(t0, NS));   // last entry with t >= 0
       }
     }
   }
@@ -234,14 +244,15 @@ struct Consumer {
   int8_t* q;  // the workgroup's queue: QS entries of ENT KB
   int lane, wi, wj;
   int slot;   // queue entry of the current step pair
+  static constexpr int NS = G::NS;
   // fragments of the current entry (parity p) and of the next one (parity 1 - p)
-  v4i abuf[2][2], bbuf[2][2][NB];
+  v4i abuf[2][NS], bbuf[2][NS][NB];
   v4i ring0[W], ring1[M3 ? 1 : W];
 
   template <int P>
   __device__ inline void read(int sl) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < NS; ++h) {
       const int8_t* base = q + (sl * G::ENT + h * E) * 1024 + lane * 16;
       abuf[P][h] = *reinterpret_cast<const v4i*>(base + wi * 1024);
 #pragma unroll
@@ -249,7 +260,7 @@ struct Consumer {
     }
   }
 
-  // One entry: ring steps V = 2C and 2C + 1 (V mod W static).  The entry two
+  // One entry: ring steps V = NS C .. NS C + NS - 1 (V mod W static).  The entry two
   // back has been used by every wavefront (they all passed the previous
   // barrier), so its queue slot is refilled first; once this wavefront's loads
   // of the next entry have landed, the barrier makes everybody's loads of it
@@ -264,8 +275,8 @@ struct Consumer {
     __builtin_amdgcn_s_barrier();
     read<1 - PAR>(slot + 1 == QS ? 0 : slot + 1);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      constexpr int V0 = 2 * C;
+    for (int h = 0; h < NS; ++h) {
+      constexpr int V0 = NS * C;
       const int V = V0 + h;
       ring0[V % W] = bbuf[PAR][h][0];
       if (!M3) ring1[V % W] = bbuf[PAR][h][NB - 1];
@@ -293,7 +304,7 @@ struct Consumer {
   // One unit: a chunk of ring-filling entries, then chunks with MFMAs.
   template <int Q0, int Q1>
   __device__ inline void unit(v4i (&acc)[NACC][W], Producer<W, M3>& P, const Band& g) {
-    const int ne = unit_entries(g, W);
+    const int ne = unit_entries(g, W, NS);
     chunk<0, false, Q0, Q1>(acc, P, G::CH);
     for (int e0 = G::CH; e0 < ne; e0 += G::CH) chunk<0, true, Q0, Q1>(acc, P, ne - e0);
   }
