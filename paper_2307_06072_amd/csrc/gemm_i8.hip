@@ -27,11 +27,11 @@
 // fragments of NS consecutive steps for the workgroup's 2 x 2 tiles; each
 // fragment is loaded once and read by the two wavefronts that need it.  The
 // four wavefronts walk the (band, pass, k-block, step pair) sequence in
-// lockstep, each issuing a quarter of the loads QS - 2 entries ahead; one
+// lockstep, each issuing a quarter of the loads QS - 1 entries ahead; one
 // barrier per entry publishes the loads, and every wavefront reads its
-// fragments from LDS two entries ahead of their use.  This keeps about 2 QS
-// steps of loads in flight without spending registers on them.  Fragments outside the operand are read from a zero block, so no
-// load is conditional.
+// fragments from LDS one entry ahead of their use.  This keeps about QS
+// entries of loads in flight without spending registers on them.  The digit
+// planes carry zero slices around their digits, so no load is conditional.
 //
 // When a band is complete its W diagonals are combined into Re and Im
 // (4M, eq. 5: the accumulators hold Re and Im directly, the B side supplying
@@ -84,10 +84,6 @@ __device__ inline void map_block(int b, int nblk, int gm, int gn, int& split, in
   gj = in / rows_here;
 }
 
-// floor and ceiling of a / b for b > 0 and any sign of a
-__device__ inline int fdiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
-__device__ inline int cdiv(int a, int b) { return -fdiv(-a, b); }
-
 // Band geometry: diagonals [d0, d0 + W) and the s range holding its pairs.
 struct Band {
   int d0, s_lo, s_hi;
@@ -98,7 +94,7 @@ struct Band {
   }
 };
 
-// Compile-time shape of the fragment queue.  An entry holds two consecutive
+// Compile-time shape of the fragment queue.  An entry holds NS consecutive
 // steps; per step: the A fragment X_s of the workgroup's two row tiles and the
 // B fragments Y_{d0-s} of its two column tiles for each B plane.
 template <int W, bool M3>
@@ -108,13 +104,14 @@ struct Q {
   static constexpr int E = 2 + 2 * NB;      // fragments per step
   static constexpr int ENT = NS * E;        // fragments per entry
   static constexpr int PW = ENT / 4;        // loads each wavefront issues per entry
-  static constexpr int QS = 128 / ENT;      // entries in the queue (128 KB of LDS)
+  static constexpr int QS = 160 / ENT;      // entries in the queue (at most 160 KB of LDS)
   static constexpr int VM = (QS - 3) * PW;  // own loads still allowed in flight when the next entry must have landed
+  static constexpr int VM0 = (QS - 2) * PW; // the same for entry 0 after the prologue
   static constexpr int NPASS = M3 ? 3 : 2;
   static constexpr int NACC = M3 ? 3 : 2;
   static constexpr int CH = W / NS;         // entries per chunk (W steps: one turn of the ring)
   static_assert(CH % 2 == 0, "entries alternate between two register buffers");
-  static_assert(VM < 64, "vmcnt range");
+  static_assert(VM0 < 64, "vmcnt range");
 };
 
 // Steps of a unit (band, pass, k-block): s from s_lo - W (the first W steps
@@ -126,28 +123,42 @@ __device__ inline int unit_entries(const Band& g, int W, int NS) {
   return (n + per - 1) / per * 2;
 }
 
+// Zero slices around each digit plane.  A unit reads X_s for s in
+// [s_lo - W, s_hi + 2 NS - 1] and Y_t for t = d0 - s, i.e. t in
+// [2 - W - 2 NS, S_B - 1 + W]; the planes carry that many zero slices below
+// and above their S digits so that every load of a unit is unconditional and
+// the pairs outside the operands multiply zeros.
+__host__ __device__ inline void pads_for(int W, int& alo, int& ahi, int& blo, int& bhi) {
+  const int NS = (W % 8 == 0) ? 4 : 2;
+  alo = W;
+  ahi = 2 * NS - 1;
+  blo = W + 2 * NS - 2;
+  bhi = W;
+}
+
 // This wavefront's share of the loads, walking the (band, pass, k-block,
 // entry) sequence.  Load i of an entry is fragment f = wv * PW + i: the A
 // fragment of row tile c or a B fragment of column tile c, of step h of the
-// entry.  Within a unit its source moves by a constant stride per entry and is
-// valid on a precomputed range of entries (outside it the zero block is read),
-// so an entry costs a few scalar instructions per load.
+// entry.  Within a unit its (wave-uniform) source moves by a constant stride
+// per entry, so a load costs a 64-bit scalar add and the instruction itself;
+// only the end of a unit branches.
 template <int W, bool M3>
 struct Producer {
   using G = Q<W, M3>;
   static constexpr int PW = G::PW;
-  const int8_t* zp;
-  size_t xplane, yplane;
+  size_t xplane, yplane;  // bytes per slice of a plane
   int SA, SB, Dmax, nbands, kb0, kb1;
+  int xs, ys, xlo, ylo;   // slices per plane (with pads) and lower pads
+  unsigned lane16;
   // per load (static index i)
-  const int8_t* tb[PW];  // lane-offset base of the tile's planes
+  const int8_t* tb[PW];   // the tile's planes (wave-uniform)
   int isa[PW], hh[PW], sel[PW], foff[PW];
   // walk state
   int band, pass, kb, e, ne;
   Band g;
   bool done;
-  int64_t off[PW], dlt[PW];
-  int elo[PW], ehi[PW];
+  const int8_t* src[PW];
+  int64_t dlt[PW];
 
   __device__ inline void share(int wv, const int8_t* X0, const int8_t* X1, const int8_t* Y0, const int8_t* Y1) {
 #pragma unroll
@@ -164,7 +175,7 @@ struct Producer {
     }
   }
 
-  // set source offsets, strides and valid entry ranges for the unit (band, pass, kb)
+  // set sources and strides for the unit (band, pass, kb)
   __device__ inline void unit_begin() {
     ne = unit_entries(g, W, G::NS);
     e = 0;
@@ -178,23 +189,14 @@ struct Producer {
     const int64_t ko = (int64_t)kb * 1024;
 #pragma unroll
     for (int i = 0; i < PW; ++i) {
-      const int h = hh[i];
-      // step of entry e: s = s0 + NS e + h; valid while s <= s_hi and (A) s >= s_lo, (B) 0 <= d0 - s < SB
-      // (all quantities below are >= 0 except where noted, so / and % floor)
-      constexpr int NS = G::NS;
-      const int top = fdiv(g.s_hi - s0 - h, NS);  // last entry with s <= s_hi
+      const int h = hh[i];  // entry e loads step s = s0 + NS e + h
       if (isa[i]) {
-        off[i] = ((int64_t)pa * SA + s0 + h) * (int64_t)xplane + ko;
-        dlt[i] = NS * (int64_t)xplane;
-        elo[i] = cdiv(g.s_lo - s0 - h, NS);  // first entry with s >= s_lo
-        ehi[i] = top;
+        src[i] = tb[i] + ((int64_t)(pa * xs + xlo + s0 + h) * (int64_t)xplane + ko);
+        dlt[i] = G::NS * (int64_t)xplane;
       } else {
         const int pl = sel[i] ? pb1 : pb0;
-        const int t0 = g.d0 - s0 - h;  // t of entry 0
-        off[i] = ((int64_t)pl * SB + t0) * (int64_t)yplane + ko;
-        dlt[i] = -NS * (int64_t)yplane;
-        elo[i] = cdiv(t0 - (SB - 1), NS);  // first entry with t <= SB - 1
-        ehi[i] = min(top, fdiv(t0, NS));   // last entry with t >= 0
+        src[i] = tb[i] + ((int64_t)(pl * ys + ylo + g.d0 - s0 - h) * (int64_t)yplane + ko);
+        dlt[i] = -G::NS * (int64_t)yplane;
       }
     }
   }
@@ -212,7 +214,14 @@ struct Producer {
       if (++pass >= G::NPASS) {
         pass = 0;
         if (++band >= nbands) {
+          // past the end: keep reloading the tile's first fragment (never consumed)
           done = true;
+          ne = 0x7fffffff;
+#pragma unroll
+          for (int i = 0; i < PW; ++i) {
+            src[i] = tb[i];
+            dlt[i] = 0;
+          }
           return;
         }
         g.set(band, W, Dmax, SA, SB);
@@ -220,19 +229,16 @@ struct Producer {
     }
     unit_begin();
   }
-  __device__ inline void advance() {
-#pragma unroll
-    for (int i = 0; i < PW; ++i) off[i] += dlt[i];
-    if (++e >= ne && !done) next_unit();
+  // load i of the current entry into the entry at `dst`
+  __device__ inline void issue(int i, int8_t* dst) const {
+    __builtin_amdgcn_global_load_lds(src[i] + lane16, (lds_void*)(dst + foff[i]), 16, 0, 0);
   }
-  // issue this wavefront's loads of the current entry into the entry at `dst`
-  __device__ inline void issue(int8_t* dst) const {
+  __device__ inline void step() {
 #pragma unroll
-    for (int i = 0; i < PW; ++i) {
-      const bool ok = !done && e >= elo[i] && e <= ehi[i];
-      const int8_t* src = ok ? (const int8_t*)((uintptr_t)tb[i] + (uintptr_t)off[i]) : zp;
-      __builtin_amdgcn_global_load_lds(src, (lds_void*)(dst + foff[i]), 16, 0, 0);
-    }
+    for (int i = 0; i < PW; ++i) src[i] += dlt[i];
+  }
+  __device__ inline void tail() {
+    if (__builtin_expect(++e >= ne, 0)) next_unit();
   }
 };
 
@@ -240,10 +246,10 @@ template <int W, bool M3>
 struct Consumer {
   using G = Q<W, M3>;
   static_assert(W % 4 == 0, "a ring turn is an even number of entries");
-  static constexpr int NB = G::NB, E = G::E, QS = G::QS, NACC = G::NACC;
+  static constexpr int NB = G::NB, E = G::E, QS = G::QS, NACC = G::NACC, PW = G::PW;
   int8_t* q;  // the workgroup's queue: QS entries of ENT KB
   int lane, wi, wj;
-  int slot;   // queue entry of the current step pair
+  int slot;   // queue entry of the current steps
   static constexpr int NS = G::NS;
   // fragments of the current entry (parity p) and of the next one (parity 1 - p)
   v4i abuf[2][NS], bbuf[2][NS][NB];
@@ -260,19 +266,17 @@ struct Consumer {
     }
   }
 
-  // One entry: ring steps V = NS C .. NS C + NS - 1 (V mod W static).  The entry two
-  // back has been used by every wavefront (they all passed the previous
-  // barrier), so its queue slot is refilled first; once this wavefront's loads
-  // of the next entry have landed, the barrier makes everybody's loads of it
-  // visible, and it is read into the other register buffer.
+  // One entry: ring steps V = NS C .. NS C + NS - 1 (V mod W static).  Once
+  // this wavefront's loads of the next entry have landed, the barrier makes
+  // everybody's loads of it visible (it is read into the other register
+  // buffer) and tells that every wavefront has used the previous entry, whose
+  // queue slot is then refilled by loads spread between the MFMAs.
   template <int C, bool MF, int Q0, int Q1>
   __device__ inline void entry(v4i (&acc)[NACC][W], Producer<W, M3>& P) {
     constexpr int PAR = C & 1;
-    const int back2 = slot >= 2 ? slot - 2 : slot + QS - 2;
-    P.issue(q + back2 * G::ENT * 1024);
-    P.advance();
     wait_vmcnt<G::VM>();
     __builtin_amdgcn_s_barrier();
+    int8_t* dst = q + (slot == 0 ? QS - 1 : slot - 1) * G::ENT * 1024;
     read<1 - PAR>(slot + 1 == QS ? 0 : slot + 1);
 #pragma unroll
     for (int h = 0; h < NS; ++h) {
@@ -280,16 +284,22 @@ struct Consumer {
       const int V = V0 + h;
       ring0[V % W] = bbuf[PAR][h][0];
       if (!M3) ring1[V % W] = bbuf[PAR][h][NB - 1];
-      if (MF) {
 #pragma unroll
-        for (int r = 0; r < W; ++r) {
+      for (int r = 0; r < W; ++r) {
+        if (MF) {
           const int j = (V - r + W) % W;  // slot r holds the B fragment of diagonal d0 + j
           acc[Q0][j] = mfma(abuf[PAR][h], ring0[r], acc[Q0][j]);
           if (!M3) acc[Q1][j] = mfma(abuf[PAR][h], ring1[r], acc[Q1][j]);
         }
+        // spread this wavefront's loads over the entry
+        constexpr int per = (PW + NS - 1) / NS;
+        const int i = h * per + r;
+        if (r < per && i < PW) P.issue(i, dst);
       }
     }
+    P.step();
     slot = slot + 1 == QS ? 0 : slot + 1;
+    P.tail();
   }
 
   template <int C, bool MF, int Q0, int Q1>
@@ -332,7 +342,11 @@ __global__ __launch_bounds__(256) void gemm_i8_kernel(GemmArgs a) {
   Producer<W, M3> P;
   P.xplane = (size_t)a.mt * a.kblocks * 1024;  // bytes per (op, s) plane
   P.yplane = (size_t)a.nt * a.kblocks * 1024;
-  P.zp = a.zero + lane * 16;
+  P.lane16 = (unsigned)lane * 16u;
+  P.xs = a.xs;
+  P.ys = a.ys;
+  P.xlo = a.xlo;
+  P.ylo = a.ylo;
   P.SA = a.SAp;
   P.SB = a.SBp;
   P.Dmax = a.Dmax;
@@ -340,8 +354,8 @@ __global__ __launch_bounds__(256) void gemm_i8_kernel(GemmArgs a) {
   P.kb0 = kb0;
   P.kb1 = kb1;
   {
-    const int8_t* X0 = a.X + (size_t)(2 * gi) * a.kblocks * 1024 + lane * 16;  // row tiles 2gi, 2gi+1
-    const int8_t* Y0 = a.Y + (size_t)(2 * gj) * a.kblocks * 1024 + lane * 16;  // column tiles 2gj, 2gj+1
+    const int8_t* X0 = a.X + (size_t)(2 * gi) * a.kblocks * 1024;  // row tiles 2gi, 2gi+1
+    const int8_t* Y0 = a.Y + (size_t)(2 * gj) * a.kblocks * 1024;  // column tiles 2gj, 2gj+1
     P.share(wv, X0, X0 + (size_t)a.kblocks * 1024, Y0, Y0 + (size_t)a.kblocks * 1024);
   }
   P.start();
@@ -352,13 +366,15 @@ __global__ __launch_bounds__(256) void gemm_i8_kernel(GemmArgs a) {
   c.wi = wi;
   c.wj = wj;
   c.slot = 0;
-  // fill entries 0 .. QS-3, then read entry 0
+  // fill entries 0 .. QS-2, then read entry 0
 #pragma unroll 1
-  for (int i = 0; i < G::QS - 2; ++i) {
-    P.issue(c.q + i * G::ENT * 1024);
-    P.advance();
+  for (int u = 0; u < G::QS - 1; ++u) {
+#pragma unroll
+    for (int i = 0; i < G::PW; ++i) P.issue(i, c.q + u * G::ENT * 1024);
+    P.step();
+    P.tail();
   }
-  wait_vmcnt<G::VM>();
+  wait_vmcnt<G::VM0>();
   __builtin_amdgcn_s_barrier();
   c.template read<0>(0);
 
@@ -426,7 +442,7 @@ __global__ __launch_bounds__(256) void gemm_i8_kernel(GemmArgs a) {
       }
     }
   }
-  // the producer ran past the end of the stream (zero-block loads): drain them
+  // the producer ran past the end of the stream: drain its loads before the LDS is released
   wait_vmcnt<0>();
 
   const size_t ob = ((size_t)(split * a.mt * a.nt + tile) * 64 + lane) * 8;
@@ -457,6 +473,8 @@ hipError_t launch_w(const GemmArgs& a, hipStream_t stream) {
 }
 
 }  // namespace
+
+void gemm_i8_pads(int band, int* alo, int* ahi, int* blo, int* bhi) { pads_for(band, *alo, *ahi, *blo, *bhi); }
 
 hipError_t launch_gemm_i8(const GemmArgs& a, int band, hipStream_t stream) {
   switch (band) {

@@ -74,8 +74,10 @@ hipError_t launch_scan(const DOperand& op, RowStat* stats, ScanSummary* summary,
 //   out        INT8: int8 planes [nops][Sp][Rpad/16][Kpad/64][64][16];
 //              FP64: double planes [nops][Sp][Rpad/16][Kpad/4][64].
 enum class Third { NONE = 0, SUM = 1, NEG_IM = 2 };
-hipError_t launch_split_i8(const DOperand& op, int prec, int L, int S, int Sp, Third third,
-                           const int32_t* G, int Rpad, int Kpad, int8_t* out, int* status,
+// INT8 planes hold Sstride slices each: pad_lo zero slices, the Sp digit
+// slices, then zero slices up to Sstride (all written by the split).
+hipError_t launch_split_i8(const DOperand& op, int prec, int L, int S, int Sp, int Sstride, int pad_lo,
+                           Third third, const int32_t* G, int Rpad, int Kpad, int8_t* out, int* status,
                            hipStream_t stream);
 hipError_t launch_split_f64(const DOperand& op, int prec, int L, int S, int Sp, int w, Third third,
                             const int32_t* G, int Rpad, int Kpad, double* out, int* status,
@@ -91,14 +93,18 @@ struct GemmArgs {
   int mt, nt;        // 16-row tiles of A, 16-column tiles of B
   int kblocks;       // Kpad / 64 (INT8) or Kpad / 4 (FP64)
   int ksplit;        // contraction chunks
-  int SAp, SBp;      // slice counts of the A and B planes
+  int SAp, SBp;      // slice counts of the A and B operands
+  int xs, ys;        // slices per A / B plane including the zero pads
+  int xlo, ylo;      // zero slices below slice 0 of an A / B plane
   int Dmax;          // highest emitted diagonal
   int mode3m;        // 1: planes are (Re, Im, Re+Im) on both sides; 0: A (Re, Im), B (Re, Im, -Im)
   void* digits;      // [ksplit][tiles][Dmax+1][64][8] digit type
   int64_t* top;      // [ksplit][tiles][64][8]
   int32_t* lnz;      // [ksplit][tiles][64][8]
-  const int8_t* zero;  // 1 KB of zeros: stands in for fragments outside the operand
 };
+// Zero slices the INT8 slice GEMM of band width `band` needs below (lo) and
+// above (hi) the digits of the A and B planes.
+void gemm_i8_pads(int band, int* alo, int* ahi, int* blo, int* bhi);
 hipError_t launch_gemm_i8(const GemmArgs& a, int band, hipStream_t stream);
 
 struct GemmF64Args {

@@ -110,12 +110,13 @@ struct Plan {
   int m, n, k, p, L, mode3m, trunc, f64;
   int w, x;
   int SA, SB, SAp, SBp, Dmax, cutoff;
+  int xs, ys, xlo, ylo;  // slices per plane with zero pads, lower pads
   int block;
   int mpad, npad, kpad, mt, nt, kblocks, ksplit;
   int nopsA, nopsB;
   long long pairs;
   double algo_ops, bound_bits;
-  size_t off_G, off_H, off_X, off_Y, off_dig, off_top, off_lnz, off_zero, total;
+  size_t off_G, off_H, off_X, off_Y, off_dig, off_top, off_lnz, total;
 };
 
 int plan_slices(Plan& P, int spreadA, int spreadB, int hatA, int hatB, const mpcg_options* opt) {
@@ -170,6 +171,10 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
       return set_err(MPCG_EINVAL, "block_override (band width) must be 8, 12 or 16");
     P.SAp = P.SA;
     P.SBp = P.SB;
+    int ahi, bhi;
+    gemm_i8_pads(P.block, &P.xlo, &ahi, &P.ylo, &bhi);
+    P.xs = P.xlo + P.SA + ahi;
+    P.ys = P.ylo + P.SB + bhi;
     P.kblocks = P.kpad / 64;
     // int32 accumulators: terms per diagonal * 64*64 must stay below 2^31
     const long long terms_per_k = (long long)(P.mode3m ? 1 : 2) * std::min(P.SA, P.SB);
@@ -184,6 +189,9 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
     P.block = 2;
     P.SAp = (int)round_up(P.SA, 2);
     P.SBp = (int)round_up(P.SB, 2);
+    P.xs = P.SAp;
+    P.ys = P.SBp;
+    P.xlo = P.ylo = 0;
     P.kblocks = P.kpad / 4;
     int want = std::max(1, ceil_div(512, groups));
     P.ksplit = std::min(want, std::max(1, P.kpad / 64));
@@ -209,12 +217,11 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
   size_t o = 0;
   P.off_G = o; o = align256(o + 4 * (size_t)P.mpad);
   P.off_H = o; o = align256(o + 4 * (size_t)P.npad);
-  P.off_X = o; o = align256(o + (size_t)P.nopsA * P.SAp * P.mpad * (size_t)P.kpad * esz);
-  P.off_Y = o; o = align256(o + (size_t)P.nopsB * P.SBp * P.npad * (size_t)P.kpad * esz);
+  P.off_X = o; o = align256(o + (size_t)P.nopsA * P.xs * P.mpad * (size_t)P.kpad * esz);
+  P.off_Y = o; o = align256(o + (size_t)P.nopsB * P.ys * P.npad * (size_t)P.kpad * esz);
   P.off_dig = o; o = align256(o + (size_t)P.ksplit * tiles * nd * 512 * dig_bytes);
   P.off_top = o; o = align256(o + (size_t)P.ksplit * tiles * 512 * 8);
   P.off_lnz = o; o = align256(o + (size_t)P.ksplit * tiles * 512 * 4);
-  P.off_zero = o; o = align256(o + 1024);
   P.total = o;
   return MPCG_OK;
 }
@@ -381,9 +388,9 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
   const Third thirdA = P.mode3m ? Third::SUM : Third::NONE;
   const Third thirdB = P.mode3m ? Third::SUM : Third::NEG_IM;
   if (!P.f64) {
-    HIP_TRY(launch_split_i8(opA, prec_bits, L, P.SA, P.SAp, thirdA, G, P.mpad, P.kpad,
+    HIP_TRY(launch_split_i8(opA, prec_bits, L, P.SA, P.SAp, P.xs, P.xlo, thirdA, G, P.mpad, P.kpad,
                             reinterpret_cast<int8_t*>(base + P.off_X), g_status, g_stream));
-    HIP_TRY(launch_split_i8(opB, prec_bits, L, P.SB, P.SBp, thirdB, H, P.npad, P.kpad,
+    HIP_TRY(launch_split_i8(opB, prec_bits, L, P.SB, P.SBp, P.ys, P.ylo, thirdB, H, P.npad, P.kpad,
                             reinterpret_cast<int8_t*>(base + P.off_Y), g_status, g_stream));
   } else {
     HIP_TRY(launch_split_f64(opA, prec_bits, L, P.SA, P.SAp, P.w, thirdA, G, P.mpad, P.kpad,
@@ -403,8 +410,7 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
     ga.mt = P.mt; ga.nt = P.nt; ga.kblocks = P.kblocks; ga.ksplit = P.ksplit;
     ga.SAp = P.SAp; ga.SBp = P.SBp; ga.Dmax = P.Dmax; ga.mode3m = P.mode3m;
     ga.digits = base + P.off_dig; ga.top = top; ga.lnz = lnz;
-    ga.zero = reinterpret_cast<const int8_t*>(base + P.off_zero);
-    HIP_TRY(launch_fill_zero(base + P.off_zero, 1024, g_stream));
+    ga.xs = P.xs; ga.ys = P.ys; ga.xlo = P.xlo; ga.ylo = P.ylo;
     HIP_TRY(launch_gemm_i8(ga, P.block, g_stream));
   } else {
     GemmF64Args ga{};

@@ -24,7 +24,8 @@
 // indices).  Digits go to LDS in the matrix-core operand order and leave as
 // contiguous fragments:
 //   INT8: fragment = 16 rows x 64 k, lane l holds row l%16, k = 16*(l/16)..+16
-//         (16 bytes), planes [op][s][R/16][K/64][1024 B].
+//         (16 bytes), planes [op][pad_lo + s][R/16][K/64][1024 B] with zero
+//         slices around the digits (Sstride slices per plane).
 //   FP64: fragment = 16 rows x 4 k, lane l holds row l%16, k = l/16 (one
 //         double), planes [op][s][R/16][K/4][64 doubles].
 #include "mpcg_internal.h"
@@ -81,9 +82,10 @@ struct Layout<double> {
 };
 
 template <typename DT, bool ROWCONTIG>
-__global__ __launch_bounds__(256) void split_kernel(DOperand op, int prec, int L, int S, int Sp, int w,
-                                                    int third, const int32_t* __restrict__ G, int Rpad,
-                                                    int Kpad, DT* __restrict__ out, int* status) {
+__global__ __launch_bounds__(256) void split_kernel(DOperand op, int prec, int L, int S, int Sp, int Sstride,
+                                                    int pad_lo, int w, int third,
+                                                    const int32_t* __restrict__ G, int Rpad, int Kpad,
+                                                    DT* __restrict__ out, int* status) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   DT* lds = reinterpret_cast<DT*>(lds_raw);
   constexpr int FRAG = Layout<DT>::FRAG_BYTES / (int)sizeof(DT);  // elements per (op, digit) tile
@@ -192,39 +194,56 @@ __global__ __launch_bounds__(256) void split_kernel(DOperand op, int prec, int L
       if (s >= Sp) continue;
       const uint4* src = reinterpret_cast<const uint4*>(lds_raw + (size_t)oj * Layout<DT>::FRAG_BYTES);
       uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<unsigned char*>(out) +
-                                            Layout<DT>::tile_base((int64_t)o * Sp + s, rt, kt, Rpad / 16, Kpad));
+                                            Layout<DT>::tile_base((int64_t)o * Sstride + pad_lo + s, rt, kt,
+                                                                  Rpad / 16, Kpad));
       dst[u] = src[u];
     }
     __syncthreads();
   }
+  // zero slices around the digits (this tile of every plane)
+  const int npad = Sstride - Sp;
+  if (npad > 0) {
+    constexpr int units = Layout<DT>::FRAG_BYTES / 16;
+    for (int idx = t; idx < nops * npad * units; idx += 256) {
+      const int u = idx % units;
+      const int oj = idx / units;
+      const int o = oj / npad, j = oj % npad;
+      const int sl = j < pad_lo ? j : Sp + j;  // plane slice index
+      uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<unsigned char*>(out) +
+                                            Layout<DT>::tile_base((int64_t)o * Sstride + sl, rt, kt, Rpad / 16, Kpad));
+      dst[u] = make_uint4(0u, 0u, 0u, 0u);
+    }
+  }
 }
 
 template <typename DT>
-hipError_t launch_split_t(const DOperand& op, int prec, int L, int S, int Sp, int w, Third third,
-                          const int32_t* G, int Rpad, int Kpad, DT* out, int* status, hipStream_t stream) {
+hipError_t launch_split_t(const DOperand& op, int prec, int L, int S, int Sp, int Sstride, int pad_lo, int w,
+                          Third third, const int32_t* G, int Rpad, int Kpad, DT* out, int* status,
+                          hipStream_t stream) {
   const int g = 56 / w;
   const int nops = third == Third::NONE ? 2 : 3;
   const size_t lds = (size_t)nops * g * Layout<DT>::FRAG_BYTES;
   dim3 grid(Kpad / 64, Rpad / 16);
   if (op.rs == 1)
-    split_kernel<DT, true><<<grid, dim3(256), lds, stream>>>(op, prec, L, S, Sp, w, (int)third, G, Rpad, Kpad,
+    split_kernel<DT, true><<<grid, dim3(256), lds, stream>>>(op, prec, L, S, Sp, Sstride, pad_lo, w, (int)third, G, Rpad, Kpad,
                                                              out, status);
   else
-    split_kernel<DT, false><<<grid, dim3(256), lds, stream>>>(op, prec, L, S, Sp, w, (int)third, G, Rpad, Kpad,
+    split_kernel<DT, false><<<grid, dim3(256), lds, stream>>>(op, prec, L, S, Sp, Sstride, pad_lo, w, (int)third, G, Rpad, Kpad,
                                                               out, status);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_split_i8(const DOperand& op, int prec, int L, int S, int Sp, Third third, const int32_t* G,
-                           int Rpad, int Kpad, int8_t* out, int* status, hipStream_t stream) {
-  return launch_split_t<int8_t>(op, prec, L, S, Sp, 7, third, G, Rpad, Kpad, out, status, stream);
+hipError_t launch_split_i8(const DOperand& op, int prec, int L, int S, int Sp, int Sstride, int pad_lo,
+                           Third third, const int32_t* G, int Rpad, int Kpad, int8_t* out, int* status,
+                           hipStream_t stream) {
+  return launch_split_t<int8_t>(op, prec, L, S, Sp, Sstride, pad_lo, 7, third, G, Rpad, Kpad, out, status, stream);
 }
 
 hipError_t launch_split_f64(const DOperand& op, int prec, int L, int S, int Sp, int w, Third third,
                             const int32_t* G, int Rpad, int Kpad, double* out, int* status, hipStream_t stream) {
-  return launch_split_t<double>(op, prec, L, S, Sp, w, third, G, Rpad, Kpad, out, status, stream);
+  return launch_split_t<double>(op, prec, L, S, Sp, Sp, 0, w, third, G, Rpad, Kpad, out, status, stream);
 }
 
 }  // namespace mpcg
