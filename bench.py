@@ -110,12 +110,18 @@ def cpu_baseline(A, B, m, n, k, p, target_s):
     import oracle
     threads = oracle.default_threads()
     rng = np.random.default_rng(12345)
+    # calibrate on growing samples until one takes at least a second
     probe = max(threads, 8)
-    rows = rng.integers(0, m, probe)
-    cols = rng.integers(0, n, probe)
-    t0 = time.perf_counter()
-    oracle.cgemm_entries(A, B, rows, cols, p, nthreads=threads)
-    per = (time.perf_counter() - t0) / probe
+    while True:
+        rows = rng.integers(0, m, probe)
+        cols = rng.integers(0, n, probe)
+        t0 = time.perf_counter()
+        oracle.cgemm_entries(A, B, rows, cols, p, nthreads=threads)
+        dt = time.perf_counter() - t0
+        if dt >= 1.0 or probe >= m * n:
+            break
+        probe = min(m * n, probe * 4)
+    per = dt / probe
     nent = int(max(threads, min(m * n, target_s / max(per, 1e-9))))
     rows = rng.integers(0, m, nent)
     cols = rng.integers(0, n, nent)
