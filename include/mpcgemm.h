@@ -63,7 +63,8 @@ enum {
     MPCG_ERANGE = -3,      /* input exponent outside [-2^30, 2^30] or output exponent overflow */
     MPCG_EHIP = -4,        /* HIP runtime error (text in mpcg_last_error) */
     MPCG_EUNSUPPORTED = -5,/* valid request this build cannot serve */
-    MPCG_EDOMAIN = -6      /* nonzero input whose significand top bit is clear */
+    MPCG_EDOMAIN = -6,     /* nonzero input whose significand top bit is clear */
+    MPCG_ESPREAD = -7      /* an operand's exponent spread exceeded mpcg_options.max_spread */
 };
 
 typedef struct {
@@ -112,6 +113,14 @@ typedef struct {
     int ksplit_override;  /* > 0: number of contraction chunks; 0 = planner's choice */
     int block_override;   /* > 0: band width of the INT8 slice GEMM, the number of consecutive
                              anti-diagonals s + t a wavefront accumulates at once (8, 12 or 16) */
+    int max_spread;       /* > 0: size the slices for row/column exponent spreads of at most
+                             max_spread (as for mpcg_workspace_size) instead of reading the
+                             exponent scan back.  The call then never synchronizes, and with a
+                             workspace set by mpcg_set_workspace it allocates nothing, so it may
+                             be captured into a HIP graph (timing off).  The scales still come
+                             from the data; an operand whose spread exceeds the bound makes
+                             mpcg_stream_status return MPCG_ESPREAD (that result is invalid),
+                             and input exponents beyond 2^30 are reported there as MPCG_ERANGE. */
 } mpcg_options;
 
 /* Plan and timing report of one multiplication. */
@@ -132,6 +141,40 @@ typedef struct {
 int mp_cgemm_ex(int m, int n, int k, const mpcg_cmat *A, int lda, const mpcg_cmat *B, int ldb,
                 mpcg_cmat *C, int ldc, int prec_bits, int mode, int scheme,
                 const mpcg_options *opt, mpcg_info *info);
+
+/*
+ * One product of a batch: C := A B with A m x k (lda), B k x n (ldb), C m x n
+ * (ldc).  The mpcg_cmat structs are host structs holding device pointers.
+ */
+typedef struct {
+    int m, n, k;
+    const mpcg_cmat *A;
+    int lda;
+    const mpcg_cmat *B;
+    int ldb;
+    mpcg_cmat *C;
+    int ldc;
+} mpcg_problem;
+
+/*
+ * mp_cgemm_batched - count independent products C_i := A_i B_i (eq. 1 for
+ * each) sharing prec_bits, mode and scheme, INT8 slices.  `problems` is a host
+ * array.  Each stage of the whole batch is one launch: one exponent scan per
+ * side, one read-back of all the spreads (one stream synchronization; none
+ * with opt->max_spread > 0), one split per side, one persistent slice-GEMM
+ * launch per band-width class over all (problem, output tile group,
+ * contraction chunk) items, balanced longest-first across the compute units,
+ * and one rounding launch.  The band width and contraction chunks are chosen
+ * per problem from its size class (opt->block_override / ksplit_override
+ * force them).  Results are the same bits as mp_cgemm on each problem.
+ * Every problem is validated as for mp_cgemm, and C_i must not overlap any
+ * A_j, B_j or another C_j.  info (may be NULL) receives the largest S_A, S_B,
+ * cutoff, ksplit and band width and the summed pairs and algo_ops.
+ * Returns MPCG_OK, MPCG_EINVAL, MPCG_ENOMEM, MPCG_ERANGE, MPCG_EHIP,
+ * MPCG_EUNSUPPORTED (FP64 slices).
+ */
+int mp_cgemm_batched(int count, const mpcg_problem *problems, int prec_bits, int mode, int scheme,
+                     const mpcg_options *opt, mpcg_info *info);
 
 /* Issue subsequent work on this HIP stream (hipStream_t as void*; NULL = null stream). */
 int mpcg_set_stream(void *hip_stream);
@@ -154,8 +197,9 @@ size_t mpcg_workspace_size(int m, int n, int k, int prec_bits, int mode, int sch
 /*
  * Synchronize `hip_stream` and return (and clear) the device status of the
  * work issued so far: MPCG_OK, MPCG_ERANGE (an output exponent overflowed
- * int32; that entry was written as zero) or MPCG_EDOMAIN (a nonzero input had
- * its significand top bit clear).
+ * int32 and that entry was written as zero, or, with max_spread, an input
+ * exponent was beyond 2^30), MPCG_EDOMAIN (a nonzero input had its
+ * significand top bit clear) or MPCG_ESPREAD (max_spread was too small).
  */
 int mpcg_stream_status(void *hip_stream);
 

@@ -24,6 +24,7 @@ MPCG_ERANGE = -3
 MPCG_EHIP = -4
 MPCG_EUNSUPPORTED = -5
 MPCG_EDOMAIN = -6
+MPCG_ESPREAD = -7
 
 MPCG_4M = 0
 MPCG_3M = 1
@@ -51,7 +52,8 @@ class mpcg_cmat(ctypes.Structure):
 
 class mpcg_options(ctypes.Structure):
     _fields_ = [("slice_type", ctypes.c_int), ("cutoff_override", ctypes.c_int),
-                ("ksplit_override", ctypes.c_int), ("block_override", ctypes.c_int)]
+                ("ksplit_override", ctypes.c_int), ("block_override", ctypes.c_int),
+                ("max_spread", ctypes.c_int)]
 
 
 class mpcg_info(ctypes.Structure):
@@ -64,6 +66,13 @@ class mpcg_info(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
+class mpcg_problem(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int), ("n", ctypes.c_int), ("k", ctypes.c_int),
+                ("A", ctypes.POINTER(mpcg_cmat)), ("lda", ctypes.c_int),
+                ("B", ctypes.POINTER(mpcg_cmat)), ("ldb", ctypes.c_int),
+                ("C", ctypes.POINTER(mpcg_cmat)), ("ldc", ctypes.c_int)]
+
+
 _P = ctypes.POINTER
 _i = ctypes.c_int
 _vp = ctypes.c_void_p
@@ -72,6 +81,8 @@ _lib.mp_cgemm.restype = _i
 _lib.mp_cgemm_ex.argtypes = [_i, _i, _i, _P(mpcg_cmat), _i, _P(mpcg_cmat), _i, _P(mpcg_cmat), _i, _i, _i, _i,
                              _P(mpcg_options), _P(mpcg_info)]
 _lib.mp_cgemm_ex.restype = _i
+_lib.mp_cgemm_batched.argtypes = [_i, _P(mpcg_problem), _i, _i, _i, _P(mpcg_options), _P(mpcg_info)]
+_lib.mp_cgemm_batched.restype = _i
 _lib.mpcg_set_stream.argtypes = [_vp]
 _lib.mpcg_set_stream.restype = _i
 _lib.mpcg_set_workspace.argtypes = [_vp, ctypes.c_size_t]
@@ -89,7 +100,7 @@ _lib.mpcg_last_timing.restype = _i
 _lib.mpcg_timing_report.argtypes = [_P(ctypes.c_float), _P(ctypes.c_int)]
 _lib.mpcg_timing_report.restype = _i
 
-EXPORTS = ["mp_cgemm", "mp_cgemm_ex", "mpcg_set_stream", "mpcg_set_workspace", "mpcg_workspace_size",
+EXPORTS = ["mp_cgemm", "mp_cgemm_ex", "mp_cgemm_batched", "mpcg_set_stream", "mpcg_set_workspace", "mpcg_workspace_size",
            "mpcg_stream_status", "mpcg_last_error", "mpcg_enable_timing", "mpcg_last_timing",
            "mpcg_timing_report"]
 
@@ -144,7 +155,7 @@ def _torch():
 
 def device_empty(rows: int, cols: int, prec_bits: int, ld: int | None = None, device="cuda") -> DeviceCMat:
     torch = _torch()
-    ld = rows if ld is None else ld
+    ld = max(1, rows) if ld is None else ld
     L = (prec_bits + 63) // 64
 
     def part():
@@ -162,7 +173,8 @@ def to_device(host, device="cuda") -> DeviceCMat:
         return DevicePart(torch.from_numpy(np.ascontiguousarray(p.sign)).to(device),
                           torch.from_numpy(np.ascontiguousarray(p.exp)).to(device),
                           torch.from_numpy(np.ascontiguousarray(p.mant).view(np.int64)).to(device))
-    return DeviceCMat(host.rows, host.cols, host.ld, host.L, part(host.re), part(host.im))
+    # an empty matrix still has a leading dimension of at least 1 (BLAS convention)
+    return DeviceCMat(host.rows, host.cols, max(1, host.ld), host.L, part(host.re), part(host.im))
 
 
 def to_numpy(dev: DeviceCMat):
@@ -243,12 +255,34 @@ def mp_cgemm(m, n, k, A: DeviceCMat, lda, B: DeviceCMat, ldb, C: DeviceCMat, ldc
 
 def mp_cgemm_ex(m, n, k, A: DeviceCMat, lda, B: DeviceCMat, ldb, C: DeviceCMat, ldc, prec_bits,
                 mode=MPCG_3M, scheme=MPCG_EXACT, slice_type=MPCG_SLICE_INT8, cutoff_override=0,
-                ksplit_override=0, block_override=0) -> dict:
+                ksplit_override=0, block_override=0, max_spread=0) -> dict:
     a, b, c = A.struct(), B.struct(), C.struct()
-    opt = mpcg_options(slice_type, cutoff_override, ksplit_override, block_override)
+    opt = mpcg_options(slice_type, cutoff_override, ksplit_override, block_override, max_spread)
     info = mpcg_info()
     _check(_lib.mp_cgemm_ex(m, n, k, ctypes.byref(a), lda, ctypes.byref(b), ldb, ctypes.byref(c), ldc,
                             prec_bits, mode, scheme, ctypes.byref(opt), ctypes.byref(info)))
+    return info.as_dict()
+
+
+def mp_cgemm_batched_raw(count, problems, prec_bits, mode, scheme, options=None, info=None) -> int:
+    return int(_lib.mp_cgemm_batched(count, problems, prec_bits, mode, scheme, options, info))
+
+
+def mp_cgemm_batched(problems, prec_bits, mode=MPCG_3M, scheme=MPCG_EXACT, cutoff_override=0,
+                     ksplit_override=0, block_override=0, max_spread=0) -> dict:
+    """problems: sequence of (A, B, C) DeviceCMat triples (C := A B each, leading
+    dimensions from the matrices).  Returns the summed plan report."""
+    keep = []
+    arr = (mpcg_problem * max(1, len(problems)))()
+    for t, (A, B, C) in enumerate(problems):
+        a, b, c = A.struct(), B.struct(), C.struct()
+        keep += [a, b, c]
+        arr[t] = mpcg_problem(A.rows, B.cols, A.cols, ctypes.pointer(a), A.ld, ctypes.pointer(b), B.ld,
+                              ctypes.pointer(c), C.ld)
+    opt = mpcg_options(MPCG_SLICE_INT8, cutoff_override, ksplit_override, block_override, max_spread)
+    info = mpcg_info()
+    _check(_lib.mp_cgemm_batched(len(problems), arr, prec_bits, mode, scheme, ctypes.byref(opt),
+                                 ctypes.byref(info)))
     return info.as_dict()
 
 

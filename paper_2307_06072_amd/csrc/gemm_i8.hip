@@ -320,17 +320,16 @@ struct Consumer {
   }
 };
 
+// One work item: the 2 x 2 tile group (gi, gj) of contraction chunk `split`.
 template <int W, bool M3>
-__global__ __launch_bounds__(256) void gemm_i8_kernel(GemmArgs a) {
+__device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& a, int split, int gi, int gj,
+                                                                 int8_t* lds_queue) {
   using G = Q<W, M3>;
   using C = Consumer<W, M3>;
   constexpr int NACC = G::NACC;
-  extern __shared__ __attribute__((aligned(1024))) int8_t lds_queue[];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
-  int split, gi, gj;
-  map_block(blockIdx.x, gridDim.x, a.mt >> 1, a.nt >> 1, split, gi, gj);
   const int wi = wv & 1, wj = wv >> 1;
   const int ti = 2 * gi + wi;
   const int tj = 2 * gj + wj;
@@ -456,6 +455,33 @@ __global__ __launch_bounds__(256) void gemm_i8_kernel(GemmArgs a) {
 }
 
 template <int W, bool M3>
+__global__ __launch_bounds__(256) void gemm_i8_kernel(GemmArgs a) {
+  extern __shared__ __attribute__((aligned(1024))) int8_t lds_queue[];
+  int split, gi, gj;
+  map_block(blockIdx.x, gridDim.x, a.mt >> 1, a.nt >> 1, split, gi, gj);
+  gemm_item<W, M3>(a, split, gi, gj, lds_queue);
+}
+
+// Persistent form for a batch of products: block b works through its list of
+// items (problem, gi, gj, split), the lists balanced by the host
+// (longest-processing-time first).  The queue is drained at the end of an
+// item; the barrier keeps a fast wavefront from refilling it while another
+// still reads the previous item's last entry.
+template <int W, bool M3>
+__global__ __launch_bounds__(256) void gemm_i8_batched_kernel(const GemmArgs* __restrict__ probs,
+                                                              const int4* __restrict__ items,
+                                                              const int* __restrict__ first) {
+  extern __shared__ __attribute__((aligned(1024))) int8_t lds_queue[];
+  const int i0 = first[blockIdx.x], i1 = first[blockIdx.x + 1];
+  for (int i = i0; i < i1; ++i) {
+    const int4 it = items[i];
+    const GemmArgs a = probs[it.x];
+    gemm_item<W, M3>(a, it.w, it.y, it.z, lds_queue);
+    __syncthreads();
+  }
+}
+
+template <int W, bool M3>
 hipError_t launch_wm(const GemmArgs& a, hipStream_t stream) {
   using G = Q<W, M3>;
   const int blocks = (a.mt / 2) * (a.nt / 2) * a.ksplit;
@@ -472,6 +498,25 @@ hipError_t launch_w(const GemmArgs& a, hipStream_t stream) {
   return a.mode3m ? launch_wm<W, true>(a, stream) : launch_wm<W, false>(a, stream);
 }
 
+template <int W, bool M3>
+hipError_t launch_batched_wm(const GemmArgs* probs, const int4* items, const int* first, int blocks,
+                             hipStream_t stream) {
+  using G = Q<W, M3>;
+  const size_t lds = (size_t)G::QS * G::ENT * 1024;
+  hipError_t e = hipFuncSetAttribute((const void*)gemm_i8_batched_kernel<W, M3>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  gemm_i8_batched_kernel<W, M3><<<dim3(blocks), dim3(256), lds, stream>>>(probs, items, first);
+  return hipGetLastError();
+}
+
+template <int W>
+hipError_t launch_batched_w(const GemmArgs* probs, const int4* items, const int* first, int blocks, int mode3m,
+                            hipStream_t stream) {
+  return mode3m ? launch_batched_wm<W, true>(probs, items, first, blocks, stream)
+                : launch_batched_wm<W, false>(probs, items, first, blocks, stream);
+}
+
 }  // namespace
 
 void gemm_i8_pads(int band, int* alo, int* ahi, int* blo, int* bhi) { pads_for(band, *alo, *ahi, *blo, *bhi); }
@@ -481,6 +526,17 @@ hipError_t launch_gemm_i8(const GemmArgs& a, int band, hipStream_t stream) {
     case 8: return launch_w<8>(a, stream);
     case 12: return launch_w<12>(a, stream);
     case 16: return launch_w<16>(a, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_gemm_i8_batched(const GemmArgs* probs, const int4* items, const int* first, int blocks,
+                                  int band, int mode3m, hipStream_t stream) {
+  if (blocks <= 0) return hipSuccess;
+  switch (band) {
+    case 8: return launch_batched_w<8>(probs, items, first, blocks, mode3m, stream);
+    case 12: return launch_batched_w<12>(probs, items, first, blocks, mode3m, stream);
+    case 16: return launch_batched_w<16>(probs, items, first, blocks, mode3m, stream);
     default: return hipErrorInvalidValue;
   }
 }

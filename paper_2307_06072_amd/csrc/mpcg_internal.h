@@ -13,6 +13,7 @@ constexpr int32_t EXP_LIMIT = 1 << 30;  // |exp| of a nonzero input
 constexpr int ST_IN_RANGE = 1;   // input exponent outside [-2^30, 2^30]
 constexpr int ST_DENORM = 2;     // nonzero input with clear top significand bit
 constexpr int ST_OUT_RANGE = 4;  // output exponent does not fit int32
+constexpr int ST_SPREAD = 8;     // exponent spread beyond the caller's bound (planning without read-back)
 
 // One real component of a column-major matrix (read side).
 struct DPart {
@@ -60,8 +61,11 @@ struct ScanSummary {
 // ----------------------------------------------------------------------------
 
 // Exponent scan of one operand: stats[R], summary.  `stats` and `summary` are
-// initialised by the launcher's own fill kernel.
-hipError_t launch_scan(const DOperand& op, RowStat* stats, ScanSummary* summary, hipStream_t stream);
+// initialised by the launcher's own fill kernel.  With status_word != NULL the
+// summary's status bits, and ST_SPREAD if the spread exceeds `limit`, are also
+// OR-ed into *status_word (for calls that do not read the summary back).
+hipError_t launch_scan(const DOperand& op, RowStat* stats, ScanSummary* summary, int limit, int* status_word,
+                       hipStream_t stream);
 
 // Digit planes of one operand.
 //   nops       planes per slice index: 2 (Re, Im), 3 (Re, Im, Re+Im) or
@@ -140,5 +144,61 @@ hipError_t launch_fill_zero(void* p, size_t n, hipStream_t stream);
 
 // C := +0 everywhere.
 hipError_t launch_zero(DOutPart cre, DOutPart cim, int m, int n, int64_t ldc, int L, hipStream_t stream);
+
+
+// ----------------------------------------------------------------------------
+// Batched launches.  Every stage of a batch of independent products is one
+// launch: job j (an operand or a problem) owns the blocks
+// [first[j], first[j+1]) of the grid, found by a binary search over `first`.
+// The job tables live in device memory.
+// ----------------------------------------------------------------------------
+__device__ inline int job_of_block(const int* __restrict__ first, int njobs, int b) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+struct ScanJob {
+  DOperand op;
+  RowStat* stats;
+  ScanSummary* summary;
+  int kchunk, rblocks;  // contraction chunk of one block, row blocks
+};
+// Block counts of the three scan launches for one operand (init, scan, summary).
+void scan_blocks(const DOperand& op, int* init_blocks, int* scan_blocks, int* kchunk, int* rblocks);
+// rows_contiguous: every job has rs == 1 (A operands); else ks == 1 (B operands).
+hipError_t launch_scan_batched(const ScanJob* jobs, int njobs, const int* first_init, int init_blocks,
+                               const int* first_scan, int scan_blocks_total, bool rows_contiguous, int limit,
+                               int* status_word, hipStream_t stream);
+
+struct ScaleJob {
+  const RowStat* stats;
+  int R, Rpad, x;
+  int32_t* G;
+};
+hipError_t launch_scales_batched(const ScaleJob* jobs, int njobs, const int* first, int blocks, hipStream_t stream);
+
+struct SplitJob {
+  DOperand op;
+  int S, Sp, Sstride, pad_lo, third, Rpad, Kpad;
+  const int32_t* G;
+  int8_t* out;
+};
+// One block per 16 x 64 tile: job j has (Kpad/64) * (Rpad/16) blocks.
+hipError_t launch_split_i8_batched(const SplitJob* jobs, int njobs, const int* first, int blocks, int prec, int L,
+                                   bool rows_contiguous, int* status, hipStream_t stream);
+
+// Persistent slice GEMM: block b runs items[first[b] .. first[b+1]) in order;
+// an item is (problem, tile-group row, tile-group column, contraction chunk).
+hipError_t launch_gemm_i8_batched(const GemmArgs* probs, const int4* items, const int* first, int blocks,
+                                  int band, int mode3m, hipStream_t stream);
+
+// Round: job j is problem j with 2 mt nt blocks (one thread per digit byte of a tile).
+hipError_t launch_round_batched(const RoundArgs* jobs, int njobs, const int* first, int blocks,
+                                hipStream_t stream);
 
 }  // namespace mpcg

@@ -116,7 +116,8 @@ struct Plan {
   int nopsA, nopsB;
   long long pairs;
   double algo_ops, bound_bits;
-  size_t off_G, off_H, off_X, off_Y, off_dig, off_top, off_lnz, total;
+  int want_groups;   // contraction chunks are added until this many work items exist
+  size_t off_G, off_H, off_X, off_Y, off_dig, off_top, off_lnz, off_scan, total;
 };
 
 int plan_slices(Plan& P, int spreadA, int spreadB, int hatA, int hatB, const mpcg_options* opt) {
@@ -155,6 +156,11 @@ int plan_slices(Plan& P, int spreadA, int spreadB, int hatA, int hatB, const mpc
   return MPCG_OK;
 }
 
+// Row statistics of A and B and the two summaries.
+size_t scan_bytes(int m, int n) {
+  return align256(sizeof(RowStat) * (size_t)m) + align256(sizeof(RowStat) * (size_t)n) + 256;
+}
+
 int plan_layout(Plan& P, const mpcg_options* opt) {
   P.mpad = (int)round_up(P.m, 32);
   P.npad = (int)round_up(P.n, 32);
@@ -182,7 +188,7 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
     const long long kb_max = kc_max / 64;
     if (kb_max < 1) return set_err(MPCG_EUNSUPPORTED, "precision/spread too large for int32 slice accumulation");
     int ks = (int)((P.kblocks + kb_max - 1) / kb_max);
-    int want = std::max(1, ceil_div(512, groups));
+    int want = std::max(1, ceil_div(P.want_groups, groups));
     ks = std::max(ks, std::min(want, P.kblocks));
     P.ksplit = ks;
   } else {
@@ -193,7 +199,7 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
     P.ys = P.SBp;
     P.xlo = P.ylo = 0;
     P.kblocks = P.kpad / 4;
-    int want = std::max(1, ceil_div(512, groups));
+    int want = std::max(1, ceil_div(P.want_groups, groups));
     P.ksplit = std::min(want, std::max(1, P.kpad / 64));
   }
   if (opt && opt->ksplit_override > 0) {
@@ -222,6 +228,7 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
   P.off_dig = o; o = align256(o + (size_t)P.ksplit * tiles * nd * 512 * dig_bytes);
   P.off_top = o; o = align256(o + (size_t)P.ksplit * tiles * 512 * 8);
   P.off_lnz = o; o = align256(o + (size_t)P.ksplit * tiles * 512 * 4);
+  P.off_scan = o; o = align256(o + scan_bytes(P.m, P.n));
   P.total = o;
   return MPCG_OK;
 }
@@ -295,8 +302,9 @@ int validate(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* 
   if (opt) {
     if (opt->slice_type != MPCG_SLICE_INT8 && opt->slice_type != MPCG_SLICE_FP64)
       return set_err(MPCG_EINVAL, "bad slice_type %d", opt->slice_type);
-    if (opt->cutoff_override < 0 || opt->ksplit_override < 0 || opt->block_override < 0)
-      return set_err(MPCG_EINVAL, "negative option override");
+    if (opt->cutoff_override < 0 || opt->ksplit_override < 0 || opt->block_override < 0 || opt->max_spread < 0)
+      return set_err(MPCG_EINVAL, "negative option");
+    if (opt->max_spread > (1 << 24)) return set_err(MPCG_EINVAL, "max_spread %d too large", opt->max_spread);
   }
   if (lda < std::max(1, m)) return set_err(MPCG_EINVAL, "lda %d < max(1, m=%d)", lda, m);
   if (ldb < std::max(1, k)) return set_err(MPCG_EINVAL, "ldb %d < max(1, k=%d)", ldb, k);
@@ -341,43 +349,59 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
     return MPCG_OK;
   }
 
-  // ---- exponent scan -------------------------------------------------------
+  // ---- exponent scan and plan ----------------------------------------------
   DOperand opA{dpart(A->re, (int64_t)lda * k), dpart(A->im, (int64_t)lda * k), m, k, 1, lda};
   DOperand opB{dpart(B->re, (int64_t)ldb * n), dpart(B->im, (int64_t)ldb * n), n, k, ldb, 1};
-  const size_t sA = align256(sizeof(RowStat) * (size_t)m), sB = align256(sizeof(RowStat) * (size_t)n);
-  if ((st = ensure_scan(sA + sB + 256))) return st;
-  RowStat* statA = reinterpret_cast<RowStat*>(g_scan);
-  RowStat* statB = reinterpret_cast<RowStat*>((char*)g_scan + sA);
-  ScanSummary* summ = reinterpret_cast<ScanSummary*>((char*)g_scan + sA + sB);
-  if ((st = record(0))) return st;
-  HIP_TRY(launch_scan(opA, statA, summ, g_stream));
-  HIP_TRY(launch_scan(opB, statB, summ + 1, g_stream));
-  HIP_TRY(hipMemcpyAsync(g_host_summary, summ, 2 * sizeof(ScanSummary), hipMemcpyDeviceToHost, g_stream));
-  if ((st = record(1))) return st;
-  HIP_TRY(hipStreamSynchronize(g_stream));
-  const ScanSummary sa = g_host_summary[0], sb = g_host_summary[1];
-  if ((sa.status | sb.status) & ST_IN_RANGE)
-    return set_err(MPCG_ERANGE, "input exponent outside [-2^30, 2^30]");
-  if (sa.nonzero == 0 || sb.nonzero == 0) {
-    HIP_TRY(launch_zero(cre, cim, m, n, ldc, L, g_stream));
-    return MPCG_OK;
-  }
-
-  // ---- plan ----------------------------------------------------------------
   Plan P{};
   P.m = m; P.n = n; P.k = k; P.p = prec_bits;
   P.mode3m = mode == MPCG_3M;
   P.trunc = scheme == MPCG_TRUNCATED;
   P.f64 = opt && opt->slice_type == MPCG_SLICE_FP64;
-  if ((st = plan_slices(P, sa.spread, sb.spread, sa.hat, sb.hat, opt))) return st;
-  if ((st = plan_layout(P, opt))) return st;
+  P.want_groups = 512;
+  const int bound = opt ? opt->max_spread : 0;
+  const size_t sA = align256(sizeof(RowStat) * (size_t)m), sB = align256(sizeof(RowStat) * (size_t)n);
+  void* ws = nullptr;
+  RowStat *statA, *statB;
+  if (bound > 0) {
+    // planned from the caller's bound: no read-back, the scan lives in the workspace
+    if ((st = plan_slices(P, bound, bound, bound, bound, opt))) return st;
+    if ((st = plan_layout(P, opt))) return st;
+    if ((st = ensure_workspace(P.total, &ws))) return st;
+    char* sc = static_cast<char*>(ws) + P.off_scan;
+    statA = reinterpret_cast<RowStat*>(sc);
+    statB = reinterpret_cast<RowStat*>(sc + sA);
+    ScanSummary* summ = reinterpret_cast<ScanSummary*>(sc + sA + sB);
+    if ((st = record(0))) return st;
+    HIP_TRY(launch_scan(opA, statA, summ, bound, g_status, g_stream));
+    HIP_TRY(launch_scan(opB, statB, summ + 1, bound, g_status, g_stream));
+    if ((st = record(1))) return st;
+  } else {
+    if ((st = ensure_scan(sA + sB + 256))) return st;
+    statA = reinterpret_cast<RowStat*>(g_scan);
+    statB = reinterpret_cast<RowStat*>((char*)g_scan + sA);
+    ScanSummary* summ = reinterpret_cast<ScanSummary*>((char*)g_scan + sA + sB);
+    if ((st = record(0))) return st;
+    HIP_TRY(launch_scan(opA, statA, summ, 0, nullptr, g_stream));
+    HIP_TRY(launch_scan(opB, statB, summ + 1, 0, nullptr, g_stream));
+    HIP_TRY(hipMemcpyAsync(g_host_summary, summ, 2 * sizeof(ScanSummary), hipMemcpyDeviceToHost, g_stream));
+    if ((st = record(1))) return st;
+    HIP_TRY(hipStreamSynchronize(g_stream));
+    const ScanSummary sa = g_host_summary[0], sb = g_host_summary[1];
+    if ((sa.status | sb.status) & ST_IN_RANGE)
+      return set_err(MPCG_ERANGE, "input exponent outside [-2^30, 2^30]");
+    if (sa.nonzero == 0 || sb.nonzero == 0) {
+      HIP_TRY(launch_zero(cre, cim, m, n, ldc, L, g_stream));
+      return MPCG_OK;
+    }
+    if ((st = plan_slices(P, sa.spread, sb.spread, sa.hat, sb.hat, opt))) return st;
+    if ((st = plan_layout(P, opt))) return st;
+    if ((st = ensure_workspace(P.total, &ws))) return st;
+  }
   if (info) {
     info->S_A = P.SA; info->S_B = P.SB; info->w = P.w; info->cutoff = P.cutoff;
     info->nprod = P.mode3m ? 3 : 4; info->ksplit = P.ksplit; info->block = P.block;
     info->pairs = P.pairs; info->algo_ops = P.algo_ops; info->bound_bits = P.bound_bits;
   }
-  void* ws = nullptr;
-  if ((st = ensure_workspace(P.total, &ws))) return st;
   char* base = static_cast<char*>(ws);
   int32_t* G = reinterpret_cast<int32_t*>(base + P.off_G);
   int32_t* H = reinterpret_cast<int32_t*>(base + P.off_H);
@@ -438,6 +462,493 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
   return MPCG_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Batches of independent products.
+// ---------------------------------------------------------------------------
+
+// Host-built job tables, copied to the device in one transfer through a
+// pinned staging buffer.  A later call waits for the previous transfer before
+// it rewrites the staging buffer.
+void* g_stage = nullptr;
+size_t g_stage_bytes = 0;
+hipEvent_t g_stage_ev = nullptr;
+bool g_stage_pending = false;
+void* g_tab = nullptr;
+size_t g_tab_bytes = 0;
+ScanSummary* g_bsum = nullptr;  // pinned read-back of a batch's summaries
+size_t g_bsum_count = 0;
+int g_num_cu = 0;
+
+struct Tables {
+  std::vector<char> bytes;
+  template <typename T>
+  size_t add(const std::vector<T>& v) {
+    const size_t off = align256(bytes.size());
+    bytes.resize(off + std::max<size_t>(1, v.size()) * sizeof(T));
+    if (!v.empty()) memcpy(bytes.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+  }
+};
+
+// Copy the tables to the device (asynchronously on the library stream);
+// returns the device base address.
+int upload_tables(const Tables& t, char** dev) {
+  const size_t n = align256(t.bytes.size());
+  if (g_stage_pending) {
+    HIP_TRY(hipEventSynchronize(g_stage_ev));
+    g_stage_pending = false;
+  }
+  if (n > g_stage_bytes) {
+    if (g_stage) HIP_TRY(hipHostFree(g_stage));
+    g_stage = nullptr;
+    g_stage_bytes = 0;
+    HIP_TRY(hipHostMalloc(&g_stage, n, 0));
+    g_stage_bytes = n;
+  }
+  if (n > g_tab_bytes) {
+    if (g_tab) {
+      HIP_TRY(hipStreamSynchronize(g_stream));
+      HIP_TRY(hipFree(g_tab));
+    }
+    g_tab = nullptr;
+    g_tab_bytes = 0;
+    HIP_TRY(hipMalloc(&g_tab, n));
+    g_tab_bytes = n;
+  }
+  if (!g_stage_ev) HIP_TRY(hipEventCreateWithFlags(&g_stage_ev, hipEventDisableTiming));
+  memcpy(g_stage, t.bytes.data(), t.bytes.size());
+  HIP_TRY(hipMemcpyAsync(g_tab, g_stage, t.bytes.size(), hipMemcpyHostToDevice, g_stream));
+  HIP_TRY(hipEventRecord(g_stage_ev, g_stream));
+  g_stage_pending = true;
+  *dev = static_cast<char*>(g_tab);
+  return MPCG_OK;
+}
+
+int num_cu() {
+  if (!g_num_cu) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    if (g_num_cu <= 0) g_num_cu = 256;
+  }
+  return MPCG_OK;
+}
+
+// Ring steps of one (pass, k-block) pass over all bands of the INT8 slice
+// GEMM (the same geometry as the kernel's units).
+long long band_steps(int W, int SA, int SB, int Dmax) {
+  const int NS = (W % 8 == 0) ? 4 : 2;
+  const int nbands = (Dmax + W) / W;
+  long long total = 0;
+  for (int b = 0; b < nbands; ++b) {
+    const int d0 = Dmax + 1 - W * (b + 1);
+    const int s_lo = std::max(0, d0 - (SB - 1)), s_hi = std::min(SA - 1, d0 + W - 1);
+    const int n = s_hi - (s_lo - W) + 1;
+    total += (long long)ceil_div(n, 2 * NS) * 2 * NS;
+  }
+  return total;
+}
+
+// Band width for a problem of this size class.  The ring wastes about W / S
+// of its MFMAs on pairs outside the slice square and spends W steps per unit
+// filling, while wider bands amortise the per-step overhead; on MI355X the
+// widest band measured fastest for every slice count from S = 40 (256 bits)
+// to S = 165 (1024 bits), so the class rule is a constant for now.
+int pick_band(const Plan& P) {
+  (void)P;
+  return 16;
+}
+
+struct BatchProblem {
+  int idx;  // index in the caller's array
+  Plan P;
+  DOperand opA, opB;
+  DOutPart cre, cim;
+  size_t ws_off;      // problem's region in the workspace
+  size_t scan_off;    // its statistics in the scan area
+  int spread[4];      // spreads the plan was made for (A, B, hat A, hat B)
+};
+
+int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, int scheme,
+                const mpcg_options* opt, mpcg_info* info) {
+  g_err.clear();
+  if (count < 0) return set_err(MPCG_EINVAL, "negative batch count %d", count);
+  if (count > 0 && !probs) return set_err(MPCG_EINVAL, "problems is NULL");
+  if (opt && opt->slice_type == MPCG_SLICE_FP64)
+    return set_err(MPCG_EUNSUPPORTED, "batched products use INT8 slices");
+  if (info) memset(info, 0, sizeof(*info));
+  std::vector<Region> outs;
+  for (int i = 0; i < count; ++i) {
+    const mpcg_problem& q = probs[i];
+    int st = validate(q.m, q.n, q.k, q.A, q.lda, q.B, q.ldb, q.C, q.ldc, prec_bits, mode, scheme, opt);
+    if (st) {
+      const std::string e = g_err;
+      return set_err(st, "problem %d: %s", i, e.c_str());
+    }
+    if (q.m > 0 && q.n > 0) {
+      const int L = (prec_bits + 63) / 64;
+      Region r[6];
+      check_part(q.C->re, q.m, q.n, q.ldc, L, "C.re", r);
+      check_part(q.C->im, q.m, q.n, q.ldc, L, "C.im", r + 3);
+      for (auto& x : r) outs.push_back(x);
+    }
+  }
+  // outputs of different problems must not overlap each other or any input
+  for (size_t a = 0; a < outs.size(); ++a)
+    for (size_t b = a + 1; b < outs.size(); ++b)
+      if (a / 6 != b / 6 && overlap(outs[a], outs[b]))
+        return set_err(MPCG_EINVAL, "outputs of problems %zu and %zu overlap", a / 6, b / 6);
+  {
+    const int L = (prec_bits + 63) / 64;
+    for (int i = 0; i < count; ++i) {
+      const mpcg_problem& q = probs[i];
+      if (q.m == 0 || q.n == 0 || q.k == 0) continue;
+      Region ra[12];
+      check_part(q.A->re, q.m, q.k, q.lda, L, "A.re", ra);
+      check_part(q.A->im, q.m, q.k, q.lda, L, "A.im", ra + 3);
+      check_part(q.B->re, q.k, q.n, q.ldb, L, "B.re", ra + 6);
+      check_part(q.B->im, q.k, q.n, q.ldb, L, "B.im", ra + 9);
+      for (size_t a = 0; a < outs.size(); ++a)
+        for (auto& x : ra)
+          if (overlap(outs[a], x)) return set_err(MPCG_EINVAL, "an output overlaps problem %d's inputs", i);
+    }
+  }
+  bool any = false;
+  for (int i = 0; i < count; ++i) any |= probs[i].m > 0 && probs[i].n > 0;
+  if (!any) return MPCG_OK;
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_timing_valid = false;
+  int st;
+  if ((st = ensure_status_and_pinned())) return st;
+  if ((st = num_cu())) return st;
+  const int L = (prec_bits + 63) / 64;
+  const int bound = opt ? opt->max_spread : 0;
+
+  std::vector<BatchProblem> bp;
+  size_t scan_total = 0;
+  for (int i = 0; i < count; ++i) {
+    const mpcg_problem& q = probs[i];
+    if (q.m == 0 || q.n == 0) continue;
+    const DOutPart cre = doutpart(q.C->re, (int64_t)q.ldc * q.n), cim = doutpart(q.C->im, (int64_t)q.ldc * q.n);
+    if (q.k == 0) {
+      HIP_TRY(launch_zero(cre, cim, q.m, q.n, q.ldc, L, g_stream));
+      continue;
+    }
+    BatchProblem b{};
+    b.idx = i;
+    b.opA = DOperand{dpart(q.A->re, (int64_t)q.lda * q.k), dpart(q.A->im, (int64_t)q.lda * q.k), q.m, q.k, 1, q.lda};
+    b.opB = DOperand{dpart(q.B->re, (int64_t)q.ldb * q.n), dpart(q.B->im, (int64_t)q.ldb * q.n), q.n, q.k, q.ldb, 1};
+    b.cre = cre;
+    b.cim = cim;
+    b.scan_off = scan_total;
+    scan_total += scan_bytes(q.m, q.n);
+    bp.push_back(b);
+  }
+  if (bp.empty()) return MPCG_OK;
+  const int np = (int)bp.size();
+
+  // ---- plans (from the bound, or after the scan read-back) ------------------
+  auto make_plan = [&](BatchProblem& b, int spA, int spB, int hA, int hB, int want) -> int {
+    Plan& P = b.P;
+    P = Plan{};
+    P.m = b.opA.R; P.n = b.opB.R; P.k = b.opA.K; P.p = prec_bits;
+    P.mode3m = mode == MPCG_3M;
+    P.trunc = scheme == MPCG_TRUNCATED;
+    P.f64 = 0;
+    P.want_groups = want;
+    b.spread[0] = spA; b.spread[1] = spB; b.spread[2] = hA; b.spread[3] = hB;
+    int r = plan_slices(P, spA, spB, hA, hB, opt);
+    if (r) return r;
+    mpcg_options o = opt ? *opt : mpcg_options{};
+    if (!o.block_override) {
+      // the band width from the size class (needs S, which plan_slices set)
+      o.block_override = pick_band(P);
+    }
+    return plan_layout(P, &o);
+  };
+
+  // scan area: library-owned, or (with a bound) at the end of the workspace
+  std::vector<ScanJob> sjA(np), sjB(np);
+  std::vector<int> fiA(np + 1), fsA(np + 1), fiB(np + 1), fsB(np + 1);
+  // scan area: per problem the row statistics of A and B, then all summaries
+  // (A and B of problem t at 2t, 2t + 1) for one read-back
+  const size_t summ_at = align256(scan_total);
+  scan_total = summ_at + align256(2 * sizeof(ScanSummary) * (size_t)np);
+  auto fill_scan_jobs = [&](char* scan_base) {
+    int ia = 0, sa = 0, ib = 0, sb = 0;
+    for (int t = 0; t < np; ++t) {
+      BatchProblem& b = bp[t];
+      char* sc = scan_base + b.scan_off;
+      const size_t sA = align256(sizeof(RowStat) * (size_t)b.opA.R);
+      ScanSummary* summ = reinterpret_cast<ScanSummary*>(scan_base + summ_at) + 2 * t;
+      int i0, n0, kc, rb;
+      sjA[t].op = b.opA; sjA[t].stats = reinterpret_cast<RowStat*>(sc); sjA[t].summary = summ;
+      scan_blocks(b.opA, &i0, &n0, &kc, &rb);
+      sjA[t].kchunk = kc; sjA[t].rblocks = rb;
+      fiA[t] = ia; ia += i0; fsA[t] = sa; sa += n0;
+      sjB[t].op = b.opB; sjB[t].stats = reinterpret_cast<RowStat*>(sc + sA); sjB[t].summary = summ + 1;
+      scan_blocks(b.opB, &i0, &n0, &kc, &rb);
+      sjB[t].kchunk = kc; sjB[t].rblocks = rb;
+      fiB[t] = ib; ib += i0; fsB[t] = sb; sb += n0;
+    }
+    fiA[np] = ia; fsA[np] = sa; fiB[np] = ib; fsB[np] = sb;
+  };
+  Tables scanT;
+  size_t o_sjA = 0, o_sjB = 0, o_fiA = 0, o_fsA = 0, o_fiB = 0, o_fsB = 0;
+  auto add_scan_tables = [&](Tables& T) {
+    o_sjA = T.add(sjA); o_sjB = T.add(sjB);
+    o_fiA = T.add(fiA); o_fsA = T.add(fsA); o_fiB = T.add(fiB); o_fsB = T.add(fsB);
+  };
+  auto launch_scans = [&](char* dev, int* status_word, int limit) -> int {
+    HIP_TRY(launch_scan_batched(reinterpret_cast<ScanJob*>(dev + o_sjA), np, reinterpret_cast<int*>(dev + o_fiA),
+                                fiA[np], reinterpret_cast<int*>(dev + o_fsA), fsA[np], true, limit, status_word,
+                                g_stream));
+    HIP_TRY(launch_scan_batched(reinterpret_cast<ScanJob*>(dev + o_sjB), np, reinterpret_cast<int*>(dev + o_fiB),
+                                fiB[np], reinterpret_cast<int*>(dev + o_fsB), fsB[np], false, limit, status_word,
+                                g_stream));
+    return MPCG_OK;
+  };
+
+  // A batch with few output tile groups splits the contraction of every
+  // problem in proportion, so that each compute unit gets about two items.
+  auto balance_chunks = [&]() -> int {
+    long long total = 0;
+    for (auto& b : bp) total += (long long)(b.P.mt / 2) * (b.P.nt / 2) * b.P.ksplit;
+    if (total >= 2ll * g_num_cu || (opt && opt->ksplit_override)) return MPCG_OK;
+    const int f = (int)((2ll * g_num_cu + total - 1) / total);
+    for (auto& b : bp) {
+      const int groups = (b.P.mt / 2) * (b.P.nt / 2);
+      const int r = make_plan(b, b.spread[0], b.spread[1], b.spread[2], b.spread[3], groups * b.P.ksplit * f);
+      if (r) return r;
+    }
+    return MPCG_OK;
+  };
+
+  void* ws = nullptr;
+  size_t ws_total = 0;
+  auto layout_workspace = [&]() {
+    ws_total = 0;
+    for (auto& b : bp) {
+      b.ws_off = ws_total;
+      ws_total += align256(b.P.total);
+    }
+  };
+  char* scan_base = nullptr;
+  if (bound > 0) {
+    for (auto& b : bp)
+      if ((st = make_plan(b, bound, bound, bound, bound, 1))) return st;
+    if ((st = balance_chunks())) return st;
+    layout_workspace();
+    const size_t scan_at = ws_total;
+    if ((st = ensure_workspace(ws_total + align256(scan_total), &ws))) return st;
+    scan_base = static_cast<char*>(ws) + scan_at;
+    fill_scan_jobs(scan_base);
+  } else {
+    if ((st = ensure_scan(align256(scan_total) + 256))) return st;
+    scan_base = static_cast<char*>(g_scan);
+    fill_scan_jobs(scan_base);
+    add_scan_tables(scanT);
+    char* dev = nullptr;
+    if ((st = upload_tables(scanT, &dev))) return st;
+    if ((st = record(0))) return st;
+    if ((st = launch_scans(dev, nullptr, 0))) return st;
+    if ((size_t)(2 * np) > g_bsum_count) {
+      if (g_bsum) HIP_TRY(hipHostFree(g_bsum));
+      g_bsum = nullptr;
+      g_bsum_count = 0;
+      HIP_TRY(hipHostMalloc((void**)&g_bsum, 2 * np * sizeof(ScanSummary), 0));
+      g_bsum_count = 2 * np;
+    }
+    HIP_TRY(hipMemcpyAsync(g_bsum, scan_base + summ_at, 2 * np * sizeof(ScanSummary), hipMemcpyDeviceToHost,
+                           g_stream));
+    if ((st = record(1))) return st;
+    HIP_TRY(hipStreamSynchronize(g_stream));
+    std::vector<BatchProblem> live;
+    for (int t = 0; t < np; ++t) {
+      const ScanSummary sa = g_bsum[2 * t], sb = g_bsum[2 * t + 1];
+      if ((sa.status | sb.status) & ST_IN_RANGE)
+        return set_err(MPCG_ERANGE, "problem %d: input exponent outside [-2^30, 2^30]", bp[t].idx);
+      if (sa.nonzero == 0 || sb.nonzero == 0) {
+        HIP_TRY(launch_zero(bp[t].cre, bp[t].cim, bp[t].opA.R, bp[t].opB.R, probs[bp[t].idx].ldc, L, g_stream));
+        continue;
+      }
+      if ((st = make_plan(bp[t], sa.spread, sb.spread, sa.hat, sb.hat, 1))) return st;
+      live.push_back(bp[t]);
+    }
+    bp.swap(live);
+    if (bp.empty()) return MPCG_OK;
+    if ((st = balance_chunks())) return st;
+    layout_workspace();
+    if ((st = ensure_workspace(ws_total, &ws))) return st;
+  }
+  const int nl = (int)bp.size();
+  char* base = static_cast<char*>(ws);
+  (void)base;
+
+  // ---- job tables of the remaining stages ------------------------------------
+  std::vector<ScaleJob> scj;
+  std::vector<int> fsc(1, 0);
+  std::vector<SplitJob> spA, spB;
+  std::vector<int> fspA(1, 0), fspB(1, 0);
+  std::vector<GemmArgs> gargs(nl);
+  std::vector<RoundArgs> rargs(nl);
+  std::vector<int> frd(1, 0);
+  const Third thirdA = mode == MPCG_3M ? Third::SUM : Third::NONE;
+  const Third thirdB = mode == MPCG_3M ? Third::SUM : Third::NEG_IM;
+  struct Item { long long cost; int4 it; int band; };
+  std::vector<Item> items;
+  for (int t = 0; t < nl; ++t) {
+    BatchProblem& b = bp[t];
+    const Plan& P = b.P;
+    char* pb = base + b.ws_off;
+    int32_t* G = reinterpret_cast<int32_t*>(pb + P.off_G);
+    int32_t* H = reinterpret_cast<int32_t*>(pb + P.off_H);
+    char* sc = scan_base + b.scan_off;
+    const size_t sA = align256(sizeof(RowStat) * (size_t)P.m);
+    scj.push_back(ScaleJob{reinterpret_cast<RowStat*>(sc), P.m, P.mpad, P.x, G});
+    fsc.push_back(fsc.back() + ceil_div(P.mpad, 256));
+    scj.push_back(ScaleJob{reinterpret_cast<RowStat*>(sc + sA), P.n, P.npad, P.x, H});
+    fsc.push_back(fsc.back() + ceil_div(P.npad, 256));
+    spA.push_back(SplitJob{b.opA, P.SA, P.SAp, P.xs, P.xlo, (int)thirdA, P.mpad, P.kpad, G,
+                           reinterpret_cast<int8_t*>(pb + P.off_X)});
+    fspA.push_back(fspA.back() + (P.kpad / 64) * (P.mpad / 16));
+    spB.push_back(SplitJob{b.opB, P.SB, P.SBp, P.ys, P.ylo, (int)thirdB, P.npad, P.kpad, H,
+                           reinterpret_cast<int8_t*>(pb + P.off_Y)});
+    fspB.push_back(fspB.back() + (P.kpad / 64) * (P.npad / 16));
+    GemmArgs& ga = gargs[t];
+    ga = GemmArgs{};
+    ga.X = reinterpret_cast<const int8_t*>(pb + P.off_X);
+    ga.Y = reinterpret_cast<const int8_t*>(pb + P.off_Y);
+    ga.mt = P.mt; ga.nt = P.nt; ga.kblocks = P.kblocks; ga.ksplit = P.ksplit;
+    ga.SAp = P.SAp; ga.SBp = P.SBp; ga.Dmax = P.Dmax; ga.mode3m = P.mode3m;
+    ga.digits = pb + P.off_dig;
+    ga.top = reinterpret_cast<int64_t*>(pb + P.off_top);
+    ga.lnz = reinterpret_cast<int32_t*>(pb + P.off_lnz);
+    ga.xs = P.xs; ga.ys = P.ys; ga.xlo = P.xlo; ga.ylo = P.ylo;
+    RoundArgs& ra = rargs[t];
+    ra = RoundArgs{};
+    ra.digits = pb + P.off_dig;
+    ra.digit_bytes = 1;
+    ra.f64_layout = 0;
+    ra.top = ga.top; ra.lnz = ga.lnz;
+    ra.ksplit = P.ksplit; ra.mt = P.mt; ra.nt = P.nt; ra.Dmax = P.Dmax; ra.w = P.w;
+    ra.G = G; ra.H = H; ra.m = P.m; ra.n = P.n; ra.prec = prec_bits; ra.L = L;
+    ra.cre = b.cre; ra.cim = b.cim; ra.ldc = probs[b.idx].ldc; ra.status = g_status;
+    frd.push_back(frd.back() + P.mt * P.nt * 2);
+    // work items: every 2x2 tile group of every contraction chunk
+    const long long steps = band_steps(P.block, P.SAp, P.SBp, P.Dmax);
+    const int kbps = ceil_div(P.kblocks, P.ksplit);
+    const int passes = P.mode3m ? 3 : 2;
+    const int gm = P.mt / 2, gn = P.nt / 2;
+    for (int sp = 0; sp < P.ksplit; ++sp) {
+      const int kb = std::min(P.kblocks, (sp + 1) * kbps) - sp * kbps;
+      const long long cost = steps * passes * kb * (P.mode3m ? 1 : 2) * P.block + 64;
+      for (int gj = 0; gj < gn; ++gj)
+        for (int gi = 0; gi < gm; ++gi) items.push_back(Item{cost, make_int4(t, gi, gj, sp), P.block});
+    }
+    if (info) {
+      info->S_A = std::max(info->S_A, P.SA); info->S_B = std::max(info->S_B, P.SB); info->w = P.w;
+      info->cutoff = std::max(info->cutoff, P.cutoff); info->nprod = P.mode3m ? 3 : 4;
+      info->ksplit = std::max(info->ksplit, P.ksplit); info->block = std::max(info->block, P.block);
+      info->pairs += P.pairs; info->algo_ops += P.algo_ops;
+      info->bound_bits = P.bound_bits;
+    }
+  }
+  // longest processing time first onto one workgroup per compute unit, per band class
+  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
+    return a.band != b.band ? a.band > b.band : a.cost > b.cost;
+  });
+  struct Launch { int band, blocks; size_t o_items, o_first; };
+  std::vector<Launch> launches;
+  std::vector<std::vector<int4>> litems;
+  std::vector<std::vector<int>> lfirst;
+  for (size_t a = 0; a < items.size();) {
+    size_t e = a;
+    while (e < items.size() && items[e].band == items[a].band) ++e;
+    const int nitems = (int)(e - a);
+    const int nbins = std::max(1, std::min(nitems, g_num_cu));
+    // bins in XCD-major order: bin i -> block (i % per) * 8 + i / per, so that
+    // equally loaded bins fill one XCD before the next
+    std::vector<long long> load(nbins, 0);
+    std::vector<std::vector<int4>> bins(nbins);
+    typedef std::pair<long long, int> LB;
+    std::vector<LB> heap;
+    for (int i = 0; i < nbins; ++i) heap.push_back(LB(0, i));
+    auto cmp = [](const LB& x, const LB& y) { return x.first != y.first ? x.first > y.first : x.second > y.second; };
+    std::make_heap(heap.begin(), heap.end(), cmp);
+    for (size_t i = a; i < e; ++i) {
+      std::pop_heap(heap.begin(), heap.end(), cmp);
+      LB& top = heap.back();
+      bins[top.second].push_back(items[i].it);
+      top.first += items[i].cost;
+      std::push_heap(heap.begin(), heap.end(), cmp);
+    }
+    const int per = ceil_div(nbins, 8);
+    std::vector<int> block_of(nbins);
+    {
+      // block b is dispatched to XCD b % 8; give XCD x the bins [x*per, (x+1)*per)
+      std::vector<int> used(nbins, 0);
+      for (int i = 0; i < nbins; ++i) {
+        int blk = (i % per) * 8 + i / per;
+        if (blk >= nbins || used[blk]) {  // ragged tail: first free block
+          blk = 0;
+          while (used[blk]) ++blk;
+        }
+        used[blk] = 1;
+        block_of[i] = blk;
+      }
+    }
+    std::vector<std::vector<int4>> by_block(nbins);
+    for (int i = 0; i < nbins; ++i) by_block[block_of[i]] = std::move(bins[i]);
+    std::vector<int4> flat;
+    std::vector<int> first(1, 0);
+    for (int bk = 0; bk < nbins; ++bk) {
+      flat.insert(flat.end(), by_block[bk].begin(), by_block[bk].end());
+      first.push_back((int)flat.size());
+    }
+    launches.push_back(Launch{items[a].band, nbins, 0, 0});
+    litems.push_back(std::move(flat));
+    lfirst.push_back(std::move(first));
+    a = e;
+  }
+
+  Tables T;
+  if (bound > 0) add_scan_tables(T);
+  const size_t o_scj = T.add(scj), o_fsc = T.add(fsc);
+  const size_t o_spA = T.add(spA), o_fspA = T.add(fspA), o_spB = T.add(spB), o_fspB = T.add(fspB);
+  const size_t o_ga = T.add(gargs), o_ra = T.add(rargs), o_frd = T.add(frd);
+  for (size_t l = 0; l < launches.size(); ++l) {
+    launches[l].o_items = T.add(litems[l]);
+    launches[l].o_first = T.add(lfirst[l]);
+  }
+  char* dev = nullptr;
+  if ((st = upload_tables(T, &dev))) return st;
+  if (bound > 0) {
+    if ((st = record(0))) return st;
+    // the scan's status bits go to the status word; spreads are checked against the bound
+    if ((st = launch_scans(dev, g_status, bound))) return st;
+    if ((st = record(1))) return st;
+  }
+  HIP_TRY(launch_scales_batched(reinterpret_cast<ScaleJob*>(dev + o_scj), (int)scj.size(),
+                                reinterpret_cast<int*>(dev + o_fsc), fsc.back(), g_stream));
+  HIP_TRY(launch_split_i8_batched(reinterpret_cast<SplitJob*>(dev + o_spA), nl, reinterpret_cast<int*>(dev + o_fspA),
+                                  fspA.back(), prec_bits, L, true, g_status, g_stream));
+  HIP_TRY(launch_split_i8_batched(reinterpret_cast<SplitJob*>(dev + o_spB), nl, reinterpret_cast<int*>(dev + o_fspB),
+                                  fspB.back(), prec_bits, L, false, g_status, g_stream));
+  if ((st = record(2))) return st;
+  for (const Launch& l : launches)
+    HIP_TRY(launch_gemm_i8_batched(reinterpret_cast<GemmArgs*>(dev + o_ga), reinterpret_cast<int4*>(dev + l.o_items),
+                                   reinterpret_cast<int*>(dev + l.o_first), l.blocks, l.band, mode == MPCG_3M,
+                                   g_stream));
+  if ((st = record(3))) return st;
+  HIP_TRY(launch_round_batched(reinterpret_cast<RoundArgs*>(dev + o_ra), nl, reinterpret_cast<int*>(dev + o_frd),
+                               frd.back(), g_stream));
+  if ((st = record(4))) return st;
+  g_timing_valid = g_timing;
+  return MPCG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -452,6 +963,11 @@ int mp_cgemm_ex(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cma
   return run(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, mode, scheme, opt, info);
 }
 
+int mp_cgemm_batched(int count, const mpcg_problem* problems, int prec_bits, int mode, int scheme,
+                     const mpcg_options* opt, mpcg_info* info) {
+  return run_batched(count, problems, prec_bits, mode, scheme, opt, info);
+}
+
 int mpcg_set_stream(void* hip_stream) {
   std::lock_guard<std::mutex> lock(g_mu);
   g_stream = static_cast<hipStream_t>(hip_stream);
@@ -461,6 +977,12 @@ int mpcg_set_stream(void* hip_stream) {
 int mpcg_set_workspace(void* dev_ptr, size_t bytes) {
   std::lock_guard<std::mutex> lock(g_mu);
   if ((dev_ptr == nullptr) != (bytes == 0)) return set_err(MPCG_EINVAL, "workspace pointer and size disagree");
+  if (dev_ptr) {
+    // allocate the status word now, so that later calls planned from a spread
+    // bound allocate nothing
+    const int st = ensure_status_and_pinned();
+    if (st) return st;
+  }
   g_user_ws = dev_ptr;
   g_user_ws_bytes = bytes;
   return MPCG_OK;
@@ -475,6 +997,7 @@ size_t mpcg_workspace_size(int m, int n, int k, int prec_bits, int mode, int sch
   P.mode3m = mode == MPCG_3M;
   P.trunc = scheme == MPCG_TRUNCATED;
   P.f64 = opt && opt->slice_type == MPCG_SLICE_FP64;
+  P.want_groups = 512;
   if (plan_slices(P, max_spread, max_spread, max_spread, max_spread, opt)) return 0;
   if (plan_layout(P, opt)) return 0;
   return P.total;
@@ -488,6 +1011,8 @@ int mpcg_stream_status(void* hip_stream) {
   int v = 0;
   HIP_TRY(hipMemcpy(&v, g_status, sizeof(int), hipMemcpyDeviceToHost));
   HIP_TRY(hipMemset(g_status, 0, sizeof(int)));
+  if (v & ST_SPREAD) return set_err(MPCG_ESPREAD, "an operand's exponent spread exceeded max_spread");
+  if (v & ST_IN_RANGE) return set_err(MPCG_ERANGE, "input exponent outside [-2^30, 2^30]");
   if (v & ST_OUT_RANGE) return set_err(MPCG_ERANGE, "output exponent outside int32");
   if (v & ST_DENORM) return set_err(MPCG_EDOMAIN, "nonzero input with clear significand top bit");
   return MPCG_OK;

@@ -77,22 +77,23 @@ struct Stream {
   }
 };
 
+// Thread gid handles digit byte (gid mod 512) of tile gid / 512: lane
+// (gid mod 512) / 8 and slot gid mod 8 of the slice GEMM's output order, so a
+// wavefront reads 64 consecutive bytes of every digit row.
 template <typename DIG>
-__global__ __launch_bounds__(256) void round_kernel(RoundArgs a) {
-  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t total = (int64_t)a.m * a.n * 2;
-  if (gid >= total) return;
-  const int i = (int)(gid % a.m);
-  const int64_t rest = gid / a.m;
-  const int j = (int)(rest % a.n);
-  const int comp = (int)(rest / a.n);
-
-  const int ti = i >> 4, tj = j >> 4;
-  const int ii = i & 15, jj = j & 15;
-  const int lane = a.f64_layout ? jj + 16 * (ii & 3) : jj + 16 * (ii >> 2);
-  const int slot = comp * 4 + (a.f64_layout ? (ii >> 2) : (ii & 3));
+__device__ inline void round_element(const RoundArgs& a, int64_t gid) {
   const int tiles = a.mt * a.nt;
-  const int tile = tj * a.mt + ti;
+  if (gid >= (int64_t)tiles * 512) return;
+  const int tile = (int)(gid >> 9);
+  const int lane = (int)(gid >> 3) & 63, slot = (int)gid & 7;
+  const int comp = slot >> 2;
+  const int jj = lane & 15;
+  // INT8 order: lane = jj + 16 (ii / 4), slot = 4 comp + ii % 4;
+  // FP64 order: lane = jj + 16 (ii % 4), slot = 4 comp + ii / 4
+  const int ii = a.f64_layout ? (lane >> 4) + 4 * (slot & 3) : 4 * (lane >> 4) + (slot & 3);
+  const int ti = tile % a.mt, tj = tile / a.mt;
+  const int i = ti * 16 + ii, j = tj * 16 + jj;
+  if (i >= a.m || j >= a.n) return;
   const int nd = a.Dmax + 1;
   const int w = a.w;
 
@@ -209,6 +210,18 @@ __global__ __launch_bounds__(256) void round_kernel(RoundArgs a) {
   out.exp[o] = (int32_t)e_out;
 }
 
+template <typename DIG>
+__global__ __launch_bounds__(256) void round_kernel(RoundArgs a) {
+  round_element<DIG>(a, (int64_t)blockIdx.x * 256 + threadIdx.x);
+}
+
+// Batched form (INT8 digits): job j is problem j with 2 mt nt blocks.
+__global__ __launch_bounds__(256) void round_batched(const RoundArgs* __restrict__ jobs, int njobs,
+                                                     const int* __restrict__ first) {
+  const int j = job_of_block(first, njobs, blockIdx.x);
+  round_element<uint8_t>(jobs[j], (int64_t)(blockIdx.x - first[j]) * 256 + threadIdx.x);
+}
+
 __global__ void zero_kernel(DOutPart cre, DOutPart cim, int m, int n, int64_t ldc, int L) {
   const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t total = (int64_t)m * n * 2;
@@ -237,8 +250,7 @@ hipError_t launch_fill_zero(void* p, size_t n, hipStream_t stream) {
 }
 
 hipError_t launch_round(const RoundArgs& a, hipStream_t stream) {
-  const int64_t total = (int64_t)a.m * a.n * 2;
-  const int blocks = (int)((total + 255) / 256);
+  const int blocks = a.mt * a.nt * 2;  // 512 digit bytes per tile
   if (a.digit_bytes == 1)
     round_kernel<uint8_t><<<dim3(blocks), dim3(256), 0, stream>>>(a);
   else
@@ -249,6 +261,13 @@ hipError_t launch_round(const RoundArgs& a, hipStream_t stream) {
 hipError_t launch_zero(DOutPart cre, DOutPart cim, int m, int n, int64_t ldc, int L, hipStream_t stream) {
   const int64_t total = (int64_t)m * n * 2;
   zero_kernel<<<dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream>>>(cre, cim, m, n, ldc, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_round_batched(const RoundArgs* jobs, int njobs, const int* first, int blocks,
+                                hipStream_t stream) {
+  if (njobs <= 0 || blocks <= 0) return hipSuccess;
+  round_batched<<<dim3(blocks), dim3(256), 0, stream>>>(jobs, njobs, first);
   return hipGetLastError();
 }
 

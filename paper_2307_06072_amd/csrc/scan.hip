@@ -11,8 +11,8 @@ namespace mpcg {
 
 namespace {
 
-__global__ void stats_init_kernel(RowStat* stats, int R, ScanSummary* summary) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void stats_init_body(RowStat* stats, int R, ScanSummary* summary, int blk) {
+  const int r = blk * 256 + (int)threadIdx.x;
   if (r < R) {
     RowStat s;
     s.emax = INT32_MIN;
@@ -29,6 +29,10 @@ __global__ void stats_init_kernel(RowStat* stats, int R, ScanSummary* summary) {
     z.status = 0;
     *summary = z;
   }
+}
+
+__global__ __launch_bounds__(256) void stats_init_kernel(RowStat* stats, int R, ScanSummary* summary) {
+  stats_init_body(stats, R, summary, blockIdx.x);
 }
 
 struct Acc {
@@ -54,13 +58,13 @@ __device__ inline void consume(Acc& a, int32_t er, int32_t ei) {
   }
 }
 
-// Rows contiguous (A): 64 rows x 4 contraction lanes per block, grid.y splits K.
-__global__ __launch_bounds__(256) void scan_rows_kernel(DOperand op, RowStat* stats, int kchunk,
-                                                        ScanSummary* summary) {
+// Rows contiguous (A): 64 rows x 4 contraction lanes per block, by splits K.
+__device__ inline void scan_rows_body(const DOperand& op, RowStat* stats, int kchunk, ScanSummary* summary,
+                                      int bx, int by) {
   __shared__ Acc part[4][64];
   const int rl = threadIdx.x & 63, kl = threadIdx.x >> 6;
-  const int r = blockIdx.x * 64 + rl;
-  const int k0 = blockIdx.y * kchunk;
+  const int r = bx * 64 + rl;
+  const int k0 = by * kchunk;
   const int k1 = min(op.K, k0 + kchunk);
   Acc a{INT32_MIN, INT32_MAX, INT32_MAX, 0};
   if (r < op.R) {
@@ -87,13 +91,18 @@ __global__ __launch_bounds__(256) void scan_rows_kernel(DOperand op, RowStat* st
   }
 }
 
-// Contraction contiguous (B): one wavefront per row, lanes along K, grid.y splits K.
-__global__ __launch_bounds__(256) void scan_cols_kernel(DOperand op, RowStat* stats, int kchunk,
+__global__ __launch_bounds__(256) void scan_rows_kernel(DOperand op, RowStat* stats, int kchunk,
                                                         ScanSummary* summary) {
+  scan_rows_body(op, stats, kchunk, summary, blockIdx.x, blockIdx.y);
+}
+
+// Contraction contiguous (B): one wavefront per row, lanes along K, by splits K.
+__device__ inline void scan_cols_body(const DOperand& op, RowStat* stats, int kchunk, ScanSummary* summary,
+                                      int bx, int by) {
   const int lane = threadIdx.x & 63;
-  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int r = bx * 4 + (threadIdx.x >> 6);
   if (r >= op.R) return;
-  const int k0 = blockIdx.y * kchunk;
+  const int k0 = by * kchunk;
   const int k1 = min(op.K, k0 + kchunk);
   Acc a{INT32_MIN, INT32_MAX, INT32_MAX, 0};
   for (int kk = k0 + lane; kk < k1; kk += 64) {
@@ -116,8 +125,14 @@ __global__ __launch_bounds__(256) void scan_cols_kernel(DOperand op, RowStat* st
   }
 }
 
+__global__ __launch_bounds__(256) void scan_cols_kernel(DOperand op, RowStat* stats, int kchunk,
+                                                        ScanSummary* summary) {
+  scan_cols_body(op, stats, kchunk, summary, blockIdx.x, blockIdx.y);
+}
+
 // Operand-wide maxima of the spreads and the number of nonzero rows.
-__global__ __launch_bounds__(256) void summary_kernel(const RowStat* stats, int R, ScanSummary* summary) {
+__device__ inline void summary_body(const RowStat* stats, int R, ScanSummary* summary, int limit = 0,
+                                    int* status_word = nullptr) {
   __shared__ int32_t s_sp[256], s_hat[256], s_nz[256];
   int32_t sp = 0, hat = 0, nz = 0;
   for (int r = threadIdx.x; r < R; r += 256) {
@@ -144,11 +159,21 @@ __global__ __launch_bounds__(256) void summary_kernel(const RowStat* stats, int 
     summary->spread = s_sp[0];
     summary->hat = s_hat[0];
     summary->nonzero = s_nz[0];
+    if (status_word) {
+      int bits = summary->status;
+      if (s_sp[0] > limit || s_hat[0] > limit) bits |= ST_SPREAD;
+      if (bits) atomicOr(status_word, bits);
+    }
   }
 }
 
-__global__ void scales_kernel(const RowStat* stats, int R, int Rpad, int x, int32_t* G) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void summary_kernel(const RowStat* stats, int R, ScanSummary* summary,
+                                                      int limit, int* status_word) {
+  summary_body(stats, R, summary, limit, status_word);
+}
+
+__device__ inline void scales_body(const RowStat* stats, int R, int Rpad, int x, int32_t* G, int blk) {
+  const int r = blk * 256 + (int)threadIdx.x;
   if (r >= Rpad) return;
   int32_t g = 0;
   if (r < R) {
@@ -158,32 +183,105 @@ __global__ void scales_kernel(const RowStat* stats, int R, int Rpad, int x, int3
   G[r] = g;
 }
 
+__global__ __launch_bounds__(256) void scales_kernel(const RowStat* stats, int R, int Rpad, int x, int32_t* G) {
+  scales_body(stats, R, Rpad, x, G, blockIdx.x);
+}
+
+// ---- batched forms ----------------------------------------------------------
+__global__ __launch_bounds__(256) void stats_init_batched(const ScanJob* __restrict__ jobs, int njobs,
+                                                          const int* __restrict__ first) {
+  const int j = job_of_block(first, njobs, blockIdx.x);
+  const ScanJob& J = jobs[j];
+  stats_init_body(J.stats, J.op.R, J.summary, blockIdx.x - first[j]);
+}
+
+template <bool ROWS>
+__global__ __launch_bounds__(256) void scan_batched(const ScanJob* __restrict__ jobs, int njobs,
+                                                    const int* __restrict__ first) {
+  const int j = job_of_block(first, njobs, blockIdx.x);
+  const ScanJob& J = jobs[j];
+  const int local = blockIdx.x - first[j];
+  const int bx = local % J.rblocks, by = local / J.rblocks;
+  if (ROWS) scan_rows_body(J.op, J.stats, J.kchunk, J.summary, bx, by);
+  else scan_cols_body(J.op, J.stats, J.kchunk, J.summary, bx, by);
+}
+
+__global__ __launch_bounds__(256) void summary_batched(const ScanJob* __restrict__ jobs, int limit,
+                                                       int* status_word) {
+  const ScanJob& J = jobs[blockIdx.x];
+  summary_body(J.stats, J.op.R, J.summary, limit, status_word);
+}
+
+__global__ __launch_bounds__(256) void scales_batched(const ScaleJob* __restrict__ jobs, int njobs,
+                                                      const int* __restrict__ first) {
+  const int j = job_of_block(first, njobs, blockIdx.x);
+  const ScaleJob& J = jobs[j];
+  scales_body(J.stats, J.R, J.Rpad, J.x, J.G, blockIdx.x - first[j]);
+}
+
 }  // namespace
 
-hipError_t launch_scan(const DOperand& op, RowStat* stats, ScanSummary* summary, hipStream_t stream) {
+void scan_blocks(const DOperand& op, int* init_blocks, int* nblocks, int* kchunk, int* rblocks) {
   const int R = op.R, K = op.K;
-  stats_init_kernel<<<dim3((R + 255) / 256 + 1), dim3(256), 0, stream>>>(stats, R, summary);
-  if (R > 0 && K > 0) {
-    if (op.rs == 1) {
-      const int rblocks = (R + 63) / 64;
-      int ksplit = max(1, min((K + 255) / 256, 2048 / rblocks + 1));
-      const int kchunk = (K + ksplit - 1) / ksplit;
-      ksplit = (K + kchunk - 1) / kchunk;
-      scan_rows_kernel<<<dim3(rblocks, ksplit), dim3(256), 0, stream>>>(op, stats, kchunk, summary);
-    } else {
-      const int rblocks = (R + 3) / 4;
-      int ksplit = max(1, min((K + 1023) / 1024, 2048 / rblocks + 1));
-      const int kchunk = (K + ksplit - 1) / ksplit;
-      ksplit = (K + kchunk - 1) / kchunk;
-      scan_cols_kernel<<<dim3(rblocks, ksplit), dim3(256), 0, stream>>>(op, stats, kchunk, summary);
-    }
+  *init_blocks = (R + 255) / 256 + 1;
+  *nblocks = 0;
+  *kchunk = 1;
+  *rblocks = 1;
+  if (R <= 0 || K <= 0) return;
+  int rb, ksplit;
+  if (op.rs == 1) {
+    rb = (R + 63) / 64;
+    ksplit = max(1, min((K + 255) / 256, 2048 / rb + 1));
+  } else {
+    rb = (R + 3) / 4;
+    ksplit = max(1, min((K + 1023) / 1024, 2048 / rb + 1));
   }
-  summary_kernel<<<dim3(1), dim3(256), 0, stream>>>(stats, R, summary);
+  const int kc = (K + ksplit - 1) / ksplit;
+  ksplit = (K + kc - 1) / kc;
+  *kchunk = kc;
+  *rblocks = rb;
+  *nblocks = rb * ksplit;
+}
+
+hipError_t launch_scan(const DOperand& op, RowStat* stats, ScanSummary* summary, int limit, int* status_word,
+                       hipStream_t stream) {
+  int ib, nb, kchunk, rblocks;
+  scan_blocks(op, &ib, &nb, &kchunk, &rblocks);
+  stats_init_kernel<<<dim3(ib), dim3(256), 0, stream>>>(stats, op.R, summary);
+  if (nb > 0) {
+    const int ksplit = nb / rblocks;
+    if (op.rs == 1)
+      scan_rows_kernel<<<dim3(rblocks, ksplit), dim3(256), 0, stream>>>(op, stats, kchunk, summary);
+    else
+      scan_cols_kernel<<<dim3(rblocks, ksplit), dim3(256), 0, stream>>>(op, stats, kchunk, summary);
+  }
+  summary_kernel<<<dim3(1), dim3(256), 0, stream>>>(stats, op.R, summary, limit, status_word);
   return hipGetLastError();
 }
 
 hipError_t launch_scales(const RowStat* stats, int R, int Rpad, int x, int32_t* G, hipStream_t stream) {
   scales_kernel<<<dim3((Rpad + 255) / 256), dim3(256), 0, stream>>>(stats, R, Rpad, x, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_batched(const ScanJob* jobs, int njobs, const int* first_init, int init_blocks,
+                               const int* first_scan, int scan_blocks_total, bool rows_contiguous, int limit,
+                               int* status_word, hipStream_t stream) {
+  if (njobs <= 0) return hipSuccess;
+  stats_init_batched<<<dim3(init_blocks), dim3(256), 0, stream>>>(jobs, njobs, first_init);
+  if (scan_blocks_total > 0) {
+    if (rows_contiguous)
+      scan_batched<true><<<dim3(scan_blocks_total), dim3(256), 0, stream>>>(jobs, njobs, first_scan);
+    else
+      scan_batched<false><<<dim3(scan_blocks_total), dim3(256), 0, stream>>>(jobs, njobs, first_scan);
+  }
+  summary_batched<<<dim3(njobs), dim3(256), 0, stream>>>(jobs, limit, status_word);
+  return hipGetLastError();
+}
+
+hipError_t launch_scales_batched(const ScaleJob* jobs, int njobs, const int* first, int blocks, hipStream_t stream) {
+  if (njobs <= 0 || blocks <= 0) return hipSuccess;
+  scales_batched<<<dim3(blocks), dim3(256), 0, stream>>>(jobs, njobs, first);
   return hipGetLastError();
 }
 

@@ -82,17 +82,14 @@ struct Layout<double> {
 };
 
 template <typename DT, bool ROWCONTIG>
-__global__ __launch_bounds__(256) void split_kernel(DOperand op, int prec, int L, int S, int Sp, int Sstride,
-                                                    int pad_lo, int w, int third,
-                                                    const int32_t* __restrict__ G, int Rpad, int Kpad,
-                                                    DT* __restrict__ out, int* status) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
+__device__ inline void split_tile(const DOperand& op, int prec, int L, int S, int Sp, int Sstride, int pad_lo,
+                                  int w, int third, const int32_t* __restrict__ G, int Rpad, int Kpad,
+                                  DT* __restrict__ out, int* status, int kt, int rt, unsigned char* lds_raw) {
   DT* lds = reinterpret_cast<DT*>(lds_raw);
   constexpr int FRAG = Layout<DT>::FRAG_BYTES / (int)sizeof(DT);  // elements per (op, digit) tile
 
   const int g = 56 / w;  // digits per window
   const int nops = third ? 3 : 2;
-  const int kt = blockIdx.x, rt = blockIdx.y;
   const int t = threadIdx.x;
   const uint64_t low_mask = ~((1ull << (64 * L - prec)) - 1ull) | (64 * L - prec == 0 ? ~0ull : 0ull);
   const int64_t wS = (int64_t)w * S;
@@ -216,6 +213,30 @@ __global__ __launch_bounds__(256) void split_kernel(DOperand op, int prec, int L
   }
 }
 
+template <typename DT, bool ROWCONTIG>
+__global__ __launch_bounds__(256) void split_kernel(DOperand op, int prec, int L, int S, int Sp, int Sstride,
+                                                    int pad_lo, int w, int third,
+                                                    const int32_t* __restrict__ G, int Rpad, int Kpad,
+                                                    DT* __restrict__ out, int* status) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  split_tile<DT, ROWCONTIG>(op, prec, L, S, Sp, Sstride, pad_lo, w, third, G, Rpad, Kpad, out, status, blockIdx.x,
+                            blockIdx.y, lds_raw);
+}
+
+// Batched INT8 form: job j owns (Kpad/64) * (Rpad/16) blocks.
+template <bool ROWCONTIG>
+__global__ __launch_bounds__(256) void split_i8_batched(const SplitJob* __restrict__ jobs, int njobs,
+                                                        const int* __restrict__ first, int prec, int L,
+                                                        int* status) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int j = job_of_block(first, njobs, blockIdx.x);
+  const SplitJob& J = jobs[j];
+  const int local = blockIdx.x - first[j];
+  const int kts = J.Kpad / 64;
+  split_tile<int8_t, ROWCONTIG>(J.op, prec, L, J.S, J.Sp, J.Sstride, J.pad_lo, 7, J.third, J.G, J.Rpad, J.Kpad,
+                                J.out, status, local % kts, local / kts, lds_raw);
+}
+
 template <typename DT>
 hipError_t launch_split_t(const DOperand& op, int prec, int L, int S, int Sp, int Sstride, int pad_lo, int w,
                           Third third, const int32_t* G, int Rpad, int Kpad, DT* out, int* status,
@@ -244,6 +265,17 @@ hipError_t launch_split_i8(const DOperand& op, int prec, int L, int S, int Sp, i
 hipError_t launch_split_f64(const DOperand& op, int prec, int L, int S, int Sp, int w, Third third,
                             const int32_t* G, int Rpad, int Kpad, double* out, int* status, hipStream_t stream) {
   return launch_split_t<double>(op, prec, L, S, Sp, Sp, 0, w, third, G, Rpad, Kpad, out, status, stream);
+}
+
+hipError_t launch_split_i8_batched(const SplitJob* jobs, int njobs, const int* first, int blocks, int prec, int L,
+                                   bool rows_contiguous, int* status, hipStream_t stream) {
+  if (njobs <= 0 || blocks <= 0) return hipSuccess;
+  const size_t lds = (size_t)3 * (56 / 7) * Layout<int8_t>::FRAG_BYTES;  // up to three planes
+  if (rows_contiguous)
+    split_i8_batched<true><<<dim3(blocks), dim3(256), lds, stream>>>(jobs, njobs, first, prec, L, status);
+  else
+    split_i8_batched<false><<<dim3(blocks), dim3(256), lds, stream>>>(jobs, njobs, first, prec, L, status);
+  return hipGetLastError();
 }
 
 }  // namespace mpcg

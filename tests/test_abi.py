@@ -131,3 +131,58 @@ def test_injected_hip_failure_is_reported():
     env = dict(os.environ, MPCG_FAULT_INJECT="hip", HIP_VISIBLE_DEVICES="")
     r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
+
+
+# ---------------------------------------------------------------------------
+# batched entry point: validation before any device work
+# ---------------------------------------------------------------------------
+def _batch_call(probs, p=256, mode=1, scheme=0, opt=None, count=None):
+    import paper_2307_06072_amd as mp
+    keep = []
+    arr = (mp.mpcg_problem * max(1, len(probs)))()
+    for t, (m, n, k, A, B, C, lda, ldb, ldc) in enumerate(probs):
+        keep += [A, B, C]
+        arr[t] = mp.mpcg_problem(m, n, k, ctypes.pointer(A) if A is not None else None, lda,
+                                 ctypes.pointer(B) if B is not None else None, ldb,
+                                 ctypes.pointer(C) if C is not None else None, ldc)
+    o = ctypes.byref(opt) if opt is not None else None
+    return mp.mp_cgemm_batched_raw(len(probs) if count is None else count, arr, p, mode, scheme, o, None)
+
+
+def _prob(t, m=4, n=4, k=4):
+    return (m, n, k, _fake_cmat((1 + 3 * t) << 40), _fake_cmat((2 + 3 * t) << 40), _fake_cmat((3 + 3 * t) << 40),
+            max(1, m), max(1, k), max(1, m))
+
+
+def test_batched_validation():
+    import paper_2307_06072_amd as mp
+    assert _batch_call([], count=0) == mp.MPCG_OK
+    assert _batch_call([_prob(0)], count=-1) == mp.MPCG_EINVAL
+    assert mp.mp_cgemm_batched_raw(2, None, 256, 1, 0, None, None) == mp.MPCG_EINVAL
+    bad = list(_prob(1))
+    bad[6] = 2  # lda < m
+    assert _batch_call([_prob(0), tuple(bad)]) == mp.MPCG_EINVAL
+    assert "problem 1" in mp.mpcg_last_error()
+    assert _batch_call([_prob(0)], p=1) == mp.MPCG_EINVAL
+    assert _batch_call([_prob(0)], mode=3) == mp.MPCG_EINVAL
+    assert _batch_call([_prob(0)], opt=mp.mpcg_options(1, 0, 0, 0, 0)) == mp.MPCG_EUNSUPPORTED
+    assert _batch_call([_prob(0)], opt=mp.mpcg_options(0, 0, 0, 0, -4)) == mp.MPCG_EINVAL
+    # nothing to compute: empty outputs need no device
+    assert _batch_call([_prob(0, m=0), _prob(1, n=0)]) == mp.MPCG_OK
+
+
+def test_batched_outputs_must_not_overlap():
+    import paper_2307_06072_amd as mp
+    p0, p1 = _prob(0), list(_prob(1))
+    p1[5] = p0[5]  # both problems write the same C
+    assert _batch_call([p0, tuple(p1)]) == mp.MPCG_EINVAL
+    assert "overlap" in mp.mpcg_last_error()
+    p2 = list(_prob(2))
+    p2[5] = p0[3]  # problem 2 writes problem 0's A
+    assert _batch_call([p0, tuple(p2)]) == mp.MPCG_EINVAL
+
+
+def test_max_spread_option_validated():
+    import paper_2307_06072_amd as mp
+    assert _call(opt=mp.mpcg_options(0, 0, 0, 0, -1)) == mp.MPCG_EINVAL
+    assert _call(opt=mp.mpcg_options(0, 0, 0, 0, 1 << 25)) == mp.MPCG_EINVAL
