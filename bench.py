@@ -134,6 +134,119 @@ def cpu_baseline(A, B, m, n, k, p, target_s):
                       f"{dt:.1f} s wall on {threads} threads; value = 8*k*entries/s"}
 
 
+def small_latency_case():
+    """64^3 at 256 bits: FP64-4M (the paper's plain form) and INT8-3M, exact."""
+    import torch
+    import paper_2307_06072_amd as mp
+    from mpgen import workload_inputs
+    log("64^3 at 256 bits")
+    m, n, k, p, A, B = workload_inputs("cgemm64_p256")
+    dA, dB, dC = mp.to_device(A), mp.to_device(B), mp.device_empty(m, n, p)
+    out = {}
+    for sl, md in (("fp64", "4M"), ("int8", "3M")):
+        dt, info, st = time_calls(dA, dB, dC, m, n, k, p, _mode(md), _scheme("exact"), _slice(sl), steps=20, warmup=3)
+        out[f"{sl}_{md}_exact"] = {"ms_per_call": 1000 * dt / 20, "8mnk_per_s": 8.0 * m * n * k * 20 / dt,
+                                   "stage_us": st, "S_A": info["S_A"], "pairs": info["pairs"]}
+    return {"cgemm64_p256": out}
+
+
+def batched_case():
+    """256 independent products, shapes uniform on [16, 768]^3, 256 bits,
+    exponents in [-8, 8]: one mp_cgemm_batched call against one call each."""
+    import torch
+    import paper_2307_06072_amd as mp
+    from mpgen import batched_inputs
+    log("batched: 256 uneven products at 256 bits")
+    p = 256
+    batch = batched_inputs(256, 4, p, 8)
+    devs = [(mp.to_device(A), mp.to_device(B), mp.device_empty(m, n, p)) for (m, n, k, A, B) in batch]
+    del batch
+    work = sum(8.0 * A.rows * B.cols * A.cols for (A, B, _) in devs)
+    mp.mpcg_set_stream()
+    info = mp.mp_cgemm_batched(devs, p, mp.MPCG_3M)
+    torch.cuda.synchronize()
+    mp.mpcg_enable_timing(True)
+    mp.mpcg_timing_report()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        info = mp.mp_cgemm_batched(devs, p, mp.MPCG_3M)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    us, nc = mp.mpcg_timing_report()
+    mp.mpcg_enable_timing(False)
+    st = [u / max(1, nc) for u in us]
+    t0 = time.perf_counter()
+    for (dA, dB, dC) in devs:
+        mp.mp_cgemm(dA.rows, dB.cols, dA.cols, dA, dA.ld, dB, dB.ld, dC, dC.ld, p, mp.MPCG_3M, mp.MPCG_EXACT)
+    torch.cuda.synchronize()
+    dt1 = time.perf_counter() - t0
+    if mp.mpcg_stream_status() != 0:
+        raise RuntimeError(mp.mpcg_last_error())
+    return {"batched256_p256": {"ms_per_call": 1000 * dt, "8mnk_per_s": work / dt, "stage_us": st,
+                                "gemm_frac_of_peak": info["algo_ops"] / (st[2] * 1e-6) / 1e12 / PEAK_INT8_TOPS,
+                                "one_call_each_ms": 1000 * dt1, "speedup_over_one_call_each": dt1 / dt,
+                                "pairs_total": info["pairs"], "block": info["block"]}}
+
+
+def lu_update_stream():
+    """The 31 trailing-update products of a blocked LU of order 4096 with
+    block 128 (r x 128 times 128 x r, r = 3968 ... 128) at 256 bits, planned
+    from a spread bound and captured in one HIP graph; the graph is replayed."""
+    import torch
+    import paper_2307_06072_amd as mp
+    from mpgen import random_cmat
+    log("LU trailing-update stream: 31 products, graph-captured")
+    p, b, N, R, bound = 256, 128, 4096, 2, 8
+    sizes = [N - b * (j + 1) for j in range(N // b - 1)]
+    ops = []
+    for j, r in enumerate(sizes):
+        A = mp.to_device(random_cmat([5, j], 0, r, b, p, R))
+        B = mp.to_device(random_cmat([5, j], 1, b, r, p, R))
+        ops.append((A, B, mp.device_empty(r, r, p)))
+    opt = mp.mpcg_options(mp.MPCG_SLICE_INT8, 0, 0, 0, bound)
+    wsz = max(mp.mpcg_workspace_size(r, r, b, p, mp.MPCG_3M, mp.MPCG_EXACT, opt, bound) for r in sizes)
+    ws = torch.empty(wsz, dtype=torch.uint8, device="cuda")
+    work = sum(8.0 * r * r * b for r in sizes)
+    mp.mpcg_set_workspace(ws.data_ptr(), wsz)
+    try:
+        def issue():
+            for (A, B, C) in ops:
+                mp.mp_cgemm_ex(A.rows, B.cols, A.cols, A, A.ld, B, B.ld, C, C.ld, p, mp.MPCG_3M, mp.MPCG_EXACT,
+                               max_spread=bound)
+        mp.mpcg_set_stream()
+        issue()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        issue()
+        torch.cuda.synchronize()
+        eager = time.perf_counter() - t0
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side, capture_error_mode="thread_local"):
+                mp.mpcg_set_stream(side.cuda_stream)
+                issue()
+        mp.mpcg_set_stream()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g.replay()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        if mp.mpcg_stream_status() != 0:
+            raise RuntimeError(mp.mpcg_last_error())
+    finally:
+        mp.mpcg_set_workspace(None, 0)
+        mp.mpcg_set_stream()
+    return {"lu_updates_n4096_b128_p256": {"ms_per_replay": 1000 * dt, "8mnk_per_s": work / dt,
+                                           "eager_ms": 1000 * eager, "products": len(sizes), "max_spread": bound}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,6 +346,11 @@ def main() -> int:
             extra["cgemm2048_p1024_truncated"] = {"ms_per_call": 1000 * dtt / 2, "8mnk_per_s": 8.0 * m * n * k * 2 / dtt,
                                                   "cutoff": infot["cutoff"], "pairs": infot["pairs"],
                                                   "gemm_frac_of_peak": infot["algo_ops"] / (stt[2] * 1e-6) / 1e12 / PEAK_INT8_TOPS}
+
+    if not args.no_extras:
+        extra.update(small_latency_case())
+        extra.update(batched_case())
+        extra.update(lu_update_stream())
 
     cpu = None
     if not args.no_cpu_baseline:
