@@ -21,8 +21,10 @@
 // that only fill the ring and is padded with steps on zero fragments to an
 // even number of queue entries.
 //
-// Operand fragments (16 rows x 64 k, 16 bytes per lane) stream from the digit
-// planes into a workgroup-shared queue in LDS by direct global->LDS loads
+// Operand fragments (16 rows x 64 k, 16 bytes per lane, 1 KB contiguous) stream
+// from the tile-major digit planes (consecutive slices of a tile are k-rows
+// apart, so the walk touches few pages: striding whole planes per step thrashes
+// the TLB) into a workgroup-shared queue in LDS by direct global->LDS loads
 // (16 bytes per lane: one fragment per instruction).  A queue entry holds the
 // fragments of NS consecutive steps for the workgroup's 2 x 2 tiles; each
 // fragment is loaded once and read by the two wavefronts that need it.  The
@@ -146,7 +148,7 @@ template <int W, bool M3>
 struct Producer {
   using G = Q<W, M3>;
   static constexpr int PW = G::PW;
-  size_t xplane, yplane;  // bytes per slice of a plane
+  size_t xplane, yplane;  // bytes between consecutive slices of a tile's plane
   int SA, SB, Dmax, nbands, kb0, kb1;
   int xs, ys, xlo, ylo;   // slices per plane (with pads) and lower pads
   unsigned lane16;
@@ -284,17 +286,19 @@ struct Consumer {
       const int V = V0 + h;
       ring0[V % W] = bbuf[PAR][h][0];
       if (!M3) ring1[V % W] = bbuf[PAR][h][NB - 1];
+      // in accumulator order: the same accumulator recurs only W MFMAs later,
+      // also across steps
 #pragma unroll
-      for (int r = 0; r < W; ++r) {
+      for (int j = 0; j < W; ++j) {
         if (MF) {
-          const int j = (V - r + W) % W;  // slot r holds the B fragment of diagonal d0 + j
+          const int r = (V - j + W) % W;  // ring slot holding the B fragment of diagonal d0 + j
           acc[Q0][j] = mfma(abuf[PAR][h], ring0[r], acc[Q0][j]);
           if (!M3) acc[Q1][j] = mfma(abuf[PAR][h], ring1[r], acc[Q1][j]);
         }
         // spread this wavefront's loads over the entry
         constexpr int per = (PW + NS - 1) / NS;
-        const int i = h * per + r;
-        if (r < per && i < PW) P.issue(i, dst);
+        const int i = h * per + j;
+        if (j < per && i < PW) P.issue(i, dst);
       }
     }
     P.step();
@@ -339,8 +343,10 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
   const int kb1 = min(a.kblocks, kb0 + kbps);
 
   Producer<W, M3> P;
-  P.xplane = (size_t)a.mt * a.kblocks * 1024;  // bytes per (op, s) plane
-  P.yplane = (size_t)a.nt * a.kblocks * 1024;
+  // tile-major planes: consecutive slices of one tile and plane are a k-row
+  // (kblocks fragments) apart, so a unit's loads stay within a few pages
+  P.xplane = (size_t)a.kblocks * 1024;
+  P.yplane = (size_t)a.kblocks * 1024;
   P.lane16 = (unsigned)lane * 16u;
   P.xs = a.xs;
   P.ys = a.ys;
@@ -353,9 +359,11 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
   P.kb0 = kb0;
   P.kb1 = kb1;
   {
-    const int8_t* X0 = a.X + (size_t)(2 * gi) * a.kblocks * 1024;  // row tiles 2gi, 2gi+1
-    const int8_t* Y0 = a.Y + (size_t)(2 * gj) * a.kblocks * 1024;  // column tiles 2gj, 2gj+1
-    P.share(wv, X0, X0 + (size_t)a.kblocks * 1024, Y0, Y0 + (size_t)a.kblocks * 1024);
+    const size_t xtile = (size_t)(M3 ? 3 : 2) * a.xs * a.kblocks * 1024;  // bytes of one row tile
+    const size_t ytile = (size_t)3 * a.ys * a.kblocks * 1024;             // bytes of one column tile
+    const int8_t* X0 = a.X + (size_t)(2 * gi) * xtile;  // row tiles 2gi, 2gi+1
+    const int8_t* Y0 = a.Y + (size_t)(2 * gj) * ytile;  // column tiles 2gj, 2gj+1
+    P.share(wv, X0, X0 + xtile, Y0, Y0 + ytile);
   }
   P.start();
 

@@ -538,7 +538,7 @@ int num_cu() {
 // Ring steps of one (pass, k-block) pass over all bands of the INT8 slice
 // GEMM (the same geometry as the kernel's units).
 long long band_steps(int W, int SA, int SB, int Dmax) {
-  const int NS = (W % 8 == 0) ? 4 : 2;
+  const int NS = (W % 8 == 0) ? 4 : 2;  // steps per queue entry; units are whole entry pairs
   const int nbands = (Dmax + W) / W;
   long long total = 0;
   for (int b = 0; b < nbands; ++b) {

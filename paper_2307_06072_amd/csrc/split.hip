@@ -24,8 +24,8 @@
 // indices).  Digits go to LDS in the matrix-core operand order and leave as
 // contiguous fragments:
 //   INT8: fragment = 16 rows x 64 k, lane l holds row l%16, k = 16*(l/16)..+16
-//         (16 bytes), planes [op][pad_lo + s][R/16][K/64][1024 B] with zero
-//         slices around the digits (Sstride slices per plane).
+//         (16 bytes), tile-major [R/16][op][pad_lo + s][K/64][1024 B] with
+//         zero slices around the digits (Sstride slices per plane).
 //   FP64: fragment = 16 rows x 4 k, lane l holds row l%16, k = l/16 (one
 //         double), planes [op][s][R/16][K/4][64 doubles].
 #include "mpcg_internal.h"
@@ -67,8 +67,11 @@ template <>
 struct Layout<int8_t> {
   static constexpr int FRAG_BYTES = 1024;  // one 16 x 64 int8 fragment per tile
   __device__ static inline int offset(int rl, int kl) { return (rl + 16 * (kl >> 4)) * 16 + (kl & 15); }
-  __device__ static inline size_t tile_base(int64_t plane, int rt, int kt, int Rt, int Kpad) {
-    return ((size_t)(plane * Rt + rt) * (size_t)(Kpad / 64) + kt) * 1024;  // bytes
+  // tile-major: all planes (and slices) of one 16-row tile are contiguous, so
+  // a tile's fragments span a compact range (32-bit offsets from the tile)
+  __device__ static inline size_t tile_base(int64_t plane, int rt, int kt, int Rt, int Kpad, int64_t per_tile) {
+    (void)Rt;
+    return ((size_t)((int64_t)rt * per_tile + plane) * (size_t)(Kpad / 64) + kt) * 1024;  // bytes
   }
 };
 
@@ -76,7 +79,8 @@ template <>
 struct Layout<double> {
   static constexpr int FRAG_BYTES = 8192;  // sixteen 16 x 4 fp64 fragments per tile
   __device__ static inline int offset(int rl, int kl) { return (kl >> 2) * 64 + rl + 16 * (kl & 3); }
-  __device__ static inline size_t tile_base(int64_t plane, int rt, int kt, int Rt, int Kpad) {
+  __device__ static inline size_t tile_base(int64_t plane, int rt, int kt, int Rt, int Kpad, int64_t per_tile) {
+    (void)per_tile;
     return ((size_t)(plane * Rt + rt) * (size_t)(Kpad / 4) + (size_t)kt * 16) * 64 * sizeof(double);
   }
 };
@@ -192,7 +196,7 @@ __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, in
       const uint4* src = reinterpret_cast<const uint4*>(lds_raw + (size_t)oj * Layout<DT>::FRAG_BYTES);
       uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<unsigned char*>(out) +
                                             Layout<DT>::tile_base((int64_t)o * Sstride + pad_lo + s, rt, kt,
-                                                                  Rpad / 16, Kpad));
+                                                                  Rpad / 16, Kpad, (int64_t)nops * Sstride));
       dst[u] = src[u];
     }
     __syncthreads();
@@ -207,7 +211,8 @@ __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, in
       const int o = oj / npad, j = oj % npad;
       const int sl = j < pad_lo ? j : Sp + j;  // plane slice index
       uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<unsigned char*>(out) +
-                                            Layout<DT>::tile_base((int64_t)o * Sstride + sl, rt, kt, Rpad / 16, Kpad));
+                                            Layout<DT>::tile_base((int64_t)o * Sstride + sl, rt, kt, Rpad / 16, Kpad,
+                                                                  (int64_t)nops * Sstride));
       dst[u] = make_uint4(0u, 0u, 0u, 0u);
     }
   }
