@@ -39,8 +39,8 @@
 // (4M, eq. 5: the accumulators hold Re and Im directly, the B side supplying
 // -Im B; 3M, eq. 6: T1, T2, T3 with Re = T1 - T2, Im = T3 - T1 - T2) and pushed,
 // least significant first, through a per-element int64 carry chain that emits
-// one normalised base-2^7 digit per diagonal; the final carry is the signed top
-// of the exact result.
+// one normalised base-2^7 digit per diagonal, stored contiguously per output
+// component; the final carry is the signed top of the exact result.
 //
 // Workgroups are 2 x 2 tiles; their order is XCD-aware so that the workgroups
 // resident on one XCD cover a compact block of the output and share operand
@@ -95,6 +95,13 @@ struct Band {
     s_hi = min(SA - 1, d0 + W - 1);
   }
 };
+
+// 16-digit chunks per output component: the bands cover digits q = Dmax - d
+// for q < W * nbands.
+__host__ __device__ inline int digit_chunks(int Dmax, int W) {
+  const int nbands = (Dmax + W) / W;
+  return (nbands * W + 15) / 16;
+}
 
 // Compile-time shape of the fragment queue.  An entry holds NS consecutive
 // steps; per step: the A fragment X_s of the workgroup's two row tiles and the
@@ -392,8 +399,10 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
     cre[r] = cim[r] = 0;
     lre[r] = lim[r] = -1;
   }
-  const int nd = a.Dmax + 1;
-  uint64_t* dig = reinterpret_cast<uint64_t*>(a.digits) + ((size_t)(split * a.mt * a.nt + tile) * nd) * 64 + lane;
+  // this lane's digit bytes: [split][tile][slot 8][chunk][lane][16]
+  const int nchunk = digit_chunks(a.Dmax, W);
+  const size_t slot_stride = (size_t)nchunk * 1024;
+  uint8_t* dig = reinterpret_cast<uint8_t*>(a.digits) + (size_t)(split * a.mt * a.nt + tile) * 8 * slot_stride + lane * 16;
 
 #pragma unroll 1
   for (int band = 0; band < P.nbands; ++band) {
@@ -418,36 +427,55 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
 #pragma unroll 1
         for (int kb = kb0; kb < kb1; ++kb) c.template unit<0, 1>(acc, P, g);
     }
-    // the band is complete: emit its diagonals least significant first
+    // the band is complete: push its diagonals through the carry chains, least
+    // significant first; digit q = Dmax - d of component slot k goes to
+    // digits[k][q / 16][lane][q % 16]: each output component's digits are
+    // contiguous in 16-digit chunks (one 16-byte word per lane and chunk)
+    uint32_t wre[4][W / 4], wim[4][W / 4];
 #pragma unroll
-    for (int j = W - 1; j >= 0; --j) {
+    for (int jj = 0; jj < W; ++jj) {
+      const int j = W - 1 - jj;  // q = W band + jj
       const int d = g.d0 + j;
-      if (d >= 0) {
-        uint64_t packed = 0;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          int64_t vre, vim;
-          if constexpr (M3) {
-            const int64_t t1 = acc[0][j][r], t2 = acc[1][j][r], t3 = acc[2][j][r];
-            vre = t1 - t2;
-            vim = t3 - t1 - t2;
-          } else {
-            vre = acc[0][j][r];
-            vim = acc[1][j][r];
-          }
+      for (int r = 0; r < 4; ++r) {
+        int64_t vre, vim;
+        if constexpr (M3) {
+          const int64_t t1 = acc[0][j][r], t2 = acc[1][j][r], t3 = acc[2][j][r];
+          vre = t1 - t2;
+          vim = t3 - t1 - t2;
+        } else {
+          vre = acc[0][j][r];
+          vim = acc[1][j][r];
+        }
+        uint32_t dre = 0, dim = 0;
+        if (d >= 0) {  // diagonals below 0 (the last band's overhang) are empty
           cre[r] += vre;
           cim[r] += vim;
-          const uint64_t dre = (uint64_t)(cre[r] & 127), dim = (uint64_t)(cim[r] & 127);
+          dre = (uint32_t)(cre[r] & 127);
+          dim = (uint32_t)(cim[r] & 127);
           cre[r] >>= 7;
           cim[r] >>= 7;
           if (dre && lre[r] < 0) lre[r] = d;
           if (dim && lim[r] < 0) lim[r] = d;
-          packed |= dre << (8 * r);
-          packed |= dim << (8 * (4 + r));
         }
-        dig[(size_t)d * 64] = packed;
+        if (jj % 4 == 0) {
+          wre[r][jj / 4] = dre;
+          wim[r][jj / 4] = dim;
+        } else {
+          wre[r][jj / 4] |= dre << (8 * (jj % 4));
+          wim[r][jj / 4] |= dim << (8 * (jj % 4));
+        }
       }
     }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int u = 0; u < W / 4; ++u) {
+        const int q = W * band + 4 * u;
+        const size_t at = ((size_t)(q >> 4) * 64) * 16 + (q & 15);
+        *reinterpret_cast<uint32_t*>(dig + (size_t)r * slot_stride + at) = wre[r][u];
+        *reinterpret_cast<uint32_t*>(dig + (size_t)(4 + r) * slot_stride + at) = wim[r][u];
+      }
   }
   // the producer ran past the end of the stream: drain its loads before the LDS is released
   wait_vmcnt<0>();
@@ -528,6 +556,7 @@ hipError_t launch_batched_w(const GemmArgs* probs, const int4* items, const int*
 }  // namespace
 
 void gemm_i8_pads(int band, int* alo, int* ahi, int* blo, int* bhi) { pads_for(band, *alo, *ahi, *blo, *bhi); }
+int gemm_i8_digit_chunks(int Dmax, int band) { return digit_chunks(Dmax, band); }
 
 hipError_t launch_gemm_i8(const GemmArgs& a, int band, hipStream_t stream) {
   switch (band) {

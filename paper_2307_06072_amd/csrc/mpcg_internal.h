@@ -102,13 +102,16 @@ struct GemmArgs {
   int xlo, ylo;      // zero slices below slice 0 of an A / B plane
   int Dmax;          // highest emitted diagonal
   int mode3m;        // 1: planes are (Re, Im, Re+Im) on both sides; 0: A (Re, Im), B (Re, Im, -Im)
-  void* digits;      // [ksplit][tiles][Dmax+1][64][8] digit type
+  void* digits;      // [ksplit][tiles][slot 8][chunk][lane 64][16] uint8 digits, q = Dmax - d
+                     // (chunk = q / 16; gemm_i8_digit_chunks chunks per component)
   int64_t* top;      // [ksplit][tiles][64][8]
   int32_t* lnz;      // [ksplit][tiles][64][8]
 };
 // Zero slices the INT8 slice GEMM of band width `band` needs below (lo) and
 // above (hi) the digits of the A and B planes.
 void gemm_i8_pads(int band, int* alo, int* ahi, int* blo, int* bhi);
+// 16-digit chunks per output component of the INT8 slice GEMM.
+int gemm_i8_digit_chunks(int Dmax, int band);
 hipError_t launch_gemm_i8(const GemmArgs& a, int band, hipStream_t stream);
 
 struct GemmF64Args {
@@ -123,8 +126,9 @@ hipError_t launch_gemm_f64(const GemmF64Args& a, hipStream_t stream);
 
 // Merge chunk streams (if ksplit > 1), round to prec, write C.
 struct RoundArgs {
-  const void* digits;  // uint8 (w = 7) or uint32 (w > 8) digits
+  const void* digits;  // uint8 (w = 7, INT8 chunked layout) or uint32 (FP64 form) digits
   int digit_bytes;     // 1 or 4
+  int nchunk;          // INT8: 16-digit chunks per component
   int f64_layout;      // 1: element (i, j) of a 16x16 tile sits in lane j + 16*(i%4), slot i/4
                        //    (fp64 matrix-core output order); 0: lane j + 16*(i/4), slot i%4
   const int64_t* top;
@@ -197,8 +201,8 @@ hipError_t launch_split_i8_batched(const SplitJob* jobs, int njobs, const int* f
 hipError_t launch_gemm_i8_batched(const GemmArgs* probs, const int4* items, const int* first, int blocks,
                                   int band, int mode3m, hipStream_t stream);
 
-// Round: job j is problem j with 2 mt nt blocks (one thread per digit byte of a tile).
-hipError_t launch_round_batched(const RoundArgs* jobs, int njobs, const int* first, int blocks,
+// Round (INT8 digits): job j is problem j with 2 mt nt blocks (tile, component).
+hipError_t launch_round_batched(const RoundArgs* jobs, int njobs, const int* first, int blocks, int L,
                                 hipStream_t stream);
 
 }  // namespace mpcg

@@ -117,6 +117,7 @@ struct Plan {
   long long pairs;
   double algo_ops, bound_bits;
   int want_groups;   // contraction chunks are added until this many work items exist
+  int nchunk;        // INT8: 16-digit chunks per output component
   size_t off_G, off_H, off_X, off_Y, off_dig, off_top, off_lnz, off_scan, total;
 };
 
@@ -225,7 +226,12 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
   P.off_H = o; o = align256(o + 4 * (size_t)P.npad);
   P.off_X = o; o = align256(o + (size_t)P.nopsA * P.xs * P.mpad * (size_t)P.kpad * esz);
   P.off_Y = o; o = align256(o + (size_t)P.nopsB * P.ys * P.npad * (size_t)P.kpad * esz);
-  P.off_dig = o; o = align256(o + (size_t)P.ksplit * tiles * nd * 512 * dig_bytes);
+  if (P.f64) {
+    P.off_dig = o; o = align256(o + (size_t)P.ksplit * tiles * nd * 512 * dig_bytes);
+  } else {  // [ksplit][tiles][slot 8][chunk][lane 64][16] digit bytes
+    P.nchunk = gemm_i8_digit_chunks(P.Dmax, P.block);
+    P.off_dig = o; o = align256(o + (size_t)P.ksplit * tiles * 8 * P.nchunk * 1024);
+  }
   P.off_top = o; o = align256(o + (size_t)P.ksplit * tiles * 512 * 8);
   P.off_lnz = o; o = align256(o + (size_t)P.ksplit * tiles * 512 * 4);
   P.off_scan = o; o = align256(o + scan_bytes(P.m, P.n));
@@ -451,6 +457,7 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
   RoundArgs ra{};
   ra.digits = base + P.off_dig;
   ra.digit_bytes = P.f64 ? 4 : 1;
+  ra.nchunk = P.nchunk;
   ra.f64_layout = P.f64;
   ra.top = top; ra.lnz = lnz;
   ra.ksplit = P.ksplit; ra.mt = P.mt; ra.nt = P.nt; ra.Dmax = P.Dmax; ra.w = P.w;
@@ -830,6 +837,7 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
     ra = RoundArgs{};
     ra.digits = pb + P.off_dig;
     ra.digit_bytes = 1;
+    ra.nchunk = P.nchunk;
     ra.f64_layout = 0;
     ra.top = ga.top; ra.lnz = ga.lnz;
     ra.ksplit = P.ksplit; ra.mt = P.mt; ra.nt = P.nt; ra.Dmax = P.Dmax; ra.w = P.w;
@@ -943,7 +951,7 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
                                    g_stream));
   if ((st = record(3))) return st;
   HIP_TRY(launch_round_batched(reinterpret_cast<RoundArgs*>(dev + o_ra), nl, reinterpret_cast<int*>(dev + o_frd),
-                               frd.back(), g_stream));
+                               frd.back(), L, g_stream));
   if ((st = record(4))) return st;
   g_timing_valid = g_timing;
   return MPCG_OK;

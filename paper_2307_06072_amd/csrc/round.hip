@@ -215,13 +215,6 @@ __global__ __launch_bounds__(256) void round_kernel(RoundArgs a) {
   round_element<DIG>(a, (int64_t)blockIdx.x * 256 + threadIdx.x);
 }
 
-// Batched form (INT8 digits): job j is problem j with 2 mt nt blocks.
-__global__ __launch_bounds__(256) void round_batched(const RoundArgs* __restrict__ jobs, int njobs,
-                                                     const int* __restrict__ first) {
-  const int j = job_of_block(first, njobs, blockIdx.x);
-  round_element<uint8_t>(jobs[j], (int64_t)(blockIdx.x - first[j]) * 256 + threadIdx.x);
-}
-
 __global__ void zero_kernel(DOutPart cre, DOutPart cim, int m, int n, int64_t ldc, int L) {
   const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t total = (int64_t)m * n * 2;
@@ -241,6 +234,245 @@ __global__ void fill_zero_kernel(uint32_t* p, size_t n32) {
   if (i < n32) p[i] = 0;
 }
 
+// ---- INT8 digits: chunked per component --------------------------------------
+//
+// Digit q = Dmax - d of a component lives at chunk q / 16, byte q % 16 of its
+// own 16-byte words ([slot][chunk][lane][16], 1 KB per chunk and slot), so a
+// thread reads its digits 16 at a time.  A block is one (tile, component):
+// 256 threads, thread t holds element (ii, jj) = (t % 16, t / 16), so the
+// stores of a wavefront cover 16 consecutive rows of 4 columns.  The digits
+// the p-bit result can depend on (from the lowest bit of limb 0 up to the
+// leading bit) are copied into the thread's part of LDS with 16-byte loads,
+// all issued together, and the rounding reads them there.
+
+struct Win8 {
+  const uint8_t* lds;  // digit q at lds[q - qbase]
+  int qbase;
+  const uint8_t* glob; // the component's stream (digit q at glob[(q >> 4) * 1024 + (q & 15)])
+  int Dmax, neg, z;    // z: lowest nonzero digit as an index d (largest d), -1 if none
+  uint64_t U;
+  __device__ inline uint64_t gn(int q) const { return glob[(size_t)(q >> 4) * 1024 + (q & 15)]; }
+  __device__ inline uint64_t ln(int q) const { return lds[q - qbase]; }
+  // magnitude digit q (inside the window)
+  __device__ inline uint64_t m(int q) const {
+    const int d = Dmax - q;
+    if (!neg) return ln(q);
+    if (z < 0 || d > z) return 0;
+    return d == z ? 128 - ln(q) : 127 - ln(q);
+  }
+  // magnitude digit q read from global memory (outside any window)
+  __device__ inline uint64_t mg(int q) const {
+    const int d = Dmax - q;
+    if (!neg) return gn(q);
+    if (z < 0 || d > z) return 0;
+    return d == z ? 128 - gn(q) : 127 - gn(q);
+  }
+  // bits [pos, pos + 64) of |X|, bit 0 = lowest bit of digit q = 0
+  __device__ uint64_t field(int64_t pos) const {
+    const int64_t nbits = 7ll * (Dmax + 1);
+    uint64_t r = 0;
+    const int64_t lo = pos < 0 ? 0 : pos;
+    const int64_t hi = pos + 64;
+    if (lo < nbits) {
+      const int q0 = (int)(lo / 7);
+      const int q1 = (int)min((hi - 1) / 7, (int64_t)Dmax);
+      for (int q = q0; q <= q1; ++q) {
+        const uint64_t v = m(q);
+        const int64_t sh = 7ll * q - pos;
+        if (sh >= 0) {
+          if (sh < 64) r |= v << sh;
+        } else if (-sh < 64) {
+          r |= v >> (-sh);
+        }
+      }
+    }
+    if (hi > nbits && U) {
+      const int64_t sh = nbits - pos;
+      if (sh >= 0) {
+        if (sh < 64) r |= U << sh;
+      } else if (-sh < 64) {
+        r |= U >> (-sh);
+      }
+    }
+    return r;
+  }
+  __device__ inline int bit(int64_t pos) const {
+    if (pos < 0) return 0;
+    const int64_t nbits = 7ll * (Dmax + 1);
+    if (pos >= nbits) {
+      const int64_t sh = pos - nbits;
+      return sh < 64 ? (int)((U >> sh) & 1) : 0;
+    }
+    const int q = (int)(pos / 7);
+    return (int)((m(q) >> (pos - 7ll * q)) & 1);
+  }
+};
+
+// bytes of LDS per thread for L limbs: the window spans at most
+// ceil(64 L / 7) + 3 digits, copied as whole 16-digit chunks
+__host__ __device__ inline int round_i8_window_bytes(int L) {
+  const int digits = (64 * L + 6) / 7 + 3;
+  return 16 * ((digits + 15) / 16 + 1);
+}
+
+__device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_all) {
+  const int tiles = a.mt * a.nt;
+  const int tile = blk >> 1, comp = blk & 1;
+  const int t = threadIdx.x;
+  const int ii = t & 15, jj = t >> 4;
+  const int lane = jj + 16 * (ii >> 2), slot = 4 * comp + (ii & 3);
+  const int ti = tile % a.mt, tj = tile / a.mt;
+  const int i = ti * 16 + ii, j = tj * 16 + jj;
+  const int WB = round_i8_window_bytes(a.L);
+  uint8_t* lds = lds_all + (size_t)t * WB;
+  if (i >= a.m || j >= a.n) return;  // no barrier follows
+
+  const size_t sstride = (size_t)tiles * 8 * a.nchunk * 1024;  // one contraction chunk's digits
+  uint8_t* g0 = reinterpret_cast<uint8_t*>(const_cast<void*>(a.digits)) +
+                ((size_t)tile * 8 + slot) * a.nchunk * 1024 + (size_t)lane * 16;
+  const size_t tb0 = ((size_t)tile * 64 + lane) * 8 + slot;
+  const int Dmax = a.Dmax;
+
+  int64_t T;
+  int z;
+  if (a.ksplit == 1) {
+    T = a.top[tb0];
+    z = a.lnz[tb0];
+  } else {
+    // add the chunk streams exactly, least significant digit first, 16 digits
+    // at a time; the sum replaces chunk 0's digits
+    int64_t c = 0;
+    int qz = -1;
+    const int nq = Dmax + 1;
+    for (int ch = 0; ch * 16 < nq; ++ch) {
+      uint4 acc[1];
+      uint32_t out[4] = {0, 0, 0, 0};
+      int32_t sum[16];
+#pragma unroll
+      for (int b = 0; b < 16; ++b) sum[b] = 0;
+      for (int q = 0; q < a.ksplit; ++q) {
+        acc[0] = *reinterpret_cast<const uint4*>(g0 + q * sstride + (size_t)ch * 1024);
+        const uint32_t wv[4] = {acc[0].x, acc[0].y, acc[0].z, acc[0].w};
+#pragma unroll
+        for (int b = 0; b < 16; ++b) sum[b] += (int32_t)((wv[b >> 2] >> (8 * (b & 3))) & 255u);
+      }
+#pragma unroll
+      for (int b = 0; b < 16; ++b) {
+        const int qq = ch * 16 + b;
+        if (qq < nq) {
+          const int64_t sv = c + sum[b];
+          const uint32_t dg = (uint32_t)(sv & 127);
+          c = sv >> 7;
+          out[b >> 2] |= dg << (8 * (b & 3));
+          if (dg && qz < 0) qz = qq;
+        }
+      }
+      *reinterpret_cast<uint4*>(g0 + (size_t)ch * 1024) = make_uint4(out[0], out[1], out[2], out[3]);
+    }
+    z = qz < 0 ? -1 : Dmax - qz;
+    T = c;
+    for (int q = 0; q < a.ksplit; ++q) T += a.top[(size_t)q * tiles * 64 * 8 + tb0];
+  }
+
+  DOutPart out = comp ? a.cim : a.cre;
+  const int64_t o = (int64_t)j * a.ldc + i;
+  const int L = a.L, p = a.prec;
+  if (T == 0 && z < 0) {  // exact zero -> +0
+    out.sign[o] = 0;
+    out.exp[o] = EXP_ZERO;
+    for (int l = 0; l < L; ++l) out.mant[(int64_t)l * out.ls + o] = 0;
+    return;
+  }
+  Win8 st;
+  st.glob = g0;
+  st.Dmax = Dmax;
+  st.neg = T < 0;
+  st.z = z;
+  st.U = !st.neg ? (uint64_t)T : (z < 0 ? (uint64_t)(-T) : (uint64_t)(-T - 1));
+  const int64_t nbits = 7ll * (Dmax + 1);
+  // leading bit of |X|
+  int64_t lead;
+  if (st.U) {
+    lead = nbits + 63 - __builtin_clzll(st.U);
+  } else {
+    lead = -1;
+    for (int q = Dmax; q >= 0; --q) {
+      const uint64_t v = st.mg(q);
+      if (v) {
+        lead = 7ll * q + 63 - __builtin_clzll(v);
+        break;
+      }
+    }
+  }
+  // lowest set bit of X (= of |X|)
+  int64_t lowset;
+  if (z >= 0)
+    lowset = 7ll * (Dmax - z) + __builtin_ctzll(st.gn(Dmax - z));
+  else
+    lowset = nbits + __builtin_ctzll((uint64_t)T);
+
+  // the digits that limbs and rounding read: from the rounding bit or the
+  // lowest bit of limb 0, whichever is lower (the rounding bit lies one below
+  // limb 0 when p = 64 L), to the leading bit (above it the magnitude digits
+  // are zero)
+  const int64_t off = lead + 1 - 64ll * L;
+  const int64_t lowest = min(off, lead - (int64_t)p);
+  const int qlo = lowest <= 0 ? 0 : (int)(lowest / 7);
+  const int qhi = (int)min(lead / 7, (int64_t)Dmax);
+  st.qbase = (qlo >> 4) << 4;
+  st.lds = lds;
+  for (int ch = qlo >> 4; ch <= (qhi >> 4) && qhi >= 0; ++ch)
+    *reinterpret_cast<uint4*>(lds + (ch * 16 - st.qbase)) = *reinterpret_cast<const uint4*>(g0 + (size_t)ch * 1024);
+
+  const int64_t low = lead - p + 1;  // lowest kept bit of |X|
+  int round_up = 0;
+  if (low > 0) {
+    const int rbit = st.bit(low - 1);
+    const int sticky = lowset < low - 1;
+    const int lsb = st.bit(low);
+    round_up = rbit && (sticky || lsb);
+  }
+  const int keep_from = 64 * L - p;  // 0..63
+  uint64_t carry = round_up ? (1ull << keep_from) : 0;
+  int64_t e_out = lead + 1 + (int64_t)a.G[i] + (int64_t)a.H[j] - 7ll * (Dmax + 2);
+  uint64_t limbs_hi = 0;
+  for (int l = 0; l < L; ++l) {
+    uint64_t f = st.field(off + 64ll * l);
+    if (l == 0 && keep_from) f &= ~((1ull << keep_from) - 1ull);
+    const uint64_t sum = f + carry;
+    carry = (sum < f) ? 1 : 0;
+    limbs_hi = sum;
+    if (l < L - 1) out.mant[(int64_t)l * out.ls + o] = sum;
+  }
+  if (carry) {  // significand overflowed to 2^p: 2^(p-1) with exponent + 1
+    limbs_hi = 1ull << 63;
+    e_out += 1;
+  }
+  if (e_out > INT32_MAX || e_out <= (int64_t)INT32_MIN) {
+    atomicOr(a.status, ST_OUT_RANGE);
+    out.sign[o] = 0;
+    out.exp[o] = EXP_ZERO;
+    for (int l = 0; l < L; ++l) out.mant[(int64_t)l * out.ls + o] = 0;
+    return;
+  }
+  out.mant[(int64_t)(L - 1) * out.ls + o] = limbs_hi;
+  out.sign[o] = (uint8_t)st.neg;
+  out.exp[o] = (int32_t)e_out;
+}
+
+__global__ __launch_bounds__(256) void round_i8_kernel(RoundArgs a) {
+  extern __shared__ __align__(16) uint8_t lds_win[];
+  round_i8_block(a, blockIdx.x, lds_win);
+}
+
+// Batched form: job j is problem j with 2 mt nt blocks (tile, component).
+__global__ __launch_bounds__(256) void round_i8_batched(const RoundArgs* __restrict__ jobs, int njobs,
+                                                        const int* __restrict__ first) {
+  extern __shared__ __align__(16) uint8_t lds_win[];
+  const int j = job_of_block(first, njobs, blockIdx.x);
+  round_i8_block(jobs[j], blockIdx.x - first[j], lds_win);
+}
+
 }  // namespace
 
 hipError_t launch_fill_zero(void* p, size_t n, hipStream_t stream) {
@@ -250,11 +482,16 @@ hipError_t launch_fill_zero(void* p, size_t n, hipStream_t stream) {
 }
 
 hipError_t launch_round(const RoundArgs& a, hipStream_t stream) {
-  const int blocks = a.mt * a.nt * 2;  // 512 digit bytes per tile
-  if (a.digit_bytes == 1)
-    round_kernel<uint8_t><<<dim3(blocks), dim3(256), 0, stream>>>(a);
-  else
-    round_kernel<uint32_t><<<dim3(blocks), dim3(256), 0, stream>>>(a);
+  const int blocks = a.mt * a.nt * 2;
+  if (a.digit_bytes == 1) {
+    const size_t lds = (size_t)256 * round_i8_window_bytes(a.L);
+    hipError_t e = hipFuncSetAttribute((const void*)round_i8_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    round_i8_kernel<<<dim3(blocks), dim3(256), lds, stream>>>(a);
+  } else {
+    round_kernel<uint32_t><<<dim3(blocks), dim3(256), 0, stream>>>(a);  // 512 digit words per tile
+  }
   return hipGetLastError();
 }
 
@@ -264,10 +501,14 @@ hipError_t launch_zero(DOutPart cre, DOutPart cim, int m, int n, int64_t ldc, in
   return hipGetLastError();
 }
 
-hipError_t launch_round_batched(const RoundArgs* jobs, int njobs, const int* first, int blocks,
+hipError_t launch_round_batched(const RoundArgs* jobs, int njobs, const int* first, int blocks, int L,
                                 hipStream_t stream) {
   if (njobs <= 0 || blocks <= 0) return hipSuccess;
-  round_batched<<<dim3(blocks), dim3(256), 0, stream>>>(jobs, njobs, first);
+  const size_t lds = (size_t)256 * round_i8_window_bytes(L);
+  hipError_t e = hipFuncSetAttribute((const void*)round_i8_batched, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  round_i8_batched<<<dim3(blocks), dim3(256), lds, stream>>>(jobs, njobs, first);
   return hipGetLastError();
 }
 

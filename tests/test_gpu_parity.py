@@ -128,3 +128,15 @@ def test_config_512_p512_sampled():
                 if e[t, comp] != EXP_ZERO:
                     assert part.sign[j, i] == s[t, comp]
                     assert np.array_equal(part.mant[:, j, i], mm[t, comp])
+
+
+@pytest.mark.parametrize("p", [64, 128, 192])
+def test_rounding_bit_below_limb_zero(p):
+    """p = 64 L puts the rounding bit one below the lowest significand limb; on
+    every 112th component or so that bit opens a new 16-digit chunk.  Whole
+    matrices, bit for bit, so many such components are checked."""
+    m, n, k = 160, 144, 40
+    A = random_cmat(90 + p, 0, m, k, p, 12)
+    B = random_cmat(90 + p, 1, k, n, p, 12)
+    _check_exact(A, B, p, M3)
+    _check_exact(A, B, p, M4)
