@@ -280,7 +280,10 @@ struct Consumer {
   // everybody's loads of it visible (it is read into the other register
   // buffer) and tells that every wavefront has used the previous entry, whose
   // queue slot is then refilled by loads spread between the MFMAs.
-  template <int C, bool MF, int Q0, int Q1>
+  // RAMP: the first ring turn with MFMAs of a band whose s range starts above
+  // 0; at its step i the ring slots of diagonals j > i still hold the zero
+  // pads beyond t = S_B - 1, so those MFMAs are skipped.
+  template <int C, bool MF, int Q0, int Q1, bool RAMP = false>
   __device__ inline void entry(v4i (&acc)[NACC][W], Producer<W, M3>& P) {
     constexpr int PAR = C & 1;
     wait_vmcnt<G::VM>();
@@ -297,7 +300,7 @@ struct Consumer {
       // also across steps
 #pragma unroll
       for (int j = 0; j < W; ++j) {
-        if (MF) {
+        if (MF && (!RAMP || j <= V)) {
           const int r = (V - j + W) % W;  // ring slot holding the B fragment of diagonal d0 + j
           acc[Q0][j] = mfma(abuf[PAR][h], ring0[r], acc[Q0][j]);
           if (!M3) acc[Q1][j] = mfma(abuf[PAR][h], ring1[r], acc[Q1][j]);
@@ -313,12 +316,12 @@ struct Consumer {
     P.tail();
   }
 
-  template <int C, bool MF, int Q0, int Q1>
+  template <int C, bool MF, int Q0, int Q1, bool RAMP = false>
   __device__ inline void chunk(v4i (&acc)[NACC][W], Producer<W, M3>& P, int left) {
     if constexpr (C < G::CH) {
       if (MF && left <= C) return;
-      entry<C, MF, Q0, Q1>(acc, P);
-      chunk<C + 1, MF, Q0, Q1>(acc, P, left);
+      entry<C, MF, Q0, Q1, RAMP>(acc, P);
+      chunk<C + 1, MF, Q0, Q1, RAMP>(acc, P, left);
     }
   }
 
@@ -327,7 +330,12 @@ struct Consumer {
   __device__ inline void unit(v4i (&acc)[NACC][W], Producer<W, M3>& P, const Band& g) {
     const int ne = unit_entries(g, W, NS);
     chunk<0, false, Q0, Q1>(acc, P, G::CH);
-    for (int e0 = G::CH; e0 < ne; e0 += G::CH) chunk<0, true, Q0, Q1>(acc, P, ne - e0);
+    int e0 = G::CH;
+    if (g.s_lo > 0 && e0 < ne) {  // the ramp: pairs with t >= S_B are known zeros
+      chunk<0, true, Q0, Q1, true>(acc, P, ne - e0);
+      e0 += G::CH;
+    }
+    for (; e0 < ne; e0 += G::CH) chunk<0, true, Q0, Q1>(acc, P, ne - e0);
   }
 };
 
