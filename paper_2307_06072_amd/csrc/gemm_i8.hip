@@ -47,6 +47,8 @@
 // panels in that XCD's L2.
 #include "mpcg_internal.h"
 
+#include <type_traits>
+
 namespace mpcg {
 
 namespace {
@@ -87,12 +89,23 @@ __device__ inline void map_block(int b, int nblk, int gm, int gn, int& split, in
 }
 
 // Band geometry: diagonals [d0, d0 + W) and the s range holding its pairs.
+// A band whose pairs reach s = 0 at its first diagonal and t = 0 at its last
+// (s_lo = 0, s_hi = d0 + W - 1) is walked downward from s_hi: its ring then
+// starts on pairs with t < 0 (known zeros, skipped) and it ends at s = 0
+// with no pair outside the operands.  The others are walked upward.  Down
+// bands are the most significant ones (a suffix of the band order).
+__host__ __device__ inline bool band_down(int d0, int W, int SA, int SB) {
+  return d0 <= SB - 1 && d0 + W - 1 <= SA - 1;
+}
+
 struct Band {
   int d0, s_lo, s_hi;
+  bool down;
   __device__ inline void set(int band, int W, int Dmax, int SA, int SB) {
     d0 = Dmax + 1 - W * (band + 1);
     s_lo = max(0, d0 - (SB - 1));
     s_hi = min(SA - 1, d0 + W - 1);
+    down = band_down(d0, W, SA, SB);
   }
 };
 
@@ -123,26 +136,29 @@ struct Q {
   static_assert(VM0 < 64, "vmcnt range");
 };
 
-// Steps of a unit (band, pass, k-block): s from s_lo - W (the first W steps
-// only fill the ring) on, padded with steps on zero fragments to an even
-// number of entries of NS steps.
+// Steps of a unit (band, pass, k-block): upward, s from s_lo - W (the first
+// W steps only fill the ring) to s_hi; downward, s from s_hi to s_lo = 0;
+// padded with steps on zero fragments to an even number of entries of NS
+// steps.
 __device__ inline int unit_entries(const Band& g, int W, int NS) {
-  const int n = g.s_hi - (g.s_lo - W) + 1;
+  const int n = g.down ? g.s_hi + 1 : g.s_hi - (g.s_lo - W) + 1;
   const int per = 2 * NS;
   return (n + per - 1) / per * 2;
 }
 
-// Zero slices around each digit plane.  A unit reads X_s for s in
+// Zero slices around each digit plane.  An upward unit reads X_s for s in
 // [s_lo - W, s_hi + 2 NS - 1] and Y_t for t = d0 - s, i.e. t in
-// [2 - W - 2 NS, S_B - 1 + W]; the planes carry that many zero slices below
-// and above their S digits so that every load of a unit is unconditional and
-// the pairs outside the operands multiply zeros.
+// [2 - W - 2 NS, S_B - 1 + W]; a downward unit reads X_s for s in
+// [1 - 2 NS, s_hi] and Y_t for t in [0, S_B + W + 2 NS - 3].  The planes
+// carry that many zero slices below and above their S digits so that every
+// load of a unit is unconditional and the pairs outside the operands
+// multiply zeros.
 __host__ __device__ inline void pads_for(int W, int& alo, int& ahi, int& blo, int& bhi) {
   const int NS = (W % 8 == 0) ? 4 : 2;
   alo = W;
   ahi = 2 * NS - 1;
   blo = W + 2 * NS - 2;
-  bhi = W;
+  bhi = W + 2 * NS - 2;
 }
 
 // This wavefront's share of the loads, walking the (band, pass, k-block,
@@ -188,7 +204,10 @@ struct Producer {
   __device__ inline void unit_begin() {
     ne = unit_entries(g, W, G::NS);
     e = 0;
-    const int s0 = g.s_lo - W;
+    // step h of entry e: s = s0 + dir (NS e + h), t = t0 - dir (NS e + h)
+    const int dir = g.down ? -1 : 1;
+    const int s0 = g.down ? g.s_hi : g.s_lo - W;
+    const int t0 = g.down ? g.d0 + W - 1 - g.s_hi : g.d0 - s0;
     int pa, pb0, pb1;
     if (M3) {
       pa = pass; pb0 = pass; pb1 = 0;
@@ -198,14 +217,14 @@ struct Producer {
     const int64_t ko = (int64_t)kb * 1024;
 #pragma unroll
     for (int i = 0; i < PW; ++i) {
-      const int h = hh[i];  // entry e loads step s = s0 + NS e + h
+      const int h = hh[i];
       if (isa[i]) {
-        src[i] = tb[i] + ((int64_t)(pa * xs + xlo + s0 + h) * (int64_t)xplane + ko);
-        dlt[i] = G::NS * (int64_t)xplane;
+        src[i] = tb[i] + ((int64_t)(pa * xs + xlo + s0 + dir * h) * (int64_t)xplane + ko);
+        dlt[i] = dir * G::NS * (int64_t)xplane;
       } else {
         const int pl = sel[i] ? pb1 : pb0;
-        src[i] = tb[i] + ((int64_t)(pl * ys + ylo + g.d0 - s0 - h) * (int64_t)yplane + ko);
-        dlt[i] = -G::NS * (int64_t)yplane;
+        src[i] = tb[i] + ((int64_t)(pl * ys + ylo + t0 - dir * h) * (int64_t)yplane + ko);
+        dlt[i] = -dir * G::NS * (int64_t)yplane;
       }
     }
   }
@@ -283,7 +302,11 @@ struct Consumer {
   // RAMP: the first ring turn with MFMAs of a band whose s range starts above
   // 0; at its step i the ring slots of diagonals j > i still hold the zero
   // pads beyond t = S_B - 1, so those MFMAs are skipped.
-  template <int C, bool MF, int Q0, int Q1, bool RAMP = false>
+  // RAMP: the first ring turn of a ramped unit; at its step V the ring slots
+  // V + 1 .. W - 1 steps old have not been written (their pairs are known
+  // zeros), so those MFMAs are skipped.  DOWN: a downward unit, whose ring
+  // slot jj steps old holds the B fragment of diagonal d0 + W - 1 - jj.
+  template <int C, bool MF, int Q0, int Q1, bool RAMP = false, bool DOWN = false>
   __device__ inline void entry(v4i (&acc)[NACC][W], Producer<W, M3>& P) {
     constexpr int PAR = C & 1;
     wait_vmcnt<G::VM>();
@@ -301,9 +324,10 @@ struct Consumer {
 #pragma unroll
       for (int j = 0; j < W; ++j) {
         if (MF && (!RAMP || j <= V)) {
-          const int r = (V - j + W) % W;  // ring slot holding the B fragment of diagonal d0 + j
-          acc[Q0][j] = mfma(abuf[PAR][h], ring0[r], acc[Q0][j]);
-          if (!M3) acc[Q1][j] = mfma(abuf[PAR][h], ring1[r], acc[Q1][j]);
+          const int r = (V - j + W) % W;      // ring slot of the fragment loaded j steps ago
+          const int ja = DOWN ? W - 1 - j : j;  // its diagonal d0 + ja
+          acc[Q0][ja] = mfma(abuf[PAR][h], ring0[r], acc[Q0][ja]);
+          if (!M3) acc[Q1][ja] = mfma(abuf[PAR][h], ring1[r], acc[Q1][ja]);
         }
         // spread this wavefront's loads over the entry
         constexpr int per = (PW + NS - 1) / NS;
@@ -316,26 +340,33 @@ struct Consumer {
     P.tail();
   }
 
-  template <int C, bool MF, int Q0, int Q1, bool RAMP = false>
+  template <int C, bool MF, int Q0, int Q1, bool RAMP = false, bool DOWN = false>
   __device__ inline void chunk(v4i (&acc)[NACC][W], Producer<W, M3>& P, int left) {
     if constexpr (C < G::CH) {
       if (MF && left <= C) return;
-      entry<C, MF, Q0, Q1, RAMP>(acc, P);
-      chunk<C + 1, MF, Q0, Q1, RAMP>(acc, P, left);
+      entry<C, MF, Q0, Q1, RAMP, DOWN>(acc, P);
+      chunk<C + 1, MF, Q0, Q1, RAMP, DOWN>(acc, P, left);
     }
   }
 
-  // One unit: a chunk of ring-filling entries, then chunks with MFMAs.
-  template <int Q0, int Q1>
+  // One unit.  Upward: a chunk of ring-filling entries, then chunks with
+  // MFMAs, the first of them ramped when s_lo > 0 (its pairs with t >= S_B
+  // are known zeros).  Downward: a ramped chunk (pairs with t < 0), then
+  // chunks with MFMAs.
+  template <int Q0, int Q1, bool DOWN>
   __device__ inline void unit(v4i (&acc)[NACC][W], Producer<W, M3>& P, const Band& g) {
     const int ne = unit_entries(g, W, NS);
-    chunk<0, false, Q0, Q1>(acc, P, G::CH);
-    int e0 = G::CH;
-    if (g.s_lo > 0 && e0 < ne) {  // the ramp: pairs with t >= S_B are known zeros
-      chunk<0, true, Q0, Q1, true>(acc, P, ne - e0);
-      e0 += G::CH;
+    int e0 = 0;
+    if constexpr (DOWN) {
+      chunk<0, true, Q0, Q1, true, true>(acc, P, ne);
+    } else {
+      chunk<0, false, Q0, Q1>(acc, P, G::CH);
+      if (g.s_lo > 0 && G::CH < ne) {
+        e0 = G::CH;
+        chunk<0, true, Q0, Q1, true>(acc, P, ne - e0);
+      }
     }
-    for (; e0 < ne; e0 += G::CH) chunk<0, true, Q0, Q1>(acc, P, ne - e0);
+    for (e0 += G::CH; e0 < ne; e0 += G::CH) chunk<0, true, Q0, Q1, false, DOWN>(acc, P, ne - e0);
   }
 };
 
@@ -410,10 +441,14 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
   // this lane's digit bytes: [split][tile][slot 8][chunk][lane][16]
   const int nchunk = digit_chunks(a.Dmax, W);
   const size_t slot_stride = (size_t)nchunk * 1024;
-  uint8_t* dig = reinterpret_cast<uint8_t*>(a.digits) + (size_t)(split * a.mt * a.nt + tile) * 8 * slot_stride + lane * 16;
+  // (a wave-uniform base and 32-bit per-lane offsets: no 64-bit address per
+  // store stays live across the band loop)
+  uint8_t* dig = reinterpret_cast<uint8_t*>(a.digits) + (size_t)(split * a.mt * a.nt + tile) * 8 * slot_stride;
+  const uint32_t dig_lane = (uint32_t)lane * 16u;
 
-#pragma unroll 1
-  for (int band = 0; band < P.nbands; ++band) {
+  // One band: its units, then the carry chain over its W diagonals.
+  auto band_body = [&](const int band, auto down_tag) {
+    constexpr bool DOWN = decltype(down_tag)::value;
     Band g;
     g.set(band, W, a.Dmax, a.SAp, a.SBp);
     v4i acc[NACC][W];
@@ -424,16 +459,16 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
 
     if constexpr (M3) {  // T1 = Re Re, T2 = Im Im, T3 = (Re+Im)(Re+Im)
 #pragma unroll 1
-      for (int kb = kb0; kb < kb1; ++kb) c.template unit<0, 0>(acc, P, g);
+      for (int kb = kb0; kb < kb1; ++kb) c.template unit<0, 0, DOWN>(acc, P, g);
 #pragma unroll 1
-      for (int kb = kb0; kb < kb1; ++kb) c.template unit<1, 1>(acc, P, g);
+      for (int kb = kb0; kb < kb1; ++kb) c.template unit<1, 1, DOWN>(acc, P, g);
 #pragma unroll 1
-      for (int kb = kb0; kb < kb1; ++kb) c.template unit<2, 2>(acc, P, g);
+      for (int kb = kb0; kb < kb1; ++kb) c.template unit<2, 2, DOWN>(acc, P, g);
     } else {  // Re += ReA ReB + ImA (-ImB),  Im += ReA ImB + ImA ReB
 #pragma unroll 1
       for (int pass = 0; pass < 2; ++pass)
 #pragma unroll 1
-        for (int kb = kb0; kb < kb1; ++kb) c.template unit<0, 1>(acc, P, g);
+        for (int kb = kb0; kb < kb1; ++kb) c.template unit<0, 1, DOWN>(acc, P, g);
     }
     // the band is complete: push its diagonals through the carry chains, least
     // significant first; digit q = Dmax - d of component slot k goes to
@@ -480,11 +515,18 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
 #pragma unroll
       for (int u = 0; u < W / 4; ++u) {
         const int q = W * band + 4 * u;
-        const size_t at = ((size_t)(q >> 4) * 64) * 16 + (q & 15);
-        *reinterpret_cast<uint32_t*>(dig + (size_t)r * slot_stride + at) = wre[r][u];
-        *reinterpret_cast<uint32_t*>(dig + (size_t)(4 + r) * slot_stride + at) = wim[r][u];
+        const uint32_t at = (uint32_t)(q >> 4) * 1024u + (uint32_t)(q & 15) + dig_lane;
+        *reinterpret_cast<uint32_t*>(dig + ((uint32_t)r * (uint32_t)slot_stride + at)) = wre[r][u];
+        *reinterpret_cast<uint32_t*>(dig + ((uint32_t)(4 + r) * (uint32_t)slot_stride + at)) = wim[r][u];
       }
-  }
+  };
+  // upward bands first (least significant), then the downward ones
+  int band = 0;
+#pragma unroll 1
+  for (; band < P.nbands && !band_down(a.Dmax + 1 - W * (band + 1), W, a.SAp, a.SBp); ++band)
+    band_body(band, std::false_type{});
+#pragma unroll 1
+  for (; band < P.nbands; ++band) band_body(band, std::true_type{});
   // the producer ran past the end of the stream: drain its loads before the LDS is released
   wait_vmcnt<0>();
 

@@ -551,7 +551,9 @@ long long band_steps(int W, int SA, int SB, int Dmax) {
   for (int b = 0; b < nbands; ++b) {
     const int d0 = Dmax + 1 - W * (b + 1);
     const int s_lo = std::max(0, d0 - (SB - 1)), s_hi = std::min(SA - 1, d0 + W - 1);
-    const int n = s_hi - (s_lo - W) + 1;
+    // bands reaching s = 0 and t = 0 are walked downward without a ring fill
+    const bool down = d0 <= SB - 1 && d0 + W - 1 <= SA - 1;
+    const int n = down ? s_hi + 1 : s_hi - (s_lo - W) + 1;
     total += (long long)ceil_div(n, 2 * NS) * 2 * NS;
   }
   return total;
