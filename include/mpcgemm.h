@@ -112,7 +112,7 @@ typedef struct {
                              (no error bound is then promised); 0 = derived cutoff */
     int ksplit_override;  /* > 0: number of contraction chunks; 0 = planner's choice */
     int block_override;   /* > 0: band width of the INT8 slice GEMM, the number of consecutive
-                             anti-diagonals s + t a wavefront accumulates at once (8, 12 or 16) */
+                             anti-diagonals s + t a wavefront accumulates at once (8, 12, 16 or 20) */
     int max_spread;       /* > 0: size the slices for row/column exponent spreads of at most
                              max_spread (as for mpcg_workspace_size) instead of reading the
                              exponent scan back.  The call then never synchronizes, and with a

@@ -613,6 +613,7 @@ hipError_t launch_gemm_i8(const GemmArgs& a, int band, hipStream_t stream) {
     case 8: return launch_w<8>(a, stream);
     case 12: return launch_w<12>(a, stream);
     case 16: return launch_w<16>(a, stream);
+    case 20: return launch_w<20>(a, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -624,6 +625,7 @@ hipError_t launch_gemm_i8_batched(const GemmArgs* probs, const int4* items, cons
     case 8: return launch_batched_w<8>(probs, items, first, blocks, mode3m, stream);
     case 12: return launch_batched_w<12>(probs, items, first, blocks, mode3m, stream);
     case 16: return launch_batched_w<16>(probs, items, first, blocks, mode3m, stream);
+    case 20: return launch_batched_w<20>(probs, items, first, blocks, mode3m, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -162,6 +162,16 @@ size_t scan_bytes(int m, int n) {
   return align256(sizeof(RowStat) * (size_t)m) + align256(sizeof(RowStat) * (size_t)n) + 256;
 }
 
+// Band width for a product of this form and slice count (measured on MI355X,
+// exact 3M and 4M from S = 40 (256 bits) to S = 156 (1024 bits)): in the 3M
+// form 20 diagonals per band cut the fragment traffic per MFMA and win from
+// S = 76 up; below that the wider band's extra pairs outside the slice square
+// cost more.  The 4M form keeps two accumulators and two rings per diagonal,
+// for which 16 is the widest band that fits the registers.
+int pick_band(const Plan& P) {
+  return (P.mode3m && std::min(P.SA, P.SB) >= 64) ? 20 : 16;
+}
+
 int plan_layout(Plan& P, const mpcg_options* opt) {
   P.mpad = (int)round_up(P.m, 32);
   P.npad = (int)round_up(P.n, 32);
@@ -173,9 +183,9 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
   const int groups = (P.mpad / 32) * (P.npad / 32);
   if (!P.f64) {
     // band width: diagonals accumulated together by one wavefront
-    P.block = (opt && opt->block_override) ? opt->block_override : 16;
-    if (P.block != 8 && P.block != 12 && P.block != 16)
-      return set_err(MPCG_EINVAL, "block_override (band width) must be 8, 12 or 16");
+    P.block = (opt && opt->block_override) ? opt->block_override : pick_band(P);
+    if (P.block != 8 && P.block != 12 && P.block != 16 && P.block != 20)
+      return set_err(MPCG_EINVAL, "block_override (band width) must be 8, 12, 16 or 20");
     P.SAp = P.SA;
     P.SBp = P.SB;
     int ahi, bhi;
@@ -557,16 +567,6 @@ long long band_steps(int W, int SA, int SB, int Dmax) {
     total += (long long)ceil_div(n, 2 * NS) * 2 * NS;
   }
   return total;
-}
-
-// Band width for a problem of this size class.  The ring wastes about W / S
-// of its MFMAs on pairs outside the slice square and spends W steps per unit
-// filling, while wider bands amortise the per-step overhead; on MI355X the
-// widest band measured fastest for every slice count from S = 40 (256 bits)
-// to S = 165 (1024 bits), so the class rule is a constant for now.
-int pick_band(const Plan& P) {
-  (void)P;
-  return 16;
 }
 
 struct BatchProblem {

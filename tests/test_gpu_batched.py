@@ -68,7 +68,7 @@ def test_batched_uneven_exact(mode, p):
         assert bad == 0, (t, (m, n, k), first, info)
 
 
-@pytest.mark.parametrize("block", [8, 12, 16])
+@pytest.mark.parametrize("block", [8, 12, 16, 20])
 @pytest.mark.parametrize("ksplit", [0, 3])
 def test_batched_plan_independent(block, ksplit):
     p = 200

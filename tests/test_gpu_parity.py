@@ -55,7 +55,7 @@ def test_ragged_exact(mode, slice_type, shape):
     _check_exact(A, B, p, mode, slice_type)
 
 
-@pytest.mark.parametrize("block", [8, 12, 16])
+@pytest.mark.parametrize("block", [8, 12, 16, 20])
 @pytest.mark.parametrize("ksplit", [1, 2, 3])
 def test_tiling_independent(block, ksplit):
     """Band width and contraction chunks never change the bits."""
