@@ -66,6 +66,11 @@ def lib():
         L.oracle_exact_entry.argtypes = [i32, i32, i32, vp, i64, vp, i64, i32, i32, i32, i32, i32,
                                          vp, vp, vp, i32, vp]
         L.oracle_exact_entry.restype = i32
+        L.oracle_cgemm_acc.argtypes = [i32, i32, i32, vp, i64, vp, i64, vp, i64, vp, i64, i32, i32, i32, i32]
+        L.oracle_cgemm_acc.restype = i32
+        L.oracle_cgemm_acc_entries.argtypes = [i32, i32, i32, vp, i64, vp, i64, vp, i64, i64, vp, vp, vp, vp,
+                                               vp, i32, i32, i32, i32]
+        L.oracle_cgemm_acc_entries.restype = i32
         _lib = L
     return _lib
 
@@ -140,6 +145,51 @@ def cgemm(A: HostCMat, B: HostCMat, prec_bits: int, form: int = FORM_4M, nthread
                             nthreads or default_threads())
     _check(st, "oracle_cgemm")
     return C
+
+
+def cgemm_acc(A: HostCMat, B: HostCMat, Cin: HostCMat, prec_bits: int, sign: int = 1,
+              form: int = FORM_4M, nthreads: int | None = None) -> HostCMat:
+    """Correctly rounded C = Cin + sign * A B (every entry): the exact sum of the
+    addend and the product, rounded once per component; sign is +1 or -1."""
+    m, k = A.rows, A.cols
+    n = B.cols
+    assert B.rows == k and Cin.rows == m and Cin.cols == n
+    C = empty_cmat(m, n, prec_bits)
+    keep = []
+    a = _cmat_struct(A, keep)
+    b = _cmat_struct(B, keep)
+    cin = _cmat_struct(Cin, keep)
+    c = _cmat_struct(C, keep)
+    st = lib().oracle_cgemm_acc(m, n, k, ctypes.addressof(a), A.ld, ctypes.addressof(b), B.ld,
+                                ctypes.addressof(cin), Cin.ld, ctypes.addressof(c), C.ld, prec_bits, form,
+                                sign, nthreads or default_threads())
+    _check(st, "oracle_cgemm_acc")
+    return C
+
+
+def cgemm_acc_entries(A: HostCMat, B: HostCMat, Cin: HostCMat, rows, cols, prec_bits: int, sign: int = 1,
+                      form: int = FORM_4M, nthreads: int | None = None):
+    """Entries (rows[t], cols[t]) of the correctly rounded Cin + sign * A B, in
+    the layout of cgemm_entries."""
+    m, k = A.rows, A.cols
+    n = B.cols
+    ei = np.ascontiguousarray(rows, dtype=np.int32)
+    ej = np.ascontiguousarray(cols, dtype=np.int32)
+    nent = ei.size
+    L = (prec_bits + 63) // 64
+    sgn = np.zeros((nent, 2), np.uint8)
+    exp = np.zeros((nent, 2), np.int32)
+    mant = np.zeros((nent, 2, L), np.uint64)
+    keep = []
+    a = _cmat_struct(A, keep)
+    b = _cmat_struct(B, keep)
+    cin = _cmat_struct(Cin, keep)
+    st = lib().oracle_cgemm_acc_entries(m, n, k, ctypes.addressof(a), A.ld, ctypes.addressof(b), B.ld,
+                                        ctypes.addressof(cin), Cin.ld, nent, ei.ctypes.data, ej.ctypes.data,
+                                        sgn.ctypes.data, exp.ctypes.data, mant.ctypes.data, prec_bits, form,
+                                        sign, nthreads or default_threads())
+    _check(st, "oracle_cgemm_acc_entries")
+    return sgn, exp, mant
 
 
 def cgemm_entries(A: HostCMat, B: HostCMat, rows, cols, prec_bits: int, form: int = FORM_4M,

@@ -75,6 +75,29 @@ def rounded_product(A: HostCMat, B: HostCMat, prec_bits: int):
              for j in range(len(re[0]))] for i in range(len(re))]
 
 
+def rounded_product_acc(A: HostCMat, B: HostCMat, Cin: HostCMat, prec_bits: int, sign: int):
+    """RNE(p) of Cin + sign * AB, entry by entry (one rounding of the exact sum)."""
+    re, im = exact_product(A, B, prec_bits)
+    out = []
+    for i in range(len(re)):
+        row = []
+        for j in range(len(re[0])):
+            cr = decode(Cin.re, i, j, prec_bits)
+            ci = decode(Cin.im, i, j, prec_bits)
+            row.append((round_rne(cr + sign * re[i][j], prec_bits), round_rne(ci + sign * im[i][j], prec_bits)))
+        out.append(row)
+    return out
+
+
+def triple_value(t) -> Fraction:
+    """The exact value of a (sign, exp, q) triple from round_rne."""
+    s, e, q = t
+    if q == 0:
+        return Fraction(0)
+    v = Fraction(q) * Fraction(2) ** (e - q.bit_length())
+    return -v if s else v
+
+
 def stored_as_triple(part: HostPart, r: int, c: int, prec_bits: int):
     """A stored (output) entry as (sign, exp, q) comparable with round_rne's result."""
     e = int(part.exp[c, r])

@@ -357,6 +357,10 @@ typedef struct {
     uint8_t *p_sign;   /* [nent*2] */
     int32_t *p_exp;    /* [nent*2] */
     uint64_t *p_mant;  /* [nent*2*L] */
+    /* optional addend (eq. 1 extended to C := Cadd + sgn AB): NULL for C := AB */
+    const orc_in_cmat *Cadd;
+    int64_t ldcadd;
+    int neg_prod;      /* 1: the products enter with a minus sign */
     /* exact (unrounded) output: one entry, one component */
     int nthreads;
     int tid;
@@ -366,6 +370,7 @@ typedef struct {
 typedef struct {
     /* decoded row of A and column of B */
     orc_real *ar, *ai, *br, *bi;
+    orc_real cr, ci;   /* the addend's entry */
     uint64_t *sig_store;
     uint64_t *prod;    /* product scratch */
     uint64_t *acc;
@@ -381,7 +386,7 @@ static int scratch_init(orc_scratch *s, int k, int L, int64_t max_spread_limbs)
     s->ai = (orc_real *)calloc((size_t)k, sizeof(orc_real));
     s->br = (orc_real *)calloc((size_t)k, sizeof(orc_real));
     s->bi = (orc_real *)calloc((size_t)k, sizeof(orc_real));
-    s->sig_store = (uint64_t *)calloc((size_t)k * 4 * (size_t)L + 1, sizeof(uint64_t));
+    s->sig_store = (uint64_t *)calloc((size_t)(k + 1) * 4 * (size_t)L + 1, sizeof(uint64_t));
     s->sum_cap = (int)(max_spread_limbs + L + 4);
     s->ua.mag = (uint64_t *)calloc((size_t)s->sum_cap, sizeof(uint64_t));
     s->ub.mag = (uint64_t *)calloc((size_t)s->sum_cap, sizeof(uint64_t));
@@ -394,6 +399,9 @@ static int scratch_init(orc_scratch *s, int k, int L, int64_t max_spread_limbs)
         s->br[t].sig = s->sig_store + ((size_t)t * 4 + 2) * L;
         s->bi[t].sig = s->sig_store + ((size_t)t * 4 + 3) * L;
     }
+    s->cr.sig = s->sig_store + ((size_t)k * 4 + 0) * L;
+    s->ci.sig = s->sig_store + ((size_t)k * 4 + 1) * L;
+    s->cr.zero = s->ci.zero = 1;
     return ORC_OK;
 }
 
@@ -424,8 +432,11 @@ typedef struct {
 /*
  * Exact sum of the real-product terms of one component, then RNE.
  * 4M form: two terms per k.  3M form (Im only): (ar+ai)(br+bi) - ar br - ai bi.
+ * With an addend c (not NULL and nonzero) the exact sum is c + sgn * (products),
+ * sgn = -1 when neg_prod, rounded once.
  */
 static int eval_component(orc_scratch *s, int k, int p, int L, int comp, int form,
+                          const orc_real *addend, int neg_prod,
                           uint8_t *o_sign, int32_t *o_exp, uint64_t *o_mant, int64_t o_ls,
                           int want_exact, int *x_neg, int64_t *x_base, uint64_t *x_mag, int x_cap, int *x_n)
 {
@@ -472,6 +483,12 @@ static int eval_component(orc_scratch *s, int k, int p, int L, int comp, int for
             }
         }
     }
+    const int have_add = addend && !addend->zero;
+    if (have_add) {
+        if (addend->e - p < base) base = addend->e - p;
+        if (addend->e > topv) topv = addend->e;
+        ++nterms;
+    }
     if (nterms == 0) {
         if (want_exact) {
             *x_neg = 0; *x_base = 0; *x_n = 0;
@@ -514,7 +531,7 @@ static int eval_component(orc_scratch *s, int k, int p, int L, int comp, int for
             if (x->zero || y->zero)
                 continue;
             mag_mul(x->sig, L, y->sig, L, s->prod);
-            int neg = x->neg ^ y->neg ^ tm[q].negate;
+            int neg = x->neg ^ y->neg ^ tm[q].negate ^ neg_prod;
             acc_add_shifted(acc, nacc, s->prod, 2 * L, x->e + y->e - 2LL * p - base, neg);
         }
         if (comp == 1 && form == ORC_FORM_3M) {
@@ -527,10 +544,12 @@ static int eval_component(orc_scratch *s, int k, int p, int L, int comp, int for
             if (s->ua.zero || s->ub.zero)
                 continue;
             mag_mul(s->ua.mag, s->ua.n, s->ub.mag, s->ub.n, s->prod);
-            int neg = s->ua.neg ^ s->ub.neg;
+            int neg = s->ua.neg ^ s->ub.neg ^ neg_prod;
             acc_add_shifted(acc, nacc, s->prod, s->ua.n + s->ub.n, s->ua.base + s->ub.base - base, neg);
         }
     }
+    if (have_add)
+        acc_add_shifted(acc, nacc, addend->sig, L, addend->e - p - base, addend->neg);
     if (want_exact) {
         int neg = (int)(acc[nacc - 1] >> 63);
         if (neg)
@@ -598,17 +617,23 @@ static void *worker(void *arg)
             j = J->ej[idx];
         }
         load_row_col(&s, J, i, j);
+        if (J->Cadd) {
+            int64_t ic = (int64_t)j * J->ldcadd + i;
+            decode_entry(&J->Cadd->re, ic, J->L, J->p, &s.cr);
+            decode_entry(&J->Cadd->im, ic, J->L, J->p, &s.ci);
+        }
         for (int comp = 0; comp < 2; ++comp) {
             int st;
+            const orc_real *add = J->Cadd ? (comp ? &s.ci : &s.cr) : NULL;
             if (J->out_mode == 0) {
                 orc_out_part *C = comp ? &J->C->im : &J->C->re;
                 int64_t o = (int64_t)j * J->ldc + i;
-                st = eval_component(&s, J->k, J->p, J->L, comp, J->form, &C->sign[o], &C->exp[o],
-                                    &C->mant[o], C->limb_stride, 0, NULL, NULL, NULL, 0, NULL);
+                st = eval_component(&s, J->k, J->p, J->L, comp, J->form, add, J->neg_prod, &C->sign[o],
+                                    &C->exp[o], &C->mant[o], C->limb_stride, 0, NULL, NULL, NULL, 0, NULL);
             } else {
                 int64_t o = idx * 2 + comp;
-                st = eval_component(&s, J->k, J->p, J->L, comp, J->form, &J->p_sign[o], &J->p_exp[o],
-                                    &J->p_mant[o * J->L], 1, 0, NULL, NULL, NULL, 0, NULL);
+                st = eval_component(&s, J->k, J->p, J->L, comp, J->form, add, J->neg_prod, &J->p_sign[o],
+                                    &J->p_exp[o], &J->p_mant[o * J->L], 1, 0, NULL, NULL, NULL, 0, NULL);
             }
             if (st && !J->status)
                 J->status = st;
@@ -691,6 +716,55 @@ int oracle_cgemm(int m, int n, int k, const orc_in_cmat *A, int64_t lda, const o
     return run_jobs(&J, nthreads);
 }
 
+/* Accumulating product C := Cadd + sgn A B (sgn = +1 or -1), every entry: the
+ * exact sum of the addend and all real-product terms, one RNE per component.
+ * C and Cadd may not share memory (the oracle reads Cadd while writing C). */
+int oracle_cgemm_acc(int m, int n, int k, const orc_in_cmat *A, int64_t lda, const orc_in_cmat *B,
+                     int64_t ldb, const orc_in_cmat *Cadd, int64_t ldcadd, orc_out_cmat *C, int64_t ldc,
+                     int prec_bits, int form, int sgn, int nthreads)
+{
+    int st = check_common(m, n, k, prec_bits, lda, ldb, form);
+    if (st)
+        return st;
+    if (ldc < (m > 1 ? m : 1) || ldcadd < (m > 1 ? m : 1) || (sgn != 1 && sgn != -1) || !Cadd)
+        return ORC_EINVAL;
+    if (m == 0 || n == 0)
+        return ORC_OK;
+    orc_job J;
+    memset(&J, 0, sizeof(J));
+    J.m = m; J.n = n; J.k = k; J.p = prec_bits; J.L = (prec_bits + 63) / 64; J.form = form;
+    J.A = A; J.lda = lda; J.B = B; J.ldb = ldb;
+    J.Cadd = Cadd; J.ldcadd = ldcadd; J.neg_prod = sgn < 0;
+    J.out_mode = 0; J.C = C; J.ldc = ldc;
+    return run_jobs(&J, nthreads);
+}
+
+/* The same for selected entries (ei[t], ej[t]); outputs packed as [t][comp]. */
+int oracle_cgemm_acc_entries(int m, int n, int k, const orc_in_cmat *A, int64_t lda, const orc_in_cmat *B,
+                             int64_t ldb, const orc_in_cmat *Cadd, int64_t ldcadd, int64_t nent,
+                             const int32_t *ei, const int32_t *ej, uint8_t *o_sign, int32_t *o_exp,
+                             uint64_t *o_mant, int prec_bits, int form, int sgn, int nthreads)
+{
+    int st = check_common(m, n, k, prec_bits, lda, ldb, form);
+    if (st)
+        return st;
+    if (ldcadd < (m > 1 ? m : 1) || (sgn != 1 && sgn != -1) || !Cadd)
+        return ORC_EINVAL;
+    for (int64_t t = 0; t < nent; ++t)
+        if (ei[t] < 0 || ei[t] >= m || ej[t] < 0 || ej[t] >= n)
+            return ORC_EINVAL;
+    if (nent == 0)
+        return ORC_OK;
+    orc_job J;
+    memset(&J, 0, sizeof(J));
+    J.m = m; J.n = n; J.k = k; J.p = prec_bits; J.L = (prec_bits + 63) / 64; J.form = form;
+    J.A = A; J.lda = lda; J.B = B; J.ldb = ldb;
+    J.Cadd = Cadd; J.ldcadd = ldcadd; J.neg_prod = sgn < 0;
+    J.out_mode = 1; J.nent = nent; J.ei = ei; J.ej = ej;
+    J.p_sign = o_sign; J.p_exp = o_exp; J.p_mant = o_mant;
+    return run_jobs(&J, nthreads);
+}
+
 /* Selected entries (ei[t], ej[t]); outputs packed as [t][comp] (comp 0 = Re). */
 int oracle_cgemm_entries(int m, int n, int k, const orc_in_cmat *A, int64_t lda, const orc_in_cmat *B,
                          int64_t ldb, int64_t nent, const int32_t *ei, const int32_t *ej, uint8_t *o_sign,
@@ -738,7 +812,8 @@ int oracle_exact_entry(int m, int n, int k, const orc_in_cmat *A, int64_t lda, c
         return st;
     }
     load_row_col(&s, &J, i, j);
-    st = eval_component(&s, k, prec_bits, J.L, comp, form, NULL, NULL, NULL, 0, 1, neg, base, mag, cap, nmag);
+    st = eval_component(&s, k, prec_bits, J.L, comp, form, NULL, 0, NULL, NULL, NULL, 0, 1, neg, base, mag, cap,
+                        nmag);
     if (st == ORC_ENOMEM && s.acc_cap > cap)
         *nmag = s.acc_cap;
     scratch_free(&s);

@@ -24,6 +24,9 @@ def encode(value, prec_bits: int):
     # v = N * 2^-t with N odd
     t = v.denominator.bit_length() - 1
     N = v.numerator
+    tz = (N & -N).bit_length() - 1  # an integer value may carry trailing zero bits
+    N >>= tz
+    t -= tz
     nb = N.bit_length()
     assert nb <= prec_bits, "too many significant bits"
     e = nb - t  # value = N/2^nb * 2^e, N/2^nb in [1/2, 1)
