@@ -143,6 +143,25 @@ int mp_cgemm_ex(int m, int n, int k, const mpcg_cmat *A, int lda, const mpcg_cma
                 const mpcg_options *opt, mpcg_info *info);
 
 /*
+ * mp_cgemm_acc - the accumulating product C := C + sign * A B (sign = +1 or
+ * -1), the trailing update of the blocked complex LU (Sec. IV-B: the update
+ * of the remaining block by the product of the panel's two factors).  Each
+ * component of C becomes RNE_p of the exact sum of its current value and of
+ * the exact component of sign * A B: one rounding, as for mp_cgemm (so with
+ * C = 0 on entry the result equals mp_cgemm's, negated for sign = -1).
+ * C (ldc) is read and written in place: its entries on entry are the
+ * addend, read as their top prec_bits significand bits like every input.
+ * Arguments, layout, ownership, validation, asynchrony and the truncated
+ * scheme's bound (which then applies to the product term) are as for
+ * mp_cgemm_ex; k = 0 or an all-zero A or B leaves C unchanged.  INT8 slices
+ * only.  Returns MPCG_OK, MPCG_EINVAL (also for a sign other than +1 / -1),
+ * MPCG_ENOMEM, MPCG_ERANGE, MPCG_EHIP, MPCG_EUNSUPPORTED (FP64 slices).
+ */
+int mp_cgemm_acc(int m, int n, int k, const mpcg_cmat *A, int lda, const mpcg_cmat *B, int ldb,
+                 mpcg_cmat *C, int ldc, int prec_bits, int mode, int scheme, int sign,
+                 const mpcg_options *opt, mpcg_info *info);
+
+/*
  * One product of a batch: C := A B with A m x k (lda), B k x n (ldb), C m x n
  * (ldc).  The mpcg_cmat structs are host structs holding device pointers.
  */

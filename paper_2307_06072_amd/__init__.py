@@ -81,6 +81,9 @@ _lib.mp_cgemm.restype = _i
 _lib.mp_cgemm_ex.argtypes = [_i, _i, _i, _P(mpcg_cmat), _i, _P(mpcg_cmat), _i, _P(mpcg_cmat), _i, _i, _i, _i,
                              _P(mpcg_options), _P(mpcg_info)]
 _lib.mp_cgemm_ex.restype = _i
+_lib.mp_cgemm_acc.argtypes = [_i, _i, _i, _P(mpcg_cmat), _i, _P(mpcg_cmat), _i, _P(mpcg_cmat), _i, _i, _i, _i, _i,
+                              _P(mpcg_options), _P(mpcg_info)]
+_lib.mp_cgemm_acc.restype = _i
 _lib.mp_cgemm_batched.argtypes = [_i, _P(mpcg_problem), _i, _i, _i, _P(mpcg_options), _P(mpcg_info)]
 _lib.mp_cgemm_batched.restype = _i
 _lib.mpcg_set_stream.argtypes = [_vp]
@@ -100,7 +103,7 @@ _lib.mpcg_last_timing.restype = _i
 _lib.mpcg_timing_report.argtypes = [_P(ctypes.c_float), _P(ctypes.c_int)]
 _lib.mpcg_timing_report.restype = _i
 
-EXPORTS = ["mp_cgemm", "mp_cgemm_ex", "mp_cgemm_batched", "mpcg_set_stream", "mpcg_set_workspace", "mpcg_workspace_size",
+EXPORTS = ["mp_cgemm", "mp_cgemm_ex", "mp_cgemm_acc", "mp_cgemm_batched", "mpcg_set_stream", "mpcg_set_workspace", "mpcg_workspace_size",
            "mpcg_stream_status", "mpcg_last_error", "mpcg_enable_timing", "mpcg_last_timing",
            "mpcg_timing_report"]
 
@@ -261,6 +264,23 @@ def mp_cgemm_ex(m, n, k, A: DeviceCMat, lda, B: DeviceCMat, ldb, C: DeviceCMat, 
     info = mpcg_info()
     _check(_lib.mp_cgemm_ex(m, n, k, ctypes.byref(a), lda, ctypes.byref(b), ldb, ctypes.byref(c), ldc,
                             prec_bits, mode, scheme, ctypes.byref(opt), ctypes.byref(info)))
+    return info.as_dict()
+
+
+def mp_cgemm_acc_raw(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, mode, scheme, sign, options=None,
+                     info=None) -> int:
+    return int(_lib.mp_cgemm_acc(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, mode, scheme, sign, options, info))
+
+
+def mp_cgemm_acc(m, n, k, A: DeviceCMat, lda, B: DeviceCMat, ldb, C: DeviceCMat, ldc, prec_bits, sign=-1,
+                 mode=MPCG_3M, scheme=MPCG_EXACT, cutoff_override=0, ksplit_override=0, block_override=0,
+                 max_spread=0) -> dict:
+    """C := C + sign * A B in place (sign = +1 or -1), one rounding."""
+    a, b, c = A.struct(), B.struct(), C.struct()
+    opt = mpcg_options(MPCG_SLICE_INT8, cutoff_override, ksplit_override, block_override, max_spread)
+    info = mpcg_info()
+    _check(_lib.mp_cgemm_acc(m, n, k, ctypes.byref(a), lda, ctypes.byref(b), ldb, ctypes.byref(c), ldc,
+                             prec_bits, mode, scheme, sign, ctypes.byref(opt), ctypes.byref(info)))
     return info.as_dict()
 
 

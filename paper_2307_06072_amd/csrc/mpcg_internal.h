@@ -140,6 +140,7 @@ struct RoundArgs {
   DOutPart cre, cim;
   int64_t ldc;
   int* status;
+  int acc;  // 0: C := AB; +1 / -1: C := C + AB / C - AB (INT8 layout only), rounded once
 };
 hipError_t launch_round(const RoundArgs& a, hipStream_t stream);
 

@@ -348,11 +348,16 @@ int validate(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* 
   return MPCG_OK;
 }
 
+// acc = 0: C := AB; acc = +1 / -1: C := C + AB / C - AB, one rounding of the
+// exact sum (C's current entries are the addend).
 int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, int ldb, mpcg_cmat* C, int ldc,
-        int prec_bits, int mode, int scheme, const mpcg_options* opt, mpcg_info* info) {
+        int prec_bits, int mode, int scheme, const mpcg_options* opt, mpcg_info* info, int acc = 0) {
   g_err.clear();
   int st = validate(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, mode, scheme, opt);
   if (st) return st;
+  if (acc != 0 && acc != 1 && acc != -1) return set_err(MPCG_EINVAL, "accumulate sign must be +1 or -1");
+  if (acc && opt && opt->slice_type == MPCG_SLICE_FP64)
+    return set_err(MPCG_EUNSUPPORTED, "the accumulating form needs INT8 slices");
   if (info) memset(info, 0, sizeof(*info));
   if (m == 0 || n == 0) return MPCG_OK;
   std::lock_guard<std::mutex> lock(g_mu);
@@ -360,8 +365,8 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
   const int L = (prec_bits + 63) / 64;
   const DOutPart cre = doutpart(C->re, (int64_t)ldc * n), cim = doutpart(C->im, (int64_t)ldc * n);
   if ((st = ensure_status_and_pinned())) return st;
-  if (k == 0) {
-    HIP_TRY(launch_zero(cre, cim, m, n, ldc, L, g_stream));
+  if (k == 0) {  // empty contraction: AB = 0
+    if (!acc) HIP_TRY(launch_zero(cre, cim, m, n, ldc, L, g_stream));
     return MPCG_OK;
   }
 
@@ -405,8 +410,8 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
     const ScanSummary sa = g_host_summary[0], sb = g_host_summary[1];
     if ((sa.status | sb.status) & ST_IN_RANGE)
       return set_err(MPCG_ERANGE, "input exponent outside [-2^30, 2^30]");
-    if (sa.nonzero == 0 || sb.nonzero == 0) {
-      HIP_TRY(launch_zero(cre, cim, m, n, ldc, L, g_stream));
+    if (sa.nonzero == 0 || sb.nonzero == 0) {  // AB = 0
+      if (!acc) HIP_TRY(launch_zero(cre, cim, m, n, ldc, L, g_stream));
       return MPCG_OK;
     }
     if ((st = plan_slices(P, sa.spread, sb.spread, sa.hat, sb.hat, opt))) return st;
@@ -473,6 +478,7 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
   ra.ksplit = P.ksplit; ra.mt = P.mt; ra.nt = P.nt; ra.Dmax = P.Dmax; ra.w = P.w;
   ra.G = G; ra.H = H; ra.m = m; ra.n = n; ra.prec = prec_bits; ra.L = L;
   ra.cre = cre; ra.cim = cim; ra.ldc = ldc; ra.status = g_status;
+  ra.acc = acc;
   HIP_TRY(launch_round(ra, g_stream));
   if ((st = record(4))) return st;
   g_timing_valid = g_timing;
@@ -971,6 +977,15 @@ int mp_cgemm(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* 
 int mp_cgemm_ex(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, int ldb, mpcg_cmat* C,
                 int ldc, int prec_bits, int mode, int scheme, const mpcg_options* opt, mpcg_info* info) {
   return run(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, mode, scheme, opt, info);
+}
+
+int mp_cgemm_acc(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, int ldb, mpcg_cmat* C,
+                 int ldc, int prec_bits, int mode, int scheme, int sign, const mpcg_options* opt, mpcg_info* info) {
+  if (sign != 1 && sign != -1) {
+    g_err.clear();
+    return set_err(MPCG_EINVAL, "accumulate sign must be +1 or -1");
+  }
+  return run(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, mode, scheme, opt, info, sign);
 }
 
 int mp_cgemm_batched(int count, const mpcg_problem* problems, int prec_bits, int mode, int scheme,

@@ -305,8 +305,325 @@ struct Win8 {
     }
     const int q = (int)(pos / 7);
     return (int)((m(q) >> (pos - 7ll * q)) & 1);
+  }  // bits [pos, pos + 64) of |X| read from the digit stream (any position)
+  __device__ uint64_t fieldg(int64_t pos) const {
+    const int64_t nbits = 7ll * (Dmax + 1);
+    uint64_t r = 0;
+    const int64_t lo = pos < 0 ? 0 : pos;
+    const int64_t hi = pos + 64;
+    if (lo < nbits) {
+      const int q0 = (int)(lo / 7);
+      const int q1 = (int)min((hi - 1) / 7, (int64_t)Dmax);
+      for (int q = q0; q <= q1; ++q) {
+        const uint64_t v = mg(q);
+        const int64_t sh = 7ll * q - pos;
+        if (sh >= 0) {
+          if (sh < 64) r |= v << sh;
+        } else if (-sh < 64) {
+          r |= v >> (-sh);
+        }
+      }
+    }
+    if (hi > nbits && U) {
+      const int64_t sh = nbits - pos;
+      if (sh >= 0) {
+        if (sh < 64) r |= U << sh;
+      } else if (-sh < 64) {
+        r |= U >> (-sh);
+      }
+    }
+    return r;
   }
 };
+
+// ----------------------------------------------------------------------------
+// Accumulating form C := C + sgn X (X = A B on the digit grid), rounded once.
+// Positions are grid bits (bit 0 = lowest bit of digit q = 0; the value of grid
+// bit b is 2^(b + G_i + H_j - 7 (Dmax + 2))).  The addend's significand is at
+// most p bits, so apart from the cases where one operand lies wholly below the
+// other's lowest bit and a quarter ulp (it then only breaks a tie, or vanishes)
+// the exact sum is formed over the addend's own bit range [cb, ct1) with one
+// bit of headroom: below cb only X has bits (its tail passes through, or is
+// complemented when |C| > |X|), and above ct1 X's digits change by the carry
+// or borrow (+1 / -1) out of that range.
+// ----------------------------------------------------------------------------
+__device__ inline uint64_t lowmask(int64_t n) { return n <= 0 ? 0ull : (n >= 64 ? ~0ull : ((1ull << n) - 1ull)); }
+__device__ inline uint64_t rangemask(int64_t a, int64_t b) { return lowmask(b) & ~lowmask(a); }  // bits [a, b)
+
+struct AccC {
+  const uint64_t* mant;
+  int64_t ls, o, sh;  // sh: grid position of significand bit 0
+  int L, drop;        // drop: bits below the precision in limb 0 (ignored)
+  __device__ inline uint64_t limb(int64_t l) const {
+    if (l < 0 || l >= L) return 0;
+    uint64_t v = mant[l * ls + o];
+    if (l == 0 && drop) v &= ~((1ull << drop) - 1ull);
+    return v;
+  }
+  // bits [pos, pos + 64) of |C|
+  __device__ inline uint64_t field(int64_t pos) const {
+    const int64_t b = pos - sh;
+    if (b >= 64ll * L || b <= -64) return 0;
+    const int64_t l0 = b >= 0 ? b / 64 : -((-b + 63) / 64);
+    const int r = (int)(b - 64 * l0);
+    const uint64_t lo = limb(l0), hi = limb(l0 + 1);
+    return r ? (lo >> r) | (hi << (64 - r)) : lo;
+  }
+  __device__ inline int64_t lowest() const {
+    for (int l = 0; l < L; ++l) {
+      const uint64_t v = limb(l);
+      if (v) return sh + 64ll * l + __builtin_ctzll(v);
+    }
+    return sh;  // not reached for a nonzero addend
+  }
+};
+
+// Lowest position >= pos where |X| has bit `want`; `limit` bounds the scan.
+__device__ inline int64_t x_first_from(const Win8& st, int64_t pos, int want, int64_t limit) {
+  while (pos <= limit) {
+    const uint64_t f = st.fieldg(pos);
+    const uint64_t g = want ? f : ~f;
+    if (g) return pos + __builtin_ctzll(g);
+    pos += 64;
+  }
+  return limit;
+}
+
+struct AccSum {
+  const Win8* st;
+  const uint64_t* Y;  // the sum over [cb, cb + Wd), nl limbs
+  int64_t cb, ct1, Wd, low_x, r;
+  int nl, delta, typ, xlo;
+  __device__ inline uint64_t yfield(int64_t pos) const {
+    const int64_t b = pos - cb;
+    if (b >= Wd || b <= -64) return 0;
+    const int64_t l0 = b >= 0 ? b / 64 : -((-b + 63) / 64);
+    const int rr = (int)(b - 64 * l0);
+    const uint64_t lo = (l0 >= 0 && l0 < nl) ? Y[l0] : 0;
+    const uint64_t hi = (l0 + 1 >= 0 && l0 + 1 < nl) ? Y[l0 + 1] : 0;
+    return rr ? (lo >> rr) | (hi << (64 - rr)) : lo;
+  }
+  // bits [pos, pos + 64) of |S|
+  __device__ inline uint64_t field(int64_t pos) const {
+    if (typ == 1) {
+      uint64_t f = yfield(pos);
+      if (pos < cb) f |= st->fieldg(pos) & lowmask(cb - pos);
+      if (pos + 64 > ct1) {
+        uint64_t t = st->fieldg(pos);
+        if (delta) {
+          const uint64_t run = rangemask(ct1 - pos, r - pos);
+          t = delta > 0 ? (t & ~run) : (t | run);
+          if (r >= pos && r < pos + 64) t = delta > 0 ? (t | (1ull << (r - pos))) : (t & ~(1ull << (r - pos)));
+        }
+        f |= t & ~lowmask(ct1 - pos);
+      }
+      return f;
+    }
+    uint64_t f = yfield(pos);
+    if (xlo && pos < cb) {
+      f |= ~st->fieldg(pos) & rangemask(low_x + 1 - pos, cb - pos);
+      if (low_x >= pos && low_x < pos + 64) f |= 1ull << (low_x - pos);
+    }
+    return f;
+  }
+};
+
+// The general case: writes the rounded sum (sign, exponent, limbs) of entry o.
+__device__ void round_acc_general(const Win8& st, int64_t lead_x, int64_t low_x, int sx, const AccC& C, int sc,
+                                  int64_t gbase, int p, int L, DOutPart out, int64_t o, uint64_t* Y, int* status) {
+  const int64_t nbits = 7ll * (st.Dmax + 1);
+  const int64_t lead_c = 64ll * L - 1 + C.sh;
+  const int64_t cb = C.lowest();
+  const int64_t ct1 = lead_c + 2;
+  const int64_t Wd = ct1 - cb;  // at most p + 1 bits
+  const int nl = (int)((Wd + 63) / 64);
+  const int wr = (int)(Wd & 63);
+  const uint64_t wmask = wr ? ((1ull << wr) - 1ull) : ~0ull;
+  const int xlo = low_x < cb;
+  AccSum S;
+  S.st = &st; S.Y = Y; S.cb = cb; S.ct1 = ct1; S.Wd = Wd; S.low_x = low_x; S.nl = nl; S.xlo = xlo; S.r = 0;
+  S.delta = 0;
+  int s_out;
+  if (sc == sx) {  // |X| + |C|
+    uint64_t carry = 0;
+    for (int l = 0; l < nl; ++l) {
+      uint64_t a = st.fieldg(cb + 64ll * l);
+      if (l == nl - 1) a &= wmask;
+      const uint64_t b = C.field(cb + 64ll * l);
+      const uint64_t s1 = a + b;
+      const uint64_t c1 = s1 < a;
+      const uint64_t s2 = s1 + carry;
+      const uint64_t c2 = s2 < s1;
+      Y[l] = s2;
+      carry = c1 | c2;
+    }
+    if (wr) {
+      S.delta = (int)((Y[nl - 1] >> wr) & 1ull);
+      Y[nl - 1] &= wmask;
+    } else {
+      S.delta = (int)carry;
+    }
+    S.typ = 1;
+    s_out = sx;
+  } else {
+    int xbig;
+    if (lead_x != lead_c) {
+      xbig = lead_x > lead_c;
+    } else {
+      xbig = 1;  // equal over the range: X's tail below cb makes |X| >= |C|
+      for (int l = nl - 1; l >= 0; --l) {
+        uint64_t a = st.fieldg(cb + 64ll * l);
+        if (l == nl - 1) a &= wmask;
+        const uint64_t b = C.field(cb + 64ll * l);
+        if (a != b) {
+          xbig = a > b;
+          break;
+        }
+      }
+    }
+    uint64_t borrow = xbig ? 0ull : (uint64_t)xlo;
+    for (int l = 0; l < nl; ++l) {
+      uint64_t a = st.fieldg(cb + 64ll * l);
+      if (l == nl - 1) a &= wmask;
+      const uint64_t b = C.field(cb + 64ll * l);
+      const uint64_t u = xbig ? a : b, v = xbig ? b : a;
+      const uint64_t t = u - v;
+      const uint64_t b1 = u < v;
+      const uint64_t d = t - borrow;
+      const uint64_t b2 = t < borrow;
+      Y[l] = d;
+      borrow = b1 | b2;
+    }
+    Y[nl - 1] &= wmask;
+    if (xbig) {
+      S.delta = borrow ? -1 : 0;
+      S.typ = 1;
+      s_out = sx;
+    } else {
+      S.typ = 2;
+      s_out = sc;
+    }
+  }
+  int ynz = 0;
+  for (int l = 0; l < nl; ++l) ynz |= Y[l] != 0;
+  const int64_t scan_limit = nbits + 128;
+  // leading and lowest set bit of |S|
+  int64_t lead = INT64_MIN, lows = 0;
+  if (S.typ == 1) {
+    if (S.delta > 0) S.r = x_first_from(st, ct1, 0, scan_limit);
+    if (S.delta < 0) S.r = x_first_from(st, ct1, 1, scan_limit);
+    if (S.delta == 0) {
+      if (lead_x >= ct1) lead = lead_x;
+    } else if (S.delta > 0) {
+      lead = max(lead_x, S.r);
+    } else {
+      if (lead_x > S.r) lead = lead_x;
+      else if (S.r > ct1) lead = S.r - 1;
+    }
+    if (lead == INT64_MIN) {
+      if (ynz) {
+        for (int l = nl - 1; l >= 0; --l)
+          if (Y[l]) {
+            lead = cb + 64ll * l + 63 - __builtin_clzll(Y[l]);
+            break;
+          }
+      } else if (xlo) {
+        int64_t hi = cb;  // highest set bit of X below cb (its lowest is low_x)
+        while (hi > low_x) {
+          const int64_t start = max(hi - 64, low_x);
+          const uint64_t f = st.fieldg(start) & lowmask(hi - start);
+          if (f) {
+            lead = start + 63 - __builtin_clzll(f);
+            break;
+          }
+          hi = start;
+        }
+      }
+    }
+    if (xlo) {
+      lows = low_x;
+    } else if (ynz) {
+      for (int l = 0; l < nl; ++l)
+        if (Y[l]) {
+          lows = cb + 64ll * l + __builtin_ctzll(Y[l]);
+          break;
+        }
+    } else if (S.delta == 0) {
+      lows = x_first_from(st, ct1, 1, scan_limit);
+    } else if (S.delta > 0) {
+      lows = S.r;
+    } else {
+      lows = S.r > ct1 ? ct1 : x_first_from(st, S.r + 1, 1, scan_limit);
+    }
+  } else {
+    if (ynz) {
+      for (int l = nl - 1; l >= 0; --l)
+        if (Y[l]) {
+          lead = cb + 64ll * l + 63 - __builtin_clzll(Y[l]);
+          break;
+        }
+    } else if (xlo) {
+      lead = low_x;  // highest set bit of 2^cb - X_lo: its highest zero of X above low_x
+      int64_t hi = cb;
+      while (hi > low_x + 1) {
+        const int64_t start = max(hi - 64, low_x + 1);
+        const uint64_t f = ~st.fieldg(start) & lowmask(hi - start);
+        if (f) {
+          lead = start + 63 - __builtin_clzll(f);
+          break;
+        }
+        hi = start;
+      }
+    }
+    if (xlo) {
+      lows = low_x;
+    } else {
+      for (int l = 0; l < nl; ++l)
+        if (Y[l]) {
+          lows = cb + 64ll * l + __builtin_ctzll(Y[l]);
+          break;
+        }
+    }
+  }
+  if (lead == INT64_MIN) {  // exact cancellation -> +0
+    out.sign[o] = 0;
+    out.exp[o] = EXP_ZERO;
+    for (int l = 0; l < L; ++l) out.mant[(int64_t)l * out.ls + o] = 0;
+    return;
+  }
+  const int64_t low = lead - p + 1;
+  const int rbit = (int)(S.field(low - 1) & 1ull);
+  const int lsb = (int)(S.field(low) & 1ull);
+  const int sticky = lows < low - 1;
+  const int round_up = rbit && (sticky || lsb);
+  const int keep_from = 64 * L - p;
+  const int64_t off = lead + 1 - 64ll * L;
+  uint64_t carry = round_up ? (1ull << keep_from) : 0;
+  int64_t e_out = lead + 1 + gbase;
+  uint64_t limbs_hi = 0;
+  for (int l = 0; l < L; ++l) {
+    uint64_t f = S.field(off + 64ll * l);
+    if (l == 0 && keep_from) f &= ~((1ull << keep_from) - 1ull);
+    const uint64_t sum = f + carry;
+    carry = (sum < f) ? 1 : 0;
+    limbs_hi = sum;
+    if (l < L - 1) out.mant[(int64_t)l * out.ls + o] = sum;
+  }
+  if (carry) {
+    limbs_hi = 1ull << 63;
+    e_out += 1;
+  }
+  if (e_out > INT32_MAX || e_out <= (int64_t)INT32_MIN) {
+    atomicOr(status, ST_OUT_RANGE);
+    out.sign[o] = 0;
+    out.exp[o] = EXP_ZERO;
+    for (int l = 0; l < L; ++l) out.mant[(int64_t)l * out.ls + o] = 0;
+    return;
+  }
+  out.mant[(int64_t)(L - 1) * out.ls + o] = limbs_hi;
+  out.sign[o] = (uint8_t)s_out;
+  out.exp[o] = (int32_t)e_out;
+}
 
 // bytes of LDS per thread for L limbs: the window spans at most
 // ceil(64 L / 7) + 3 digits, copied as whole 16-digit chunks
@@ -377,7 +694,13 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
   DOutPart out = comp ? a.cim : a.cre;
   const int64_t o = (int64_t)j * a.ldc + i;
   const int L = a.L, p = a.prec;
-  if (T == 0 && z < 0) {  // exact zero -> +0
+  // accumulating form: the entry's current value is the addend
+  const int negp = a.acc < 0;
+  int32_t ce = EXP_ZERO;
+  if (a.acc) ce = out.exp[o];
+  const int cnz = ce != EXP_ZERO;
+  if (T == 0 && z < 0) {  // exact zero -> +0 (or the addend, unchanged)
+    if (cnz) return;
     out.sign[o] = 0;
     out.exp[o] = EXP_ZERO;
     for (int l = 0; l < L; ++l) out.mant[(int64_t)l * out.ls + o] = 0;
@@ -415,6 +738,28 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
   // lowest bit of limb 0, whichever is lower (the rounding bit lies one below
   // limb 0 when p = 64 L), to the leading bit (above it the magnitude digits
   // are zero)
+  const int64_t gbase = (int64_t)a.G[i] + (int64_t)a.H[j] - 7ll * (Dmax + 2);
+  const int sx = st.neg ^ negp;  // sign of the product term
+  int tie = -1;                   // >= 0: a negligible addend breaks the tie
+  if (cnz) {
+    AccC C;
+    C.mant = out.mant;
+    C.ls = out.ls;
+    C.o = o;
+    C.L = L;
+    C.drop = 64 * L - p;
+    C.sh = (int64_t)ce - 64ll * L - gbase;
+    const int sc = out.sign[o] ? 1 : 0;
+    const int64_t lead_c = 64ll * L - 1 + C.sh;
+    if (lead_c < lowset && lead_c <= lead - (int64_t)p - 2) {
+      tie = sc == sx;  // below X's lowest bit and a quarter ulp: only ties move
+    } else {
+      if (lead < C.lowest() && lead <= lead_c - (int64_t)p - 2) return;  // the sum rounds to the addend
+      round_acc_general(st, lead, lowset, sx, C, sc, gbase, p, L, out, o, reinterpret_cast<uint64_t*>(lds),
+                        a.status);
+      return;
+    }
+  }
   const int64_t off = lead + 1 - 64ll * L;
   const int64_t lowest = min(off, lead - (int64_t)p);
   const int qlo = lowest <= 0 ? 0 : (int)(lowest / 7);
@@ -430,11 +775,11 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
     const int rbit = st.bit(low - 1);
     const int sticky = lowset < low - 1;
     const int lsb = st.bit(low);
-    round_up = rbit && (sticky || lsb);
+    round_up = rbit && (sticky || (tie < 0 ? lsb : tie));
   }
   const int keep_from = 64 * L - p;  // 0..63
   uint64_t carry = round_up ? (1ull << keep_from) : 0;
-  int64_t e_out = lead + 1 + (int64_t)a.G[i] + (int64_t)a.H[j] - 7ll * (Dmax + 2);
+  int64_t e_out = lead + 1 + gbase;
   uint64_t limbs_hi = 0;
   for (int l = 0; l < L; ++l) {
     uint64_t f = st.field(off + 64ll * l);
@@ -456,7 +801,7 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
     return;
   }
   out.mant[(int64_t)(L - 1) * out.ls + o] = limbs_hi;
-  out.sign[o] = (uint8_t)st.neg;
+  out.sign[o] = (uint8_t)sx;
   out.exp[o] = (int32_t)e_out;
 }
 

@@ -186,3 +186,24 @@ def test_max_spread_option_validated():
     import paper_2307_06072_amd as mp
     assert _call(opt=mp.mpcg_options(0, 0, 0, 0, -1)) == mp.MPCG_EINVAL
     assert _call(opt=mp.mpcg_options(0, 0, 0, 0, 1 << 25)) == mp.MPCG_EINVAL
+
+
+def test_accumulate_validation():
+    """mp_cgemm_acc validates like mp_cgemm_ex, plus its sign and slice type,
+    before any device work."""
+    import paper_2307_06072_amd as mp
+    A, B, C = _fake_cmat(1 << 40), _fake_cmat(2 << 40), _fake_cmat(3 << 40)
+
+    def acc(sign=-1, opt=None, m=4, ldc=4, Cm=C):
+        return mp.mp_cgemm_acc_raw(m, 4, 4, ctypes.byref(A), 4, ctypes.byref(B), 4, ctypes.byref(Cm), ldc, 256, 1, 0,
+                                   sign, ctypes.byref(opt) if opt is not None else None, None)
+
+    for bad in (0, 2, -2):
+        assert acc(sign=bad) == mp.MPCG_EINVAL
+        assert "sign" in mp.mpcg_last_error()
+    assert acc(ldc=3) == mp.MPCG_EINVAL
+    assert acc(opt=mp.mpcg_options(mp.MPCG_SLICE_FP64, 0, 0, 0)) == mp.MPCG_EUNSUPPORTED
+    Cbad = _fake_cmat(3 << 40)
+    Cbad.re.sign = A.im.sign + 4  # the output overlaps an input
+    assert acc(Cm=Cbad) == mp.MPCG_EINVAL
+    assert acc(m=0) == 0
