@@ -190,61 +190,76 @@ def batched_case():
 
 
 def lu_update_stream():
-    """The 31 trailing-update products of a blocked LU of order 4096 with
-    block 128 (r x 128 times 128 x r, r = 3968 ... 128) at 256 bits, planned
-    from a spread bound and captured in one HIP graph; the graph is replayed."""
+    """The 31 trailing updates of a blocked LU of order 4096 with block 128
+    (A22 := A22 - L21 U12, r x 128 times 128 x r, r = 3968 ... 128) at 256
+    bits, in place through mp_cgemm_acc, planned from a spread bound and
+    captured in one HIP graph that is replayed; the same stream of plain
+    products C := L21 U12 is timed beside it."""
     import torch
     import paper_2307_06072_amd as mp
     from mpgen import random_cmat
-    log("LU trailing-update stream: 31 products, graph-captured")
+    log("LU trailing-update stream: 31 in-place updates, graph-captured")
     p, b, N, R, bound = 256, 128, 4096, 2, 8
     sizes = [N - b * (j + 1) for j in range(N // b - 1)]
     ops = []
     for j, r in enumerate(sizes):
         A = mp.to_device(random_cmat([5, j], 0, r, b, p, R))
         B = mp.to_device(random_cmat([5, j], 1, b, r, p, R))
-        ops.append((A, B, mp.device_empty(r, r, p)))
+        C = mp.to_device(random_cmat([5, j], 2, r, r, p, R + 4))  # the trailing block A22
+        ops.append((A, B, C))
     opt = mp.mpcg_options(mp.MPCG_SLICE_INT8, 0, 0, 0, bound)
     wsz = max(mp.mpcg_workspace_size(r, r, b, p, mp.MPCG_3M, mp.MPCG_EXACT, opt, bound) for r in sizes)
     ws = torch.empty(wsz, dtype=torch.uint8, device="cuda")
     work = sum(8.0 * r * r * b for r in sizes)
+    out = {}
     mp.mpcg_set_workspace(ws.data_ptr(), wsz)
     try:
-        def issue():
+        def issue_acc():
+            for (A, B, C) in ops:
+                mp.mp_cgemm_acc(A.rows, B.cols, A.cols, A, A.ld, B, B.ld, C, C.ld, p, -1, mp.MPCG_3M,
+                                mp.MPCG_EXACT, max_spread=bound)
+
+        def issue_prod():
             for (A, B, C) in ops:
                 mp.mp_cgemm_ex(A.rows, B.cols, A.cols, A, A.ld, B, B.ld, C, C.ld, p, mp.MPCG_3M, mp.MPCG_EXACT,
                                max_spread=bound)
-        mp.mpcg_set_stream()
-        issue()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        issue()
-        torch.cuda.synchronize()
-        eager = time.perf_counter() - t0
-        g = torch.cuda.CUDAGraph()
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            with torch.cuda.graph(g, stream=side, capture_error_mode="thread_local"):
-                mp.mpcg_set_stream(side.cuda_stream)
-                issue()
-        mp.mpcg_set_stream()
-        torch.cuda.synchronize()
-        g.replay()
-        torch.cuda.synchronize()
-        reps = 3
-        t0 = time.perf_counter()
-        for _ in range(reps):
+
+        for name, issue in (("acc", issue_acc), ("prod", issue_prod)):
+            mp.mpcg_set_stream()
+            issue()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            issue()
+            torch.cuda.synchronize()
+            eager = time.perf_counter() - t0
+            g = torch.cuda.CUDAGraph()
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                with torch.cuda.graph(g, stream=side, capture_error_mode="thread_local"):
+                    mp.mpcg_set_stream(side.cuda_stream)
+                    issue()
+            mp.mpcg_set_stream()
+            torch.cuda.synchronize()
             g.replay()
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / reps
-        if mp.mpcg_stream_status() != 0:
-            raise RuntimeError(mp.mpcg_last_error())
+            torch.cuda.synchronize()
+            reps = 3
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                g.replay()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            if mp.mpcg_stream_status() != 0:
+                raise RuntimeError(mp.mpcg_last_error())
+            out[name] = (dt, eager)
     finally:
         mp.mpcg_set_workspace(None, 0)
         mp.mpcg_set_stream()
-    return {"lu_updates_n4096_b128_p256": {"ms_per_replay": 1000 * dt, "8mnk_per_s": work / dt,
-                                           "eager_ms": 1000 * eager, "products": len(sizes), "max_spread": bound}}
+    (dt, eager), (dtp, eagerp) = out["acc"], out["prod"]
+    return {"lu_updates_n4096_b128_p256": {"form": "A22 := A22 - L21 U12 in place (mp_cgemm_acc)",
+                                           "ms_per_replay": 1000 * dt, "8mnk_per_s": work / dt,
+                                           "eager_ms": 1000 * eager, "products": len(sizes), "max_spread": bound,
+                                           "plain_product_ms_per_replay": 1000 * dtp}}
 
 
 def main() -> int:

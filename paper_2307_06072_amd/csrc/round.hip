@@ -305,7 +305,8 @@ struct Win8 {
     }
     const int q = (int)(pos / 7);
     return (int)((m(q) >> (pos - 7ll * q)) & 1);
-  }  // bits [pos, pos + 64) of |X| read from the digit stream (any position)
+  }  // bits [pos, pos + 64) of |X| read from the digit stream (any position):
+  // the at most 10 digits come from at most two 16-digit chunks, loaded whole
   __device__ uint64_t fieldg(int64_t pos) const {
     const int64_t nbits = 7ll * (Dmax + 1);
     uint64_t r = 0;
@@ -314,8 +315,16 @@ struct Win8 {
     if (lo < nbits) {
       const int q0 = (int)(lo / 7);
       const int q1 = (int)min((hi - 1) / 7, (int64_t)Dmax);
+      const int c0 = q0 >> 4;
+      const uint4 v0 = *reinterpret_cast<const uint4*>(glob + (size_t)c0 * 1024);
+      const uint4 v1 = (q1 >> 4) != c0 ? *reinterpret_cast<const uint4*>(glob + (size_t)(c0 + 1) * 1024) : v0;
       for (int q = q0; q <= q1; ++q) {
-        const uint64_t v = mg(q);
+        const uint4 cv = (q >> 4) == c0 ? v0 : v1;
+        const int b = q & 15;
+        const uint32_t w = b < 8 ? (b < 4 ? cv.x : cv.y) : (b < 12 ? cv.z : cv.w);
+        const uint64_t raw = (w >> (8 * (b & 3))) & 255u;
+        const int d = Dmax - q;
+        const uint64_t v = !neg ? raw : ((z < 0 || d > z) ? 0ull : (d == z ? 128 - raw : 127 - raw));
         const int64_t sh = 7ll * q - pos;
         if (sh >= 0) {
           if (sh < 64) r |= v << sh;

@@ -176,3 +176,46 @@ def test_acc_truncated_bound():
             g = gn << (ge - e0)
             rhs = (scale[0] << (scale[1] + 4 - p - e0)) + (abs(gn) << (ge - p - e0))
             assert abs(g - exact) <= rhs, (i, j, comp)
+
+
+def test_acc_graph_replay_accumulates():
+    """Planned from a spread bound with a caller workspace the in-place update
+    is capturable; every replay applies it once more (C_n = C_{n-1} - A B,
+    rounded), checked against the oracle from the previous state."""
+    import torch
+    import paper_2307_06072_amd as mp
+    p, m, n, k, bound = 192, 40, 36, 64, 12
+    A = random_cmat(91, 0, m, k, p, 6)
+    B = random_cmat(91, 1, k, n, p, 6)
+    C0 = random_cmat(91, 2, m, n, p, 10)
+    dA, dB, dC = mp.to_device(A), mp.to_device(B), mp.to_device(C0)
+    opt = mp.mpcg_options(mp.MPCG_SLICE_INT8, 0, 0, 0, bound)
+    wsz = mp.mpcg_workspace_size(m, n, k, p, M3, EXACT, opt, bound)
+    ws = torch.empty(wsz, dtype=torch.uint8, device="cuda")
+    mp.mpcg_set_workspace(ws.data_ptr(), wsz)
+    try:
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side, capture_error_mode="thread_local"):
+                mp.mpcg_set_stream(side.cuda_stream)
+                mp.mp_cgemm_acc(m, n, k, dA, m, dB, k, dC, m, p, -1, M3, EXACT, max_spread=bound)
+        mp.mpcg_set_stream()
+        torch.cuda.synchronize()
+        prev = C0
+        assert mismatches(device_result_to_host(dC, p), C0, m, n)[0] == 0  # capture ran nothing
+        for rep in range(3):
+            dA.re.exp.add_(0)  # eager work between replays
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            got = device_result_to_host(dC, p)
+            ref = oracle.cgemm_acc(A, B, prev, p, -1)
+            bad, first = mismatches(got, ref, m, n)
+            assert bad == 0, (rep, first)
+            prev = ref
+        assert mp.mpcg_stream_status() == 0
+    finally:
+        mp.mpcg_set_workspace(None, 0)
+        mp.mpcg_set_stream()
