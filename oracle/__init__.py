@@ -88,7 +88,8 @@ class use_library:
         lib()
         self.saved = _lib
         L = ctypes.CDLL(self.path)
-        for name in ("oracle_cgemm", "oracle_cgemm_entries", "oracle_exact_entry"):
+        for name in ("oracle_cgemm", "oracle_cgemm_entries", "oracle_exact_entry", "oracle_cgemm_acc",
+                     "oracle_cgemm_acc_entries"):
             getattr(L, name).argtypes = getattr(self.saved, name).argtypes
             getattr(L, name).restype = getattr(self.saved, name).restype
         _lib = L

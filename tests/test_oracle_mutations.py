@@ -77,3 +77,54 @@ def test_planted_mistake_is_caught(name, source, tmp_path):
     with oracle.use_library(str(so)):
         failed = _pin_suite()
     assert failed, f"planted mistake {name} was not caught by any pin"
+
+
+# ---------------------------------------------------------------------------
+# the accumulating form (C := Cin + sign AB): mistakes in the addend's term
+# ---------------------------------------------------------------------------
+ACC_MUTATIONS = {
+    "acc_addend_dropped": ("acc_add_shifted(acc, nacc, addend->sig, L, addend->e - p - base, addend->neg);", ""),
+    "acc_addend_sign_ignored": ("acc_add_shifted(acc, nacc, addend->sig, L, addend->e - p - base, addend->neg);",
+                                "acc_add_shifted(acc, nacc, addend->sig, L, addend->e - p - base, 0);"),
+    "acc_addend_shifted_by_one": ("acc_add_shifted(acc, nacc, addend->sig, L, addend->e - p - base, addend->neg);",
+                                  "acc_add_shifted(acc, nacc, addend->sig, L, addend->e - p - base + 1, addend->neg);"),
+    "acc_product_sign_ignored": ("int neg = x->neg ^ y->neg ^ tm[q].negate ^ neg_prod;",
+                                 "int neg = x->neg ^ y->neg ^ tm[q].negate;"),
+}
+
+
+def _acc_pin_suite():
+    from tests import test_oracle_acc as apins
+    failed = []
+
+    def attempt(name, fn, *args):
+        try:
+            fn(*args)
+        except AssertionError:
+            failed.append(name)
+
+    for trial in range(0, 48, 4):
+        attempt(f"acc_brute{trial}", apins.test_acc_bruteforce_random, trial)
+    attempt("acc_cancel", apins.test_acc_cancellation_against_fractions, 53)
+    attempt("acc_zero_addend", apins.test_acc_zero_addend_is_the_product)
+    attempt("acc_zero_product", apins.test_acc_zero_product_returns_addend)
+    attempt("acc_symmetry", apins.test_acc_sign_symmetry, 64)
+    return failed
+
+
+def test_acc_pins_pass_on_the_real_oracle():
+    assert _acc_pin_suite() == []
+
+
+@pytest.mark.parametrize("name", sorted(ACC_MUTATIONS))
+def test_planted_accumulate_mistake_is_caught(name, source, tmp_path):
+    old, new = ACC_MUTATIONS[name]
+    assert old in source, f"mutation anchor for {name} not found"
+    c = tmp_path / "mut.c"
+    so = tmp_path / "libmut.so"
+    c.write_text(source.replace(old, new))
+    subprocess.run(["gcc", "-O1", "-std=gnu11", "-fPIC", "-shared", "-pthread", "-o", str(so), str(c)],
+                   check=True)
+    with oracle.use_library(str(so)):
+        failed = _acc_pin_suite()
+    assert failed, f"planted mistake {name} was not caught by any pin"
