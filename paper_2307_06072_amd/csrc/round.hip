@@ -387,22 +387,31 @@ struct AccC {
   }
 };
 
-// Lowest position >= pos where |X| has bit `want`; `limit` bounds the scan.
-__device__ inline int64_t x_first_from(const Win8& st, int64_t pos, int want, int64_t limit) {
-  while (pos <= limit) {
-    const uint64_t f = st.fieldg(pos);
-    const uint64_t g = want ? f : ~f;
-    if (g) return pos + __builtin_ctzll(g);
-    pos += 64;
-  }
-  return limit;
-}
-
 struct AccSum {
   const Win8* st;
   const uint64_t* Y;  // the sum over [cb, cb + Wd), nl limbs
-  int64_t cb, ct1, Wd, low_x, r;
-  int nl, delta, typ, xlo;
+  const uint64_t* Xw; // |X| bits [xw0, xw0 + 64 nx) in binary (nx = 0: none)
+  int64_t cb, ct1, Wd, low_x, r, xw0;
+  int nl, delta, typ, xlo, nx;
+  // bits [pos, pos + 64) of |X|: from the binary window when inside it
+  __device__ inline uint64_t xf(int64_t pos) const {
+    const int64_t b = pos - xw0;
+    if (nx && b >= 0 && b + 64 <= 64ll * nx) {
+      const int64_t w = b >> 6;
+      const int rr = (int)(b & 63);
+      return rr ? (Xw[w] >> rr) | (Xw[w + 1] << (64 - rr)) : Xw[w];
+    }
+    return st->fieldg(pos);
+  }
+  __device__ inline int64_t first_from(int64_t pos, int want, int64_t limit) const {
+    while (pos <= limit) {
+      const uint64_t f = xf(pos);
+      const uint64_t g = want ? f : ~f;
+      if (g) return pos + __builtin_ctzll(g);
+      pos += 64;
+    }
+    return limit;
+  }
   __device__ inline uint64_t yfield(int64_t pos) const {
     const int64_t b = pos - cb;
     if (b >= Wd || b <= -64) return 0;
@@ -416,9 +425,9 @@ struct AccSum {
   __device__ inline uint64_t field(int64_t pos) const {
     if (typ == 1) {
       uint64_t f = yfield(pos);
-      if (pos < cb) f |= st->fieldg(pos) & lowmask(cb - pos);
+      if (pos < cb) f |= xf(pos) & lowmask(cb - pos);
       if (pos + 64 > ct1) {
-        uint64_t t = st->fieldg(pos);
+        uint64_t t = xf(pos);
         if (delta) {
           const uint64_t run = rangemask(ct1 - pos, r - pos);
           t = delta > 0 ? (t & ~run) : (t | run);
@@ -430,7 +439,7 @@ struct AccSum {
     }
     uint64_t f = yfield(pos);
     if (xlo && pos < cb) {
-      f |= ~st->fieldg(pos) & rangemask(low_x + 1 - pos, cb - pos);
+      f |= ~xf(pos) & rangemask(low_x + 1 - pos, cb - pos);
       if (low_x >= pos && low_x < pos + 64) f |= 1ull << (low_x - pos);
     }
     return f;
@@ -439,7 +448,8 @@ struct AccSum {
 
 // The general case: writes the rounded sum (sign, exponent, limbs) of entry o.
 __device__ void round_acc_general(const Win8& st, int64_t lead_x, int64_t low_x, int sx, const AccC& C, int sc,
-                                  int64_t gbase, int p, int L, DOutPart out, int64_t o, uint64_t* Y, int* status) {
+                                  int64_t gbase, int p, int L, DOutPart out, int64_t o, uint64_t* Y, uint64_t* Xw,
+                                  int nx, int* status) {
   const int64_t nbits = 7ll * (st.Dmax + 1);
   const int64_t lead_c = 64ll * L - 1 + C.sh;
   const int64_t cb = C.lowest();
@@ -452,11 +462,56 @@ __device__ void round_acc_general(const Win8& st, int64_t lead_x, int64_t low_x,
   AccSum S;
   S.st = &st; S.Y = Y; S.cb = cb; S.ct1 = ct1; S.Wd = Wd; S.low_x = low_x; S.nl = nl; S.xlo = xlo; S.r = 0;
   S.delta = 0;
+  // |X| around the addend's range in binary, built once from the digits
+  S.Xw = Xw;
+  S.nx = nx;
+  S.xw0 = cb - 128;
+  if (nx) {
+    for (int w = 0; w < nx; ++w) Xw[w] = 0;
+    const int64_t wlo = max(S.xw0, (int64_t)0), whi = min(S.xw0 + 64ll * nx, nbits);
+    if (wlo < whi) {
+      const int q0 = (int)(wlo / 7), q1 = (int)((whi - 1) / 7);
+      int cc = -1;
+      uint4 cv = make_uint4(0, 0, 0, 0);
+      for (int q = q0; q <= q1; ++q) {
+        if ((q >> 4) != cc) {
+          cc = q >> 4;
+          cv = *reinterpret_cast<const uint4*>(st.glob + (size_t)cc * 1024);
+        }
+        const int b = q & 15;
+        const uint32_t wd = b < 8 ? (b < 4 ? cv.x : cv.y) : (b < 12 ? cv.z : cv.w);
+        const uint64_t raw = (wd >> (8 * (b & 3))) & 255u;
+        const int d = st.Dmax - q;
+        const uint64_t v = !st.neg ? raw : ((st.z < 0 || d > st.z) ? 0ull : (d == st.z ? 128 - raw : 127 - raw));
+        if (!v) continue;
+        const int64_t bp = 7ll * q - S.xw0;  // >= -6
+        if (bp < 0) {
+          Xw[0] |= v >> (-bp);
+        } else {
+          const int64_t w = bp >> 6;
+          const int rr = (int)(bp & 63);
+          if (w < nx) Xw[w] |= v << rr;
+          if (rr > 57 && w + 1 < nx) Xw[w + 1] |= v >> (64 - rr);
+        }
+      }
+    }
+    if (st.U && nbits < S.xw0 + 64ll * nx) {  // the top above the digits
+      const int64_t bp = nbits - S.xw0;
+      if (bp < 0) {
+        if (-bp < 64) Xw[0] |= st.U >> (-bp);
+      } else {
+        const int64_t w = bp >> 6;
+        const int rr = (int)(bp & 63);
+        Xw[w] |= st.U << rr;
+        if (rr && w + 1 < nx) Xw[w + 1] |= st.U >> (64 - rr);
+      }
+    }
+  }
   int s_out;
   if (sc == sx) {  // |X| + |C|
     uint64_t carry = 0;
     for (int l = 0; l < nl; ++l) {
-      uint64_t a = st.fieldg(cb + 64ll * l);
+      uint64_t a = S.xf(cb + 64ll * l);
       if (l == nl - 1) a &= wmask;
       const uint64_t b = C.field(cb + 64ll * l);
       const uint64_t s1 = a + b;
@@ -481,7 +536,7 @@ __device__ void round_acc_general(const Win8& st, int64_t lead_x, int64_t low_x,
     } else {
       xbig = 1;  // equal over the range: X's tail below cb makes |X| >= |C|
       for (int l = nl - 1; l >= 0; --l) {
-        uint64_t a = st.fieldg(cb + 64ll * l);
+        uint64_t a = S.xf(cb + 64ll * l);
         if (l == nl - 1) a &= wmask;
         const uint64_t b = C.field(cb + 64ll * l);
         if (a != b) {
@@ -492,7 +547,7 @@ __device__ void round_acc_general(const Win8& st, int64_t lead_x, int64_t low_x,
     }
     uint64_t borrow = xbig ? 0ull : (uint64_t)xlo;
     for (int l = 0; l < nl; ++l) {
-      uint64_t a = st.fieldg(cb + 64ll * l);
+      uint64_t a = S.xf(cb + 64ll * l);
       if (l == nl - 1) a &= wmask;
       const uint64_t b = C.field(cb + 64ll * l);
       const uint64_t u = xbig ? a : b, v = xbig ? b : a;
@@ -519,8 +574,8 @@ __device__ void round_acc_general(const Win8& st, int64_t lead_x, int64_t low_x,
   // leading and lowest set bit of |S|
   int64_t lead = INT64_MIN, lows = 0;
   if (S.typ == 1) {
-    if (S.delta > 0) S.r = x_first_from(st, ct1, 0, scan_limit);
-    if (S.delta < 0) S.r = x_first_from(st, ct1, 1, scan_limit);
+    if (S.delta > 0) S.r = S.first_from(ct1, 0, scan_limit);
+    if (S.delta < 0) S.r = S.first_from(ct1, 1, scan_limit);
     if (S.delta == 0) {
       if (lead_x >= ct1) lead = lead_x;
     } else if (S.delta > 0) {
@@ -540,7 +595,7 @@ __device__ void round_acc_general(const Win8& st, int64_t lead_x, int64_t low_x,
         int64_t hi = cb;  // highest set bit of X below cb (its lowest is low_x)
         while (hi > low_x) {
           const int64_t start = max(hi - 64, low_x);
-          const uint64_t f = st.fieldg(start) & lowmask(hi - start);
+          const uint64_t f = S.xf(start) & lowmask(hi - start);
           if (f) {
             lead = start + 63 - __builtin_clzll(f);
             break;
@@ -558,11 +613,11 @@ __device__ void round_acc_general(const Win8& st, int64_t lead_x, int64_t low_x,
           break;
         }
     } else if (S.delta == 0) {
-      lows = x_first_from(st, ct1, 1, scan_limit);
+      lows = S.first_from(ct1, 1, scan_limit);
     } else if (S.delta > 0) {
       lows = S.r;
     } else {
-      lows = S.r > ct1 ? ct1 : x_first_from(st, S.r + 1, 1, scan_limit);
+      lows = S.r > ct1 ? ct1 : S.first_from(S.r + 1, 1, scan_limit);
     }
   } else {
     if (ynz) {
@@ -576,7 +631,7 @@ __device__ void round_acc_general(const Win8& st, int64_t lead_x, int64_t low_x,
       int64_t hi = cb;
       while (hi > low_x + 1) {
         const int64_t start = max(hi - 64, low_x + 1);
-        const uint64_t f = ~st.fieldg(start) & lowmask(hi - start);
+        const uint64_t f = ~S.xf(start) & lowmask(hi - start);
         if (f) {
           lead = start + 63 - __builtin_clzll(f);
           break;
@@ -636,9 +691,25 @@ __device__ void round_acc_general(const Win8& st, int64_t lead_x, int64_t low_x,
 
 // bytes of LDS per thread for L limbs: the window spans at most
 // ceil(64 L / 7) + 3 digits, copied as whole 16-digit chunks
+// (an odd number of 16-byte units, so that the 64 lanes' windows start in
+// 16 different bank groups instead of 4)
 __host__ __device__ inline int round_i8_window_bytes(int L) {
   const int digits = (64 * L + 6) / 7 + 3;
-  return 16 * ((digits + 15) / 16 + 1);
+  const int units = (digits + 15) / 16 + 1;
+  return 16 * (units | 1);
+}
+
+// The accumulating form also keeps, per thread, the sum over the addend's
+// range (L + 2 words) and |X| in binary around it (L + 6 words), when 256
+// threads' worth fits the LDS (p <= 2304); beyond that |X| is read from the
+// digit stream directly.
+__host__ __device__ inline int round_i8_acc_words(int L) { return L + 6; }
+__host__ __device__ inline int round_i8_lds_bytes(int L, int acc) {
+  const int wb = round_i8_window_bytes(L);
+  if (!acc) return wb;
+  const int need = 16 * (((8 * ((L + 2) + round_i8_acc_words(L)) + 15) / 16) | 1);
+  const int b = need > wb ? need : wb;
+  return 256 * b <= 160 * 1024 ? b : wb;
 }
 
 __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_all) {
@@ -649,7 +720,7 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
   const int lane = jj + 16 * (ii >> 2), slot = 4 * comp + (ii & 3);
   const int ti = tile % a.mt, tj = tile / a.mt;
   const int i = ti * 16 + ii, j = tj * 16 + jj;
-  const int WB = round_i8_window_bytes(a.L);
+  const int WB = round_i8_lds_bytes(a.L, a.acc);
   uint8_t* lds = lds_all + (size_t)t * WB;
   if (i >= a.m || j >= a.n) return;  // no barrier follows
 
@@ -764,8 +835,9 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
       tie = sc == sx;  // below X's lowest bit and a quarter ulp: only ties move
     } else {
       if (lead < C.lowest() && lead <= lead_c - (int64_t)p - 2) return;  // the sum rounds to the addend
-      round_acc_general(st, lead, lowset, sx, C, sc, gbase, p, L, out, o, reinterpret_cast<uint64_t*>(lds),
-                        a.status);
+      uint64_t* Yw = reinterpret_cast<uint64_t*>(lds);
+      const int nx = WB >= 8 * ((L + 2) + round_i8_acc_words(L)) ? round_i8_acc_words(L) : 0;
+      round_acc_general(st, lead, lowset, sx, C, sc, gbase, p, L, out, o, Yw, Yw + (L + 2), nx, a.status);
       return;
     }
   }
@@ -838,7 +910,7 @@ hipError_t launch_fill_zero(void* p, size_t n, hipStream_t stream) {
 hipError_t launch_round(const RoundArgs& a, hipStream_t stream) {
   const int blocks = a.mt * a.nt * 2;
   if (a.digit_bytes == 1) {
-    const size_t lds = (size_t)256 * round_i8_window_bytes(a.L);
+    const size_t lds = (size_t)256 * round_i8_lds_bytes(a.L, a.acc);
     hipError_t e = hipFuncSetAttribute((const void*)round_i8_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
