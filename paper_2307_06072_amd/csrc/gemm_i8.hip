@@ -17,9 +17,11 @@
 // B fragments Y_t with s + t in the band form a sliding window of W registers
 // (a ring: the fragment loaded at step v enters slot v mod W), so each step
 // needs one A fragment X_s and one new B fragment Y_{d0-s} and issues W MFMAs
-// (every pair (s, t) of the band exactly once).  A unit starts with W steps
-// that only fill the ring and is padded with steps on zero fragments to an
-// even number of queue entries.
+// (every pair (s, t) of the band exactly once).  Only a unit whose walk
+// starts at s = 0 and ends short of s_hi = d0 + W - 1 begins with W steps
+// that only fill the ring; the others start on pairs outside the operands,
+// whose MFMAs the first ring turn skips.  Units are padded with steps on zero
+// fragments to an even number of queue entries.
 //
 // Operand fragments (16 rows x 64 k, 16 bytes per lane, 1 KB contiguous) stream
 // from the tile-major digit planes (consecutive slices of a tile are k-rows
@@ -136,12 +138,13 @@ struct Q {
   static_assert(VM0 < 64, "vmcnt range");
 };
 
-// Steps of a unit (band, pass, k-block): upward, s from s_lo - W (the first
-// W steps only fill the ring) to s_hi; downward, s from s_hi to s_lo = 0;
-// padded with steps on zero fragments to an even number of entries of NS
-// steps.
+// Steps of a unit (band, pass, k-block): upward from s_lo > 0, s from s_lo to
+// s_hi (the first ring turn skips the slots not yet written: their pairs have
+// t > S_B - 1); upward from s_lo = 0, s from -W (the first W steps only fill
+// the ring) to s_hi; downward, s from s_hi to 0; padded with steps on zero
+// fragments to an even number of entries of NS steps.
 __device__ inline int unit_entries(const Band& g, int W, int NS) {
-  const int n = g.down ? g.s_hi + 1 : g.s_hi - (g.s_lo - W) + 1;
+  const int n = g.down ? g.s_hi + 1 : (g.s_lo > 0 ? g.s_hi - g.s_lo + 1 : g.s_hi - (g.s_lo - W) + 1);
   const int per = 2 * NS;
   return (n + per - 1) / per * 2;
 }
@@ -206,7 +209,7 @@ struct Producer {
     e = 0;
     // step h of entry e: s = s0 + dir (NS e + h), t = t0 - dir (NS e + h)
     const int dir = g.down ? -1 : 1;
-    const int s0 = g.down ? g.s_hi : g.s_lo - W;
+    const int s0 = g.down ? g.s_hi : (g.s_lo > 0 ? g.s_lo : g.s_lo - W);
     const int t0 = g.down ? g.d0 + W - 1 - g.s_hi : g.d0 - s0;
     int pa, pb0, pb1;
     if (M3) {
@@ -299,9 +302,6 @@ struct Consumer {
   // everybody's loads of it visible (it is read into the other register
   // buffer) and tells that every wavefront has used the previous entry, whose
   // queue slot is then refilled by loads spread between the MFMAs.
-  // RAMP: the first ring turn with MFMAs of a band whose s range starts above
-  // 0; at its step i the ring slots of diagonals j > i still hold the zero
-  // pads beyond t = S_B - 1, so those MFMAs are skipped.
   // RAMP: the first ring turn of a ramped unit; at its step V the ring slots
   // V + 1 .. W - 1 steps old have not been written (their pairs are known
   // zeros), so those MFMAs are skipped.  DOWN: a downward unit, whose ring
@@ -349,24 +349,19 @@ struct Consumer {
     }
   }
 
-  // One unit.  Upward: a chunk of ring-filling entries, then chunks with
-  // MFMAs, the first of them ramped when s_lo > 0 (its pairs with t >= S_B
-  // are known zeros).  Downward: a ramped chunk (pairs with t < 0), then
-  // chunks with MFMAs.
-  template <int Q0, int Q1, bool DOWN>
+  // One unit.  KIND 0: upward from s_lo > 0, a ramped first turn (its pairs
+  // with t >= S_B are known zeros); 1: upward from s_lo = 0, a chunk of
+  // ring-filling entries first; 2: downward, a ramped first turn (pairs with
+  // t < 0).  Then chunks with MFMAs.
+  template <int Q0, int Q1, int KIND>
   __device__ inline void unit(v4i (&acc)[NACC][W], Producer<W, M3>& P, const Band& g) {
     const int ne = unit_entries(g, W, NS);
-    int e0 = 0;
-    if constexpr (DOWN) {
-      chunk<0, true, Q0, Q1, true, true>(acc, P, ne);
-    } else {
+    if constexpr (KIND == 1) {
       chunk<0, false, Q0, Q1>(acc, P, G::CH);
-      if (g.s_lo > 0 && G::CH < ne) {
-        e0 = G::CH;
-        chunk<0, true, Q0, Q1, true>(acc, P, ne - e0);
-      }
+    } else {
+      chunk<0, true, Q0, Q1, true, KIND == 2>(acc, P, ne);
     }
-    for (e0 += G::CH; e0 < ne; e0 += G::CH) chunk<0, true, Q0, Q1, false, DOWN>(acc, P, ne - e0);
+    for (int e0 = G::CH; e0 < ne; e0 += G::CH) chunk<0, true, Q0, Q1, false, KIND == 2>(acc, P, ne - e0);
   }
 };
 
@@ -447,8 +442,8 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
   const uint32_t dig_lane = (uint32_t)lane * 16u;
 
   // One band: its units, then the carry chain over its W diagonals.
-  auto band_body = [&](const int band, auto down_tag) {
-    constexpr bool DOWN = decltype(down_tag)::value;
+  auto band_body = [&](const int band, auto kind_tag) {
+    constexpr int KIND = decltype(kind_tag)::value;
     Band g;
     g.set(band, W, a.Dmax, a.SAp, a.SBp);
     v4i acc[NACC][W];
@@ -459,16 +454,16 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
 
     if constexpr (M3) {  // T1 = Re Re, T2 = Im Im, T3 = (Re+Im)(Re+Im)
 #pragma unroll 1
-      for (int kb = kb0; kb < kb1; ++kb) c.template unit<0, 0, DOWN>(acc, P, g);
+      for (int kb = kb0; kb < kb1; ++kb) c.template unit<0, 0, KIND>(acc, P, g);
 #pragma unroll 1
-      for (int kb = kb0; kb < kb1; ++kb) c.template unit<1, 1, DOWN>(acc, P, g);
+      for (int kb = kb0; kb < kb1; ++kb) c.template unit<1, 1, KIND>(acc, P, g);
 #pragma unroll 1
-      for (int kb = kb0; kb < kb1; ++kb) c.template unit<2, 2, DOWN>(acc, P, g);
+      for (int kb = kb0; kb < kb1; ++kb) c.template unit<2, 2, KIND>(acc, P, g);
     } else {  // Re += ReA ReB + ImA (-ImB),  Im += ReA ImB + ImA ReB
 #pragma unroll 1
       for (int pass = 0; pass < 2; ++pass)
 #pragma unroll 1
-        for (int kb = kb0; kb < kb1; ++kb) c.template unit<0, 1, DOWN>(acc, P, g);
+        for (int kb = kb0; kb < kb1; ++kb) c.template unit<0, 1, KIND>(acc, P, g);
     }
     // the band is complete: push its diagonals through the carry chains, least
     // significant first; digit q = Dmax - d of component slot k goes to
@@ -520,13 +515,19 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
         *reinterpret_cast<uint32_t*>(dig + ((uint32_t)(4 + r) * (uint32_t)slot_stride + at)) = wim[r][u];
       }
   };
-  // upward bands first (least significant), then the downward ones
+  // least significant first: upward bands with s_lo > 0, the upward band(s)
+  // from s_lo = 0 that stop short of d0 + W - 1, then the downward ones (each
+  // class is a contiguous run of the band order)
   int band = 0;
 #pragma unroll 1
-  for (; band < P.nbands && !band_down(a.Dmax + 1 - W * (band + 1), W, a.SAp, a.SBp); ++band)
-    band_body(band, std::false_type{});
+  for (; band < P.nbands && a.Dmax + 1 - W * (band + 1) > a.SBp - 1 &&
+         !band_down(a.Dmax + 1 - W * (band + 1), W, a.SAp, a.SBp); ++band)
+    band_body(band, std::integral_constant<int, 0>{});
 #pragma unroll 1
-  for (; band < P.nbands; ++band) band_body(band, std::true_type{});
+  for (; band < P.nbands && !band_down(a.Dmax + 1 - W * (band + 1), W, a.SAp, a.SBp); ++band)
+    band_body(band, std::integral_constant<int, 1>{});
+#pragma unroll 1
+  for (; band < P.nbands; ++band) band_body(band, std::integral_constant<int, 2>{});
   // the producer ran past the end of the stream: drain its loads before the LDS is released
   wait_vmcnt<0>();
 

@@ -569,7 +569,8 @@ long long band_steps(int W, int SA, int SB, int Dmax) {
     const int s_lo = std::max(0, d0 - (SB - 1)), s_hi = std::min(SA - 1, d0 + W - 1);
     // bands reaching s = 0 and t = 0 are walked downward without a ring fill
     const bool down = d0 <= SB - 1 && d0 + W - 1 <= SA - 1;
-    const int n = down ? s_hi + 1 : s_hi - (s_lo - W) + 1;
+    // downward and s_lo > 0 units need no ring fill
+    const int n = down ? s_hi + 1 : (s_lo > 0 ? s_hi - s_lo + 1 : s_hi - (s_lo - W) + 1);
     total += (long long)ceil_div(n, 2 * NS) * 2 * NS;
   }
   return total;
