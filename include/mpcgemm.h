@@ -195,6 +195,17 @@ typedef struct {
 int mp_cgemm_batched(int count, const mpcg_problem *problems, int prec_bits, int mode, int scheme,
                      const mpcg_options *opt, mpcg_info *info);
 
+/*
+ * mp_cgemm_batched_acc - the batched accumulating product: C_i := C_i +
+ * sign * A_i B_i in place for every problem (sign = +1 or -1), each entry
+ * rounded once as in mp_cgemm_acc, with the launches of mp_cgemm_batched.
+ * The same validation and returns as mp_cgemm_batched (MPCG_EINVAL also for
+ * a sign other than +1 / -1); a problem with k = 0 or an all-zero A_i or B_i
+ * leaves its C_i unchanged.
+ */
+int mp_cgemm_batched_acc(int count, const mpcg_problem *problems, int prec_bits, int mode, int scheme, int sign,
+                         const mpcg_options *opt, mpcg_info *info);
+
 /* Issue subsequent work on this HIP stream (hipStream_t as void*; NULL = null stream). */
 int mpcg_set_stream(void *hip_stream);
 

@@ -86,6 +86,8 @@ _lib.mp_cgemm_acc.argtypes = [_i, _i, _i, _P(mpcg_cmat), _i, _P(mpcg_cmat), _i, 
 _lib.mp_cgemm_acc.restype = _i
 _lib.mp_cgemm_batched.argtypes = [_i, _P(mpcg_problem), _i, _i, _i, _P(mpcg_options), _P(mpcg_info)]
 _lib.mp_cgemm_batched.restype = _i
+_lib.mp_cgemm_batched_acc.argtypes = [_i, _P(mpcg_problem), _i, _i, _i, _i, _P(mpcg_options), _P(mpcg_info)]
+_lib.mp_cgemm_batched_acc.restype = _i
 _lib.mpcg_set_stream.argtypes = [_vp]
 _lib.mpcg_set_stream.restype = _i
 _lib.mpcg_set_workspace.argtypes = [_vp, ctypes.c_size_t]
@@ -103,7 +105,7 @@ _lib.mpcg_last_timing.restype = _i
 _lib.mpcg_timing_report.argtypes = [_P(ctypes.c_float), _P(ctypes.c_int)]
 _lib.mpcg_timing_report.restype = _i
 
-EXPORTS = ["mp_cgemm", "mp_cgemm_ex", "mp_cgemm_acc", "mp_cgemm_batched", "mpcg_set_stream", "mpcg_set_workspace", "mpcg_workspace_size",
+EXPORTS = ["mp_cgemm", "mp_cgemm_ex", "mp_cgemm_acc", "mp_cgemm_batched", "mp_cgemm_batched_acc", "mpcg_set_stream", "mpcg_set_workspace", "mpcg_workspace_size",
            "mpcg_stream_status", "mpcg_last_error", "mpcg_enable_timing", "mpcg_last_timing",
            "mpcg_timing_report"]
 
@@ -303,6 +305,28 @@ def mp_cgemm_batched(problems, prec_bits, mode=MPCG_3M, scheme=MPCG_EXACT, cutof
     info = mpcg_info()
     _check(_lib.mp_cgemm_batched(len(problems), arr, prec_bits, mode, scheme, ctypes.byref(opt),
                                  ctypes.byref(info)))
+    return info.as_dict()
+
+
+def mp_cgemm_batched_acc_raw(count, problems, prec_bits, mode, scheme, sign, options=None, info=None) -> int:
+    return int(_lib.mp_cgemm_batched_acc(count, problems, prec_bits, mode, scheme, sign, options, info))
+
+
+def mp_cgemm_batched_acc(problems, prec_bits, sign=-1, mode=MPCG_3M, scheme=MPCG_EXACT, cutoff_override=0,
+                         ksplit_override=0, block_override=0, max_spread=0) -> dict:
+    """problems: sequence of (A, B, C) DeviceCMat triples; C := C + sign * A B
+    in place for each.  Returns the summed plan report."""
+    keep = []
+    arr = (mpcg_problem * max(1, len(problems)))()
+    for t, (A, B, C) in enumerate(problems):
+        a, b, c = A.struct(), B.struct(), C.struct()
+        keep += [a, b, c]
+        arr[t] = mpcg_problem(A.rows, B.cols, A.cols, ctypes.pointer(a), A.ld, ctypes.pointer(b), B.ld,
+                              ctypes.pointer(c), C.ld)
+    opt = mpcg_options(MPCG_SLICE_INT8, cutoff_override, ksplit_override, block_override, max_spread)
+    info = mpcg_info()
+    _check(_lib.mp_cgemm_batched_acc(len(problems), arr, prec_bits, mode, scheme, sign, ctypes.byref(opt),
+                                     ctypes.byref(info)))
     return info.as_dict()
 
 

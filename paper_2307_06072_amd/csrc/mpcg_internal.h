@@ -203,7 +203,7 @@ hipError_t launch_gemm_i8_batched(const GemmArgs* probs, const int4* items, cons
                                   int band, int mode3m, hipStream_t stream);
 
 // Round (INT8 digits): job j is problem j with 2 mt nt blocks (tile, component).
-hipError_t launch_round_batched(const RoundArgs* jobs, int njobs, const int* first, int blocks, int L,
+hipError_t launch_round_batched(const RoundArgs* jobs, int njobs, const int* first, int blocks, int L, int acc,
                                 hipStream_t stream);
 
 }  // namespace mpcg

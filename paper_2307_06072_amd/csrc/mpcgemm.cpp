@@ -586,10 +586,12 @@ struct BatchProblem {
   int spread[4];      // spreads the plan was made for (A, B, hat A, hat B)
 };
 
+// acc = 0: C_i := A_i B_i; +1 / -1: C_i := C_i +- A_i B_i in place, one rounding.
 int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, int scheme,
-                const mpcg_options* opt, mpcg_info* info) {
+                const mpcg_options* opt, mpcg_info* info, int acc = 0) {
   g_err.clear();
   if (count < 0) return set_err(MPCG_EINVAL, "negative batch count %d", count);
+  if (acc != 0 && acc != 1 && acc != -1) return set_err(MPCG_EINVAL, "accumulate sign must be +1 or -1");
   if (count > 0 && !probs) return set_err(MPCG_EINVAL, "problems is NULL");
   if (opt && opt->slice_type == MPCG_SLICE_FP64)
     return set_err(MPCG_EUNSUPPORTED, "batched products use INT8 slices");
@@ -647,8 +649,8 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
     const mpcg_problem& q = probs[i];
     if (q.m == 0 || q.n == 0) continue;
     const DOutPart cre = doutpart(q.C->re, (int64_t)q.ldc * q.n), cim = doutpart(q.C->im, (int64_t)q.ldc * q.n);
-    if (q.k == 0) {
-      HIP_TRY(launch_zero(cre, cim, q.m, q.n, q.ldc, L, g_stream));
+    if (q.k == 0) {  // A B = 0: C := 0, or C unchanged when accumulating
+      if (!acc) HIP_TRY(launch_zero(cre, cim, q.m, q.n, q.ldc, L, g_stream));
       continue;
     }
     BatchProblem b{};
@@ -786,7 +788,8 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
       if ((sa.status | sb.status) & ST_IN_RANGE)
         return set_err(MPCG_ERANGE, "problem %d: input exponent outside [-2^30, 2^30]", bp[t].idx);
       if (sa.nonzero == 0 || sb.nonzero == 0) {
-        HIP_TRY(launch_zero(bp[t].cre, bp[t].cim, bp[t].opA.R, bp[t].opB.R, probs[bp[t].idx].ldc, L, g_stream));
+        if (!acc)
+          HIP_TRY(launch_zero(bp[t].cre, bp[t].cim, bp[t].opA.R, bp[t].opB.R, probs[bp[t].idx].ldc, L, g_stream));
         continue;
       }
       if ((st = make_plan(bp[t], sa.spread, sb.spread, sa.hat, sb.hat, 1))) return st;
@@ -852,6 +855,7 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
     ra.ksplit = P.ksplit; ra.mt = P.mt; ra.nt = P.nt; ra.Dmax = P.Dmax; ra.w = P.w;
     ra.G = G; ra.H = H; ra.m = P.m; ra.n = P.n; ra.prec = prec_bits; ra.L = L;
     ra.cre = b.cre; ra.cim = b.cim; ra.ldc = probs[b.idx].ldc; ra.status = g_status;
+    ra.acc = acc;
     frd.push_back(frd.back() + P.mt * P.nt * 2);
     // work items: every 2x2 tile group of every contraction chunk
     const long long steps = band_steps(P.block, P.SAp, P.SBp, P.Dmax);
@@ -960,7 +964,7 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
                                    g_stream));
   if ((st = record(3))) return st;
   HIP_TRY(launch_round_batched(reinterpret_cast<RoundArgs*>(dev + o_ra), nl, reinterpret_cast<int*>(dev + o_frd),
-                               frd.back(), L, g_stream));
+                               frd.back(), L, acc, g_stream));
   if ((st = record(4))) return st;
   g_timing_valid = g_timing;
   return MPCG_OK;
@@ -992,6 +996,15 @@ int mp_cgemm_acc(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cm
 int mp_cgemm_batched(int count, const mpcg_problem* problems, int prec_bits, int mode, int scheme,
                      const mpcg_options* opt, mpcg_info* info) {
   return run_batched(count, problems, prec_bits, mode, scheme, opt, info);
+}
+
+int mp_cgemm_batched_acc(int count, const mpcg_problem* problems, int prec_bits, int mode, int scheme, int sign,
+                         const mpcg_options* opt, mpcg_info* info) {
+  if (sign != 1 && sign != -1) {
+    g_err.clear();
+    return set_err(MPCG_EINVAL, "accumulate sign must be +1 or -1");
+  }
+  return run_batched(count, problems, prec_bits, mode, scheme, opt, info, sign);
 }
 
 int mpcg_set_stream(void* hip_stream) {

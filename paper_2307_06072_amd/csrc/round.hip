@@ -927,10 +927,10 @@ hipError_t launch_zero(DOutPart cre, DOutPart cim, int m, int n, int64_t ldc, in
   return hipGetLastError();
 }
 
-hipError_t launch_round_batched(const RoundArgs* jobs, int njobs, const int* first, int blocks, int L,
+hipError_t launch_round_batched(const RoundArgs* jobs, int njobs, const int* first, int blocks, int L, int acc,
                                 hipStream_t stream) {
   if (njobs <= 0 || blocks <= 0) return hipSuccess;
-  const size_t lds = (size_t)256 * round_i8_window_bytes(L);
+  const size_t lds = (size_t)256 * round_i8_lds_bytes(L, acc);
   hipError_t e = hipFuncSetAttribute((const void*)round_i8_batched, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;

@@ -207,3 +207,11 @@ def test_accumulate_validation():
     Cbad.re.sign = A.im.sign + 4  # the output overlaps an input
     assert acc(Cm=Cbad) == mp.MPCG_EINVAL
     assert acc(m=0) == 0
+
+
+def test_batched_accumulate_validation():
+    import paper_2307_06072_amd as mp
+    arr = (mp.mpcg_problem * 1)()
+    assert mp.mp_cgemm_batched_acc_raw(1, arr, 256, 1, 0, 0) == mp.MPCG_EINVAL
+    assert "sign" in mp.mpcg_last_error()
+    assert mp.mp_cgemm_batched_acc_raw(0, arr, 256, 1, 0, -1) == 0  # empty batch

@@ -219,3 +219,33 @@ def test_acc_graph_replay_accumulates():
     finally:
         mp.mpcg_set_workspace(None, 0)
         mp.mpcg_set_stream()
+
+
+@pytest.mark.parametrize("mode", [M3, M4])
+def test_batched_acc_uneven(mode):
+    """The batched accumulating form: uneven problems (including empty and
+    k = 0 ones), each against the oracle's once-rounded sum."""
+    import torch
+    import paper_2307_06072_amd as mp
+    p = 190
+    shapes = [(37, 45, 71), (1, 1, 1), (16, 48, 130), (50, 3, 200), (64, 64, 64), (0, 5, 5), (9, 11, 0),
+              (40, 36, 400)]
+    batch, devs = [], []
+    for t, (m, n, k) in enumerate(shapes):
+        A = random_cmat([120, t], 0, m, k, p, 8, zero_frac=0.05)
+        B = random_cmat([120, t], 1, k, n, p, 8, zero_frac=0.05)
+        Cin = _regime_addend(130 + t, m, n, p, 8, base_shift=8) if m and n else empty_cmat(m, n, p)
+        batch.append((A, B, Cin))
+        devs.append((mp.to_device(A), mp.to_device(B), mp.to_device(Cin)))
+    mp.mpcg_set_stream()
+    mp.mp_cgemm_batched_acc(devs, p, -1, mode)
+    torch.cuda.synchronize()
+    assert mp.mpcg_stream_status() == 0
+    for t, ((A, B, Cin), (_, _, dC)) in enumerate(zip(batch, devs)):
+        m, n = A.rows, B.cols
+        if m == 0 or n == 0:
+            continue
+        got = device_result_to_host(dC, p)
+        ref = Cin if A.cols == 0 else oracle.cgemm_acc(A, B, Cin, p, -1)
+        bad, first = mismatches(got, ref, m, n)
+        assert bad == 0, (t, shapes[t], first)
