@@ -361,10 +361,12 @@ __device__ inline uint64_t rangemask(int64_t a, int64_t b) { return lowmask(b) &
 
 struct AccC {
   const uint64_t* mant;
+  const uint64_t* cw = nullptr;  // the limbs copied to LDS (low bits already dropped), if any
   int64_t ls, o, sh;  // sh: grid position of significand bit 0
   int L, drop;        // drop: bits below the precision in limb 0 (ignored)
   __device__ inline uint64_t limb(int64_t l) const {
     if (l < 0 || l >= L) return 0;
+    if (cw) return cw[l];
     uint64_t v = mant[l * ls + o];
     if (l == 0 && drop) v &= ~((1ull << drop) - 1ull);
     return v;
@@ -469,29 +471,45 @@ __device__ void round_acc_general(const Win8& st, int64_t lead_x, int64_t low_x,
   if (nx) {
     for (int w = 0; w < nx; ++w) Xw[w] = 0;
     const int64_t wlo = max(S.xw0, (int64_t)0), whi = min(S.xw0 + 64ll * nx, nbits);
-    if (wlo < whi) {
-      const int q0 = (int)(wlo / 7), q1 = (int)((whi - 1) / 7);
-      int cc = -1;
-      uint4 cv = make_uint4(0, 0, 0, 0);
-      for (int q = q0; q <= q1; ++q) {
-        if ((q >> 4) != cc) {
-          cc = q >> 4;
-          cv = *reinterpret_cast<const uint4*>(st.glob + (size_t)cc * 1024);
+    if (wlo < whi && !(st.neg && st.z < 0)) {
+      // the stored digits in binary, four at a time (bytes of 7-bit digits
+      // packed to 28 bits); digits beyond Dmax are masked off
+      const int q0 = (int)(wlo / 7) & ~3, q1 = (int)((whi - 1) / 7);
+      for (int c = q0 >> 4; c <= (q1 >> 4); ++c) {
+        const uint4 cv = *reinterpret_cast<const uint4*>(st.glob + (size_t)c * 1024);
+        const uint32_t words[4] = {cv.x, cv.y, cv.z, cv.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int qq = 16 * c + 4 * k;
+          if (qq + 3 < q0 || qq > q1) continue;
+          const uint32_t wd = words[k];
+          uint64_t v = (wd & 0x7Fu) | ((wd >> 1) & 0x3F80u) | ((wd >> 2) & 0x1FC000u) | ((wd >> 3) & 0xFE00000u);
+          const int nvalid = st.Dmax - qq + 1;
+          if (nvalid < 4) v &= lowmask(7ll * (nvalid < 0 ? 0 : nvalid));
+          if (!v) continue;
+          const int64_t bp = 7ll * qq - S.xw0;  // >= -27
+          if (bp < 0) {
+            Xw[0] |= v >> (-bp);
+          } else {
+            const int64_t w = bp >> 6;
+            const int rr = (int)(bp & 63);
+            if (w < nx) Xw[w] |= v << rr;
+            if (rr > 36 && w + 1 < nx) Xw[w + 1] |= v >> (64 - rr);
+          }
         }
-        const int b = q & 15;
-        const uint32_t wd = b < 8 ? (b < 4 ? cv.x : cv.y) : (b < 12 ? cv.z : cv.w);
-        const uint64_t raw = (wd >> (8 * (b & 3))) & 255u;
-        const int d = st.Dmax - q;
-        const uint64_t v = !st.neg ? raw : ((st.z < 0 || d > st.z) ? 0ull : (d == st.z ? 128 - raw : 127 - raw));
-        if (!v) continue;
-        const int64_t bp = 7ll * q - S.xw0;  // >= -6
-        if (bp < 0) {
-          Xw[0] |= v >> (-bp);
-        } else {
-          const int64_t w = bp >> 6;
-          const int rr = (int)(bp & 63);
-          if (w < nx) Xw[w] |= v << rr;
-          if (rr > 57 && w + 1 < nx) Xw[w + 1] |= v >> (64 - rr);
+      }
+      if (st.neg) {
+        // |X| below the top is the two's complement of the digit integer: its
+        // bits inverted, plus the +1 carried up from below its lowest set bit
+        const int64_t ra = wlo - S.xw0, rb = whi - S.xw0;
+        for (int w = 0; w < nx; ++w) Xw[w] ^= rangemask(ra - 64ll * w, rb - 64ll * w);
+        if (low_x >= wlo) {
+          uint64_t carry = 1ull << (ra & 63);
+          for (int w = (int)(ra >> 6); w < nx && carry; ++w) {
+            const uint64_t sum = Xw[w] + carry;
+            carry = sum < Xw[w] ? 1ull : 0ull;
+            Xw[w] = sum;
+          }
         }
       }
     }
@@ -700,14 +718,14 @@ __host__ __device__ inline int round_i8_window_bytes(int L) {
 }
 
 // The accumulating form also keeps, per thread, the sum over the addend's
-// range (L + 2 words) and |X| in binary around it (L + 6 words), when 256
-// threads' worth fits the LDS (p <= 2304); beyond that |X| is read from the
-// digit stream directly.
+// range (L + 2 words), |X| in binary around it (L + 6 words) and the addend's
+// limbs (L words), when 256 threads' worth fits the LDS (p <= 1280); beyond
+// that |X| and the addend are read from global memory directly.
 __host__ __device__ inline int round_i8_acc_words(int L) { return L + 6; }
 __host__ __device__ inline int round_i8_lds_bytes(int L, int acc) {
   const int wb = round_i8_window_bytes(L);
   if (!acc) return wb;
-  const int need = 16 * (((8 * ((L + 2) + round_i8_acc_words(L)) + 15) / 16) | 1);
+  const int need = 16 * (((8 * ((L + 2) + round_i8_acc_words(L) + L) + 15) / 16) | 1);
   const int b = need > wb ? need : wb;
   return 256 * b <= 160 * 1024 ? b : wb;
 }
@@ -836,7 +854,13 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
     } else {
       if (lead < C.lowest() && lead <= lead_c - (int64_t)p - 2) return;  // the sum rounds to the addend
       uint64_t* Yw = reinterpret_cast<uint64_t*>(lds);
-      const int nx = WB >= 8 * ((L + 2) + round_i8_acc_words(L)) ? round_i8_acc_words(L) : 0;
+      const int have = WB >= 8 * ((L + 2) + round_i8_acc_words(L) + L);
+      const int nx = have ? round_i8_acc_words(L) : 0;
+      if (have) {
+        uint64_t* Cw = Yw + (L + 2) + nx;
+        for (int l = 0; l < L; ++l) Cw[l] = C.limb(l);
+        C.cw = Cw;
+      }
       round_acc_general(st, lead, lowset, sx, C, sc, gbase, p, L, out, o, Yw, Yw + (L + 2), nx, a.status);
       return;
     }

@@ -249,3 +249,16 @@ def test_batched_acc_uneven(mode):
         ref = Cin if A.cols == 0 else oracle.cgemm_acc(A, B, Cin, p, -1)
         bad, first = mismatches(got, ref, m, n)
         assert bad == 0, (t, shapes[t], first)
+
+
+@pytest.mark.parametrize("sign", [1, -1])
+def test_acc_regimes_wide_precision(sign):
+    """Above 1280 bits the rounding kernel reads the product and the addend
+    from global memory directly (no binary window in LDS)."""
+    p, m, n, k = 2000, 17, 15, 24
+    A = random_cmat(210, 0, m, k, p, 6, zero_frac=0.05)
+    B = random_cmat(210, 1, k, n, p, 6, zero_frac=0.05)
+    Cin = _regime_addend(211, m, n, p, 6, base_shift=6)
+    _check(A, B, Cin, p, sign, M3)
+    Rn = oracle.cgemm(A, B, p)
+    _check(A, B, _flip_last_bit(Rn, p), p, -1)
