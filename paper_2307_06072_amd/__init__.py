@@ -36,7 +36,7 @@ MPCG_SLICE_FP64 = 1
 EXP_ZERO = np.iinfo(np.int32).min
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+    raise ImportError(f"{LIB_PATH} is missing: build it first (python paper_2307_06072_amd/build.py)")
 
 _lib = ctypes.CDLL(LIB_PATH)
 
