@@ -146,3 +146,25 @@ def test_unnormalized_input_status():
     mp.matmul(dA, dB, p, mode=M3)
     torch.cuda.synchronize()
     assert mp.mpcg_stream_status() == mp.MPCG_EDOMAIN
+
+
+def test_acc_full_size_update_sampled():
+    """The accumulating form at full size: a 2048 x 2048 x 128 update
+    C := C - A B at 1024 bits (an LU trailing update of the 2048 family's
+    precision), checked on sampled entries against the oracle."""
+    import torch
+    import paper_2307_06072_amd as mp
+    p, m, n, k = 1024, 2048, 2048, 128
+    A = random_cmat(33, 0, m, k, p, 8)
+    B = random_cmat(33, 1, k, n, p, 8)
+    Cin = random_cmat(33, 2, m, n, p, 12)
+    ri, ci = _sample(m, n, 5, 400, rows=(0, m - 1), cols=(n - 1,))
+    _say(f"acc 2048x2048x128 p=1024: oracle on {ri.size} entries")
+    s, e, mm = oracle.cgemm_acc_entries(A, B, Cin, ri, ci, p, -1)
+    dA, dB, dC = mp.to_device(A), mp.to_device(B), mp.to_device(Cin)
+    mp.mpcg_set_stream()
+    mp.mp_cgemm_acc(m, n, k, dA, m, dB, k, dC, m, p, -1, M3, EXACT)
+    torch.cuda.synchronize()
+    assert mp.mpcg_stream_status() == 0
+    from tests.gpu_util import device_result_to_host
+    _check_sampled(device_result_to_host(dC, p), ri, ci, s, e, mm, "acc 2048")
