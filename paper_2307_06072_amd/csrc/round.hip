@@ -246,66 +246,11 @@ __global__ void fill_zero_kernel(uint32_t* p, size_t n32) {
 // all issued together, and the rounding reads them there.
 
 struct Win8 {
-  const uint8_t* lds;  // digit q at lds[q - qbase]
-  int qbase;
   const uint8_t* glob; // the component's stream (digit q at glob[(q >> 4) * 1024 + (q & 15)])
   int Dmax, neg, z;    // z: lowest nonzero digit as an index d (largest d), -1 if none
   uint64_t U;
   __device__ inline uint64_t gn(int q) const { return glob[(size_t)(q >> 4) * 1024 + (q & 15)]; }
-  __device__ inline uint64_t ln(int q) const { return lds[q - qbase]; }
-  // magnitude digit q (inside the window)
-  __device__ inline uint64_t m(int q) const {
-    const int d = Dmax - q;
-    if (!neg) return ln(q);
-    if (z < 0 || d > z) return 0;
-    return d == z ? 128 - ln(q) : 127 - ln(q);
-  }
-  // magnitude digit q read from global memory (outside any window)
-  __device__ inline uint64_t mg(int q) const {
-    const int d = Dmax - q;
-    if (!neg) return gn(q);
-    if (z < 0 || d > z) return 0;
-    return d == z ? 128 - gn(q) : 127 - gn(q);
-  }
-  // bits [pos, pos + 64) of |X|, bit 0 = lowest bit of digit q = 0
-  __device__ uint64_t field(int64_t pos) const {
-    const int64_t nbits = 7ll * (Dmax + 1);
-    uint64_t r = 0;
-    const int64_t lo = pos < 0 ? 0 : pos;
-    const int64_t hi = pos + 64;
-    if (lo < nbits) {
-      const int q0 = (int)(lo / 7);
-      const int q1 = (int)min((hi - 1) / 7, (int64_t)Dmax);
-      for (int q = q0; q <= q1; ++q) {
-        const uint64_t v = m(q);
-        const int64_t sh = 7ll * q - pos;
-        if (sh >= 0) {
-          if (sh < 64) r |= v << sh;
-        } else if (-sh < 64) {
-          r |= v >> (-sh);
-        }
-      }
-    }
-    if (hi > nbits && U) {
-      const int64_t sh = nbits - pos;
-      if (sh >= 0) {
-        if (sh < 64) r |= U << sh;
-      } else if (-sh < 64) {
-        r |= U >> (-sh);
-      }
-    }
-    return r;
-  }
-  __device__ inline int bit(int64_t pos) const {
-    if (pos < 0) return 0;
-    const int64_t nbits = 7ll * (Dmax + 1);
-    if (pos >= nbits) {
-      const int64_t sh = pos - nbits;
-      return sh < 64 ? (int)((U >> sh) & 1) : 0;
-    }
-    const int q = (int)(pos / 7);
-    return (int)((m(q) >> (pos - 7ll * q)) & 1);
-  }  // bits [pos, pos + 64) of |X| read from the digit stream (any position):
+  // bits [pos, pos + 64) of |X| read from the digit stream (any position):
   // the at most 10 digits come from at most two 16-digit chunks, loaded whole
   __device__ uint64_t fieldg(int64_t pos) const {
     const int64_t nbits = 7ll * (Dmax + 1);
@@ -345,6 +290,80 @@ struct Win8 {
   }
 };
 
+__device__ inline uint64_t lowmask(int64_t n) { return n <= 0 ? 0ull : (n >= 64 ? ~0ull : ((1ull << n) - 1ull)); }
+__device__ inline uint64_t rangemask(int64_t a, int64_t b) { return lowmask(b) & ~lowmask(a); }  // bits [a, b)
+
+// Bits [xw0, xw0 + 64 nx) of |X| in binary, as the words Xw[0 .. nx).  One
+// pass over the 16-digit chunks of the stream: four 7-bit digits (one 32-bit
+// word of a chunk) are packed to 28 bits at a time and collected in a
+// two-word register window, and each word is stored once, low to high.  For
+// negative X the digit bits of the range are the two's complement of the
+// digit integer: inverted, plus the +1 carried up from below its lowest set
+// bit (low_x), which enters here when low_x lies in or above the range.  The
+// top U lies above the digits.
+__device__ void build_xwin(const Win8& st, int64_t xw0, int nx, int64_t low_x, uint64_t* Xw) {
+  const int64_t nbits = 7ll * (st.Dmax + 1);
+  const int64_t wlo = max(xw0, (int64_t)0), whi = min(xw0 + 64ll * nx, nbits);
+  const bool digits = wlo < whi && !(st.neg && st.z < 0);
+  const bool inv = digits && st.neg;
+  const int64_t ra = wlo - xw0, rb = whi - xw0;  // the digit bits within the window
+  const int wplus = inv && low_x >= wlo ? (int)(ra >> 6) : -1;
+  int w = 0;                // next word to store
+  uint64_t lo = 0, hi = 0;  // window bits [64 w, 64 w + 128)
+  uint64_t cin = 0;         // carry of the +1 into word w
+  auto flush = [&]() {
+    uint64_t v = lo;
+    if (inv) {
+      v ^= rangemask(ra - 64ll * w, rb - 64ll * w);
+      const uint64_t add = cin + (w == wplus ? 1ull << (ra & 63) : 0ull);
+      const uint64_t s = v + add;
+      cin = s < v ? 1ull : 0ull;
+      v = s;
+    }
+    Xw[w] = v;
+    lo = hi;
+    hi = 0;
+    ++w;
+  };
+  if (digits) {
+    const int q0 = (int)(wlo / 7) & ~3, q1 = (int)((whi - 1) / 7);
+    for (int c = q0 >> 4; c <= (q1 >> 4); ++c) {
+      const uint4 cv = *reinterpret_cast<const uint4*>(st.glob + (size_t)c * 1024);
+      const uint32_t words[4] = {cv.x, cv.y, cv.z, cv.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int qq = 16 * c + 4 * k;
+        if (qq + 3 < q0 || qq > q1) continue;
+        const uint32_t wd = words[k];
+        uint64_t v = (wd & 0x7Fu) | ((wd >> 1) & 0x3F80u) | ((wd >> 2) & 0x1FC000u) | ((wd >> 3) & 0xFE00000u);
+        const int nvalid = st.Dmax - qq + 1;  // digits beyond Dmax are not part of X
+        if (nvalid < 4) v &= lowmask(7ll * (nvalid < 0 ? 0 : nvalid));
+        int64_t bp = 7ll * qq - xw0;  // >= -27
+        if (bp < 0) {
+          v >>= -bp;
+          bp = 0;
+        }
+        while (bp >= 64ll * (w + 1)) flush();  // bp < 64 nx
+        const int rr = (int)(bp - 64ll * w);
+        lo |= v << rr;
+        if (rr > 36) hi |= v >> (64 - rr);
+      }
+    }
+  }
+  while (w < nx) flush();
+  if (st.U && nbits < xw0 + 64ll * nx) {  // the top above the digits
+    const int64_t bp = nbits - xw0;
+    if (bp < 0) {
+      if (-bp < 64) Xw[0] |= st.U >> (-bp);
+    } else {
+      const int64_t wu = bp >> 6;
+      const int rr = (int)(bp & 63);
+      Xw[wu] |= st.U << rr;
+      if (rr && wu + 1 < nx) Xw[wu + 1] |= st.U >> (64 - rr);
+    }
+  }
+}
+
 // ----------------------------------------------------------------------------
 // Accumulating form C := C + sgn X (X = A B on the digit grid), rounded once.
 // Positions are grid bits (bit 0 = lowest bit of digit q = 0; the value of grid
@@ -356,8 +375,6 @@ struct Win8 {
 // complemented when |C| > |X|), and above ct1 X's digits change by the carry
 // or borrow (+1 / -1) out of that range.
 // ----------------------------------------------------------------------------
-__device__ inline uint64_t lowmask(int64_t n) { return n <= 0 ? 0ull : (n >= 64 ? ~0ull : ((1ull << n) - 1ull)); }
-__device__ inline uint64_t rangemask(int64_t a, int64_t b) { return lowmask(b) & ~lowmask(a); }  // bits [a, b)
 
 struct AccC {
   const uint64_t* mant;
@@ -468,63 +485,7 @@ __device__ void round_acc_general(const Win8& st, int64_t lead_x, int64_t low_x,
   S.Xw = Xw;
   S.nx = nx;
   S.xw0 = cb - 128;
-  if (nx) {
-    for (int w = 0; w < nx; ++w) Xw[w] = 0;
-    const int64_t wlo = max(S.xw0, (int64_t)0), whi = min(S.xw0 + 64ll * nx, nbits);
-    if (wlo < whi && !(st.neg && st.z < 0)) {
-      // the stored digits in binary, four at a time (bytes of 7-bit digits
-      // packed to 28 bits); digits beyond Dmax are masked off
-      const int q0 = (int)(wlo / 7) & ~3, q1 = (int)((whi - 1) / 7);
-      for (int c = q0 >> 4; c <= (q1 >> 4); ++c) {
-        const uint4 cv = *reinterpret_cast<const uint4*>(st.glob + (size_t)c * 1024);
-        const uint32_t words[4] = {cv.x, cv.y, cv.z, cv.w};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int qq = 16 * c + 4 * k;
-          if (qq + 3 < q0 || qq > q1) continue;
-          const uint32_t wd = words[k];
-          uint64_t v = (wd & 0x7Fu) | ((wd >> 1) & 0x3F80u) | ((wd >> 2) & 0x1FC000u) | ((wd >> 3) & 0xFE00000u);
-          const int nvalid = st.Dmax - qq + 1;
-          if (nvalid < 4) v &= lowmask(7ll * (nvalid < 0 ? 0 : nvalid));
-          if (!v) continue;
-          const int64_t bp = 7ll * qq - S.xw0;  // >= -27
-          if (bp < 0) {
-            Xw[0] |= v >> (-bp);
-          } else {
-            const int64_t w = bp >> 6;
-            const int rr = (int)(bp & 63);
-            if (w < nx) Xw[w] |= v << rr;
-            if (rr > 36 && w + 1 < nx) Xw[w + 1] |= v >> (64 - rr);
-          }
-        }
-      }
-      if (st.neg) {
-        // |X| below the top is the two's complement of the digit integer: its
-        // bits inverted, plus the +1 carried up from below its lowest set bit
-        const int64_t ra = wlo - S.xw0, rb = whi - S.xw0;
-        for (int w = 0; w < nx; ++w) Xw[w] ^= rangemask(ra - 64ll * w, rb - 64ll * w);
-        if (low_x >= wlo) {
-          uint64_t carry = 1ull << (ra & 63);
-          for (int w = (int)(ra >> 6); w < nx && carry; ++w) {
-            const uint64_t sum = Xw[w] + carry;
-            carry = sum < Xw[w] ? 1ull : 0ull;
-            Xw[w] = sum;
-          }
-        }
-      }
-    }
-    if (st.U && nbits < S.xw0 + 64ll * nx) {  // the top above the digits
-      const int64_t bp = nbits - S.xw0;
-      if (bp < 0) {
-        if (-bp < 64) Xw[0] |= st.U >> (-bp);
-      } else {
-        const int64_t w = bp >> 6;
-        const int rr = (int)(bp & 63);
-        Xw[w] |= st.U << rr;
-        if (rr && w + 1 < nx) Xw[w + 1] |= st.U >> (64 - rr);
-      }
-    }
-  }
+  if (nx) build_xwin(st, S.xw0, nx, low_x, Xw);
   int s_out;
   if (sc == sx) {  // |X| + |C|
     uint64_t carry = 0;
@@ -707,13 +668,12 @@ __device__ void round_acc_general(const Win8& st, int64_t lead_x, int64_t low_x,
   out.exp[o] = (int32_t)e_out;
 }
 
-// bytes of LDS per thread for L limbs: the window spans at most
-// ceil(64 L / 7) + 3 digits, copied as whole 16-digit chunks
-// (an odd number of 16-byte units, so that the 64 lanes' windows start in
-// 16 different bank groups instead of 4)
+// bytes of LDS per thread for L limbs: |X| in binary over the significand
+// and one word below it (L + 1 words), or the accumulating form's sum over
+// the addend's range (L + 2 words), in an odd number of 16-byte units so that
+// the 64 lanes' areas start in 16 different bank groups instead of 4
 __host__ __device__ inline int round_i8_window_bytes(int L) {
-  const int digits = (64 * L + 6) / 7 + 3;
-  const int units = (digits + 15) / 16 + 1;
+  const int units = (8 * (L + 2) + 15) / 16;
   return 16 * (units | 1);
 }
 
@@ -811,17 +771,22 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
   st.z = z;
   st.U = !st.neg ? (uint64_t)T : (z < 0 ? (uint64_t)(-T) : (uint64_t)(-T - 1));
   const int64_t nbits = 7ll * (Dmax + 1);
-  // leading bit of |X|
-  int64_t lead;
+  // leading bit of |X|: in the top, else in the highest nonzero magnitude
+  // digit, found a 16-digit chunk (one load) at a time
+  int64_t lead = -1;
   if (st.U) {
     lead = nbits + 63 - __builtin_clzll(st.U);
   } else {
-    lead = -1;
-    for (int q = Dmax; q >= 0; --q) {
-      const uint64_t v = st.mg(q);
-      if (v) {
-        lead = 7ll * q + 63 - __builtin_clzll(v);
-        break;
+    for (int c = Dmax >> 4; c >= 0 && lead < 0; --c) {
+      const uint4 cv = *reinterpret_cast<const uint4*>(g0 + (size_t)c * 1024);
+      const uint32_t words[4] = {cv.x, cv.y, cv.z, cv.w};
+#pragma unroll
+      for (int b = 15; b >= 0; --b) {
+        const int q = 16 * c + b;
+        const uint64_t raw = (words[b >> 2] >> (8 * (b & 3))) & 255u;
+        const int d = Dmax - q;
+        const uint64_t v = q > Dmax ? 0ull : !st.neg ? raw : ((z < 0 || d > z) ? 0ull : (d == z ? 128 - raw : 127 - raw));
+        if (lead < 0 && v) lead = 7ll * q + 63 - __builtin_clzll(v);
       }
     }
   }
@@ -832,10 +797,6 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
   else
     lowset = nbits + __builtin_ctzll((uint64_t)T);
 
-  // the digits that limbs and rounding read: from the rounding bit or the
-  // lowest bit of limb 0, whichever is lower (the rounding bit lies one below
-  // limb 0 when p = 64 L), to the leading bit (above it the magnitude digits
-  // are zero)
   const int64_t gbase = (int64_t)a.G[i] + (int64_t)a.H[j] - 7ll * (Dmax + 2);
   const int sx = st.neg ^ negp;  // sign of the product term
   int tie = -1;                   // >= 0: a negligible addend breaks the tie
@@ -865,21 +826,24 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
       return;
     }
   }
+  // |X| in binary from 64 bits below the significand's lowest limb bit (off)
+  // up to its leading bit: limb l is word l + 1, and the rounding bit lies in
+  // word 0 or above
   const int64_t off = lead + 1 - 64ll * L;
-  const int64_t lowest = min(off, lead - (int64_t)p);
-  const int qlo = lowest <= 0 ? 0 : (int)(lowest / 7);
-  const int qhi = (int)min(lead / 7, (int64_t)Dmax);
-  st.qbase = (qlo >> 4) << 4;
-  st.lds = lds;
-  for (int ch = qlo >> 4; ch <= (qhi >> 4) && qhi >= 0; ++ch)
-    *reinterpret_cast<uint4*>(lds + (ch * 16 - st.qbase)) = *reinterpret_cast<const uint4*>(g0 + (size_t)ch * 1024);
+  const int64_t xw0 = off - 64;
+  uint64_t* Xw = reinterpret_cast<uint64_t*>(lds);
+  build_xwin(st, xw0, L + 1, lowset, Xw);
+  auto xbit = [&](int64_t pos) -> int {
+    const int64_t r = pos - xw0;
+    return (int)((Xw[r >> 6] >> (r & 63)) & 1ull);
+  };
 
   const int64_t low = lead - p + 1;  // lowest kept bit of |X|
   int round_up = 0;
   if (low > 0) {
-    const int rbit = st.bit(low - 1);
+    const int rbit = xbit(low - 1);
     const int sticky = lowset < low - 1;
-    const int lsb = st.bit(low);
+    const int lsb = xbit(low);
     round_up = rbit && (sticky || (tie < 0 ? lsb : tie));
   }
   const int keep_from = 64 * L - p;  // 0..63
@@ -887,7 +851,7 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
   int64_t e_out = lead + 1 + gbase;
   uint64_t limbs_hi = 0;
   for (int l = 0; l < L; ++l) {
-    uint64_t f = st.field(off + 64ll * l);
+    uint64_t f = Xw[l + 1];
     if (l == 0 && keep_from) f &= ~((1ull << keep_from) - 1ull);
     const uint64_t sum = f + carry;
     carry = (sum < f) ? 1 : 0;
