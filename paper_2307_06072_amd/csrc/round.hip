@@ -378,12 +378,10 @@ __device__ void build_xwin(const Win8& st, int64_t xw0, int nx, int64_t low_x, u
 
 struct AccC {
   const uint64_t* mant;
-  const uint64_t* cw = nullptr;  // the limbs copied to LDS (low bits already dropped), if any
   int64_t ls, o, sh;  // sh: grid position of significand bit 0
   int L, drop;        // drop: bits below the precision in limb 0 (ignored)
   __device__ inline uint64_t limb(int64_t l) const {
     if (l < 0 || l >= L) return 0;
-    if (cw) return cw[l];
     uint64_t v = mant[l * ls + o];
     if (l == 0 && drop) v &= ~((1ull << drop) - 1ull);
     return v;
@@ -678,14 +676,15 @@ __host__ __device__ inline int round_i8_window_bytes(int L) {
 }
 
 // The accumulating form also keeps, per thread, the sum over the addend's
-// range (L + 2 words), |X| in binary around it (L + 6 words) and the addend's
-// limbs (L words), when 256 threads' worth fits the LDS (p <= 1280); beyond
-// that |X| and the addend are read from global memory directly.
-__host__ __device__ inline int round_i8_acc_words(int L) { return L + 6; }
+// range (L + 2 words) and |X| in binary from two words below the addend's
+// lowest bit (L + 4 words), when 256 threads' worth fits the LDS (p <= 2304);
+// beyond that |X| is read from global memory directly.  Bits of |X| outside
+// the window, and the addend's limbs, are always read from global memory.
+__host__ __device__ inline int round_i8_acc_words(int L) { return L + 4; }
 __host__ __device__ inline int round_i8_lds_bytes(int L, int acc) {
   const int wb = round_i8_window_bytes(L);
   if (!acc) return wb;
-  const int need = 16 * (((8 * ((L + 2) + round_i8_acc_words(L) + L) + 15) / 16) | 1);
+  const int need = 16 * (((8 * ((L + 2) + round_i8_acc_words(L)) + 15) / 16) | 1);
   const int b = need > wb ? need : wb;
   return 256 * b <= 160 * 1024 ? b : wb;
 }
@@ -815,12 +814,10 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
     } else {
       if (lead < C.lowest() && lead <= lead_c - (int64_t)p - 2) return;  // the sum rounds to the addend
       uint64_t* Yw = reinterpret_cast<uint64_t*>(lds);
-      const int have = WB >= 8 * ((L + 2) + round_i8_acc_words(L) + L);
+      const int have = WB >= 8 * ((L + 2) + round_i8_acc_words(L));
       const int nx = have ? round_i8_acc_words(L) : 0;
       if (have) {
-        uint64_t* Cw = Yw + (L + 2) + nx;
-        for (int l = 0; l < L; ++l) Cw[l] = C.limb(l);
-        C.cw = Cw;
+
       }
       round_acc_general(st, lead, lowset, sx, C, sc, gbase, p, L, out, o, Yw, Yw + (L + 2), nx, a.status);
       return;

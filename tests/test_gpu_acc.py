@@ -251,11 +251,13 @@ def test_batched_acc_uneven(mode):
         assert bad == 0, (t, shapes[t], first)
 
 
+@pytest.mark.parametrize("p", [2000, 2600])
 @pytest.mark.parametrize("sign", [1, -1])
-def test_acc_regimes_wide_precision(sign):
-    """Above 1280 bits the rounding kernel reads the product and the addend
-    from global memory directly (no binary window in LDS)."""
-    p, m, n, k = 2000, 17, 15, 24
+def test_acc_regimes_wide_precision(sign, p):
+    """Up to 2304 bits the rounding kernel keeps |X| around the addend's range
+    in LDS; above that (2600 bits) it reads the product from global memory
+    directly (no binary window)."""
+    m, n, k = 17, 15, 24
     A = random_cmat(210, 0, m, k, p, 6, zero_frac=0.05)
     B = random_cmat(210, 1, k, n, p, 6, zero_frac=0.05)
     Cin = _regime_addend(211, m, n, p, 6, base_shift=6)
