@@ -815,8 +815,10 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
   std::vector<int> frd(1, 0);
   const Third thirdA = mode == MPCG_3M ? Third::SUM : Third::NONE;
   const Third thirdB = mode == MPCG_3M ? Third::SUM : Third::NEG_IM;
-  struct Item { long long cost; int4 it; int band; };
-  std::vector<Item> items;
+  // work items come in groups of equal cost: the 2 x 2 tile groups of one
+  // contraction chunk of one problem
+  struct Group { long long cost; int band, t, sp, gm, gn; };
+  std::vector<Group> groups;
   for (int t = 0; t < nl; ++t) {
     BatchProblem& b = bp[t];
     const Plan& P = b.P;
@@ -865,8 +867,7 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
     for (int sp = 0; sp < P.ksplit; ++sp) {
       const int kb = std::min(P.kblocks, (sp + 1) * kbps) - sp * kbps;
       const long long cost = steps * passes * kb * (P.mode3m ? 1 : 2) * P.block + 64;
-      for (int gj = 0; gj < gn; ++gj)
-        for (int gi = 0; gi < gm; ++gi) items.push_back(Item{cost, make_int4(t, gi, gj, sp), P.block});
+      groups.push_back(Group{cost, P.block, t, sp, gm, gn});
     }
     if (info) {
       info->S_A = std::max(info->S_A, P.SA); info->S_B = std::max(info->S_B, P.SB); info->w = P.w;
@@ -876,35 +877,53 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
       info->bound_bits = P.bound_bits;
     }
   }
-  // longest processing time first onto one workgroup per compute unit, per band class
-  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
+  // longest processing time first onto one workgroup per compute unit, per
+  // band class (sorting the groups orders their items the same way)
+  std::stable_sort(groups.begin(), groups.end(), [](const Group& a, const Group& b) {
     return a.band != b.band ? a.band > b.band : a.cost > b.cost;
   });
   struct Launch { int band, blocks; size_t o_items, o_first; };
   std::vector<Launch> launches;
   std::vector<std::vector<int4>> litems;
   std::vector<std::vector<int>> lfirst;
-  for (size_t a = 0; a < items.size();) {
+  for (size_t a = 0; a < groups.size();) {
     size_t e = a;
-    while (e < items.size() && items[e].band == items[a].band) ++e;
-    const int nitems = (int)(e - a);
-    const int nbins = std::max(1, std::min(nitems, g_num_cu));
+    long long nitems = 0;
+    while (e < groups.size() && groups[e].band == groups[a].band) {
+      nitems += (long long)groups[e].gm * groups[e].gn;
+      ++e;
+    }
+    const int nbins = (int)std::max(1ll, std::min(nitems, (long long)g_num_cu));
+    // each item goes to the least loaded bin (lowest index on ties): a binary
+    // min-heap of (load, bin), whose top is replaced and sifted down once per
+    // item (all loads 0 with ascending bins is already a heap)
+    struct LB { long long load; int bin; };
+    auto lt = [](const LB& x, const LB& y) { return x.load != y.load ? x.load < y.load : x.bin < y.bin; };
+    std::vector<LB> heap(nbins);
+    for (int i = 0; i < nbins; ++i) heap[i] = LB{0, i};
+    std::vector<std::vector<int4>> bins(nbins);
+    for (auto& v : bins) v.reserve((size_t)(nitems / nbins) + 8);
+    for (size_t g = a; g < e; ++g) {
+      const Group& gr = groups[g];
+      for (int gj = 0; gj < gr.gn; ++gj)
+        for (int gi = 0; gi < gr.gm; ++gi) {
+          LB top = heap[0];
+          bins[top.bin].push_back(make_int4(gr.t, gi, gj, gr.sp));
+          top.load += gr.cost;
+          int i = 0;
+          for (;;) {
+            int c = 2 * i + 1;
+            if (c >= nbins) break;
+            if (c + 1 < nbins && lt(heap[c + 1], heap[c])) ++c;
+            if (!lt(heap[c], top)) break;
+            heap[i] = heap[c];
+            i = c;
+          }
+          heap[i] = top;
+        }
+    }
     // bins in XCD-major order: bin i -> block (i % per) * 8 + i / per, so that
     // equally loaded bins fill one XCD before the next
-    std::vector<long long> load(nbins, 0);
-    std::vector<std::vector<int4>> bins(nbins);
-    typedef std::pair<long long, int> LB;
-    std::vector<LB> heap;
-    for (int i = 0; i < nbins; ++i) heap.push_back(LB(0, i));
-    auto cmp = [](const LB& x, const LB& y) { return x.first != y.first ? x.first > y.first : x.second > y.second; };
-    std::make_heap(heap.begin(), heap.end(), cmp);
-    for (size_t i = a; i < e; ++i) {
-      std::pop_heap(heap.begin(), heap.end(), cmp);
-      LB& top = heap.back();
-      bins[top.second].push_back(items[i].it);
-      top.first += items[i].cost;
-      std::push_heap(heap.begin(), heap.end(), cmp);
-    }
     const int per = ceil_div(nbins, 8);
     std::vector<int> block_of(nbins);
     {
@@ -928,7 +947,7 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
       flat.insert(flat.end(), by_block[bk].begin(), by_block[bk].end());
       first.push_back((int)flat.size());
     }
-    launches.push_back(Launch{items[a].band, nbins, 0, 0});
+    launches.push_back(Launch{groups[a].band, nbins, 0, 0});
     litems.push_back(std::move(flat));
     lfirst.push_back(std::move(first));
     a = e;
