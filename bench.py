@@ -276,6 +276,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration)")
+    ap.add_argument("--family", choices=["batched", "lu"], default=None,
+                    help="only run one comparison family (for profiling) and print its record")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -298,6 +300,10 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 3}))
+        return 0
+    if args.family:
+        rec = batched_case() if args.family == "batched" else lu_update_stream()
+        print(json.dumps({"family": args.family, **rec}), flush=True)
         return 0
     log(f"generating {args.workload}")
     m, n, k, p, A, B = workload_inputs(args.workload)
