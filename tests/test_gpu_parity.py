@@ -74,6 +74,16 @@ def test_precisions(p):
     _check_exact(A, B, p, M4)
 
 
+@pytest.mark.parametrize("p", [2047, 3000, 4096])
+def test_wide_precisions(p):
+    """Up to the largest supported precision (4096 bits, 64 limbs): the
+    rounding kernel's binary window of |X| then spans 65 words per thread."""
+    A = random_cmat(p, 0, 9, 14, p, 6, zero_frac=0.05)
+    B = random_cmat(p, 1, 14, 11, p, 6, zero_frac=0.05)
+    _check_exact(A, B, p, M3)
+    _check_exact(A, B, p, M4)
+
+
 def test_wide_exponent_spread():
     p = 96
     A = random_cmat(21, 0, 24, 40, p, 70)
