@@ -301,7 +301,7 @@ __device__ inline uint64_t rangemask(int64_t a, int64_t b) { return lowmask(b) &
 // digit integer: inverted, plus the +1 carried up from below its lowest set
 // bit (low_x), which enters here when low_x lies in or above the range.  The
 // top U lies above the digits.
-__device__ void build_xwin(const Win8& st, int64_t xw0, int nx, int64_t low_x, uint64_t* Xw) {
+__device__ __attribute__((always_inline)) inline void build_xwin(const Win8 st, int64_t xw0, int nx, int64_t low_x, uint64_t* Xw) {
   const int64_t nbits = 7ll * (st.Dmax + 1);
   const int64_t wlo = max(xw0, (int64_t)0), whi = min(xw0 + 64ll * nx, nbits);
   const bool digits = wlo < whi && !(st.neg && st.z < 0);
@@ -464,7 +464,7 @@ struct AccSum {
 };
 
 // The general case: writes the rounded sum (sign, exponent, limbs) of entry o.
-__device__ void round_acc_general(const Win8& st, int64_t lead_x, int64_t low_x, int sx, const AccC& C, int sc,
+__device__ __attribute__((always_inline)) inline void round_acc_general(const Win8& st, int64_t lead_x, int64_t low_x, int sx, const AccC& C, int sc,
                                   int64_t gbase, int p, int L, DOutPart out, int64_t o, uint64_t* Y, uint64_t* Xw,
                                   int nx, int* status) {
   const int64_t nbits = 7ll * (st.Dmax + 1);
@@ -666,6 +666,113 @@ __device__ void round_acc_general(const Win8& st, int64_t lead_x, int64_t low_x,
   out.exp[o] = (int32_t)e_out;
 }
 
+// The common general case in one pass.  |X| is built in binary over a window
+// anchored at the addend's leading bit: L + 3 words, from 64 L + 126 bits
+// below lead_C to 65 bits above it, so the addend's significand (its bit 0
+// at window bit 127) lies wholly inside.  The addend is added or subtracted
+// across the whole window; X's bits below the window only borrow one unit
+// (when |C| > |X|) and set the sticky bit.  The sum is rounded from the
+// window.  Returns false, having written nothing, when X reaches above the
+// window or cancellation leaves the rounding bit or the lowest limb below
+// it; the caller then takes the general path.  Sw: 2 (L + 3) words of this
+// thread's LDS (the window, then the addend's aligned words).
+__device__ __attribute__((always_inline)) inline bool round_acc_window(const Win8& st, int64_t lead_x, int64_t low_x, int sx, const AccC& C, int sc,
+                                 int64_t gbase, int p, int L, DOutPart out, int64_t o, uint64_t* Sw, int* status) {
+  const int64_t lead_c = 64ll * L - 1 + C.sh;
+  if (lead_x > lead_c + 64) return false;
+  const int nx = L + 3;
+  const int64_t xw0 = lead_c + 66 - 64ll * nx;
+  uint64_t* Cw = Sw + nx;
+  build_xwin(st, xw0, nx, low_x, Sw);
+  for (int w = 0; w < nx; ++w) Cw[w] = C.field(xw0 + 64ll * w);
+  const int tail = low_x < xw0;  // X has set bits below the window
+  int s_out;
+  if (sc == sx) {  // |X| + |C| < 2^(lead_c + 66): no carry out of the window
+    uint64_t carry = 0;
+    for (int w = 0; w < nx; ++w) {
+      const uint64_t a = Sw[w], b = Cw[w];
+      const uint64_t s1 = a + b, c1 = s1 < a;
+      const uint64_t s2 = s1 + carry, c2 = s2 < s1;
+      Sw[w] = s2;
+      carry = c1 | c2;
+    }
+    s_out = sx;
+  } else {
+    int cmp = 0;  // sign of (|X| in the window) - |C|
+    for (int w = nx - 1; w >= 0 && !cmp; --w)
+      if (Sw[w] != Cw[w]) cmp = Sw[w] > Cw[w] ? 1 : -1;
+    if (cmp == 0) {
+      if (tail) return false;  // only X's bits below the window remain
+      out.sign[o] = 0;         // exact cancellation -> +0
+      out.exp[o] = EXP_ZERO;
+      for (int l = 0; l < L; ++l) out.mant[(int64_t)l * out.ls + o] = 0;
+      return true;
+    }
+    const int xbig = cmp > 0;
+    uint64_t borrow = xbig ? 0ull : (uint64_t)tail;
+    for (int w = 0; w < nx; ++w) {
+      const uint64_t u = xbig ? Sw[w] : Cw[w], v = xbig ? Cw[w] : Sw[w];
+      const uint64_t t = u - v, b1 = u < v;
+      const uint64_t d = t - borrow, b2 = t < borrow;
+      Sw[w] = d;
+      borrow = b1 | b2;
+    }
+    s_out = xbig ? sx : sc;
+  }
+  int64_t lead = -1;
+  for (int w = nx - 1; w >= 0; --w)
+    if (Sw[w]) {
+      lead = xw0 + 64ll * w + 63 - __builtin_clzll(Sw[w]);
+      break;
+    }
+  if (lead < 0) return false;
+  const int64_t low = lead - p + 1;         // lowest kept bit
+  const int64_t off = lead + 1 - 64ll * L;  // lowest bit of limb 0
+  if (min(off, low - 1) < xw0) return false;
+  auto sbit = [&](int64_t pos) -> int {
+    const int64_t r = pos - xw0;
+    return (int)((Sw[r >> 6] >> (r & 63)) & 1ull);
+  };
+  const int rbit = sbit(low - 1), lsb = sbit(low);
+  int sticky = tail;
+  {
+    const int64_t r = low - 1 - xw0;  // bits of the window below the rounding bit
+    const int wr = (int)(r >> 6);
+    for (int w = 0; w < wr && !sticky; ++w) sticky = Sw[w] != 0;
+    if (!sticky) sticky = (Sw[wr] & lowmask(r & 63)) != 0;
+  }
+  const int round_up = rbit && (sticky || lsb);
+  const int keep_from = 64 * L - p;
+  uint64_t carry = round_up ? (1ull << keep_from) : 0;
+  int64_t e_out = lead + 1 + gbase;
+  uint64_t limbs_hi = 0;
+  for (int l = 0; l < L; ++l) {
+    const int64_t r = off + 64ll * l - xw0;  // r + 64 <= 64 nx
+    const int w = (int)(r >> 6), sh = (int)(r & 63);
+    uint64_t f = sh ? (Sw[w] >> sh) | (Sw[w + 1] << (64 - sh)) : Sw[w];
+    if (l == 0 && keep_from) f &= ~((1ull << keep_from) - 1ull);
+    const uint64_t sum = f + carry;
+    carry = (sum < f) ? 1 : 0;
+    limbs_hi = sum;
+    if (l < L - 1) out.mant[(int64_t)l * out.ls + o] = sum;
+  }
+  if (carry) {
+    limbs_hi = 1ull << 63;
+    e_out += 1;
+  }
+  if (e_out > INT32_MAX || e_out <= (int64_t)INT32_MIN) {
+    atomicOr(status, ST_OUT_RANGE);
+    out.sign[o] = 0;
+    out.exp[o] = EXP_ZERO;
+    for (int l = 0; l < L; ++l) out.mant[(int64_t)l * out.ls + o] = 0;
+    return true;
+  }
+  out.mant[(int64_t)(L - 1) * out.ls + o] = limbs_hi;
+  out.sign[o] = (uint8_t)s_out;
+  out.exp[o] = (int32_t)e_out;
+  return true;
+}
+
 // bytes of LDS per thread for L limbs: |X| in binary over the significand
 // and one word below it (L + 1 words), or the accumulating form's sum over
 // the addend's range (L + 2 words), in an odd number of 16-byte units so that
@@ -814,11 +921,10 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
     } else {
       if (lead < C.lowest() && lead <= lead_c - (int64_t)p - 2) return;  // the sum rounds to the addend
       uint64_t* Yw = reinterpret_cast<uint64_t*>(lds);
+      if (WB >= 16 * (L + 3) && round_acc_window(st, lead, lowset, sx, C, sc, gbase, p, L, out, o, Yw, a.status))
+        return;
       const int have = WB >= 8 * ((L + 2) + round_i8_acc_words(L));
       const int nx = have ? round_i8_acc_words(L) : 0;
-      if (have) {
-
-      }
       round_acc_general(st, lead, lowset, sx, C, sc, gbase, p, L, out, o, Yw, Yw + (L + 2), nx, a.status);
       return;
     }
