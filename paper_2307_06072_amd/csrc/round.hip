@@ -240,10 +240,10 @@ __global__ void fill_zero_kernel(uint32_t* p, size_t n32) {
 // own 16-byte words ([slot][chunk][lane][16], 1 KB per chunk and slot), so a
 // thread reads its digits 16 at a time.  A block is one (tile, component):
 // 256 threads, thread t holds element (ii, jj) = (t % 16, t / 16), so the
-// stores of a wavefront cover 16 consecutive rows of 4 columns.  The digits
-// the p-bit result can depend on (from the lowest bit of limb 0 up to the
-// leading bit) are copied into the thread's part of LDS with 16-byte loads,
-// all issued together, and the rounding reads them there.
+// stores of a wavefront cover 16 consecutive rows of 4 columns.  The bits
+// the p-bit result depends on (one word below the lowest bit of limb 0 up to
+// the leading bit) are packed from the digits into binary 64-bit words in the
+// thread's part of LDS, and the limbs, round bit and tie bit are read there.
 
 struct Win8 {
   const uint8_t* glob; // the component's stream (digit q at glob[(q >> 4) * 1024 + (q & 15)])
