@@ -88,6 +88,32 @@ def test_acc_regimes(p, mode, sign):
     _check(A, B, Cin, p, sign, mode)
 
 
+@pytest.mark.parametrize("sign", [1, -1])
+@pytest.mark.parametrize("mode", [M3, M4])
+def test_acc_window_limits(mode, sign):
+    """Exact two-bit products X_i = 2^100 + 2^-e_i (A row i = [1, 2^-e_i],
+    B = [2^100, 1]^T, imaginary parts zero) against addends that step across
+    the limits of the one-pass accumulating form: C's leading bit moves from
+    145 bits below X's to above it (X reaching more than 64 bits above C is
+    left to the general case), and C = -2^100 with the small term moving down
+    until the cancelled sum's rounding bit falls below the window."""
+    from fractions import Fraction
+    from tests.mp_util import cmat_from_values
+    p = 128
+    cases = []
+    for sh in range(-145, 6):
+        c = Fraction(2) ** (100 + sh) * (1 + Fraction(1, 128))
+        cases.append((50, c if sh % 2 else -c))
+    for e in range(0, 90, 3):
+        cases.append((e, -Fraction(2) ** 100))
+    m = len(cases)
+    A = cmat_from_values([[1, Fraction(1, 2 ** e)] for e, _ in cases], [[0, 0] for _ in cases], p)
+    B = cmat_from_values([[2 ** 100], [1]], [[0], [0]], p)
+    Cin = cmat_from_values([[c] for _, c in cases], [[0] for _ in cases], p)
+    assert m == A.rows
+    _check(A, B, Cin, p, sign, mode)
+
+
 @pytest.mark.parametrize("p", [64, 200, 1024])
 def test_acc_cancellation(p):
     """Cin = RNE(AB): C - AB is the rounding error of each entry, far below both
