@@ -41,6 +41,16 @@
  * ERRORS: functions return MPCG_OK (0) or a negative code.  Argument errors
  * are detected on the host before any device work is issued.  The text of the
  * last error of the calling thread is returned by mpcg_last_error().
+ *
+ * THREADS AND DEVICES: the stream, the workspace (library-owned or set by
+ * mpcg_set_workspace) and the host staging buffers are per process and shared
+ * by all threads.  The library's own device buffers are allocated on the
+ * device current at its first allocation, so every call must be made with
+ * that device current (one GPU per process).  Calls from several threads are
+ * safe:
+ * an internal lock serializes them (they do not issue work concurrently), and
+ * a thread's mpcg_set_stream changes the stream for every thread.  Work
+ * issued by two calls on one stream shares the workspace in stream order.
  */
 #ifndef MPCGEMM_H
 #define MPCGEMM_H
