@@ -47,10 +47,10 @@
  * by all threads.  The library's own device buffers are allocated on the
  * device current at its first allocation, so every call must be made with
  * that device current (one GPU per process).  Calls from several threads are
- * safe:
- * an internal lock serializes them (they do not issue work concurrently), and
- * a thread's mpcg_set_stream changes the stream for every thread.  Work
- * issued by two calls on one stream shares the workspace in stream order.
+ * safe: an internal lock serializes them (they do not issue work
+ * concurrently), and a thread's mpcg_set_stream changes the stream for every
+ * thread.  Work issued by two calls on one stream shares the workspace in
+ * stream order.
  */
 #ifndef MPCGEMM_H
 #define MPCGEMM_H
