@@ -49,8 +49,11 @@
  * that device current (one GPU per process).  Calls from several threads are
  * safe: an internal lock serializes them (they do not issue work
  * concurrently), and a thread's mpcg_set_stream changes the stream for every
- * thread.  Work issued by two calls on one stream shares the workspace in
- * stream order.
+ * thread.  Calls on one stream use the workspace in stream order; before
+ * switching to another stream while earlier calls may still be running, the
+ * caller orders the new stream after the old one (for example an event
+ * recorded on the old stream and waited on by the new), since both streams'
+ * calls use the same workspace.
  */
 #ifndef MPCGEMM_H
 #define MPCGEMM_H
@@ -216,7 +219,9 @@ int mp_cgemm_batched(int count, const mpcg_problem *problems, int prec_bits, int
 int mp_cgemm_batched_acc(int count, const mpcg_problem *problems, int prec_bits, int mode, int scheme, int sign,
                          const mpcg_options *opt, mpcg_info *info);
 
-/* Issue subsequent work on this HIP stream (hipStream_t as void*; NULL = null stream). */
+/* Issue subsequent work on this HIP stream (hipStream_t as void*; NULL = null
+ * stream).  The setting is per process.  It does not order the new stream
+ * after work still running on the old one; the caller does (see THREADS). */
 int mpcg_set_stream(void *hip_stream);
 
 /*
