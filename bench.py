@@ -189,6 +189,43 @@ def batched_case():
                                 "pairs_total": info["pairs"], "block": info["block"]}}
 
 
+def codec_case():
+    """Multi-component inputs: a 2048 x 2048 complex matrix given as
+    quad-double components (four doubles per real component, a normalised
+    expansion), converted to 256 bits by mpcg_from_doubles (HBM-bound: 64 B of
+    doubles in and 74 B of the number format out per complex entry)."""
+    import torch
+    import paper_2307_06072_amd as mp
+    from mpgen import multi_double
+    log("codec: 2048 x 2048 quad-double -> 256 bits")
+    rows = cols = 2048
+    p, nc = 256, 4
+    re = torch.from_numpy(multi_double(7, 0, nc, rows, cols, "expansion", 60)).cuda()
+    im = torch.from_numpy(multi_double(7, 1, nc, rows, cols, "expansion", 60)).cuda()
+    mp.mpcg_set_stream()
+    C = mp.from_doubles(re, im, p)
+    torch.cuda.synchronize()
+
+    def issue():
+        for t, part in ((re, C.re), (im, C.im)):
+            mp._check(mp.mpcg_from_doubles(rows, cols, nc, t.data_ptr(), rows, rows * cols, part, C.ld, p))
+    issue()
+    reps = 10
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        issue()
+    e1.record()
+    torch.cuda.synchronize()
+    if mp.mpcg_stream_status() != 0:
+        raise RuntimeError(mp.mpcg_last_error())
+    ms = e0.elapsed_time(e1) / reps
+    L = (p + 63) // 64
+    nbytes = rows * cols * 2 * (nc * 8 + 1 + 4 + 8 * L)
+    return {"codec_qd2048_p256": {"ms_per_call": ms, "entries_per_s": rows * cols / (ms * 1e-3),
+                                  "algorithmic_GBps": nbytes / (ms * 1e-3) / 1e9, "hbm_peak_GBps": PEAK_HBM_GBS}}
+
+
 def lu_update_stream():
     """The 31 trailing updates of a blocked LU of order 4096 with block 128
     (A22 := A22 - L21 U12, r x 128 times 128 x r, r = 3968 ... 128) at 256
@@ -276,7 +313,7 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration)")
-    ap.add_argument("--family", choices=["batched", "lu"], default=None,
+    ap.add_argument("--family", choices=["batched", "lu", "codec"], default=None,
                     help="only run one comparison family (for profiling) and print its record")
     args = ap.parse_args()
 
@@ -302,7 +339,7 @@ def main() -> int:
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 3}))
         return 0
     if args.family:
-        rec = batched_case() if args.family == "batched" else lu_update_stream()
+        rec = {"batched": batched_case, "lu": lu_update_stream, "codec": codec_case}[args.family]()
         print(json.dumps({"family": args.family, **rec}), flush=True)
         return 0
     log(f"generating {args.workload}")
@@ -372,6 +409,7 @@ def main() -> int:
         extra.update(small_latency_case())
         extra.update(batched_case())
         extra.update(lu_update_stream())
+        extra.update(codec_case())
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -76,7 +76,8 @@ enum {
     MPCG_ERANGE = -3,      /* input exponent outside [-2^30, 2^30] or output exponent overflow */
     MPCG_EHIP = -4,        /* HIP runtime error (text in mpcg_last_error) */
     MPCG_EUNSUPPORTED = -5,/* valid request this build cannot serve */
-    MPCG_EDOMAIN = -6,     /* nonzero input whose significand top bit is clear */
+    MPCG_EDOMAIN = -6,     /* nonzero input whose significand top bit is clear; an infinite or NaN
+                              double given to mpcg_from_doubles */
     MPCG_ESPREAD = -7      /* an operand's exponent spread exceeded mpcg_options.max_spread */
 };
 
@@ -218,6 +219,28 @@ int mp_cgemm_batched(int count, const mpcg_problem *problems, int prec_bits, int
  */
 int mp_cgemm_batched_acc(int count, const mpcg_problem *problems, int prec_bits, int mode, int scheme, int sign,
                          const mpcg_options *opt, mpcg_info *info);
+
+/*
+ * Multi-component fixed-precision inputs (double-double, triple-double,
+ * quad-double), the multi-component arithmetic the paper's concluding section
+ * names for future work: converts them into the number format above, so that
+ * they feed mp_cgemm unchanged.
+ *
+ * One real component (call once for Re and once for Im) of a rows x cols
+ * column-major matrix whose entry (r, c) is the exact sum of ncomp doubles
+ * (1 <= ncomp <= 4): component i at src[i * plane + c * ld + r], device
+ * memory, plane >= ld * cols (0 means exactly ld * cols).  Each sum is formed
+ * exactly (any finite doubles, subnormals included, any gaps between them)
+ * and rounded once to prec_bits, to nearest with ties to even, into dst
+ * (device arrays, leading dimension ldd, the layout of an mpcg_part); an
+ * exactly zero sum is written as +0.  Host-side validation as for mp_cgemm
+ * (MPCG_EINVAL for a bad dimension, ncomp, precision, NULL pointer or dst
+ * overlapping src).  An infinite or NaN component writes +0 and is reported
+ * as MPCG_EDOMAIN by mpcg_stream_status.  Asynchronous on the library's
+ * stream; allocates nothing after the first call of the process.
+ */
+int mpcg_from_doubles(int rows, int cols, int ncomp, const double *src, int ld, long long plane, mpcg_part *dst,
+                      int ldd, int prec_bits);
 
 /* Issue subsequent work on this HIP stream (hipStream_t as void*; NULL = null
  * stream).  The setting is per process.  It does not order the new stream

@@ -194,3 +194,43 @@ def batched_inputs(count: int = 256, seed: int = 4, prec_bits: int = 256, exp_ra
         B = random_cmat([seed, idx], 1, k, n, prec_bits, exp_range)
         out.append((m, n, k, A, B))
     return out
+
+
+def multi_double(seed, which: int, ncomp: int, rows: int, cols: int, kind: str = "expansion",
+                 exp_range: int = 30) -> np.ndarray:
+    """Multi-component inputs (double-double to quad-double): a float64 array
+    (ncomp, cols, rows), entry (r, c) standing for the sum of its components.
+
+    kind "expansion": the normalised form of multi-component arithmetic, each
+    component at most half an ulp of the one before (random sign and
+    significand), the leading one's exponent uniform on [-exp_range, exp_range];
+    "random": independent doubles with exponents over [-exp_range, exp_range]
+    (overlaps, gaps and sign changes); "extreme": subnormals, values near the
+    largest double, zeros and exact cancellations mixed in."""
+    rng = np.random.default_rng([seed, which, ncomp])
+    shape = (cols, rows)
+    if kind == "random":
+        x = rng.uniform(-1.0, 1.0, size=(ncomp,) + shape)
+        return np.ldexp(x, rng.integers(-exp_range, exp_range + 1, size=(ncomp,) + shape))
+    out = np.zeros((ncomp,) + shape)
+    lead = rng.uniform(0.5, 1.0, size=shape) * rng.choice([-1.0, 1.0], size=shape)
+    out[0] = np.ldexp(lead, rng.integers(-exp_range, exp_range + 1, size=shape))
+    for i in range(1, ncomp):
+        # at most half an ulp of the previous component: |x| < 2^(e - 53) with
+        # 2^(e-1) <= |prev| < 2^e, times a random fraction and sign
+        _, e = np.frexp(out[i - 1])
+        f = rng.uniform(-1.0, 1.0, size=shape)
+        out[i] = np.where(out[i - 1] != 0, np.ldexp(f, e - 54), 0.0)
+    if kind == "extreme":
+        pick = rng.integers(0, 6, size=shape)
+        tiny = np.ldexp(rng.uniform(0.0, 1.0, size=shape), -1060)  # subnormal range
+        huge = np.ldexp(rng.uniform(0.5, 1.0, size=shape), 1023) * rng.choice([-1.0, 1.0], size=shape)
+        for i in range(ncomp):
+            out[i] = np.where(pick == 0, tiny * (i + 1), out[i])
+            out[i] = np.where(pick == 1, huge if i == 0 else np.ldexp(out[i], -i * 300), out[i])
+            out[i] = np.where((pick == 2) & (i % 2 == 1), 0.0, out[i])
+        if ncomp >= 2:
+            out[1] = np.where(pick == 3, -out[0], out[1])  # exact cancellation of the leading pair
+        if ncomp >= 3:
+            out[2] = np.where(pick == 4, np.ldexp(out[0], -700), out[2])  # a far gap
+    return out

@@ -104,10 +104,12 @@ _lib.mpcg_last_timing.argtypes = [_P(ctypes.c_float)]
 _lib.mpcg_last_timing.restype = _i
 _lib.mpcg_timing_report.argtypes = [_P(ctypes.c_float), _P(ctypes.c_int)]
 _lib.mpcg_timing_report.restype = _i
+_lib.mpcg_from_doubles.argtypes = [_i, _i, _i, _vp, _i, ctypes.c_longlong, _P(mpcg_part), _i, _i]
+_lib.mpcg_from_doubles.restype = _i
 
 EXPORTS = ["mp_cgemm", "mp_cgemm_ex", "mp_cgemm_acc", "mp_cgemm_batched", "mp_cgemm_batched_acc", "mpcg_set_stream", "mpcg_set_workspace", "mpcg_workspace_size",
            "mpcg_stream_status", "mpcg_last_error", "mpcg_enable_timing", "mpcg_last_timing",
-           "mpcg_timing_report"]
+           "mpcg_timing_report", "mpcg_from_doubles"]
 
 
 class MPCGError(RuntimeError):
@@ -222,6 +224,29 @@ def mpcg_stream_status(stream=None) -> int:
     if stream is None:
         stream = current_stream_handle()
     return int(_lib.mpcg_stream_status(stream))
+
+
+def mpcg_from_doubles(rows, cols, ncomp, src_ptr, ld, plane, dst: DevicePart, ldd, prec_bits) -> int:
+    return int(_lib.mpcg_from_doubles(rows, cols, ncomp, src_ptr, ld, plane, ctypes.byref(dst.struct()), ldd,
+                                      prec_bits))
+
+
+def from_doubles(re, im, prec_bits: int) -> DeviceCMat:
+    """Multi-component inputs: re and im are float64 device tensors of shape
+    (ncomp, cols, rows) (component planes, column-major entries); entry
+    (r, c) of each part is the exact sum of its ncomp doubles.  Returns the
+    complex matrix in the library's format at prec_bits, each sum rounded
+    once (mpcg_from_doubles, on the library's stream)."""
+    torch = _torch()
+    ncomp, cols, rows = re.shape
+    if im.shape != re.shape or re.dtype != torch.float64 or im.dtype != torch.float64:
+        raise ValueError("re and im must be float64 tensors of the same shape (ncomp, cols, rows)")
+    re, im = re.contiguous(), im.contiguous()
+    C = device_empty(rows, cols, prec_bits, device=re.device)
+    for t, part in ((re, C.re), (im, C.im)):
+        _check(mpcg_from_doubles(rows, cols, ncomp, t.data_ptr(), max(1, rows), max(1, rows) * cols, part,
+                                     C.ld, prec_bits))
+    return C
 
 
 def mpcg_enable_timing(on: bool = True) -> int:

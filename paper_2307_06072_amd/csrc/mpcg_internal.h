@@ -14,6 +14,7 @@ constexpr int ST_IN_RANGE = 1;   // input exponent outside [-2^30, 2^30]
 constexpr int ST_DENORM = 2;     // nonzero input with clear top significand bit
 constexpr int ST_OUT_RANGE = 4;  // output exponent does not fit int32
 constexpr int ST_SPREAD = 8;     // exponent spread beyond the caller's bound (planning without read-back)
+constexpr int ST_NONFINITE = 16;  // infinite or NaN double given to the multi-component codec
 
 // One real component of a column-major matrix (read side).
 struct DPart {
@@ -149,6 +150,8 @@ hipError_t launch_fill_zero(void* p, size_t n, hipStream_t stream);
 
 // C := +0 everywhere.
 hipError_t launch_zero(DOutPart cre, DOutPart cim, int m, int n, int64_t ldc, int L, hipStream_t stream);
+hipError_t launch_from_doubles(const double* src, int rows, int cols, int ncomp, int64_t ld, int64_t plane,
+                               DOutPart out, int64_t ldo, int prec, int L, int* status, hipStream_t stream);
 
 
 // ----------------------------------------------------------------------------

@@ -1073,6 +1073,34 @@ int mpcg_stream_status(void* hip_stream) {
   if (v & ST_IN_RANGE) return set_err(MPCG_ERANGE, "input exponent outside [-2^30, 2^30]");
   if (v & ST_OUT_RANGE) return set_err(MPCG_ERANGE, "output exponent outside int32");
   if (v & ST_DENORM) return set_err(MPCG_EDOMAIN, "nonzero input with clear significand top bit");
+  if (v & ST_NONFINITE) return set_err(MPCG_EDOMAIN, "infinite or NaN double input");
+  return MPCG_OK;
+}
+
+int mpcg_from_doubles(int rows, int cols, int ncomp, const double* src, int ld, long long plane, mpcg_part* dst,
+                      int ldd, int prec_bits) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_err.clear();
+  if (rows < 0 || cols < 0) return set_err(MPCG_EINVAL, "negative dimension");
+  if (ncomp < 1 || ncomp > 4) return set_err(MPCG_EINVAL, "ncomp %d outside [1, 4]", ncomp);
+  if (prec_bits < MPCG_MIN_PREC || prec_bits > MPCG_MAX_PREC)
+    return set_err(MPCG_EINVAL, "prec_bits %d outside [%d, %d]", prec_bits, MPCG_MIN_PREC, MPCG_MAX_PREC);
+  if (ld < std::max(1, rows) || ldd < std::max(1, rows)) return set_err(MPCG_EINVAL, "leading dimension < rows");
+  if (!src || !dst) return set_err(MPCG_EINVAL, "NULL pointer");
+  const int64_t n = (int64_t)ld * cols;
+  const int64_t pl = plane ? (int64_t)plane : n;
+  if (ncomp > 1 && pl < n) return set_err(MPCG_EINVAL, "plane stride %lld < ld*cols %lld", plane, (long long)n);
+  const int L = (prec_bits + 63) / 64;
+  Region rd[3];
+  int st = check_part(*dst, rows, cols, ldd, L, "dst", rd);
+  if (st) return st;
+  const Region rs{(uintptr_t)src, (uintptr_t)src + (uintptr_t)(8 * (pl * (ncomp - 1) + n))};
+  for (int a = 0; a < 3; ++a)
+    if (overlap(rd[a], rs)) return set_err(MPCG_EINVAL, "dst overlaps the source doubles");
+  if (rows == 0 || cols == 0) return MPCG_OK;
+  if ((st = ensure_status_and_pinned())) return st;
+  HIP_TRY(launch_from_doubles(src, rows, cols, ncomp, ld, pl, doutpart(*dst, (int64_t)ldd * cols), ldd, prec_bits, L,
+                              g_status, g_stream));
   return MPCG_OK;
 }
 

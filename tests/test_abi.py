@@ -215,3 +215,30 @@ def test_batched_accumulate_validation():
     assert mp.mp_cgemm_batched_acc_raw(1, arr, 256, 1, 0, 0) == mp.MPCG_EINVAL
     assert "sign" in mp.mpcg_last_error()
     assert mp.mp_cgemm_batched_acc_raw(0, arr, 256, 1, 0, -1) == 0  # empty batch
+
+
+# ---------------------------------------------------------------------------
+# the multi-component input codec: host-side validation
+# ---------------------------------------------------------------------------
+def _codec(rows=4, cols=3, ncomp=2, src=7 << 40, ld=4, plane=0, dst=True, ldd=4, p=128, dst_part=None):
+    import paper_2307_06072_amd as mp
+    part = dst_part if dst_part is not None else mp.mpcg_part(8 << 40, (8 << 40) + (1 << 24), (8 << 40) + (2 << 24), 0)
+    return mp._lib.mpcg_from_doubles(rows, cols, ncomp, src, ld, plane, ctypes.byref(part) if dst else None, ldd, p)
+
+
+@pytest.mark.parametrize("kw", [dict(rows=-1), dict(cols=-2), dict(ncomp=0), dict(ncomp=5), dict(p=1),
+                                dict(p=4097), dict(ld=3), dict(ldd=3), dict(src=0), dict(dst=False),
+                                dict(plane=11)])
+def test_codec_rejects_bad_arguments(kw):
+    import paper_2307_06072_amd as mp
+    assert _codec(**kw) == mp.MPCG_EINVAL
+    assert mp.mpcg_last_error()
+
+
+def test_codec_rejects_dst_overlapping_src():
+    import paper_2307_06072_amd as mp
+    src = 9 << 40
+    # dst's exponent array inside the source doubles
+    part = mp.mpcg_part(8 << 40, src + 16, (8 << 40) + (2 << 24), 0)
+    assert _codec(src=src, dst_part=part) == mp.MPCG_EINVAL
+    assert "overlap" in mp.mpcg_last_error()
