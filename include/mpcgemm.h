@@ -73,7 +73,8 @@ enum {
     MPCG_OK = 0,
     MPCG_EINVAL = -1,      /* bad dimension, leading dimension, precision, enum, NULL, aliasing */
     MPCG_ENOMEM = -2,      /* workspace too small / allocation failed */
-    MPCG_ERANGE = -3,      /* input exponent outside [-2^30, 2^30] or output exponent overflow */
+    MPCG_ERANGE = -3,      /* input exponent outside [-2^30, 2^30], output exponent overflow, or a
+                              double component beyond the largest double (mpcg_to_doubles) */
     MPCG_EHIP = -4,        /* HIP runtime error (text in mpcg_last_error) */
     MPCG_EUNSUPPORTED = -5,/* valid request this build cannot serve */
     MPCG_EDOMAIN = -6,     /* nonzero input whose significand top bit is clear; an infinite or NaN
@@ -241,6 +242,23 @@ int mp_cgemm_batched_acc(int count, const mpcg_problem *problems, int prec_bits,
  */
 int mpcg_from_doubles(int rows, int cols, int ncomp, const double *src, int ld, long long plane, mpcg_part *dst,
                       int ldd, int prec_bits);
+
+/*
+ * The opposite conversion: each entry of one real component (the layout of
+ * an mpcg_part, leading dimension lds, its top prec_bits significand bits)
+ * written as ncomp doubles (1 <= ncomp <= 4), component i at
+ * dst[i * plane + c * ld + r] (device memory, plane >= ld * cols, 0 means
+ * exactly ld * cols).  Greedy: component i is the double nearest the value
+ * minus the components before it (ties to even, gradual underflow, the sign
+ * kept on a zero that underflows); an exactly zero remainder gives +0.  With
+ * enough components (a normalised expansion needs one per 53 significant
+ * bits) their sum is the entry exactly.  A component beyond the largest
+ * double is written as +-infinity and reported as MPCG_ERANGE by
+ * mpcg_stream_status (the later components then continue from the
+ * unbounded rounding).  Host-side validation as for mpcg_from_doubles.
+ */
+int mpcg_to_doubles(int rows, int cols, const mpcg_part *src, int lds, int prec_bits, int ncomp, double *dst, int ld,
+                    long long plane);
 
 /* Issue subsequent work on this HIP stream (hipStream_t as void*; NULL = null
  * stream).  The setting is per process.  It does not order the new stream

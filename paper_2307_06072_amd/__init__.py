@@ -106,10 +106,12 @@ _lib.mpcg_timing_report.argtypes = [_P(ctypes.c_float), _P(ctypes.c_int)]
 _lib.mpcg_timing_report.restype = _i
 _lib.mpcg_from_doubles.argtypes = [_i, _i, _i, _vp, _i, ctypes.c_longlong, _P(mpcg_part), _i, _i]
 _lib.mpcg_from_doubles.restype = _i
+_lib.mpcg_to_doubles.argtypes = [_i, _i, _P(mpcg_part), _i, _i, _i, _vp, _i, ctypes.c_longlong]
+_lib.mpcg_to_doubles.restype = _i
 
 EXPORTS = ["mp_cgemm", "mp_cgemm_ex", "mp_cgemm_acc", "mp_cgemm_batched", "mp_cgemm_batched_acc", "mpcg_set_stream", "mpcg_set_workspace", "mpcg_workspace_size",
            "mpcg_stream_status", "mpcg_last_error", "mpcg_enable_timing", "mpcg_last_timing",
-           "mpcg_timing_report", "mpcg_from_doubles"]
+           "mpcg_timing_report", "mpcg_from_doubles", "mpcg_to_doubles"]
 
 
 class MPCGError(RuntimeError):
@@ -247,6 +249,25 @@ def from_doubles(re, im, prec_bits: int) -> DeviceCMat:
         _check(mpcg_from_doubles(rows, cols, ncomp, t.data_ptr(), max(1, rows), max(1, rows) * cols, part,
                                      C.ld, prec_bits))
     return C
+
+
+def mpcg_to_doubles(rows, cols, src: DevicePart, lds, prec_bits, ncomp, dst_ptr, ld, plane) -> int:
+    return int(_lib.mpcg_to_doubles(rows, cols, ctypes.byref(src.struct()), lds, prec_bits, ncomp, dst_ptr, ld,
+                                    plane))
+
+
+def to_doubles(C: DeviceCMat, prec_bits: int, ncomp: int):
+    """The opposite of from_doubles: (re, im) float64 device tensors of shape
+    (ncomp, cols, rows), each entry's components chosen greedily (each the
+    double nearest what the earlier ones leave; mpcg_to_doubles)."""
+    torch = _torch()
+    out = []
+    for part in (C.re, C.im):
+        t = torch.empty((ncomp, C.cols, max(1, C.rows)), dtype=torch.float64, device=part.exp.device)
+        _check(mpcg_to_doubles(C.rows, C.cols, part, C.ld, prec_bits, ncomp, t.data_ptr(), max(1, C.rows),
+                               max(1, C.rows) * C.cols))
+        out.append(t)
+    return tuple(out)
 
 
 def mpcg_enable_timing(on: bool = True) -> int:

@@ -168,3 +168,119 @@ hipError_t launch_from_doubles(const double* src, int rows, int cols, int ncomp,
 }
 
 }  // namespace mpcg
+
+namespace mpcg {
+
+namespace {
+
+// The opposite conversion: each stored entry (p-bit significand, L limbs) as
+// ncomp doubles, greedily: component i is the double nearest (ties to even,
+// with gradual underflow) to what the components before it leave of the
+// value.  The remainder is kept exactly as a magnitude over the entry's limbs
+// (bit 0 = 2^(exp - 64 L)) and a sign; rounding a component up leaves a
+// remainder of the opposite sign.  A component beyond the largest double is
+// written as infinity and reported; what remains after the last component is
+// dropped (zero when the components cover the significand).
+__global__ __launch_bounds__(CODEC_THREADS) void to_doubles_kernel(DPart in, int rows, int cols, int64_t ldi,
+                                                                  int prec, int L, int ncomp, double* __restrict__ dst,
+                                                                  int64_t ld, int64_t plane, int* status) {
+  extern __shared__ uint64_t rem_all[];
+  uint64_t* R = rem_all + (size_t)threadIdx.x * L;
+  const int64_t e = (int64_t)blockIdx.x * CODEC_THREADS + threadIdx.x;
+  if (e >= (int64_t)rows * cols) return;  // no barrier follows
+  const int r = (int)(e % rows), j = (int)(e / rows);
+  const int64_t o = (int64_t)j * ldi + r;
+  double* out = dst + (int64_t)j * ld + r;
+
+  const int32_t ex = in.exp[o];
+  int sgn = in.sign[o] ? 1 : 0;
+  int nonzero = ex != EXP_ZERO;
+  const int keep_from = 64 * L - prec;
+  for (int l = 0; l < L; ++l) {
+    uint64_t v = nonzero ? in.mant[(int64_t)l * in.ls + o] : 0ull;
+    if (l == 0) v &= ~lowbits(keep_from);  // only the top prec bits are the value
+    R[l] = v;
+  }
+  const int64_t base = nonzero ? (int64_t)ex - 64 * L : 0;  // exponent of grid bit 0
+  auto limb = [&](int l) -> uint64_t { return (l >= 0 && l < L) ? R[l] : 0ull; };
+  // bits [pos, pos + 64) of the remainder (zero outside its limbs)
+  auto field = [&](int pos) -> uint64_t {
+    const int li = pos >> 6, sh = pos & 63;  // floor division, also for pos < 0
+    const uint64_t x = limb(li), y = limb(li + 1);
+    return sh ? (x >> sh) | (y << (64 - sh)) : x;
+  };
+  for (int c = 0; c < ncomp; ++c) {
+    int lead = -1;
+    for (int l = L - 1; l >= 0 && lead < 0 && nonzero; --l)
+      if (R[l]) lead = 64 * l + 63 - __builtin_clzll(R[l]);
+    if (lead < 0) {  // nothing left: +0
+      out[c * plane] = 0.0;
+      nonzero = 0;
+      continue;
+    }
+    // kept bits [low, lead]: at most 53, none below 2^-1074 (gradual underflow);
+    // a remainder below 2^-1075 rounds to zero
+    const int64_t sub = -1074 - base;  // grid position of 2^-1074
+    const int64_t low64 = max((int64_t)lead - 52, sub);
+    int low, up = 0;
+    uint64_t T = 0;
+    if (low64 > lead + 1) {
+      low = lead + 2;
+    } else {
+      low = (int)low64;  // >= lead - 52 >= -52 when rounding a nonzero remainder
+      T = field(low) & lowbits(lead - low + 1);
+      const int rb = low - 1;
+      int sticky = 0;
+      if (rb > 0) {
+        sticky = (limb(rb >> 6) & lowbits(rb & 63)) != 0;
+        for (int l = 0; l < (rb >> 6) && !sticky; ++l) sticky = R[l] != 0;
+      }
+      up = (rb >= 0 && ((limb(rb >> 6) >> (rb & 63)) & 1ull)) && (sticky || (T & 1ull));
+    }
+    const uint64_t q = T + (uint64_t)up;  // <= 2^53
+    const int64_t qexp = base + low;        // the component is q 2^qexp
+    double d = 0.0;
+    if (q != 0) {
+      if (qexp + 63 - __builtin_clzll(q) > 1023) {
+        d = __builtin_huge_val();
+        atomicOr(status, ST_OUT_RANGE);
+      } else {
+        d = ldexp((double)q, (int)qexp);
+      }
+    }
+    out[c * plane] = sgn ? -d : d;
+    // the remainder: its bits below `low`, or 2^low minus them (and the
+    // opposite sign) when the component was rounded up
+    if (low < 64 * L) {
+      for (int l = max(low, 0) >> 6; l < L; ++l) {
+        const int keep = low - 64 * l;  // bits of limb l below `low`
+        R[l] &= keep >= 64 ? ~0ull : lowbits(keep);
+      }
+      if (up) {
+        uint64_t borrow = 0;
+        for (int l = 0; l < L; ++l) {
+          const uint64_t v = R[l], t = 0ull - v - borrow;
+          borrow = (v | borrow) != 0;
+          const int keep = low - 64 * l;
+          R[l] = t & (keep >= 64 ? ~0ull : lowbits(keep));
+        }
+        sgn ^= 1;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_to_doubles(DPart in, int rows, int cols, int64_t ldi, int prec, int L, int ncomp, double* dst,
+                             int64_t ld, int64_t plane, int* status, hipStream_t stream) {
+  const int64_t n = (int64_t)rows * cols;
+  if (n <= 0) return hipSuccess;
+  const size_t lds = (size_t)CODEC_THREADS * L * sizeof(uint64_t);
+  const unsigned blocks = (unsigned)((n + CODEC_THREADS - 1) / CODEC_THREADS);
+  to_doubles_kernel<<<dim3(blocks), dim3(CODEC_THREADS), lds, stream>>>(in, rows, cols, ldi, prec, L, ncomp, dst,
+                                                                        ld, plane, status);
+  return hipGetLastError();
+}
+
+}  // namespace mpcg

@@ -1071,7 +1071,7 @@ int mpcg_stream_status(void* hip_stream) {
   HIP_TRY(hipMemset(g_status, 0, sizeof(int)));
   if (v & ST_SPREAD) return set_err(MPCG_ESPREAD, "an operand's exponent spread exceeded max_spread");
   if (v & ST_IN_RANGE) return set_err(MPCG_ERANGE, "input exponent outside [-2^30, 2^30]");
-  if (v & ST_OUT_RANGE) return set_err(MPCG_ERANGE, "output exponent outside int32");
+  if (v & ST_OUT_RANGE) return set_err(MPCG_ERANGE, "output exponent outside int32 (or a double component beyond the largest double)");
   if (v & ST_DENORM) return set_err(MPCG_EDOMAIN, "nonzero input with clear significand top bit");
   if (v & ST_NONFINITE) return set_err(MPCG_EDOMAIN, "infinite or NaN double input");
   return MPCG_OK;
@@ -1101,6 +1101,33 @@ int mpcg_from_doubles(int rows, int cols, int ncomp, const double* src, int ld, 
   if ((st = ensure_status_and_pinned())) return st;
   HIP_TRY(launch_from_doubles(src, rows, cols, ncomp, ld, pl, doutpart(*dst, (int64_t)ldd * cols), ldd, prec_bits, L,
                               g_status, g_stream));
+  return MPCG_OK;
+}
+
+int mpcg_to_doubles(int rows, int cols, const mpcg_part* src, int lds, int prec_bits, int ncomp, double* dst, int ld,
+                    long long plane) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_err.clear();
+  if (rows < 0 || cols < 0) return set_err(MPCG_EINVAL, "negative dimension");
+  if (ncomp < 1 || ncomp > 4) return set_err(MPCG_EINVAL, "ncomp %d outside [1, 4]", ncomp);
+  if (prec_bits < MPCG_MIN_PREC || prec_bits > MPCG_MAX_PREC)
+    return set_err(MPCG_EINVAL, "prec_bits %d outside [%d, %d]", prec_bits, MPCG_MIN_PREC, MPCG_MAX_PREC);
+  if (ld < std::max(1, rows) || lds < std::max(1, rows)) return set_err(MPCG_EINVAL, "leading dimension < rows");
+  if (!src || !dst) return set_err(MPCG_EINVAL, "NULL pointer");
+  const int64_t n = (int64_t)ld * cols;
+  const int64_t pl = plane ? (int64_t)plane : n;
+  if (ncomp > 1 && pl < n) return set_err(MPCG_EINVAL, "plane stride %lld < ld*cols %lld", plane, (long long)n);
+  const int L = (prec_bits + 63) / 64;
+  Region rs[3];
+  int st = check_part(*src, rows, cols, lds, L, "src", rs);
+  if (st) return st;
+  const Region rd{(uintptr_t)dst, (uintptr_t)dst + (uintptr_t)(8 * (pl * (ncomp - 1) + n))};
+  for (int a = 0; a < 3; ++a)
+    if (overlap(rs[a], rd)) return set_err(MPCG_EINVAL, "the doubles overlap the source");
+  if (rows == 0 || cols == 0) return MPCG_OK;
+  if ((st = ensure_status_and_pinned())) return st;
+  HIP_TRY(launch_to_doubles(dpart(*src, (int64_t)lds * cols), rows, cols, lds, prec_bits, L, ncomp, dst, ld, pl,
+                            g_status, g_stream));
   return MPCG_OK;
 }
 

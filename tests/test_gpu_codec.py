@@ -112,3 +112,62 @@ def test_codec_feeds_the_product(mode):
     ref = oracle.cgemm(codec_ref.from_doubles(ar, ai, p), codec_ref.from_doubles(br, bi, p), p)
     bad, first = mismatches(got, ref, m, n)
     assert bad == 0, (bad, first)
+
+
+def _bits(a):
+    return np.ascontiguousarray(a).view(np.uint64)
+
+
+@pytest.mark.parametrize("p", [2, 53, 64, 106, 200, 256, 1024, 3000])
+@pytest.mark.parametrize("ncomp", [1, 2, 3, 4])
+def test_to_doubles_parity(ncomp, p):
+    """Stored entries (exponents over +-1000: subnormal remainders included)
+    written as ncomp doubles, against the oracle bit for bit (signed zeros
+    too)."""
+    import torch
+    import paper_2307_06072_amd as mp
+    from mpgen import random_cmat
+    A = random_cmat([31, p, ncomp], 0, 23, 17, p, 1000, zero_frac=0.1)
+    _say(f"to_doubles p={p} ncomp={ncomp}")
+    mp.mpcg_set_stream()
+    re, im = mp.to_doubles(mp.to_device(A), p, ncomp)
+    torch.cuda.synchronize()
+    assert mp.mpcg_stream_status() == 0
+    ref_re, ref_im = codec_ref.to_doubles(A, p, ncomp)
+    assert np.array_equal(_bits(re.cpu().numpy()), _bits(ref_re))
+    assert np.array_equal(_bits(im.cpu().numpy()), _bits(ref_im))
+
+
+@pytest.mark.parametrize("ncomp", [2, 4])
+def test_codec_round_trip(ncomp):
+    """Expansions converted exactly on the device and back give themselves."""
+    import torch
+    import paper_2307_06072_amd as mp
+    rows, cols, p = 301, 133, 64 * 4 * ncomp
+    re = multi_double(32, 0, ncomp, rows, cols, "expansion", exp_range=400)
+    im = multi_double(32, 1, ncomp, rows, cols, "expansion", exp_range=400)
+    C, _, st = _device(re, im, p)
+    assert st == 0
+    bre, bim = mp.to_doubles(C, p, ncomp)
+    torch.cuda.synchronize()
+    assert mp.mpcg_stream_status() == 0
+    assert np.array_equal(_bits(bre.cpu().numpy()), _bits(re))
+    assert np.array_equal(_bits(bim.cpu().numpy()), _bits(im))
+
+
+def test_to_doubles_overflow():
+    import torch
+    import paper_2307_06072_amd as mp
+    from mpgen import random_cmat, scale_exponents
+    p = 128
+    A = random_cmat(33, 0, 9, 7, p, 4)
+    for part in (A.re, A.im):
+        scale_exponents(part, rows=[0, 1], shift=1022)  # exponents 1018-1026: some beyond 2^1024
+    mp.mpcg_set_stream()
+    re, im = mp.to_doubles(mp.to_device(A), p, 2)
+    torch.cuda.synchronize()
+    assert mp.mpcg_stream_status() == mp.MPCG_ERANGE
+    ref_re, ref_im = codec_ref.to_doubles(A, p, 2)
+    assert np.isinf(ref_re).any()
+    assert np.array_equal(_bits(re.cpu().numpy()), _bits(ref_re))
+    assert np.array_equal(_bits(im.cpu().numpy()), _bits(ref_im))

@@ -90,3 +90,56 @@ def test_non_finite_gives_zero():
     for bad in (math.inf, -math.inf, math.nan):
         v, part = _one([1.0, bad], 64)
         assert v == 0 and part.exp[0, 0] == EXP_ZERO
+
+
+def test_round_double_is_float_in_range():
+    """The written-out IEEE rounding against Python's correctly rounded
+    float(Fraction), including subnormals, ties and the underflow to -0."""
+    rng = np.random.default_rng(31)
+    cases = [Fraction(1) + Fraction(1, 2 ** 53), Fraction(3, 2 ** 1076), -Fraction(1, 2 ** 1075),
+             Fraction(5, 2 ** 1076), -Fraction(2 ** 1024 - 2 ** 971), Fraction(1, 3), -Fraction(10 ** 30, 7)]
+    for _ in range(3000):
+        num = int(rng.integers(1, 2 ** 62)) * (1 if rng.random() < 0.5 else -1)
+        sh = int(rng.integers(-1150, 960))  # |x| < 2^1022
+        cases.append(Fraction(num) * Fraction(2) ** sh + Fraction(int(rng.integers(0, 3)), 2 ** 1100))
+    for x in cases:
+        v, overflow = codec_ref.round_double(x)
+        assert not overflow
+        f = float(x)
+        assert (v == Fraction(f)) and (v != 0 or math.copysign(1.0, f) == (-1.0 if x < 0 else 1.0)), x
+
+
+def test_round_double_overflow():
+    assert codec_ref.round_double(Fraction(2 ** 1024 - 2 ** 970))[1]       # the tie rounds up to 2^1024
+    assert not codec_ref.round_double(Fraction(2 ** 1024 - 2 ** 971))[0] == 0
+
+
+@pytest.mark.parametrize("ncomp", [1, 2, 3, 4])
+def test_to_doubles_round_trip(ncomp):
+    """A normalised expansion converted exactly and back gives itself."""
+    comps = multi_double(13, 2, ncomp, 7, 6, "expansion", exp_range=300)
+    part = codec_ref.from_doubles_part(comps, 64 * 4 * ncomp)
+    back = codec_ref.to_doubles_part(part, 64 * 4 * ncomp, ncomp)
+    assert np.array_equal(back.view(np.uint64), comps.view(np.uint64))
+
+
+def test_to_doubles_greedy_worked():
+    """Greedy components derived by hand."""
+    from tests.mp_util import part_from_values
+    p = 200
+    two = Fraction(2)
+    vals = [[1 + two ** -60], [-(1 + two ** -53)], [1 + two ** -53 + two ** -150], [3 * two ** -1076],
+            [two ** -1075]]
+    part = part_from_values(vals, p)
+    d = codec_ref.to_doubles_part(part, p, 3)
+    # exact in two components, the third +0
+    assert [d[i, 0, 0] for i in range(3)] == [1.0, 2.0 ** -60, 0.0]
+    # a tie rounds to the even neighbour 1, the rest follows with the sign
+    assert [d[i, 0, 1] for i in range(3)] == [-1.0, -(2.0 ** -53), 0.0]
+    # above the tie: up to 1 + 2^-52; the remainder -2^-53 + 2^-150 needs 98
+    # bits, so it splits into -2^-53 and 2^-150
+    assert [d[i, 0, 2] for i in range(3)] == [1.0 + 2.0 ** -52, -(2.0 ** -53), 2.0 ** -150]
+    # 1.5 * 2^-1075 rounds up to the smallest subnormal, leaving -2^-1076 (below half of it: -0)
+    assert d[0, 0, 3] == 5e-324 and d[1, 0, 3] == 0.0 and math.copysign(1.0, d[1, 0, 3]) == -1.0
+    # 2^-1075 exactly: a tie between 0 and 2^-1074 goes to +0, and stays for the next component
+    assert d[0, 0, 4] == 0.0 and math.copysign(1.0, d[0, 0, 4]) == 1.0
