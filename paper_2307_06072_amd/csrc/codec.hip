@@ -4,12 +4,15 @@
 //
 // Each entry of a real component is the exact sum of up to four doubles.  A
 // thread forms that sum exactly in a two's-complement fixed-point
-// accumulator spanning the whole double range: bit 0 is 2^-1074 (the lowest
-// subnormal bit), the largest finite double's top bit is bit 2097, so four
-// of them stay below bit 2100, and 34 limbs (2176 bits) leave the top bit
-// for the sign.  The sum is then rounded once to prec_bits, to nearest with
-// ties to even, exactly as the rounding kernel rounds a product: leading bit,
-// p kept bits, round bit, sticky bit, renormalisation on carry-out.
+// accumulator on a grid whose bit 0 is 2^-1074 (the lowest subnormal bit):
+// the largest finite double's top bit is bit 2097, so four of them stay
+// below bit 2100, and 34 limbs (2176 bits) leave the top bit for the sign.
+// Only the limbs the components touch (and one above) are used: a first
+// pass holds them in an 8-limb row when they span at most 512 bits (every
+// normalised expansion), a second pass takes the rest with the full row.
+// The sum is then rounded once to prec_bits, to nearest with ties to even,
+// exactly as the rounding kernel rounds a product: leading bit, p kept bits,
+// round bit, sticky bit, renormalisation on carry-out.
 #include "mpcg_internal.h"
 
 namespace mpcg {
@@ -17,7 +20,12 @@ namespace mpcg {
 namespace {
 
 constexpr int ACC_LIMBS = 34;
+constexpr int NARROW_LIMBS = 8;  // the first pass: components within 512 bits of each other
+constexpr int NARROW_STRIDE = 9; // its LDS row stride (odd, so that lanes spread over the banks)
 constexpr int CODEC_THREADS = 128;
+// an exponent no converted double sum can have (theirs lie in [-1073, 1027]):
+// marks an entry the first pass leaves to the second
+constexpr int32_t EXP_PENDING = INT32_MIN + 1;
 
 __device__ inline uint64_t lowbits(int n) { return n <= 0 ? 0ull : (n >= 64 ? ~0ull : ((1ull << n) - 1ull)); }
 
@@ -50,16 +58,23 @@ __device__ inline void acc_add(uint64_t* A, int off, uint64_t m, int neg, int to
   }
 }
 
+// Two passes over the entries: the first (WIDE = false) gives each thread an
+// LDS row of NARROW_LIMBS limbs, indexed from the lowest limb its components
+// touch, and marks the entries whose components span more; the second (WIDE)
+// converts only those, with a row over the whole double range.
+template <bool WIDE>
 __global__ __launch_bounds__(CODEC_THREADS) void from_doubles_kernel(const double* __restrict__ src, int rows,
                                                                     int cols, int ncomp, int64_t ld, int64_t plane,
                                                                     DOutPart out, int64_t ldo, int prec, int L,
                                                                     int* status) {
+  constexpr int ROW = WIDE ? ACC_LIMBS : NARROW_STRIDE;
   extern __shared__ uint64_t acc_all[];
-  uint64_t* A = acc_all + (size_t)threadIdx.x * ACC_LIMBS;
+  uint64_t* A = acc_all + (size_t)threadIdx.x * ROW;
   const int64_t e = (int64_t)blockIdx.x * CODEC_THREADS + threadIdx.x;
   if (e >= (int64_t)rows * cols) return;  // no barrier follows
   const int r = (int)(e % rows), j = (int)(e / rows);
   const int64_t o = (int64_t)j * ldo + r;
+  if (WIDE && out.exp[o] != EXP_PENDING) return;
 
   // the components, and the limbs they touch: the sum is formed in two's
   // complement over limbs [lo, top] (one limb above the highest touched for
@@ -98,8 +113,17 @@ __global__ __launch_bounds__(CODEC_THREADS) void from_doubles_kernel(const doubl
     write_zero();
     return;
   }
+  // row limb i is grid limb b0 + i; from here on limbs and bits are counted
+  // in the row (the grid has no set bits below limb lo)
+  const int b0 = WIDE ? 0 : lo;
+  if (!WIDE && top - b0 >= NARROW_LIMBS) {
+    out.exp[o] = EXP_PENDING;
+    return;
+  }
+  lo -= b0;
+  top -= b0;
   for (int l = lo; l <= top; ++l) A[l] = 0;
-  for (int i = 0; i < nz; ++i) acc_add(A, pos[i], mm[i], sg[i], top);
+  for (int i = 0; i < nz; ++i) acc_add(A, pos[i] - 64 * b0, mm[i], sg[i], top);
   const int neg = (int)(A[top] >> 63);
   if (neg) {  // magnitude: the two's complement
     uint64_t c = 1;
@@ -134,7 +158,7 @@ __global__ __launch_bounds__(CODEC_THREADS) void from_doubles_kernel(const doubl
   }
   const int keep_from = 64 * L - prec;  // 0..63
   uint64_t carry = round_up ? (1ull << keep_from) : 0ull;
-  int64_t e_out = (int64_t)lead + 1 - 1074;
+  int64_t e_out = (int64_t)lead + 64 * b0 + 1 - 1074;
   const int off = lead + 1 - 64 * L;
   uint64_t limbs_hi = 0;
   for (int l = 0; l < L; ++l) {
@@ -160,10 +184,11 @@ hipError_t launch_from_doubles(const double* src, int rows, int cols, int ncomp,
                                DOutPart out, int64_t ldo, int prec, int L, int* status, hipStream_t stream) {
   const int64_t n = (int64_t)rows * cols;
   if (n <= 0) return hipSuccess;
-  const size_t lds = (size_t)CODEC_THREADS * ACC_LIMBS * sizeof(uint64_t);
   const unsigned blocks = (unsigned)((n + CODEC_THREADS - 1) / CODEC_THREADS);
-  from_doubles_kernel<<<dim3(blocks), dim3(CODEC_THREADS), lds, stream>>>(src, rows, cols, ncomp, ld, plane, out,
-                                                                          ldo, prec, L, status);
+  from_doubles_kernel<false><<<dim3(blocks), dim3(CODEC_THREADS), (size_t)CODEC_THREADS * NARROW_STRIDE * 8, stream>>>(
+      src, rows, cols, ncomp, ld, plane, out, ldo, prec, L, status);
+  from_doubles_kernel<true><<<dim3(blocks), dim3(CODEC_THREADS), (size_t)CODEC_THREADS * ACC_LIMBS * 8, stream>>>(
+      src, rows, cols, ncomp, ld, plane, out, ldo, prec, L, status);
   return hipGetLastError();
 }
 
