@@ -62,19 +62,44 @@ __device__ inline void acc_add(uint64_t* A, int off, uint64_t m, int neg, int to
 // LDS row of NARROW_LIMBS limbs, indexed from the lowest limb its components
 // touch, and marks the entries whose components span more; the second (WIDE)
 // converts only those, with a row over the whole double range.
+__device__ inline void from_doubles_entry(const double* __restrict__ src, int rows, int ncomp, int64_t ld,
+                                          int64_t plane, DOutPart out, int64_t ldo, int prec, int L, int* status,
+                                          int* pending, int64_t e, uint64_t* A, bool wide);
+
+// The marks of one call: `pending` is set by the first pass when it leaves
+// an entry to the second, cleared before the first pass.
+__global__ void clear_flag_kernel(int* pending) { *pending = 0; }
+
 template <bool WIDE>
 __global__ __launch_bounds__(CODEC_THREADS) void from_doubles_kernel(const double* __restrict__ src, int rows,
                                                                     int cols, int ncomp, int64_t ld, int64_t plane,
                                                                     DOutPart out, int64_t ldo, int prec, int L,
-                                                                    int* status) {
+                                                                    int* status, int* pending) {
   constexpr int ROW = WIDE ? ACC_LIMBS : NARROW_STRIDE;
   extern __shared__ uint64_t acc_all[];
   uint64_t* A = acc_all + (size_t)threadIdx.x * ROW;
-  const int64_t e = (int64_t)blockIdx.x * CODEC_THREADS + threadIdx.x;
-  if (e >= (int64_t)rows * cols) return;  // no barrier follows
+  const int64_t n = (int64_t)rows * cols;
+  if (!WIDE) {
+    const int64_t e = (int64_t)blockIdx.x * CODEC_THREADS + threadIdx.x;
+    if (e < n) from_doubles_entry(src, rows, ncomp, ld, plane, out, ldo, prec, L, status, pending, e, A, false);
+    return;
+  }
+  // the second pass: a small grid walking all entries, only if any was marked
+  if (*reinterpret_cast<volatile int*>(pending) == 0) return;
+  for (int64_t e = (int64_t)blockIdx.x * CODEC_THREADS + threadIdx.x; e < n; e += (int64_t)gridDim.x * CODEC_THREADS) {
+    const int r = (int)(e % rows), j = (int)(e / rows);
+    if (out.exp[(int64_t)j * ldo + r] == EXP_PENDING)
+      from_doubles_entry(src, rows, ncomp, ld, plane, out, ldo, prec, L, status, pending, e, A, true);
+  }
+}
+
+// One entry (wide: a row over the whole double range; else NARROW_LIMBS limbs
+// from the lowest touched one, the entry marked when its span is larger).
+__device__ inline void from_doubles_entry(const double* __restrict__ src, int rows, int ncomp, int64_t ld,
+                                          int64_t plane, DOutPart out, int64_t ldo, int prec, int L, int* status,
+                                          int* pending, int64_t e, uint64_t* A, bool wide) {
   const int r = (int)(e % rows), j = (int)(e / rows);
   const int64_t o = (int64_t)j * ldo + r;
-  if (WIDE && out.exp[o] != EXP_PENDING) return;
 
   // the components, and the limbs they touch: the sum is formed in two's
   // complement over limbs [lo, top] (one limb above the highest touched for
@@ -115,9 +140,10 @@ __global__ __launch_bounds__(CODEC_THREADS) void from_doubles_kernel(const doubl
   }
   // row limb i is grid limb b0 + i; from here on limbs and bits are counted
   // in the row (the grid has no set bits below limb lo)
-  const int b0 = WIDE ? 0 : lo;
-  if (!WIDE && top - b0 >= NARROW_LIMBS) {
+  const int b0 = wide ? 0 : lo;
+  if (!wide && top - b0 >= NARROW_LIMBS) {
     out.exp[o] = EXP_PENDING;
+    *pending = 1;
     return;
   }
   lo -= b0;
@@ -181,14 +207,17 @@ __global__ __launch_bounds__(CODEC_THREADS) void from_doubles_kernel(const doubl
 }  // namespace
 
 hipError_t launch_from_doubles(const double* src, int rows, int cols, int ncomp, int64_t ld, int64_t plane,
-                               DOutPart out, int64_t ldo, int prec, int L, int* status, hipStream_t stream) {
+                               DOutPart out, int64_t ldo, int prec, int L, int* status, int* pending,
+                               hipStream_t stream) {
   const int64_t n = (int64_t)rows * cols;
   if (n <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)((n + CODEC_THREADS - 1) / CODEC_THREADS);
+  clear_flag_kernel<<<dim3(1), dim3(1), 0, stream>>>(pending);
   from_doubles_kernel<false><<<dim3(blocks), dim3(CODEC_THREADS), (size_t)CODEC_THREADS * NARROW_STRIDE * 8, stream>>>(
-      src, rows, cols, ncomp, ld, plane, out, ldo, prec, L, status);
-  from_doubles_kernel<true><<<dim3(blocks), dim3(CODEC_THREADS), (size_t)CODEC_THREADS * ACC_LIMBS * 8, stream>>>(
-      src, rows, cols, ncomp, ld, plane, out, ldo, prec, L, status);
+      src, rows, cols, ncomp, ld, plane, out, ldo, prec, L, status, pending);
+  const unsigned wide_blocks = blocks < 1024u ? blocks : 1024u;
+  from_doubles_kernel<true><<<dim3(wide_blocks), dim3(CODEC_THREADS), (size_t)CODEC_THREADS * ACC_LIMBS * 8, stream>>>(
+      src, rows, cols, ncomp, ld, plane, out, ldo, prec, L, status, pending);
   return hipGetLastError();
 }
 

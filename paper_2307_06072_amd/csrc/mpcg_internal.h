@@ -153,7 +153,8 @@ hipError_t launch_zero(DOutPart cre, DOutPart cim, int m, int n, int64_t ldc, in
 hipError_t launch_to_doubles(DPart in, int rows, int cols, int64_t ldi, int prec, int L, int ncomp, double* dst,
                              int64_t ld, int64_t plane, int* status, hipStream_t stream);
 hipError_t launch_from_doubles(const double* src, int rows, int cols, int ncomp, int64_t ld, int64_t plane,
-                               DOutPart out, int64_t ldo, int prec, int L, int* status, hipStream_t stream);
+                               DOutPart out, int64_t ldo, int prec, int L, int* status, int* pending,
+                               hipStream_t stream);
 
 
 // ----------------------------------------------------------------------------

@@ -1099,8 +1099,9 @@ int mpcg_from_doubles(int rows, int cols, int ncomp, const double* src, int ld, 
     if (overlap(rd[a], rs)) return set_err(MPCG_EINVAL, "dst overlaps the source doubles");
   if (rows == 0 || cols == 0) return MPCG_OK;
   if ((st = ensure_status_and_pinned())) return st;
+  // the codec's pass flag lives in the status allocation, 64 bytes after the status word
   HIP_TRY(launch_from_doubles(src, rows, cols, ncomp, ld, pl, doutpart(*dst, (int64_t)ldd * cols), ldd, prec_bits, L,
-                              g_status, g_stream));
+                              g_status, g_status + 16, g_stream));
   return MPCG_OK;
 }
 

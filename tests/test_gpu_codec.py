@@ -54,11 +54,14 @@ def test_codec_parity(kind, ncomp, p):
     _zeros_are_plus(got)
 
 
-def test_codec_large_sampled():
-    """A 1031 x 517 quad-double matrix (many blocks), checked on sampled entries."""
+@pytest.mark.parametrize("kinds", [("random", "expansion"), ("extreme", "extreme")])
+def test_codec_large_sampled(kinds):
+    """A 1031 x 517 quad-double matrix (4166 blocks: the second pass walks it
+    with a smaller grid), checked on sampled entries; the extreme inputs have
+    many entries spanning more than 512 bits."""
     rows, cols, p = 1031, 517, 256
-    re = multi_double(22, 0, 4, rows, cols, "random", exp_range=200)
-    im = multi_double(22, 1, 4, rows, cols, "expansion", exp_range=200)
+    re = multi_double(22, 0, 4, rows, cols, kinds[0], exp_range=200)
+    im = multi_double(22, 1, 4, rows, cols, kinds[1], exp_range=200)
     _say("codec 1031 x 517 QD p=256")
     _, got, st = _device(re, im, p)
     assert st == 0
