@@ -58,10 +58,6 @@ __device__ inline void acc_add(uint64_t* A, int off, uint64_t m, int neg, int to
   }
 }
 
-// Two passes over the entries: the first (WIDE = false) gives each thread an
-// LDS row of NARROW_LIMBS limbs, indexed from the lowest limb its components
-// touch, and marks the entries whose components span more; the second (WIDE)
-// converts only those, with a row over the whole double range.
 __device__ inline void from_doubles_entry(const double* __restrict__ src, int rows, int ncomp, int64_t ld,
                                           int64_t plane, DOutPart out, int64_t ldo, int prec, int L, int* status,
                                           int* pending, int64_t e, uint64_t* A, bool wide);
@@ -70,6 +66,10 @@ __device__ inline void from_doubles_entry(const double* __restrict__ src, int ro
 // an entry to the second, cleared before the first pass.
 __global__ void clear_flag_kernel(int* pending) { *pending = 0; }
 
+// Two passes over the entries: the first (WIDE = false) gives each thread an
+// LDS row of NARROW_LIMBS limbs, indexed from the lowest limb its components
+// touch, and marks the entries whose components span more; the second (WIDE)
+// converts only those, with a row over the whole double range.
 template <bool WIDE>
 __global__ __launch_bounds__(CODEC_THREADS) void from_doubles_kernel(const double* __restrict__ src, int rows,
                                                                     int cols, int ncomp, int64_t ld, int64_t plane,
