@@ -222,6 +222,53 @@ int mp_cgemm_batched_acc(int count, const mpcg_problem *problems, int prec_bits,
                          const mpcg_options *opt, mpcg_info *info);
 
 /*
+ * mp_zgetrf - blocked complex LU factorization with partial pivoting, P A =
+ * L U, in place (Sec. IV-B: the factorization whose trailing updates A22 -
+ * L21 U12 are matrix products).  A is n x n (device arrays, leading
+ * dimension lda >= max(1, n)); on return its strict lower triangle holds L
+ * (unit diagonal not stored) and its upper triangle U.  ipiv (device int32
+ * [n], caller-owned) receives the interchanges, 0-based: row c was exchanged
+ * with row ipiv[c] >= c, in the order c = 0, 1, ...  nb is the block width
+ * (the paper's K; 0 means 64).
+ *
+ * Order of operations (each product or update rounded once per component,
+ * to nearest with ties to even, as in mp_cgemm_acc):
+ *   for each block column j of width jb:
+ *     for each column c of the block:
+ *       pivot: the first row r >= c with the largest RNE(|Re a_rc| + |Im a_rc|)
+ *       (LAPACK's |Re| + |Im| magnitude, rounded once); rows c and r
+ *       exchanged over all n columns;
+ *       reciprocal of the pivot y: conj(y) * x, x from a seed of 1/|y|^2 (64
+ *       bits; exact for a power of two) and Newton steps x := x + x (1 - |y|^2 x)
+ *       until at least prec_bits + 4 bits are reached;
+ *       column below the pivot := each entry times the reciprocal;
+ *       rank-1 update of the rest of the block column;
+ *     U12 := L11^-1 A12 by rank-1 updates; A22 := A22 - L21 U12 (k = jb).
+ * A zero pivot column is multiplied by zero and reported in the return value.
+ * mode (MPCG_4M / MPCG_3M) selects the product form, which does not change a
+ * bit of the result.  Synchronous (returns after the device work); allocates
+ * a scratch buffer of about 22 n (8L + 5) bytes.
+ * Returns 0, c + 1 if the first exactly zero pivot was in column c (as
+ * LAPACK's info), MPCG_EINVAL (bad n, lda, nb, precision, mode, NULL pointer,
+ * overlapping arrays), MPCG_ERANGE, MPCG_EHIP.
+ */
+int mp_zgetrf(int n, mpcg_cmat *A, int lda, int *ipiv, int nb, int prec_bits, int mode);
+
+/*
+ * mp_zgetrs - solves A X = B with the factors of mp_zgetrf (same n, lda,
+ * ipiv, prec_bits): B (n x nrhs, device, leading dimension ldb >= max(1, n))
+ * is overwritten by X.  The interchanges are applied to B; then, row by row,
+ * Y_c := RNE(B_c - L(c, 0:c) Y(0:c, :)) for c = 1 .. n-1 (one rounding per
+ * entry) and, for c = n-1 down to 0, X_c := RNE(RNE(Y_c - U(c, c+1:n)
+ * X(c+1:n, :)) * reciprocal of U(c, c)), the reciprocal formed as in
+ * mp_zgetrf (Sec. IV-B: forward and backward substitution).  Synchronous.
+ * Returns 0, MPCG_EINVAL (also for B overlapping A or ipiv), MPCG_ERANGE,
+ * MPCG_EHIP.
+ */
+int mp_zgetrs(int n, int nrhs, const mpcg_cmat *A, int lda, const int *ipiv, mpcg_cmat *B, int ldb, int prec_bits,
+              int mode);
+
+/*
  * Multi-component fixed-precision inputs (double-double, triple-double,
  * quad-double), the multi-component arithmetic the paper's concluding section
  * names for future work: converts them into the number format above, so that

@@ -108,8 +108,12 @@ _lib.mpcg_from_doubles.argtypes = [_i, _i, _i, _vp, _i, ctypes.c_longlong, _P(mp
 _lib.mpcg_from_doubles.restype = _i
 _lib.mpcg_to_doubles.argtypes = [_i, _i, _P(mpcg_part), _i, _i, _i, _vp, _i, ctypes.c_longlong]
 _lib.mpcg_to_doubles.restype = _i
+_lib.mp_zgetrf.argtypes = [_i, _P(mpcg_cmat), _i, _vp, _i, _i, _i]
+_lib.mp_zgetrf.restype = _i
+_lib.mp_zgetrs.argtypes = [_i, _i, _P(mpcg_cmat), _i, _vp, _P(mpcg_cmat), _i, _i, _i]
+_lib.mp_zgetrs.restype = _i
 
-EXPORTS = ["mp_cgemm", "mp_cgemm_ex", "mp_cgemm_acc", "mp_cgemm_batched", "mp_cgemm_batched_acc", "mpcg_set_stream", "mpcg_set_workspace", "mpcg_workspace_size",
+EXPORTS = ["mp_cgemm", "mp_cgemm_ex", "mp_cgemm_acc", "mp_cgemm_batched", "mp_cgemm_batched_acc", "mp_zgetrf", "mp_zgetrs", "mpcg_set_stream", "mpcg_set_workspace", "mpcg_workspace_size",
            "mpcg_stream_status", "mpcg_last_error", "mpcg_enable_timing", "mpcg_last_timing",
            "mpcg_timing_report", "mpcg_from_doubles", "mpcg_to_doubles"]
 
@@ -374,6 +378,30 @@ def mp_cgemm_batched_acc(problems, prec_bits, sign=-1, mode=MPCG_3M, scheme=MPCG
     _check(_lib.mp_cgemm_batched_acc(len(problems), arr, prec_bits, mode, scheme, sign, ctypes.byref(opt),
                                      ctypes.byref(info)))
     return info.as_dict()
+
+
+def mp_zgetrf_raw(n, A, lda, ipiv_ptr, nb, prec_bits, mode) -> int:
+    return int(_lib.mp_zgetrf(n, A, lda, ipiv_ptr, nb, prec_bits, mode))
+
+
+def mp_zgetrf(n, A: DeviceCMat, lda, ipiv, nb, prec_bits, mode=MPCG_3M) -> int:
+    """Blocked LU with partial pivoting in place; ipiv is an int32 device
+    tensor of n entries (0-based interchanges).  Returns 0 or c + 1 for the
+    first zero pivot in column c (negative codes raise)."""
+    a = A.struct()
+    st = int(_lib.mp_zgetrf(n, ctypes.byref(a), lda, ipiv.data_ptr() if n else None, nb, prec_bits, mode))
+    return st if st > 0 else _check(st)
+
+
+def mp_zgetrs_raw(n, nrhs, A, lda, ipiv_ptr, B, ldb, prec_bits, mode) -> int:
+    return int(_lib.mp_zgetrs(n, nrhs, A, lda, ipiv_ptr, B, ldb, prec_bits, mode))
+
+
+def mp_zgetrs(n, nrhs, A: DeviceCMat, lda, ipiv, B: DeviceCMat, ldb, prec_bits, mode=MPCG_3M) -> int:
+    """Solve A X = B with the factors of mp_zgetrf; B is overwritten by X."""
+    a, b = A.struct(), B.struct()
+    return _check(_lib.mp_zgetrs(n, nrhs, ctypes.byref(a), lda, ipiv.data_ptr() if n else None, ctypes.byref(b),
+                                 ldb, prec_bits, mode))
 
 
 def matmul(A: DeviceCMat, B: DeviceCMat, prec_bits: int, mode=MPCG_3M, scheme=MPCG_EXACT,

@@ -150,6 +150,23 @@ hipError_t launch_fill_zero(void* p, size_t n, hipStream_t stream);
 
 // C := +0 everywhere.
 hipError_t launch_zero(DOutPart cre, DOutPart cim, int m, int n, int64_t ldc, int L, hipStream_t stream);
+// Blocked LU helpers (one stream-ordered launch each).
+// copy: rows x cols block, mode 0 plain, 1 conjugate, 2 componentwise |.|.
+hipError_t launch_lu_copy(DPart sre, DPart sim, int64_t lds, DOutPart dre, DOutPart dim, int64_t ldd, int rows,
+                          int cols, int L, int mode, hipStream_t stream);
+// *piv := base + first index of the largest of the m nonnegative keys; a
+// zero maximum sets *info := col + 1 if *info is 0.
+hipError_t launch_lu_pivot(DPart key, int m, int L, int base, int* piv, int* info, int col, hipStream_t stream);
+// rows `row` and *piv exchanged over ncols columns.
+hipError_t launch_lu_swap(DOutPart re, DOutPart im, int64_t ld, int ncols, int L, int row, const int* piv,
+                          hipStream_t stream);
+// interchanges ipiv[0..n) applied in order to an n x ncols block.
+hipError_t launch_lu_laswp(DOutPart re, DOutPart im, int64_t ld, int ncols, int n, int L, const int* ipiv,
+                           hipStream_t stream);
+// entry 0 := vre + i vim, each in {-1, 0, 1}.
+hipError_t launch_lu_const(DOutPart re, DOutPart im, int L, int vre, int vim, hipStream_t stream);
+// entry 0 of (xre, xim) := seed of 1 / d (d real, entry 0).
+hipError_t launch_lu_seed(DPart d, DOutPart xre, DOutPart xim, int prec, int L, hipStream_t stream);
 hipError_t launch_to_doubles(DPart in, int rows, int cols, int64_t ldi, int prec, int L, int ncomp, double* dst,
                              int64_t ld, int64_t plane, int* status, hipStream_t stream);
 hipError_t launch_from_doubles(const double* src, int rows, int cols, int ncomp, int64_t ld, int64_t plane,

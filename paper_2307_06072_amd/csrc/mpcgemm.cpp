@@ -308,8 +308,13 @@ int record(int idx) {
   return MPCG_OK;
 }
 
+// check_overlap = false is for the factorization's own calls, whose operands
+// are element-disjoint views of one matrix (the scan and split read A and B
+// before the rounding kernel writes C, in stream order) and whose arrays were
+// checked once for the whole matrix: a view's ld x cols region can run past
+// the end of its array.
 int validate(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, int ldb, mpcg_cmat* C,
-             int ldc, int prec_bits, int mode, int scheme, const mpcg_options* opt) {
+             int ldc, int prec_bits, int mode, int scheme, const mpcg_options* opt, bool check_overlap = true) {
   if (m < 0 || n < 0 || k < 0) return set_err(MPCG_EINVAL, "negative dimension (m=%d n=%d k=%d)", m, n, k);
   if (prec_bits < MPCG_MIN_PREC || prec_bits > MPCG_MAX_PREC)
     return set_err(MPCG_EINVAL, "prec_bits %d outside [%d, %d]", prec_bits, MPCG_MIN_PREC, MPCG_MAX_PREC);
@@ -332,7 +337,7 @@ int validate(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* 
   int st;
   if ((st = check_part(C->re, m, n, ldc, L, "C.re", rc))) return st;
   if ((st = check_part(C->im, m, n, ldc, L, "C.im", rc + 3))) return st;
-  for (int a = 0; a < 6; ++a)
+  for (int a = 0; a < 6 && check_overlap; ++a)
     for (int b = a + 1; b < 6; ++b)
       if (overlap(rc[a], rc[b])) return set_err(MPCG_EINVAL, "C arrays overlap each other");
   if (k == 0) return MPCG_OK;
@@ -342,7 +347,7 @@ int validate(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* 
   if ((st = check_part(A->im, m, k, lda, L, "A.im", ra + 3))) return st;
   if ((st = check_part(B->re, k, n, ldb, L, "B.re", ra + 6))) return st;
   if ((st = check_part(B->im, k, n, ldb, L, "B.im", ra + 9))) return st;
-  for (int a = 0; a < 6; ++a)
+  for (int a = 0; a < 6 && check_overlap; ++a)
     for (int b = 0; b < 12; ++b)
       if (overlap(rc[a], ra[b])) return set_err(MPCG_EINVAL, "C overlaps A or B");
   return MPCG_OK;
@@ -351,9 +356,10 @@ int validate(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* 
 // acc = 0: C := AB; acc = +1 / -1: C := C + AB / C - AB, one rounding of the
 // exact sum (C's current entries are the addend).
 int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, int ldb, mpcg_cmat* C, int ldc,
-        int prec_bits, int mode, int scheme, const mpcg_options* opt, mpcg_info* info, int acc = 0) {
+        int prec_bits, int mode, int scheme, const mpcg_options* opt, mpcg_info* info, int acc = 0,
+        bool check_overlap = true) {
   g_err.clear();
-  int st = validate(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, mode, scheme, opt);
+  int st = validate(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, mode, scheme, opt, check_overlap);
   if (st) return st;
   if (acc != 0 && acc != 1 && acc != -1) return set_err(MPCG_EINVAL, "accumulate sign must be +1 or -1");
   if (acc && opt && opt->slice_type == MPCG_SLICE_FP64)
@@ -989,6 +995,237 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
   return MPCG_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Blocked complex LU with partial pivoting (Sec. IV-B) and the solve with its
+// factors.  Every product, update and reciprocal step is a call of `run` on
+// views into the caller's matrix; the small kernels of lu.hip pick pivots,
+// exchange rows, copy and seed.
+// ---------------------------------------------------------------------------
+std::mutex g_lu_mu;
+
+// The view whose entry (0, 0) is entry (r, c) of M (leading dimension ld,
+// `cols` columns); the limb stride is the whole matrix's.
+mpcg_cmat view_at(const mpcg_cmat& M, int ld, int cols, int r, int c) {
+  const int64_t o = (int64_t)c * ld + r;
+  mpcg_cmat v{};
+  for (int h = 0; h < 2; ++h) {
+    const mpcg_part& s = h ? M.im : M.re;
+    mpcg_part& d = h ? v.im : v.re;
+    d.sign = s.sign + o;
+    d.exp = s.exp + o;
+    d.mant = s.mant + o;
+    d.limb_stride = s.limb_stride ? s.limb_stride : (int64_t)ld * cols;
+  }
+  return v;
+}
+
+// Scratch of one factorization or solve: NCOL columns of R entries (R >= the
+// longest column or row handled), plus the singularity word.
+struct LuScratch {
+  static constexpr int NCOL = 11;
+  enum { ABS = 0, KEY, TMP, ONE, OMI, YC, D, X0, X1, E, REC };
+  void* buf = nullptr;
+  mpcg_cmat M{};
+  int R = 0;
+  int* info = nullptr;
+  mpcg_cmat at(int col, int row = 0) const { return view_at(M, R, NCOL, row, col); }
+  ~LuScratch() {
+    if (buf) {
+      (void)hipStreamSynchronize(g_stream);
+      (void)hipFree(buf);
+    }
+  }
+};
+
+int lu_scratch(LuScratch& W, int R, int L) {
+  W.R = std::max(1, R);
+  const size_t ne = (size_t)W.R * LuScratch::NCOL;
+  const size_t part = align256(ne) + align256(4 * ne) + align256(8 * ne * L);
+  HIP_TRY(hipMalloc(&W.buf, 2 * part + 256));
+  char* b = static_cast<char*>(W.buf);
+  for (int h = 0; h < 2; ++h) {
+    mpcg_part& d = h ? W.M.im : W.M.re;
+    char* q = b + h * part;
+    d.sign = reinterpret_cast<uint8_t*>(q);
+    d.exp = reinterpret_cast<int32_t*>(q + align256(ne));
+    d.mant = reinterpret_cast<uint64_t*>(q + align256(ne) + align256(4 * ne));
+    d.limb_stride = (int64_t)ne;
+  }
+  W.info = reinterpret_cast<int*>(b + 2 * part);
+  HIP_TRY(launch_fill_zero(W.info, 256, g_stream));
+  const mpcg_cmat one = W.at(LuScratch::ONE), omi = W.at(LuScratch::OMI);
+  HIP_TRY(launch_lu_const(doutpart(one.re, 0), doutpart(one.im, 0), L, 1, 0, g_stream));
+  HIP_TRY(launch_lu_const(doutpart(omi.re, 0), doutpart(omi.im, 0), L, 1, -1, g_stream));
+  return MPCG_OK;
+}
+
+// One rounded product or update of the factorization (exact scheme).
+int lu_prod(int m, int n, int k, const mpcg_cmat& A, int lda, const mpcg_cmat& B, int ldb, mpcg_cmat C, int ldc,
+            int prec, int mode, int acc) {
+  return run(m, n, k, &A, lda, &B, ldb, &C, ldc, prec, mode, MPCG_EXACT, nullptr, nullptr, acc, false);
+}
+
+// Newton steps taking the seed's 60 correct bits past prec + 4.
+int lu_newton_steps(int prec) {
+  int it = 0;
+  for (long bits = 60; bits < prec + 4; bits *= 2) ++it;
+  return it;
+}
+
+// W[REC] := the reciprocal of the 1 x 1 view y: conj(y) x with x ~ 1/|y|^2
+// from the seed and Newton steps x := x + x (1 - d x), each step two rounded
+// calls.  A zero y gives zero.
+int lu_recip(LuScratch& W, const mpcg_cmat& y, int prec, int mode) {
+  const int L = (prec + 63) / 64;
+  int st;
+  const mpcg_cmat yc = W.at(LuScratch::YC), d = W.at(LuScratch::D), e = W.at(LuScratch::E);
+  mpcg_cmat x = W.at(LuScratch::X0), xn = W.at(LuScratch::X1);
+  HIP_TRY(launch_lu_copy(dpart(y.re, 0), dpart(y.im, 0), 1, doutpart(yc.re, 0), doutpart(yc.im, 0), 1, 1, 1, L, 1,
+                         g_stream));
+  if ((st = lu_prod(1, 1, 1, y, 1, yc, 1, d, 1, prec, mode, 0))) return st;  // |y|^2 (+0 imaginary)
+  HIP_TRY(launch_lu_seed(dpart(d.re, 0), doutpart(x.re, 0), doutpart(x.im, 0), prec, L, g_stream));
+  const mpcg_cmat one = W.at(LuScratch::ONE);
+  for (int it = lu_newton_steps(prec); it > 0; --it) {
+    HIP_TRY(launch_lu_copy(dpart(one.re, 0), dpart(one.im, 0), 1, doutpart(e.re, 0), doutpart(e.im, 0), 1, 1, 1, L,
+                           0, g_stream));
+    if ((st = lu_prod(1, 1, 1, d, 1, x, 1, e, 1, prec, mode, -1))) return st;  // e := 1 - d x
+    HIP_TRY(launch_lu_copy(dpart(x.re, 0), dpart(x.im, 0), 1, doutpart(xn.re, 0), doutpart(xn.im, 0), 1, 1, 1, L,
+                           0, g_stream));
+    if ((st = lu_prod(1, 1, 1, x, 1, e, 1, xn, 1, prec, mode, +1))) return st;  // x' := x + x e
+    std::swap(x, xn);
+  }
+  return lu_prod(1, 1, 1, yc, 1, x, 1, W.at(LuScratch::REC), 1, prec, mode, 0);
+}
+
+int check_square(int n, const mpcg_cmat* A, int lda, int prec_bits, int mode, Region out[6]) {
+  if (n < 0) return set_err(MPCG_EINVAL, "negative dimension n=%d", n);
+  if (prec_bits < MPCG_MIN_PREC || prec_bits > MPCG_MAX_PREC)
+    return set_err(MPCG_EINVAL, "prec_bits %d outside [%d, %d]", prec_bits, MPCG_MIN_PREC, MPCG_MAX_PREC);
+  if (mode != MPCG_4M && mode != MPCG_3M) return set_err(MPCG_EINVAL, "bad mode %d", mode);
+  if (lda < std::max(1, n)) return set_err(MPCG_EINVAL, "lda %d < max(1, n=%d)", lda, n);
+  if (!A) return set_err(MPCG_EINVAL, "A is NULL");
+  const int L = (prec_bits + 63) / 64;
+  int st;
+  if ((st = check_part(A->re, n, n, lda, L, "A.re", out))) return st;
+  if ((st = check_part(A->im, n, n, lda, L, "A.im", out + 3))) return st;
+  for (int a = 0; a < 6; ++a)
+    for (int b = a + 1; b < 6; ++b)
+      if (overlap(out[a], out[b])) return set_err(MPCG_EINVAL, "the arrays of A overlap each other");
+  return MPCG_OK;
+}
+
+int lu_factor(int n, mpcg_cmat* A, int lda, int* ipiv, int nb, int prec, int mode) {
+  g_err.clear();
+  Region ra[6];
+  int st = check_square(n, A, lda, prec, mode, ra);
+  if (st) return st;
+  if (nb < 0) return set_err(MPCG_EINVAL, "negative block width %d", nb);
+  if (n == 0) return MPCG_OK;
+  if (!ipiv) return set_err(MPCG_EINVAL, "ipiv is NULL");
+  const Region rp{(uintptr_t)ipiv, (uintptr_t)ipiv + 4 * (uintptr_t)n};
+  for (auto& r : ra)
+    if (overlap(r, rp)) return set_err(MPCG_EINVAL, "ipiv overlaps A");
+  if (nb == 0) nb = 64;
+  std::lock_guard<std::mutex> lock(g_lu_mu);
+  if ((st = ensure_status_and_pinned())) return st;
+  const int L = (prec + 63) / 64;
+  LuScratch W;
+  if ((st = lu_scratch(W, n, L))) return st;
+  const mpcg_cmat& M = *A;
+  auto at = [&](int r, int c) { return view_at(M, lda, n, r, c); };
+  const DOutPart are = doutpart(M.re, (int64_t)lda * n), aim = doutpart(M.im, (int64_t)lda * n);
+  const mpcg_cmat T = W.at(LuScratch::ABS), K = W.at(LuScratch::KEY), tmp = W.at(LuScratch::TMP);
+  for (int j = 0; j < n; j += nb) {
+    const int jb = std::min(nb, n - j);
+    for (int c = j; c < j + jb; ++c) {
+      const int mr = n - c;  // rows c .. n-1 of column c
+      const mpcg_cmat col = at(c, c);
+      // pivot: the first row of the largest RNE(|Re| + |Im|) = Re((|Re| + i|Im|)(1 - i))
+      HIP_TRY(launch_lu_copy(dpart(col.re, 0), dpart(col.im, 0), lda, doutpart(T.re, 0), doutpart(T.im, 0), W.R, mr,
+                             1, L, 2, g_stream));
+      if ((st = lu_prod(mr, 1, 1, T, W.R, W.at(LuScratch::OMI), 1, K, W.R, prec, mode, 0))) return st;
+      HIP_TRY(launch_lu_pivot(dpart(K.re, 0), mr, L, c, ipiv + c, W.info, c, g_stream));
+      HIP_TRY(launch_lu_swap(are, aim, lda, n, L, c, ipiv + c, g_stream));
+      if ((st = lu_recip(W, col, prec, mode))) return st;
+      if (mr > 1) {
+        // l := a r below the pivot, through the scratch column
+        if ((st = lu_prod(mr - 1, 1, 1, at(c + 1, c), lda, W.at(LuScratch::REC), 1, tmp, W.R, prec, mode, 0)))
+          return st;
+        const mpcg_cmat dst = at(c + 1, c);
+        HIP_TRY(launch_lu_copy(dpart(tmp.re, 0), dpart(tmp.im, 0), W.R, doutpart(dst.re, 0), doutpart(dst.im, 0), lda,
+                               mr - 1, 1, L, 0, g_stream));
+        // rank-1 update of the rest of the panel
+        if (c + 1 < j + jb &&
+            (st = lu_prod(mr - 1, j + jb - c - 1, 1, at(c + 1, c), lda, at(c, c + 1), lda, at(c + 1, c + 1), lda,
+                          prec, mode, -1)))
+          return st;
+      }
+    }
+    const int nr = n - j - jb;
+    if (nr > 0) {
+      // U12 := L11^-1 A12 (unit lower, column by column of L11)
+      for (int c = j; c + 1 < j + jb; ++c)
+        if ((st = lu_prod(j + jb - c - 1, nr, 1, at(c + 1, c), lda, at(c, j + jb), lda, at(c + 1, j + jb), lda, prec,
+                          mode, -1)))
+          return st;
+      // A22 := A22 - L21 U12, one rounding per entry
+      if ((st = lu_prod(nr, nr, jb, at(j + jb, j), lda, at(j, j + jb), lda, at(j + jb, j + jb), lda, prec, mode, -1)))
+        return st;
+    }
+  }
+  int info = 0;
+  HIP_TRY(hipMemcpyAsync(&info, W.info, sizeof(int), hipMemcpyDeviceToHost, g_stream));
+  HIP_TRY(hipStreamSynchronize(g_stream));
+  return info;
+}
+
+int lu_solve(int n, int nrhs, const mpcg_cmat* A, int lda, const int* ipiv, mpcg_cmat* B, int ldb, int prec,
+             int mode) {
+  g_err.clear();
+  Region ra[6], rb[6];
+  int st = check_square(n, A, lda, prec, mode, ra);
+  if (st) return st;
+  if (nrhs < 0) return set_err(MPCG_EINVAL, "negative nrhs %d", nrhs);
+  if (ldb < std::max(1, n)) return set_err(MPCG_EINVAL, "ldb %d < max(1, n=%d)", ldb, n);
+  if (n == 0 || nrhs == 0) return MPCG_OK;
+  if (!ipiv || !B) return set_err(MPCG_EINVAL, "ipiv or B is NULL");
+  const int L = (prec + 63) / 64;
+  if ((st = check_part(B->re, n, nrhs, ldb, L, "B.re", rb))) return st;
+  if ((st = check_part(B->im, n, nrhs, ldb, L, "B.im", rb + 3))) return st;
+  const Region rp{(uintptr_t)ipiv, (uintptr_t)ipiv + 4 * (uintptr_t)n};
+  for (int a = 0; a < 6; ++a) {
+    if (overlap(rb[a], rp)) return set_err(MPCG_EINVAL, "ipiv overlaps B");
+    for (int b = 0; b < 6; ++b)
+      if ((b > a && overlap(rb[a], rb[b])) || overlap(rb[a], ra[b]))
+        return set_err(MPCG_EINVAL, "B overlaps A or itself");
+  }
+  std::lock_guard<std::mutex> lock(g_lu_mu);
+  if ((st = ensure_status_and_pinned())) return st;
+  LuScratch W;
+  if ((st = lu_scratch(W, std::max(n, nrhs), L))) return st;
+  auto a_at = [&](int r, int c) { return view_at(*A, lda, n, r, c); };
+  auto b_at = [&](int r, int c) { return view_at(*B, ldb, nrhs, r, c); };
+  HIP_TRY(launch_lu_laswp(doutpart(B->re, (int64_t)ldb * nrhs), doutpart(B->im, (int64_t)ldb * nrhs), ldb, nrhs, n,
+                          L, ipiv, g_stream));
+  // forward: row c of Y := RNE(B_c - L(c, 0:c) Y(0:c, :)), unit diagonal
+  for (int c = 1; c < n; ++c)
+    if ((st = lu_prod(1, nrhs, c, a_at(c, 0), lda, b_at(0, 0), ldb, b_at(c, 0), ldb, prec, mode, -1))) return st;
+  // backward: row c of X := RNE(RNE(Y_c - U(c, c+1:n) X(c+1:n, :)) * recip(U(c, c)))
+  const mpcg_cmat tmp = W.at(LuScratch::TMP);  // a 1 x nrhs row, leading dimension 1
+  for (int c = n - 1; c >= 0; --c) {
+    if (c + 1 < n &&
+        (st = lu_prod(1, nrhs, n - c - 1, a_at(c, c + 1), lda, b_at(c + 1, 0), ldb, b_at(c, 0), ldb, prec, mode, -1)))
+      return st;
+    if ((st = lu_recip(W, a_at(c, c), prec, mode))) return st;
+    if ((st = lu_prod(1, nrhs, 1, W.at(LuScratch::REC), 1, b_at(c, 0), ldb, tmp, 1, prec, mode, 0))) return st;
+    const mpcg_cmat dst = b_at(c, 0);
+    HIP_TRY(launch_lu_copy(dpart(tmp.re, 0), dpart(tmp.im, 0), 1, doutpart(dst.re, 0), doutpart(dst.im, 0), ldb, 1,
+                           nrhs, L, 0, g_stream));
+  }
+  return MPCG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1024,6 +1261,15 @@ int mp_cgemm_batched_acc(int count, const mpcg_problem* problems, int prec_bits,
     return set_err(MPCG_EINVAL, "accumulate sign must be +1 or -1");
   }
   return run_batched(count, problems, prec_bits, mode, scheme, opt, info, sign);
+}
+
+int mp_zgetrf(int n, mpcg_cmat* A, int lda, int* ipiv, int nb, int prec_bits, int mode) {
+  return lu_factor(n, A, lda, ipiv, nb, prec_bits, mode);
+}
+
+int mp_zgetrs(int n, int nrhs, const mpcg_cmat* A, int lda, const int* ipiv, mpcg_cmat* B, int ldb, int prec_bits,
+              int mode) {
+  return lu_solve(n, nrhs, A, lda, ipiv, B, ldb, prec_bits, mode);
 }
 
 int mpcg_set_stream(void* hip_stream) {

@@ -242,3 +242,54 @@ def test_codec_rejects_dst_overlapping_src():
     part = mp.mpcg_part(8 << 40, src + 16, (8 << 40) + (2 << 24), 0)
     assert _codec(src=src, dst_part=part) == mp.MPCG_EINVAL
     assert "overlap" in mp.mpcg_last_error()
+
+
+# ---------------------------------------------------------------------------
+# blocked LU entry points: argument errors found on the host
+# ---------------------------------------------------------------------------
+def _getrf(n=4, lda=4, ipiv=9 << 40, nb=2, p=256, mode=1, A=None):
+    import paper_2307_06072_amd as mp
+    A = _fake_cmat(1 << 40) if A is None else A
+    return mp._lib.mp_zgetrf(n, ctypes.byref(A) if A is not False else None, lda, ipiv, nb, p, mode)
+
+
+@pytest.mark.parametrize("kw", [dict(n=-1), dict(lda=3), dict(ipiv=0), dict(nb=-1), dict(p=1), dict(p=4097),
+                                dict(mode=2), dict(A=False)])
+def test_getrf_rejects_bad_arguments(kw):
+    import paper_2307_06072_amd as mp
+    assert _getrf(**kw) == mp.MPCG_EINVAL
+    assert mp.mpcg_last_error()
+
+
+def test_getrf_rejects_ipiv_inside_a():
+    import paper_2307_06072_amd as mp
+    assert _getrf(ipiv=(1 << 40) + (1 << 24) + 8) == mp.MPCG_EINVAL  # inside A.re's exponents
+    assert "ipiv" in mp.mpcg_last_error()
+
+
+def test_getrf_getrs_empty_is_a_no_op():
+    import paper_2307_06072_amd as mp
+    assert _getrf(n=0, lda=1) == 0
+    A, B = _fake_cmat(1 << 40), _fake_cmat(2 << 40)
+    assert mp._lib.mp_zgetrs(0, 3, ctypes.byref(A), 1, None, ctypes.byref(B), 1, 256, 1) == 0
+    assert mp._lib.mp_zgetrs(4, 0, ctypes.byref(A), 4, 9 << 40, ctypes.byref(B), 4, 256, 1) == 0
+
+
+@pytest.mark.parametrize("kw", [dict(n=-1), dict(nrhs=-1), dict(lda=3), dict(ldb=3), dict(ipiv=0), dict(B=False),
+                                dict(p=1), dict(mode=5)])
+def test_getrs_rejects_bad_arguments(kw):
+    import paper_2307_06072_amd as mp
+    args = dict(n=4, nrhs=2, lda=4, ipiv=9 << 40, ldb=4, p=256, mode=1, B=None)
+    args.update(kw)
+    A = _fake_cmat(1 << 40)
+    B = _fake_cmat(2 << 40) if args["B"] is None else args["B"]
+    st = mp._lib.mp_zgetrs(args["n"], args["nrhs"], ctypes.byref(A), args["lda"], args["ipiv"],
+                           ctypes.byref(B) if B is not False else None, args["ldb"], args["p"], args["mode"])
+    assert st == mp.MPCG_EINVAL
+
+
+def test_getrs_rejects_b_overlapping_a():
+    import paper_2307_06072_amd as mp
+    A = _fake_cmat(1 << 40)
+    assert mp._lib.mp_zgetrs(4, 2, ctypes.byref(A), 4, 9 << 40, ctypes.byref(A), 4, 256, 1) == mp.MPCG_EINVAL
+    assert "overlap" in mp.mpcg_last_error()
