@@ -245,6 +245,71 @@ def codec_case():
                                   "hbm_peak_GBps": PEAK_HBM_GBS}}
 
 
+def lu_full_case(widths=(128,)):
+    """The paper's LU experiment (Sec. IV-B) at n = 1024 and 256 bits: A with
+    random entries (exponents on [-2, 2]), x_k = k + k i, b = A x rounded once
+    by mp_cgemm; mp_zgetrf with block width K, then mp_zgetrs.  Reports the
+    seconds of each and the largest relative error of x (|Re| + |Im| norm)."""
+    from fractions import Fraction
+    import torch
+    import paper_2307_06072_amd as mp
+    from mpgen import EXP_ZERO, random_cmat
+    n, p = 1024, 256
+    A = random_cmat([6, n], 0, n, n, p, 2)
+    L = (p + 63) // 64
+    xs = random_cmat([6, n], 1, n, 1, p, 0)  # overwritten below with x_k = k + k i
+    for part in (xs.re, xs.im):
+        for k in range(n):
+            v = k + 1
+            e = v.bit_length()
+            part.sign[0, k] = 0
+            part.exp[0, k] = e
+            part.mant[:, 0, k] = 0
+            part.mant[L - 1, 0, k] = v << (64 - e)
+    dx = mp.to_device(xs)
+    out = {}
+    mp.mpcg_set_stream()
+    # warm-up of every kernel on a small case
+    dW = mp.to_device(random_cmat([6, 16], 0, 16, 16, p, 2))
+    wp = torch.zeros(16, dtype=torch.int32, device="cuda")
+    mp.mp_zgetrf(16, dW, dW.ld, wp, 8, p, mp.MPCG_3M)
+    for K in widths:
+        log(f"full LU n={n} p={p} K={K}")
+        dA = mp.to_device(A)
+        dB = mp.device_empty(n, 1, p)
+        mp.mp_cgemm(n, 1, n, dA, dA.ld, dx, dx.ld, dB, dB.ld, p)
+        ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = mp.mp_zgetrf(n, dA, dA.ld, ipiv, K, p, mp.MPCG_3M)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        mp.mp_zgetrs(n, 1, dA, dA.ld, ipiv, dB, dB.ld, p, mp.MPCG_3M)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if info != 0 or mp.mpcg_stream_status() != 0:
+            raise RuntimeError(f"LU failed: info {info}, {mp.mpcg_last_error()}")
+        h = mp.to_numpy(dB)
+        err = Fraction(0)
+        for k in range(n):
+            comps = []
+            for name in ("re", "im"):
+                sg, ex, mt = h[name]
+                if ex[0, k] == EXP_ZERO:
+                    comps.append(Fraction(0))
+                    continue
+                M = 0
+                for l in range(L - 1, -1, -1):
+                    M = (M << 64) | int(mt[l, 0, k])
+                v = Fraction(M) * Fraction(2) ** (int(ex[0, k]) - 64 * L)
+                comps.append(-v if sg[0, k] else v)
+            err = max(err, (abs(comps[0] - (k + 1)) + abs(comps[1] - (k + 1))) / (2 * (k + 1)))
+        out[f"K{K}"] = {"getrf_s": t1 - t0, "getrs_s": t2 - t1, "max_rel_err": float(err)}
+        log(f"  getrf {t1 - t0:.2f} s, getrs {t2 - t1:.2f} s, max relative error {float(err):.2e}")
+        del dA, dB
+    return {"lu_full_n1024_p256": out}
+
+
 def lu_update_stream():
     """The 31 trailing updates of a blocked LU of order 4096 with block 128
     (A22 := A22 - L21 U12, r x 128 times 128 x r, r = 3968 ... 128) at 256
@@ -332,7 +397,7 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration)")
-    ap.add_argument("--family", choices=["batched", "lu", "codec"], default=None,
+    ap.add_argument("--family", choices=["batched", "lu", "codec", "lufull"], default=None,
                     help="only run one comparison family (for profiling) and print its record")
     args = ap.parse_args()
 
@@ -358,7 +423,8 @@ def main() -> int:
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 3}))
         return 0
     if args.family:
-        rec = {"batched": batched_case, "lu": lu_update_stream, "codec": codec_case}[args.family]()
+        rec = {"batched": batched_case, "lu": lu_update_stream, "codec": codec_case,
+               "lufull": lambda: lu_full_case((64, 128, 352))}[args.family]()
         print(json.dumps({"family": args.family, **rec}), flush=True)
         return 0
     log(f"generating {args.workload}")

@@ -124,14 +124,26 @@ __global__ void const_kernel(DOutPart re, DOutPart im, int L, int vre, int vim) 
   }
 }
 
-// Seed of 1/d for a real d (entry 0 of `d`): with m the top limb of d's
+// Seed of 1/d for a real d (entry t of consecutive entries, one thread
+// each): with m the top limb of d's
 // significand, q = floor((2^127 - 1) / m) in [2^63, 2^64) by restoring
 // division, kept to prec bits, with exponent 1 - e(d); so the seed is q *
 // 2^(-63 - e(d)), within 2^-62 of 1/d relatively.  A power of two gets its
 // exact reciprocal 2^(1 - e(d)) (significand 1/2, exponent 2 - e(d)), zero
 // gives zero.
-__global__ void seed_kernel(DPart d, DOutPart xre, DOutPart xim, int prec, int L) {
-  if (threadIdx.x != 0) return;
+__global__ void __launch_bounds__(LU_THREADS) seed_kernel(DPart d, DOutPart xre, DOutPart xim, int prec, int L,
+                                                          int count) {
+  const int t = blockIdx.x * LU_THREADS + threadIdx.x;
+  if (t >= count) return;
+  d.sign += t;
+  d.exp += t;
+  d.mant += t;
+  xre.sign += t;
+  xre.exp += t;
+  xre.mant += t;
+  xim.sign += t;
+  xim.exp += t;
+  xim.mant += t;
   write_small(xim, 0, L);
   const int32_t e = d.exp[0];
   if (e == EXP_ZERO) {
@@ -204,8 +216,9 @@ hipError_t launch_lu_const(DOutPart re, DOutPart im, int L, int vre, int vim, hi
   return hipGetLastError();
 }
 
-hipError_t launch_lu_seed(DPart d, DOutPart xre, DOutPart xim, int prec, int L, hipStream_t stream) {
-  seed_kernel<<<1, 64, 0, stream>>>(d, xre, xim, prec, L);
+hipError_t launch_lu_seed(DPart d, DOutPart xre, DOutPart xim, int prec, int L, int count, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  seed_kernel<<<blocks_for(count), LU_THREADS, 0, stream>>>(d, xre, xim, prec, L, count);
   return hipGetLastError();
 }
 

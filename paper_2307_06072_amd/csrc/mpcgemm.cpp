@@ -594,7 +594,7 @@ struct BatchProblem {
 
 // acc = 0: C_i := A_i B_i; +1 / -1: C_i := C_i +- A_i B_i in place, one rounding.
 int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, int scheme,
-                const mpcg_options* opt, mpcg_info* info, int acc = 0) {
+                const mpcg_options* opt, mpcg_info* info, int acc = 0, bool check_overlap = true) {
   g_err.clear();
   if (count < 0) return set_err(MPCG_EINVAL, "negative batch count %d", count);
   if (acc != 0 && acc != 1 && acc != -1) return set_err(MPCG_EINVAL, "accumulate sign must be +1 or -1");
@@ -605,12 +605,13 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
   std::vector<Region> outs;
   for (int i = 0; i < count; ++i) {
     const mpcg_problem& q = probs[i];
-    int st = validate(q.m, q.n, q.k, q.A, q.lda, q.B, q.ldb, q.C, q.ldc, prec_bits, mode, scheme, opt);
+    int st = validate(q.m, q.n, q.k, q.A, q.lda, q.B, q.ldb, q.C, q.ldc, prec_bits, mode, scheme, opt,
+                      check_overlap);
     if (st) {
       const std::string e = g_err;
       return set_err(st, "problem %d: %s", i, e.c_str());
     }
-    if (q.m > 0 && q.n > 0) {
+    if (q.m > 0 && q.n > 0 && check_overlap) {
       const int L = (prec_bits + 63) / 64;
       Region r[6];
       check_part(q.C->re, q.m, q.n, q.ldc, L, "C.re", r);
@@ -623,7 +624,7 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
     for (size_t b = a + 1; b < outs.size(); ++b)
       if (a / 6 != b / 6 && overlap(outs[a], outs[b]))
         return set_err(MPCG_EINVAL, "outputs of problems %zu and %zu overlap", a / 6, b / 6);
-  {
+  if (check_overlap) {
     const int L = (prec_bits + 63) / 64;
     for (int i = 0; i < count; ++i) {
       const mpcg_problem& q = probs[i];
@@ -1084,7 +1085,7 @@ int lu_recip(LuScratch& W, const mpcg_cmat& y, int prec, int mode) {
   HIP_TRY(launch_lu_copy(dpart(y.re, 0), dpart(y.im, 0), 1, doutpart(yc.re, 0), doutpart(yc.im, 0), 1, 1, 1, L, 1,
                          g_stream));
   if ((st = lu_prod(1, 1, 1, y, 1, yc, 1, d, 1, prec, mode, 0))) return st;  // |y|^2 (+0 imaginary)
-  HIP_TRY(launch_lu_seed(dpart(d.re, 0), doutpart(x.re, 0), doutpart(x.im, 0), prec, L, g_stream));
+  HIP_TRY(launch_lu_seed(dpart(d.re, 0), doutpart(x.re, 0), doutpart(x.im, 0), prec, L, 1, g_stream));
   const mpcg_cmat one = W.at(LuScratch::ONE);
   for (int it = lu_newton_steps(prec); it > 0; --it) {
     HIP_TRY(launch_lu_copy(dpart(one.re, 0), dpart(one.im, 0), 1, doutpart(e.re, 0), doutpart(e.im, 0), 1, 1, 1, L,
@@ -1206,6 +1207,42 @@ int lu_solve(int n, int nrhs, const mpcg_cmat* A, int lda, const int* ipiv, mpcg
   if ((st = lu_scratch(W, std::max(n, nrhs), L))) return st;
   auto a_at = [&](int r, int c) { return view_at(*A, lda, n, r, c); };
   auto b_at = [&](int r, int c) { return view_at(*B, ldb, nrhs, r, c); };
+  // the reciprocals of U's diagonal, all at once: for every entry the steps of
+  // lu_recip, each step one batched call over the n entries (1 x n rows of
+  // the scratch, leading dimension 1)
+  {
+    const mpcg_cmat dg = W.at(LuScratch::ABS), yc = W.at(LuScratch::YC), d = W.at(LuScratch::D),
+                    e = W.at(LuScratch::E), one = W.at(LuScratch::ONE), rec = W.at(LuScratch::REC);
+    mpcg_cmat x = W.at(LuScratch::X0), xn = W.at(LuScratch::X1);
+    const mpcg_cmat diag = a_at(0, 0);  // entry c of the diagonal at c (lda + 1)
+    HIP_TRY(launch_lu_copy(dpart(diag.re, 0), dpart(diag.im, 0), (int64_t)lda + 1, doutpart(dg.re, 0),
+                           doutpart(dg.im, 0), 1, 1, n, L, 0, g_stream));
+    HIP_TRY(launch_lu_copy(dpart(dg.re, 0), dpart(dg.im, 0), 1, doutpart(yc.re, 0), doutpart(yc.im, 0), 1, 1, n, L,
+                           1, g_stream));
+    std::vector<mpcg_cmat> va(n), vb(n), vc(n);
+    std::vector<mpcg_problem> probs(n);
+    auto batch = [&](const mpcg_cmat& X, const mpcg_cmat& Y, const mpcg_cmat& Z, int acc) -> int {
+      for (int i = 0; i < n; ++i) {
+        va[i] = view_at(X, 1, W.R * LuScratch::NCOL, 0, i);
+        vb[i] = view_at(Y, 1, W.R * LuScratch::NCOL, 0, i);
+        vc[i] = view_at(Z, 1, W.R * LuScratch::NCOL, 0, i);
+        probs[i] = mpcg_problem{1, 1, 1, &va[i], 1, &vb[i], 1, &vc[i], 1};
+      }
+      return run_batched(n, probs.data(), prec, mode, MPCG_EXACT, nullptr, nullptr, acc, false);
+    };
+    if ((st = batch(dg, yc, d, 0))) return st;  // |y|^2
+    HIP_TRY(launch_lu_seed(dpart(d.re, 0), doutpart(x.re, 0), doutpart(x.im, 0), prec, L, n, g_stream));
+    for (int it = lu_newton_steps(prec); it > 0; --it) {
+      HIP_TRY(launch_lu_copy(dpart(one.re, 0), dpart(one.im, 0), 0, doutpart(e.re, 0), doutpart(e.im, 0), 1, 1, n,
+                             L, 0, g_stream));
+      if ((st = batch(d, x, e, -1))) return st;  // e := 1 - d x
+      HIP_TRY(launch_lu_copy(dpart(x.re, 0), dpart(x.im, 0), 1, doutpart(xn.re, 0), doutpart(xn.im, 0), 1, 1, n, L,
+                             0, g_stream));
+      if ((st = batch(x, e, xn, +1))) return st;  // x' := x + x e
+      std::swap(x, xn);
+    }
+    if ((st = batch(yc, x, rec, 0))) return st;
+  }
   HIP_TRY(launch_lu_laswp(doutpart(B->re, (int64_t)ldb * nrhs), doutpart(B->im, (int64_t)ldb * nrhs), ldb, nrhs, n,
                           L, ipiv, g_stream));
   // forward: row c of Y := RNE(B_c - L(c, 0:c) Y(0:c, :)), unit diagonal
@@ -1217,8 +1254,7 @@ int lu_solve(int n, int nrhs, const mpcg_cmat* A, int lda, const int* ipiv, mpcg
     if (c + 1 < n &&
         (st = lu_prod(1, nrhs, n - c - 1, a_at(c, c + 1), lda, b_at(c + 1, 0), ldb, b_at(c, 0), ldb, prec, mode, -1)))
       return st;
-    if ((st = lu_recip(W, a_at(c, c), prec, mode))) return st;
-    if ((st = lu_prod(1, nrhs, 1, W.at(LuScratch::REC), 1, b_at(c, 0), ldb, tmp, 1, prec, mode, 0))) return st;
+    if ((st = lu_prod(1, nrhs, 1, W.at(LuScratch::REC, c), 1, b_at(c, 0), ldb, tmp, 1, prec, mode, 0))) return st;
     const mpcg_cmat dst = b_at(c, 0);
     HIP_TRY(launch_lu_copy(dpart(tmp.re, 0), dpart(tmp.im, 0), 1, doutpart(dst.re, 0), doutpart(dst.im, 0), ldb, 1,
                            nrhs, L, 0, g_stream));
