@@ -1062,9 +1062,14 @@ int lu_scratch(LuScratch& W, int R, int L) {
 }
 
 // One rounded product or update of the factorization (exact scheme).
+// A real operand (imaginary part +0) has exponent spread 0 in every row, so
+// products of real numbers are planned from a spread bound of 1 with no
+// read-back of the scan (a larger spread would be reported, not mis-rounded).
 int lu_prod(int m, int n, int k, const mpcg_cmat& A, int lda, const mpcg_cmat& B, int ldb, mpcg_cmat C, int ldc,
-            int prec, int mode, int acc) {
-  return run(m, n, k, &A, lda, &B, ldb, &C, ldc, prec, mode, MPCG_EXACT, nullptr, nullptr, acc, false);
+            int prec, int mode, int acc, bool real_operands = false) {
+  const mpcg_options bound{MPCG_SLICE_INT8, 0, 0, 0, 1};
+  return run(m, n, k, &A, lda, &B, ldb, &C, ldc, prec, mode, MPCG_EXACT, real_operands ? &bound : nullptr, nullptr,
+             acc, false);
 }
 
 // Newton steps taking the seed's 60 correct bits past prec + 4.
@@ -1090,10 +1095,10 @@ int lu_recip(LuScratch& W, const mpcg_cmat& y, int prec, int mode) {
   for (int it = lu_newton_steps(prec); it > 0; --it) {
     HIP_TRY(launch_lu_copy(dpart(one.re, 0), dpart(one.im, 0), 1, doutpart(e.re, 0), doutpart(e.im, 0), 1, 1, 1, L,
                            0, g_stream));
-    if ((st = lu_prod(1, 1, 1, d, 1, x, 1, e, 1, prec, mode, -1))) return st;  // e := 1 - d x
+    if ((st = lu_prod(1, 1, 1, d, 1, x, 1, e, 1, prec, mode, -1, true))) return st;  // e := 1 - d x
     HIP_TRY(launch_lu_copy(dpart(x.re, 0), dpart(x.im, 0), 1, doutpart(xn.re, 0), doutpart(xn.im, 0), 1, 1, 1, L,
                            0, g_stream));
-    if ((st = lu_prod(1, 1, 1, x, 1, e, 1, xn, 1, prec, mode, +1))) return st;  // x' := x + x e
+    if ((st = lu_prod(1, 1, 1, x, 1, e, 1, xn, 1, prec, mode, +1, true))) return st;  // x' := x + x e
     std::swap(x, xn);
   }
   return lu_prod(1, 1, 1, yc, 1, x, 1, W.at(LuScratch::REC), 1, prec, mode, 0);
