@@ -9,7 +9,9 @@ goes to stderr.
 
 Also reported in "extra": the 512^3 / 512-bit family (FP64-slice 4M vs
 INT8-slice 4M vs INT8-slice 3M, exact and truncated) with the INT8-3M over
-FP64-4M speedup, and the truncated scheme on the default workload.
+FP64-4M speedup, the truncated scheme on the default workload, a batch of
+256 products, the LU trailing-update stream, the paper's full LU problem
+(n = 1024, 256 bits, K = 128) and the multi-component codec.
 """
 from __future__ import annotations
 
@@ -494,6 +496,7 @@ def main() -> int:
         extra.update(small_latency_case())
         extra.update(batched_case())
         extra.update(lu_update_stream())
+        extra.update(lu_full_case())
         extra.update(codec_case())
 
     cpu = None
