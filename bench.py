@@ -399,6 +399,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration)")
+    ap.add_argument("--lu-widths", default="64,128,352",
+                    help="block widths K of the full-LU family (comma-separated)")
     ap.add_argument("--family", choices=["batched", "lu", "codec", "lufull"], default=None,
                     help="only run one comparison family (for profiling) and print its record")
     args = ap.parse_args()
@@ -426,7 +428,7 @@ def main() -> int:
         return 0
     if args.family:
         rec = {"batched": batched_case, "lu": lu_update_stream, "codec": codec_case,
-               "lufull": lambda: lu_full_case((64, 128, 352))}[args.family]()
+               "lufull": lambda: lu_full_case(tuple(int(v) for v in args.lu_widths.split(",")))}[args.family]()
         print(json.dumps({"family": args.family, **rec}), flush=True)
         return 0
     log(f"generating {args.workload}")
