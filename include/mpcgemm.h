@@ -136,6 +136,15 @@ typedef struct {
                              from the data; an operand whose spread exceeds the bound makes
                              mpcg_stream_status return MPCG_ESPREAD (that result is invalid),
                              and input exponents beyond 2^30 are reported there as MPCG_ERANGE. */
+    int adaptive;         /* 1: slice counts per block of rows of A and of columns of B (the
+                             adaptive numbers of divisions the paper's concluding section asks
+                             for).  After the exponent scan, rows of A and columns of B are
+                             grouped into blocks of 256, neighbouring blocks that need the same
+                             slice count (and, truncated, the same cutoff share) are merged, and
+                             if more than one block results the block products run as one
+                             batched call, each planned from its own spreads (mp_cgemm_batched).
+                             Exact-scheme bits are unchanged; the truncated bound holds per
+                             block.  INT8 slices; ignored with max_spread > 0; 0 = off. */
 } mpcg_options;
 
 /* Plan and timing report of one multiplication. */

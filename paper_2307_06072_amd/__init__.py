@@ -53,7 +53,7 @@ class mpcg_cmat(ctypes.Structure):
 class mpcg_options(ctypes.Structure):
     _fields_ = [("slice_type", ctypes.c_int), ("cutoff_override", ctypes.c_int),
                 ("ksplit_override", ctypes.c_int), ("block_override", ctypes.c_int),
-                ("max_spread", ctypes.c_int)]
+                ("max_spread", ctypes.c_int), ("adaptive", ctypes.c_int)]
 
 
 class mpcg_info(ctypes.Structure):
@@ -310,9 +310,9 @@ def mp_cgemm(m, n, k, A: DeviceCMat, lda, B: DeviceCMat, ldb, C: DeviceCMat, ldc
 
 def mp_cgemm_ex(m, n, k, A: DeviceCMat, lda, B: DeviceCMat, ldb, C: DeviceCMat, ldc, prec_bits,
                 mode=MPCG_3M, scheme=MPCG_EXACT, slice_type=MPCG_SLICE_INT8, cutoff_override=0,
-                ksplit_override=0, block_override=0, max_spread=0) -> dict:
+                ksplit_override=0, block_override=0, max_spread=0, adaptive=0) -> dict:
     a, b, c = A.struct(), B.struct(), C.struct()
-    opt = mpcg_options(slice_type, cutoff_override, ksplit_override, block_override, max_spread)
+    opt = mpcg_options(slice_type, cutoff_override, ksplit_override, block_override, max_spread, adaptive)
     info = mpcg_info()
     _check(_lib.mp_cgemm_ex(m, n, k, ctypes.byref(a), lda, ctypes.byref(b), ldb, ctypes.byref(c), ldc,
                             prec_bits, mode, scheme, ctypes.byref(opt), ctypes.byref(info)))
@@ -326,10 +326,10 @@ def mp_cgemm_acc_raw(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, mode, scheme, s
 
 def mp_cgemm_acc(m, n, k, A: DeviceCMat, lda, B: DeviceCMat, ldb, C: DeviceCMat, ldc, prec_bits, sign=-1,
                  mode=MPCG_3M, scheme=MPCG_EXACT, cutoff_override=0, ksplit_override=0, block_override=0,
-                 max_spread=0) -> dict:
+                 max_spread=0, adaptive=0) -> dict:
     """C := C + sign * A B in place (sign = +1 or -1), one rounding."""
     a, b, c = A.struct(), B.struct(), C.struct()
-    opt = mpcg_options(MPCG_SLICE_INT8, cutoff_override, ksplit_override, block_override, max_spread)
+    opt = mpcg_options(MPCG_SLICE_INT8, cutoff_override, ksplit_override, block_override, max_spread, adaptive)
     info = mpcg_info()
     _check(_lib.mp_cgemm_acc(m, n, k, ctypes.byref(a), lda, ctypes.byref(b), ldb, ctypes.byref(c), ldc,
                              prec_bits, mode, scheme, sign, ctypes.byref(opt), ctypes.byref(info)))

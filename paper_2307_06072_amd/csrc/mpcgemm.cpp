@@ -326,6 +326,7 @@ int validate(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* 
     if (opt->cutoff_override < 0 || opt->ksplit_override < 0 || opt->block_override < 0 || opt->max_spread < 0)
       return set_err(MPCG_EINVAL, "negative option");
     if (opt->max_spread > (1 << 24)) return set_err(MPCG_EINVAL, "max_spread %d too large", opt->max_spread);
+    if (opt->adaptive != 0 && opt->adaptive != 1) return set_err(MPCG_EINVAL, "adaptive must be 0 or 1");
   }
   if (lda < std::max(1, m)) return set_err(MPCG_EINVAL, "lda %d < max(1, m=%d)", lda, m);
   if (ldb < std::max(1, k)) return set_err(MPCG_EINVAL, "ldb %d < max(1, k=%d)", ldb, k);
@@ -353,6 +354,37 @@ int validate(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* 
   return MPCG_OK;
 }
 
+int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, int scheme,
+                const mpcg_options* opt, mpcg_info* info, int acc, bool check_overlap);
+mpcg_cmat view_at(const mpcg_cmat& M, int ld, int cols, int r, int c);
+
+// Contiguous blocks of rows (of A) or columns (of B) for adaptive slicing:
+// blocks of 256, neighbours with the same slice count (and, truncated, the
+// same hat spread in digits) merged.  Returns the block starts, plus the end.
+std::vector<int> adaptive_blocks(const std::vector<RowStat>& st, int p, int x, bool trunc) {
+  const int R = (int)st.size(), BLK = 256;
+  std::vector<int> starts;
+  std::vector<std::pair<int, int>> keys;
+  for (int r0 = 0; r0 < R; r0 += BLK) {
+    int spread = -1, hat = -1;
+    for (int r = r0; r < std::min(R, r0 + BLK); ++r)
+      if (st[r].emax != EXP_ZERO) {
+        spread = std::max(spread, st[r].emax - st[r].emin);
+        hat = std::max(hat, st[r].emax - st[r].ehat);
+      }
+    std::pair<int, int> key{spread < 0 ? -1 : ceil_div(p + x + spread, 7), trunc && hat >= 0 ? ceil_div(hat, 7) : 0};
+    if (!starts.empty() && (key.first < 0 || keys.back() == key)) continue;  // all-zero blocks join a neighbour
+    if (!starts.empty() && keys.back().first < 0) {
+      keys.back() = key;  // a leading all-zero block takes the next block's key
+      continue;
+    }
+    starts.push_back(r0);
+    keys.push_back(key);
+  }
+  starts.push_back(R);
+  return starts;
+}
+
 // acc = 0: C := AB; acc = +1 / -1: C := C + AB / C - AB, one rounding of the
 // exact sum (C's current entries are the addend).
 int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, int ldb, mpcg_cmat* C, int ldc,
@@ -366,7 +398,7 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
     return set_err(MPCG_EUNSUPPORTED, "the accumulating form needs INT8 slices");
   if (info) memset(info, 0, sizeof(*info));
   if (m == 0 || n == 0) return MPCG_OK;
-  std::lock_guard<std::mutex> lock(g_mu);
+  std::unique_lock<std::mutex> lock(g_mu);
   g_timing_valid = false;
   const int L = (prec_bits + 63) / 64;
   const DOutPart cre = doutpart(C->re, (int64_t)ldc * n), cim = doutpart(C->im, (int64_t)ldc * n);
@@ -419,6 +451,32 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
     if (sa.nonzero == 0 || sb.nonzero == 0) {  // AB = 0
       if (!acc) HIP_TRY(launch_zero(cre, cim, m, n, ldc, L, g_stream));
       return MPCG_OK;
+    }
+    if (opt && opt->adaptive && !P.f64) {
+      // per-block slice counts: the row and column statistics of the scan
+      std::vector<RowStat> hA(m), hB(n);
+      HIP_TRY(hipMemcpy(hA.data(), statA, sizeof(RowStat) * m, hipMemcpyDeviceToHost));
+      HIP_TRY(hipMemcpy(hB.data(), statB, sizeof(RowStat) * n, hipMemcpyDeviceToHost));
+      const int xb = P.mode3m ? 2 : 1;
+      const std::vector<int> rb = adaptive_blocks(hA, prec_bits, xb, P.trunc);
+      const std::vector<int> cb = adaptive_blocks(hB, prec_bits, xb, P.trunc);
+      const int nrb = (int)rb.size() - 1, ncb = (int)cb.size() - 1;
+      if (nrb * ncb > 1) {
+        std::vector<mpcg_cmat> va(nrb), vb(ncb), vc((size_t)nrb * ncb);
+        std::vector<mpcg_problem> probs((size_t)nrb * ncb);
+        for (int i = 0; i < nrb; ++i) va[i] = view_at(*A, lda, k, rb[i], 0);
+        for (int j = 0; j < ncb; ++j) vb[j] = view_at(*B, ldb, n, 0, cb[j]);
+        for (int i = 0; i < nrb; ++i)
+          for (int j = 0; j < ncb; ++j) {
+            const size_t t = (size_t)i * ncb + j;
+            vc[t] = view_at(*C, ldc, n, rb[i], cb[j]);
+            probs[t] = mpcg_problem{rb[i + 1] - rb[i], cb[j + 1] - cb[j], k, &va[i], lda, &vb[j], ldb, &vc[t], ldc};
+          }
+        mpcg_options o = *opt;
+        o.adaptive = 0;
+        lock.unlock();
+        return run_batched((int)probs.size(), probs.data(), prec_bits, mode, scheme, &o, info, acc, false);
+      }
     }
     if ((st = plan_slices(P, sa.spread, sb.spread, sa.hat, sb.hat, opt))) return st;
     if ((st = plan_layout(P, opt))) return st;
@@ -594,7 +652,7 @@ struct BatchProblem {
 
 // acc = 0: C_i := A_i B_i; +1 / -1: C_i := C_i +- A_i B_i in place, one rounding.
 int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, int scheme,
-                const mpcg_options* opt, mpcg_info* info, int acc = 0, bool check_overlap = true) {
+                const mpcg_options* opt, mpcg_info* info, int acc, bool check_overlap) {
   g_err.clear();
   if (count < 0) return set_err(MPCG_EINVAL, "negative batch count %d", count);
   if (acc != 0 && acc != 1 && acc != -1) return set_err(MPCG_EINVAL, "accumulate sign must be +1 or -1");
@@ -1292,7 +1350,7 @@ int mp_cgemm_acc(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cm
 
 int mp_cgemm_batched(int count, const mpcg_problem* problems, int prec_bits, int mode, int scheme,
                      const mpcg_options* opt, mpcg_info* info) {
-  return run_batched(count, problems, prec_bits, mode, scheme, opt, info);
+  return run_batched(count, problems, prec_bits, mode, scheme, opt, info, 0, true);
 }
 
 int mp_cgemm_batched_acc(int count, const mpcg_problem* problems, int prec_bits, int mode, int scheme, int sign,
@@ -1301,7 +1359,7 @@ int mp_cgemm_batched_acc(int count, const mpcg_problem* problems, int prec_bits,
     g_err.clear();
     return set_err(MPCG_EINVAL, "accumulate sign must be +1 or -1");
   }
-  return run_batched(count, problems, prec_bits, mode, scheme, opt, info, sign);
+  return run_batched(count, problems, prec_bits, mode, scheme, opt, info, sign, true);
 }
 
 int mp_zgetrf(int n, mpcg_cmat* A, int lda, int* ipiv, int nb, int prec_bits, int mode) {

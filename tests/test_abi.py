@@ -293,3 +293,9 @@ def test_getrs_rejects_b_overlapping_a():
     A = _fake_cmat(1 << 40)
     assert mp._lib.mp_zgetrs(4, 2, ctypes.byref(A), 4, 9 << 40, ctypes.byref(A), 4, 256, 1) == mp.MPCG_EINVAL
     assert "overlap" in mp.mpcg_last_error()
+
+
+def test_adaptive_option_validated():
+    import paper_2307_06072_amd as mp
+    assert _call(opt=mp.mpcg_options(0, 0, 0, 0, 0, 2)) == mp.MPCG_EINVAL
+    assert "adaptive" in mp.mpcg_last_error()
