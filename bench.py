@@ -247,6 +247,50 @@ def codec_case():
                                   "hbm_peak_GBps": PEAK_HBM_GBS}}
 
 
+def adaptive_case(A, B, p):
+    """Adaptive slicing on the 2048 workload with mixed spreads: rows 1536..2047
+    of A and columns 1536..2047 of B each get one entry raised by 2^300, so a
+    quarter of the rows and columns need S = 199 slices while the rest need
+    156.  One plan for the whole product against slice counts per block
+    (mpcg_options.adaptive); the bits are compared on the device."""
+    import torch
+    import paper_2307_06072_amd as mp
+    from mpgen import EXP_ZERO
+    log("adaptive slicing: 2048^3, 1024 bits, a quarter of the rows/columns 300 bits wider")
+    A, B = A.copy(), B.copy()
+    m, k, n = A.rows, A.cols, B.cols
+    for r in range(3 * m // 4, m):
+        if A.re.exp[3, r] != EXP_ZERO:
+            A.re.exp[3, r] += 300
+    for c in range(3 * n // 4, n):
+        if B.re.exp[c, 5] != EXP_ZERO:
+            B.re.exp[c, 5] += 300
+    dA, dB = mp.to_device(A), mp.to_device(B)
+    out, res = {}, []
+    mp.mpcg_set_stream()
+    for adaptive in (0, 1):
+        dC = mp.device_empty(m, n, p)
+        info = mp.mp_cgemm_ex(m, n, k, dA, dA.ld, dB, dB.ld, dC, dC.ld, p, mp.MPCG_3M, mp.MPCG_EXACT, adaptive=adaptive)
+        torch.cuda.synchronize()
+        reps = 2
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            mp.mp_cgemm_ex(m, n, k, dA, dA.ld, dB, dB.ld, dC, dC.ld, p, mp.MPCG_3M, mp.MPCG_EXACT, adaptive=adaptive)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        if mp.mpcg_stream_status() != 0:
+            raise RuntimeError(mp.mpcg_last_error())
+        out["adaptive" if adaptive else "one_plan"] = {"ms_per_call": 1000 * dt, "8mnk_per_s": 8.0 * m * n * k / dt,
+                                                      "max_S_A": info["S_A"], "algo_ops": info["algo_ops"]}
+        res.append(dC)
+        log(f"  adaptive={adaptive}: {1000 * dt:.1f} ms")
+    same = all(torch.equal(getattr(getattr(res[0], h), f), getattr(getattr(res[1], h), f))
+               for h in ("re", "im") for f in ("sign", "exp", "mant"))
+    out["identical_bits"] = bool(same)
+    out["speedup"] = out["one_plan"]["ms_per_call"] / out["adaptive"]["ms_per_call"]
+    return {"cgemm2048_p1024_mixed_spread": out}
+
+
 def lu_full_case(widths=(128,)):
     """The paper's LU experiment (Sec. IV-B) at n = 1024 and 256 bits: A with
     random entries (exponents on [-2, 2]), x_k = k + k i, b = A x rounded once
@@ -401,7 +445,7 @@ def main() -> int:
                     help="only run a plain device-to-device copy of BYTES (counter calibration)")
     ap.add_argument("--lu-widths", default="64,128,352",
                     help="block widths K of the full-LU family (comma-separated)")
-    ap.add_argument("--family", choices=["batched", "lu", "codec", "lufull"], default=None,
+    ap.add_argument("--family", choices=["batched", "lu", "codec", "lufull", "adaptive"], default=None,
                     help="only run one comparison family (for profiling) and print its record")
     args = ap.parse_args()
 
@@ -428,7 +472,8 @@ def main() -> int:
         return 0
     if args.family:
         rec = {"batched": batched_case, "lu": lu_update_stream, "codec": codec_case,
-               "lufull": lambda: lu_full_case(tuple(int(v) for v in args.lu_widths.split(",")))}[args.family]()
+               "lufull": lambda: lu_full_case(tuple(int(v) for v in args.lu_widths.split(","))),
+               "adaptive": lambda: adaptive_case(*workload_inputs("cgemm2048_p1024")[4:], 1024)}[args.family]()
         print(json.dumps({"family": args.family, **rec}), flush=True)
         return 0
     log(f"generating {args.workload}")
@@ -488,6 +533,7 @@ def main() -> int:
         extra["cgemm512_p512"] = fam
         del dA2, dB2, dC2
         if args.workload == "cgemm2048_p1024" and args.scheme == "exact":
+            extra.update(adaptive_case(A, B, p))
             log("default workload, truncated scheme")
             dtt, infot, stt = time_calls(dA, dB, dC, m, n, k, p, mode, _scheme("truncated"), sl, steps=2, warmup=1)
             extra["cgemm2048_p1024_truncated"] = {"ms_per_call": 1000 * dtt / 2, "8mnk_per_s": 8.0 * m * n * k * 2 / dtt,
