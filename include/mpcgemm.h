@@ -271,6 +271,7 @@ int mp_zgetrf(int n, mpcg_cmat *A, int lda, int *ipiv, int nb, int prec_bits, in
  * entry) and, for c = n-1 down to 0, X_c := RNE(RNE(Y_c - U(c, c+1:n)
  * X(c+1:n, :)) * reciprocal of U(c, c)), the reciprocal formed as in
  * mp_zgetrf (Sec. IV-B: forward and backward substitution).  Synchronous.
+ * ipiv must hold mp_zgetrf's interchanges; an entry outside [0, n) is skipped.
  * Returns 0, MPCG_EINVAL (also for B overlapping A or ipiv), MPCG_ERANGE,
  * MPCG_EHIP.
  */

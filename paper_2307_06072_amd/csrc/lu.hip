@@ -104,14 +104,15 @@ __global__ void __launch_bounds__(LU_THREADS) swap_rows_kernel(DOutPart re, DOut
 }
 
 // The interchanges ipiv[0], ..., ipiv[n-1], in that order, applied to the
-// rows of an n x ncols block (one column per thread).
+// rows of an n x ncols block (one column per thread); an entry outside
+// [0, n) is skipped rather than followed out of the block.
 __global__ void __launch_bounds__(LU_THREADS) laswp_kernel(DOutPart re, DOutPart im, int64_t ld, int ncols, int n,
                                                            int L, const int* ipiv) {
   const int j = blockIdx.x * LU_THREADS + threadIdx.x;
   if (j >= ncols) return;
   for (int c = 0; c < n; ++c) {
     const int p = ipiv[c];
-    if (p == c) continue;
+    if (p == c || p < 0 || p >= n) continue;
     swap_entry(re, (int64_t)j * ld + c, (int64_t)j * ld + p, L);
     swap_entry(im, (int64_t)j * ld + c, (int64_t)j * ld + p, L);
   }

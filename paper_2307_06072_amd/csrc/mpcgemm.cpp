@@ -455,8 +455,9 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
     if (opt && opt->adaptive && !P.f64) {
       // per-block slice counts: the row and column statistics of the scan
       std::vector<RowStat> hA(m), hB(n);
-      HIP_TRY(hipMemcpy(hA.data(), statA, sizeof(RowStat) * m, hipMemcpyDeviceToHost));
-      HIP_TRY(hipMemcpy(hB.data(), statB, sizeof(RowStat) * n, hipMemcpyDeviceToHost));
+      HIP_TRY(hipMemcpyAsync(hA.data(), statA, sizeof(RowStat) * m, hipMemcpyDeviceToHost, g_stream));
+      HIP_TRY(hipMemcpyAsync(hB.data(), statB, sizeof(RowStat) * n, hipMemcpyDeviceToHost, g_stream));
+      HIP_TRY(hipStreamSynchronize(g_stream));
       const int xb = P.mode3m ? 2 : 1;
       const std::vector<int> rb = adaptive_blocks(hA, prec_bits, xb, P.trunc);
       const std::vector<int> cb = adaptive_blocks(hB, prec_bits, xb, P.trunc);
