@@ -38,7 +38,8 @@ def _factor(A, nb, p, mode):
 
 
 @pytest.mark.parametrize("n,nb,p,mode", [(1, 1, 64, 1), (2, 1, 64, 0), (5, 2, 128, 1), (17, 8, 256, 1),
-                                         (40, 16, 256, 1), (33, 64, 128, 0), (24, 5, 1000, 1), (9, 4, 2, 1)])
+                                         (40, 16, 256, 1), (33, 64, 128, 0), (24, 5, 1000, 1), (9, 4, 2, 1),
+                                         (6, 4, 4096, 1), (65, 64, 128, 1)])
 def test_getrf_parity(n, nb, p, mode):
     A = random_cmat([51, n, p], 0, n, n, p, 2)
     _say(f"getrf n={n} nb={nb} p={p} mode={mode}")
@@ -50,7 +51,7 @@ def test_getrf_parity(n, nb, p, mode):
     assert bad == 0, (bad, first)
 
 
-@pytest.mark.parametrize("n,nrhs,nb,p", [(17, 3, 8, 256), (6, 1, 2, 64)])
+@pytest.mark.parametrize("n,nrhs,nb,p", [(17, 3, 8, 256), (6, 1, 2, 64), (5, 2, 3, 4096)])
 def test_getrs_parity(n, nrhs, nb, p):
     import torch
     import paper_2307_06072_amd as mp
