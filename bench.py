@@ -291,16 +291,24 @@ def adaptive_case(A, B, p):
     return {"cgemm2048_p1024_mixed_spread": out}
 
 
-def lu_full_case(widths=(128,)):
-    """The paper's LU experiment (Sec. IV-B) at n = 1024 and 256 bits: A with
-    random entries (exponents on [-2, 2]), x_k = k + k i, b = A x rounded once
-    by mp_cgemm; mp_zgetrf with block width K, then mp_zgetrs.  Reports the
-    seconds of each and the largest relative error of x (|Re| + |Im| norm)."""
+def lu_full_case(widths=(128,), precs=(256,)):
+    """The paper's LU experiment (Sec. IV-B) at n = 1024 and 256 (512, 768)
+    bits: A with random entries (exponents on [-2, 2]), x_k = k + k i, b = A x
+    rounded once by mp_cgemm; mp_zgetrf with block width K, then mp_zgetrs.
+    Reports the seconds of each and the largest relative error of x (|Re| +
+    |Im| norm)."""
+    rec = {}
+    for p in precs:
+        rec[f"lu_full_n1024_p{p}"] = _lu_full_one(widths, p)
+    return rec
+
+
+def _lu_full_one(widths, p):
     from fractions import Fraction
     import torch
     import paper_2307_06072_amd as mp
     from mpgen import EXP_ZERO, random_cmat
-    n, p = 1024, 256
+    n = 1024
     A = random_cmat([6, n], 0, n, n, p, 2)
     L = (p + 63) // 64
     xs = random_cmat([6, n], 1, n, 1, p, 0)  # overwritten below with x_k = k + k i
@@ -353,7 +361,7 @@ def lu_full_case(widths=(128,)):
         out[f"K{K}"] = {"getrf_s": t1 - t0, "getrs_s": t2 - t1, "max_rel_err": float(err)}
         log(f"  getrf {t1 - t0:.2f} s, getrs {t2 - t1:.2f} s, max relative error {float(err):.2e}")
         del dA, dB
-    return {"lu_full_n1024_p256": out}
+    return out
 
 
 def lu_update_stream():
@@ -445,6 +453,8 @@ def main() -> int:
                     help="only run a plain device-to-device copy of BYTES (counter calibration)")
     ap.add_argument("--lu-widths", default="64,128,352",
                     help="block widths K of the full-LU family (comma-separated)")
+    ap.add_argument("--lu-precs", default="256",
+                    help="precisions of the full-LU family (comma-separated bits)")
     ap.add_argument("--family", choices=["batched", "lu", "codec", "lufull", "adaptive"], default=None,
                     help="only run one comparison family (for profiling) and print its record")
     args = ap.parse_args()
@@ -472,7 +482,8 @@ def main() -> int:
         return 0
     if args.family:
         rec = {"batched": batched_case, "lu": lu_update_stream, "codec": codec_case,
-               "lufull": lambda: lu_full_case(tuple(int(v) for v in args.lu_widths.split(","))),
+               "lufull": lambda: lu_full_case(tuple(int(v) for v in args.lu_widths.split(",")),
+                                              tuple(int(v) for v in args.lu_precs.split(","))),
                "adaptive": lambda: adaptive_case(*workload_inputs("cgemm2048_p1024")[4:], 1024)}[args.family]()
         print(json.dumps({"family": args.family, **rec}), flush=True)
         return 0
