@@ -49,7 +49,9 @@
  * that device current (one GPU per process).  Calls from several threads are
  * safe: an internal lock serializes them (they do not issue work
  * concurrently), and a thread's mpcg_set_stream changes the stream for every
- * thread.  Calls on one stream use the workspace in stream order; before
+ * thread.  mp_zgetrf and mp_zgetrs hold a lock of their own for the whole
+ * call (two of them never overlap); another thread's products may be issued
+ * between their steps, on the same stream, which keeps both correct.  Calls on one stream use the workspace in stream order; before
  * switching to another stream while earlier calls may still be running, the
  * caller orders the new stream after the old one (for example an event
  * recorded on the old stream and waited on by the new), since both streams'
