@@ -141,7 +141,8 @@ typedef struct {
     int adaptive;         /* 1: slice counts per block of rows of A and of columns of B (the
                              adaptive numbers of divisions the paper's concluding section asks
                              for).  After the exponent scan, rows of A and columns of B are
-                             grouped into blocks of 256, neighbouring blocks that need the same
+                             grouped into blocks of 256 (or of `adaptive` rows when it is a
+                             multiple of 32 above 1), neighbouring blocks that need the same
                              slice count (and, truncated, the same cutoff share) are merged, and
                              if more than one block results the block products run as one
                              batched call, each planned from its own spreads (mp_cgemm_batched).

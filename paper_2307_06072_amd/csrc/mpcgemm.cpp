@@ -326,7 +326,8 @@ int validate(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* 
     if (opt->cutoff_override < 0 || opt->ksplit_override < 0 || opt->block_override < 0 || opt->max_spread < 0)
       return set_err(MPCG_EINVAL, "negative option");
     if (opt->max_spread > (1 << 24)) return set_err(MPCG_EINVAL, "max_spread %d too large", opt->max_spread);
-    if (opt->adaptive != 0 && opt->adaptive != 1) return set_err(MPCG_EINVAL, "adaptive must be 0 or 1");
+    if (opt->adaptive < 0 || (opt->adaptive > 1 && (opt->adaptive % 32 != 0 || opt->adaptive > (1 << 20))))
+      return set_err(MPCG_EINVAL, "adaptive must be 0, 1 or a block size that is a multiple of 32");
   }
   if (lda < std::max(1, m)) return set_err(MPCG_EINVAL, "lda %d < max(1, m=%d)", lda, m);
   if (ldb < std::max(1, k)) return set_err(MPCG_EINVAL, "ldb %d < max(1, k=%d)", ldb, k);
@@ -359,10 +360,10 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
 mpcg_cmat view_at(const mpcg_cmat& M, int ld, int cols, int r, int c);
 
 // Contiguous blocks of rows (of A) or columns (of B) for adaptive slicing:
-// blocks of 256, neighbours with the same slice count (and, truncated, the
+// blocks of BLK, neighbours with the same slice count (and, truncated, the
 // same hat spread in digits) merged.  Returns the block starts, plus the end.
-std::vector<int> adaptive_blocks(const std::vector<RowStat>& st, int p, int x, bool trunc) {
-  const int R = (int)st.size(), BLK = 256;
+std::vector<int> adaptive_blocks(const std::vector<RowStat>& st, int p, int x, bool trunc, int BLK) {
+  const int R = (int)st.size();
   std::vector<int> starts;
   std::vector<std::pair<int, int>> keys;
   for (int r0 = 0; r0 < R; r0 += BLK) {
@@ -459,8 +460,9 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
       HIP_TRY(hipMemcpyAsync(hB.data(), statB, sizeof(RowStat) * n, hipMemcpyDeviceToHost, g_stream));
       HIP_TRY(hipStreamSynchronize(g_stream));
       const int xb = P.mode3m ? 2 : 1;
-      const std::vector<int> rb = adaptive_blocks(hA, prec_bits, xb, P.trunc);
-      const std::vector<int> cb = adaptive_blocks(hB, prec_bits, xb, P.trunc);
+      const int blk = opt->adaptive == 1 ? 256 : opt->adaptive;
+      const std::vector<int> rb = adaptive_blocks(hA, prec_bits, xb, P.trunc, blk);
+      const std::vector<int> cb = adaptive_blocks(hB, prec_bits, xb, P.trunc, blk);
       const int nrb = (int)rb.size() - 1, ncb = (int)cb.size() - 1;
       if (nrb * ncb > 1) {
         std::vector<mpcg_cmat> va(nrb), vb(ncb), vc((size_t)nrb * ncb);

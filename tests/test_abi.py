@@ -297,5 +297,6 @@ def test_getrs_rejects_b_overlapping_a():
 
 def test_adaptive_option_validated():
     import paper_2307_06072_amd as mp
-    assert _call(opt=mp.mpcg_options(0, 0, 0, 0, 0, 2)) == mp.MPCG_EINVAL
-    assert "adaptive" in mp.mpcg_last_error()
+    for bad in (2, -1, 48, 1 << 21):
+        assert _call(opt=mp.mpcg_options(0, 0, 0, 0, 0, bad)) == mp.MPCG_EINVAL
+        assert "adaptive" in mp.mpcg_last_error()

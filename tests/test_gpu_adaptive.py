@@ -93,3 +93,19 @@ def test_adaptive_accumulate_matches_single_plan():
         from tests.gpu_util import device_result_to_host
         outs.append(device_result_to_host(dC, p))
     assert mismatches(outs[1], outs[0], m, n)[0] == 0
+
+
+def test_adaptive_block_size():
+    """Wide rows 64..127 only: blocks of 64 confine them, blocks of 256 widen
+    rows 0..255; the bits stay those of the single plan."""
+    m, n, k, p = 300, 200, 40, 192
+    A = random_cmat([65], 0, m, k, p, 8)
+    B = random_cmat([65], 1, k, n, p, 8)
+    for r in range(64, 128):
+        if A.re.exp[2, r] != EXP_ZERO:
+            A.re.exp[2, r] += np.int32(200)
+    C0, info0 = run_device(A, B, p, M3, EXACT, I8)
+    C1, info1 = run_device(A, B, p, M3, EXACT, I8, adaptive=1)
+    C2, info2 = run_device(A, B, p, M3, EXACT, I8, adaptive=64)
+    assert mismatches(C1, C0, m, n)[0] == 0 and mismatches(C2, C0, m, n)[0] == 0
+    assert info2["algo_ops"] < info1["algo_ops"] < info0["algo_ops"], (info0, info1, info2)
