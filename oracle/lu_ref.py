@@ -12,9 +12,10 @@ the exact result):
 * pivot of column c: the first row r >= c with the largest RNE(|Re| + |Im|)
   (LAPACK's magnitude |Re| + |Im|, rounded once), rows c and r exchanged over
   the whole matrix;
-* reciprocal of a pivot y: conj(y) x, x ~ 1/|y|^2 from a 64-bit seed
-  (floor((2^127 - 1) / m) for the top limb m of |y|^2; exact for a power of
-  two) refined by Newton steps x := x + x (1 - |y|^2 x);
+* reciprocal of a pivot y: each component of the exact 1/y rounded once to
+  p bits, RNE_p(Re y / |y|^2) and RNE_p(-Im y / |y|^2) (the correctly rounded
+  division of MPC arithmetic, Sec. II), written here with exact rationals;
+  a zero y gives zero;
 * the column below the pivot times the reciprocal; a rank-1 update of the
   rest of the block column; U12 := L11^-1 A12 by rank-1 updates; A22 := A22 -
   L21 U12 in one product;
@@ -28,7 +29,9 @@ import numpy as np
 
 import oracle
 from mpgen import EXP_ZERO, HostCMat, HostPart, limbs_for
-from oracle.fraction_ref import decode
+from fractions import Fraction
+
+from oracle.fraction_ref import decode, round_rne
 
 
 def _sub(M: HostCMat, r0: int, nr: int, c0: int, nc: int) -> HostCMat:
@@ -76,55 +79,35 @@ def _abs(S: HostCMat) -> HostCMat:
     return T
 
 
-def _conj(S: HostCMat) -> HostCMat:
-    T = S.copy()
-    nz = T.im.exp != EXP_ZERO
-    T.im.sign[nz] ^= 1
-    T.im.sign[~nz] = 0
-    T.re.sign[T.re.exp == EXP_ZERO] = 0
-    return T
-
-
-def newton_steps(prec_bits: int) -> int:
-    """Steps taking the seed's 60 correct bits past prec_bits + 4."""
-    it, bits = 0, 60
-    while bits < prec_bits + 4:
-        bits *= 2
-        it += 1
-    return it
-
-
-def seed(d: HostCMat, prec_bits: int) -> HostCMat:
-    """Seed of 1 / d for a real 1 x 1 d (imaginary part +0)."""
-    L = limbs_for(prec_bits)
-    x = _const(0, 0, prec_bits)
-    e = int(d.re.exp[0, 0])
-    if e == EXP_ZERO:
-        return x
-    m = int(d.re.mant[L - 1, 0, 0])
-    lower_zero = all(int(d.re.mant[l, 0, 0]) == 0 for l in range(L - 1))
-    if m == 1 << 63 and lower_zero:  # a power of two: its exact reciprocal
-        q, ex = m, 2 - e
-    else:
-        q = ((1 << 127) - 1) // m  # in [2^63, 2^64): 1/d ~ q 2^(-63-e)
-        if prec_bits < 64:
-            q &= ~((1 << (64 - prec_bits)) - 1)
-        ex = 1 - e
-    x.re.sign[0, 0] = d.re.sign[0, 0]
-    x.re.exp[0, 0] = ex
-    x.re.mant[L - 1, 0, 0] = np.uint64(q)
-    return x
+def _store(part: HostPart, value: Fraction, prec_bits: int) -> None:
+    """Entry (0, 0) of `part` := RNE_p(value) (an exact zero is +0)."""
+    sg, e, q = round_rne(value, prec_bits)
+    L = part.L
+    part.mant[:, 0, 0] = 0
+    if q == 0:
+        part.sign[0, 0] = 0
+        part.exp[0, 0] = EXP_ZERO
+        return
+    M = q << (64 * L - prec_bits)
+    part.sign[0, 0] = sg
+    part.exp[0, 0] = e
+    for l in range(L):
+        part.mant[l, 0, 0] = np.uint64((M >> (64 * l)) & ((1 << 64) - 1))
 
 
 def reciprocal(y: HostCMat, prec_bits: int) -> HostCMat:
-    """The reciprocal of a 1 x 1 y: conj(y) x with x ~ 1 / |y|^2."""
-    yc = _conj(y)
-    d = oracle.cgemm(y, yc, prec_bits)
-    x = seed(d, prec_bits)
-    for _ in range(newton_steps(prec_bits)):
-        e = oracle.cgemm_acc(d, x, _const(1, 0, prec_bits), prec_bits, sign=-1)  # 1 - d x
-        x = oracle.cgemm_acc(x, e, x, prec_bits, sign=+1)                         # x + x e
-    return oracle.cgemm(yc, x, prec_bits)
+    """The reciprocal of a 1 x 1 y, correctly rounded in each component:
+    RNE_p(Re y / |y|^2) + i RNE_p(-Im y / |y|^2) from exact rationals; zero
+    for y = 0."""
+    yr = decode(y.re, 0, 0, prec_bits)
+    yi = decode(y.im, 0, 0, prec_bits)
+    x = _const(0, 0, prec_bits)
+    d = yr * yr + yi * yi
+    if d == 0:
+        return x
+    _store(x.re, yr / d, prec_bits)
+    _store(x.im, -yi / d, prec_bits)
+    return x
 
 
 def _first_max(K: HostCMat, prec_bits: int) -> int:

@@ -1,8 +1,12 @@
 """Pins of the LU oracle (oracle/lu_ref.py) against things other than itself
 (no GPU needed):
 
-* the reciprocal is within 2^(3-p) |1/y| of the exact 1/y (Fractions) in each
-  component, and exact for +-2^t and +-i 2^t; the seed is within 2^-62 of 1/d;
+* the reciprocal (each component of 1/y rounded once, as MPC divides) agrees
+  with mpmath's division at a working precision far above 3p rounded to p,
+  and at p = 53 with IEEE double division 1.0 / y for real and imaginary y;
+  it is exact for +-2^t, +-i 2^t and 2^t (1 +- i); conjugating y conjugates
+  it, multiplying y by i multiplies it by -i, and scaling y by 2^3 scales it
+  by 2^-3, bit for bit;
 * matrices built as P^T L U with closed-form factors (tests/lu_cases.py) come
   back as exactly L, U and the interchanges that undo P, for every block
   width, and the solve returns the exact x_k = k + k i;
@@ -40,38 +44,80 @@ def _recip_exact(y):
     return y[0] / d, -y[1] / d
 
 
-@pytest.mark.parametrize("p", [2, 53, 64, 65, 128, 256, 1000])
-def test_reciprocal_accuracy(p):
-    for seed in range(12):
-        y = random_cmat([41, seed, p], 0, 1, 1, p, 6)
-        if seed % 3 == 0:  # a purely real or purely imaginary pivot
-            part = y.im if seed % 2 == 0 else y.re
+def _pivots(p, count, seed, R=6):
+    """Random 1 x 1 pivots; every third purely real or purely imaginary, and a
+    few with parts far apart in magnitude."""
+    out = []
+    for t in range(count):
+        y = random_cmat([41, seed, p, t], 0, 1, 1, p, R)
+        if t % 3 == 0:
+            part = y.im if t % 2 == 0 else y.re
             part.exp[...] = np.iinfo(np.int32).min
+        elif t % 5 == 1:
+            y.im.exp[...] += (3 * p + t) * (1 if t % 2 else -1)  # around and beyond 3p bits apart
+        out.append(y)
+    return out
+
+
+def _mp_round(num, den, p):
+    """RNE_p(num / den) through mpmath: the quotient at a working precision
+    far above 3p (so no rounding boundary can lie between it and the exact
+    value), then rounded to p bits by mpmath."""
+    import mpmath
+    if num == 0:
+        return Fraction(0)
+    with mpmath.workprec(8 * p + 400):
+        q = mpmath.mpf(num.numerator) / mpmath.mpf(num.denominator) * mpmath.mpf(den.denominator) / \
+            mpmath.mpf(den.numerator)
+    with mpmath.workprec(p):
+        r = +q
+    sign, man, exp, _ = r._mpf_  # read without converting (a conversion rounds at the default precision)
+    v = Fraction(int(man)) * Fraction(2) ** int(exp)
+    return -v if sign else v
+
+
+@pytest.mark.parametrize("p", [2, 3, 53, 64, 65, 128, 256, 1000])
+def test_reciprocal_matches_mpmath(p):
+    for y in _pivots(p, 15, 1):
         yv = _val(y, 0, 0, p)
+        d = yv[0] * yv[0] + yv[1] * yv[1]
         r = _val(lu_ref.reciprocal(y, p), 0, 0, p)
-        ex = _recip_exact(yv)
-        mag = _n1(ex)
-        bound = Fraction(2) ** (3 - p) * mag if p >= 64 else Fraction(2) ** (3 - p) * mag * 2
-        assert abs(r[0] - ex[0]) <= bound and abs(r[1] - ex[1]) <= bound, (p, seed)
+        assert r == (_mp_round(yv[0], d, p), _mp_round(-yv[1], d, p)), p
+
+
+def test_reciprocal_p53_real_and_imaginary_match_ieee_division():
+    rng = np.random.default_rng(45)
+    p = 53
+    for t in range(400):
+        x = float(rng.uniform(0.5, 1.0)) * 2.0 ** int(rng.integers(-60, 61)) * (1 if t % 2 else -1)
+        fx = Fraction(x)
+        if t % 4 < 2:   # y = x real: 1/y = 1/x
+            y, want = to_cmat([[(fx, Fraction(0))]], p), (Fraction(1.0 / x), Fraction(0))
+        else:           # y = i x: 1/y = -i / x
+            y, want = to_cmat([[(Fraction(0), fx)]], p), (Fraction(0), Fraction(-1.0 / x))
+        assert _val(lu_ref.reciprocal(y, p), 0, 0, p) == want, x
+
+
+@pytest.mark.parametrize("p", [2, 64, 256])
+def test_reciprocal_symmetries(p):
+    for y in _pivots(p, 12, 2):
+        yr, yi = _val(y, 0, 0, p)
+        r = _val(lu_ref.reciprocal(y, p), 0, 0, p)
+        rc = _val(lu_ref.reciprocal(to_cmat([[(yr, -yi)]], p), p), 0, 0, p)
+        assert rc == (r[0], -r[1])                       # 1/conj(y) = conj(1/y)
+        ri = _val(lu_ref.reciprocal(to_cmat([[(-yi, yr)]], p), p), 0, 0, p)
+        assert ri == (r[1], -r[0])                       # 1/(i y) = -i / y
+        r8 = _val(lu_ref.reciprocal(to_cmat([[(yr * 8, yi * 8)]], p), p), 0, 0, p)
+        assert r8 == (r[0] / 8, r[1] / 8)                # 1/(8 y) = (1/y) / 8
 
 
 @pytest.mark.parametrize("p", [2, 64, 256])
 def test_reciprocal_of_powers_of_two_is_exact(p):
     for t in (-5, 0, 3):
-        for re, im in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+        for re, im in ((1, 0), (-1, 0), (0, 1), (0, -1), (1, 1), (-1, 1)):
             y = to_cmat([[(Fraction(re) * Fraction(2) ** t, Fraction(im) * Fraction(2) ** t)]], p)
             r = _val(lu_ref.reciprocal(y, p), 0, 0, p)
             assert r == _recip_exact((Fraction(re) * Fraction(2) ** t, Fraction(im) * Fraction(2) ** t))
-
-
-def test_seed_accuracy():
-    p = 256
-    for seed in range(40):
-        d = random_cmat([42, seed], 0, 1, 1, p, 40)
-        d.im.exp[...] = np.iinfo(np.int32).min
-        dv = decode(d.re, 0, 0, p)
-        x = decode(lu_ref.seed(d, p).re, 0, 0, p)
-        assert abs(x * dv - 1) <= Fraction(1, 2 ** 62)
 
 
 @pytest.mark.parametrize("n,nb", [(1, 1), (2, 1), (7, 3), (12, 1), (12, 4), (12, 5), (12, 12), (12, 64)])
