@@ -250,16 +250,16 @@ int mp_cgemm_batched_acc(int count, const mpcg_problem *problems, int prec_bits,
  *       pivot: the first row r >= c with the largest RNE(|Re a_rc| + |Im a_rc|)
  *       (LAPACK's |Re| + |Im| magnitude, rounded once); rows c and r
  *       exchanged over all n columns;
- *       reciprocal of the pivot y: conj(y) * x, x from a seed of 1/|y|^2 (64
- *       bits; exact for a power of two) and Newton steps x := x + x (1 - |y|^2 x)
- *       until at least prec_bits + 4 bits are reached;
+ *       reciprocal of the pivot y: Re y / |y|^2 and -Im y / |y|^2, each
+ *       rounded once from its exact value (MPC's correctly rounded division,
+ *       Sec. II); a zero y gives zero;
  *       column below the pivot := each entry times the reciprocal;
  *       rank-1 update of the rest of the block column;
  *     U12 := L11^-1 A12 by rank-1 updates; A22 := A22 - L21 U12 (k = jb).
  * A zero pivot column is multiplied by zero and reported in the return value.
  * mode (MPCG_4M / MPCG_3M) selects the product form, which does not change a
  * bit of the result.  Synchronous (returns after the device work); allocates
- * a scratch buffer of about 22 n (8L + 5) bytes.
+ * a scratch buffer of about 10 n (8L + 5) bytes.
  * Returns 0, c + 1 if the first exactly zero pivot was in column c (as
  * LAPACK's info), MPCG_EINVAL (bad n, lda, nb, precision, mode, NULL pointer,
  * overlapping arrays), MPCG_ERANGE, MPCG_EHIP.

@@ -1,9 +1,9 @@
 // Scalar and row kernels of the blocked complex LU factorization (Sec. IV-B):
 // block copies (plain, conjugate, absolute value), the pivot search over a
-// column of keys, row interchanges, small constants and the seed of a pivot
-// reciprocal.  Every arithmetic step of the factorization (products, updates,
-// the Newton steps of the reciprocal) runs through the product kernels; the
-// kernels here only move, compare and seed numbers.
+// column of keys, row interchanges and small constants.  The products and
+// updates of the factorization run through the product kernels and the pivot
+// reciprocals through recip.hip; the kernels here only move and compare
+// numbers.
 #include "mpcg_internal.h"
 
 namespace mpcg {
@@ -125,62 +125,6 @@ __global__ void const_kernel(DOutPart re, DOutPart im, int L, int vre, int vim) 
   }
 }
 
-// Seed of 1/d for a real d (entry t of consecutive entries, one thread
-// each): with m the top limb of d's
-// significand, q = floor((2^127 - 1) / m) in [2^63, 2^64) by restoring
-// division, kept to prec bits, with exponent 1 - e(d); so the seed is q *
-// 2^(-63 - e(d)), within 2^-62 of 1/d relatively.  A power of two gets its
-// exact reciprocal 2^(1 - e(d)) (significand 1/2, exponent 2 - e(d)), zero
-// gives zero.
-__global__ void __launch_bounds__(LU_THREADS) seed_kernel(DPart d, DOutPart xre, DOutPart xim, int prec, int L,
-                                                          int count) {
-  const int t = blockIdx.x * LU_THREADS + threadIdx.x;
-  if (t >= count) return;
-  d.sign += t;
-  d.exp += t;
-  d.mant += t;
-  xre.sign += t;
-  xre.exp += t;
-  xre.mant += t;
-  xim.sign += t;
-  xim.exp += t;
-  xim.mant += t;
-  write_small(xim, 0, L);
-  const int32_t e = d.exp[0];
-  if (e == EXP_ZERO) {
-    write_small(xre, 0, L);
-    return;
-  }
-  const uint64_t m = d.mant[(int64_t)(L - 1) * d.ls];
-  bool pow2 = m == (1ull << 63);
-  for (int l = 0; l < L - 1 && pow2; ++l) pow2 = d.mant[l * d.ls] == 0;
-  if (pow2) {
-    int64_t ex = 2 - (int64_t)e;
-    if (ex > INT32_MAX) ex = INT32_MAX;
-    xre.sign[0] = d.sign[0];
-    xre.exp[0] = (int32_t)ex;
-    for (int l = 0; l < L; ++l) xre.mant[l * xre.ls] = (l == L - 1) ? m : 0;
-    return;
-  }
-  uint64_t r = 0x7fffffffffffffffull, q = 0;  // high half of 2^127 - 1, below m
-  for (int b = 0; b < 64; ++b) {               // bring down the 64 low bits, all ones
-    const uint64_t carry = r >> 63;
-    r = (r << 1) | 1;
-    q <<= 1;
-    if (carry || r >= m) {
-      r -= m;
-      q |= 1;
-    }
-  }
-  if (prec < 64) q &= ~((1ull << (64 - prec)) - 1);
-  int64_t ex = 1 - (int64_t)e;
-  if (ex > INT32_MAX) ex = INT32_MAX;
-  if (ex <= INT32_MIN) ex = INT32_MIN + 1;
-  xre.sign[0] = d.sign[0];
-  xre.exp[0] = (int32_t)ex;
-  for (int l = 0; l < L; ++l) xre.mant[l * xre.ls] = (l == L - 1) ? q : 0;
-}
-
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + LU_THREADS - 1) / LU_THREADS); }
 
 }  // namespace
@@ -214,12 +158,6 @@ hipError_t launch_lu_laswp(DOutPart re, DOutPart im, int64_t ld, int ncols, int 
 
 hipError_t launch_lu_const(DOutPart re, DOutPart im, int L, int vre, int vim, hipStream_t stream) {
   const_kernel<<<1, 64, 0, stream>>>(re, im, L, vre, vim);
-  return hipGetLastError();
-}
-
-hipError_t launch_lu_seed(DPart d, DOutPart xre, DOutPart xim, int prec, int L, int count, hipStream_t stream) {
-  if (count <= 0) return hipSuccess;
-  seed_kernel<<<blocks_for(count), LU_THREADS, 0, stream>>>(d, xre, xim, prec, L, count);
   return hipGetLastError();
 }
 

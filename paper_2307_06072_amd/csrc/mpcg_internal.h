@@ -165,8 +165,11 @@ hipError_t launch_lu_laswp(DOutPart re, DOutPart im, int64_t ld, int ncols, int 
                            hipStream_t stream);
 // entry 0 := vre + i vim, each in {-1, 0, 1}.
 hipError_t launch_lu_const(DOutPart re, DOutPart im, int L, int vre, int vim, hipStream_t stream);
-// entries 0 .. count-1 (consecutive) of (xre, xim) := seeds of 1 / d (d real).
-hipError_t launch_lu_seed(DPart d, DOutPart xre, DOutPart xim, int prec, int L, int count, hipStream_t stream);
+// entries 0 .. count-1 (consecutive) of (xre, xim) := the reciprocals of the
+// entries t * stride of (yre, yim), each component rounded once to prec bits
+// (nearest, ties to even); a zero entry gives zero.
+hipError_t launch_lu_recip(DPart yre, DPart yim, int64_t stride, DOutPart xre, DOutPart xim, int prec, int L,
+                           int count, hipStream_t stream);
 hipError_t launch_to_doubles(DPart in, int rows, int cols, int64_t ldi, int prec, int L, int ncomp, double* dst,
                              int64_t ld, int64_t plane, int* status, hipStream_t stream);
 hipError_t launch_from_doubles(const double* src, int rows, int cols, int ncomp, int64_t ld, int64_t plane,

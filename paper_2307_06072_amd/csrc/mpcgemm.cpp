@@ -1085,8 +1085,8 @@ mpcg_cmat view_at(const mpcg_cmat& M, int ld, int cols, int r, int c) {
 // Scratch of one factorization or solve: NCOL columns of R entries (R >= the
 // longest column or row handled), plus the singularity word.
 struct LuScratch {
-  static constexpr int NCOL = 11;
-  enum { ABS = 0, KEY, TMP, ONE, OMI, YC, D, X0, X1, E, REC };
+  static constexpr int NCOL = 5;
+  enum { ABS = 0, KEY, TMP, OMI, REC };
   void* buf = nullptr;
   mpcg_cmat M{};
   int R = 0;
@@ -1116,53 +1116,26 @@ int lu_scratch(LuScratch& W, int R, int L) {
   }
   W.info = reinterpret_cast<int*>(b + 2 * part);
   HIP_TRY(launch_fill_zero(W.info, 256, g_stream));
-  const mpcg_cmat one = W.at(LuScratch::ONE), omi = W.at(LuScratch::OMI);
-  HIP_TRY(launch_lu_const(doutpart(one.re, 0), doutpart(one.im, 0), L, 1, 0, g_stream));
+  const mpcg_cmat omi = W.at(LuScratch::OMI);
   HIP_TRY(launch_lu_const(doutpart(omi.re, 0), doutpart(omi.im, 0), L, 1, -1, g_stream));
   return MPCG_OK;
 }
 
 // One rounded product or update of the factorization (exact scheme).
-// A real operand (imaginary part +0) has exponent spread 0 in every row, so
-// products of real numbers are planned from a spread bound of 1 with no
-// read-back of the scan (a larger spread would be reported, not mis-rounded).
 int lu_prod(int m, int n, int k, const mpcg_cmat& A, int lda, const mpcg_cmat& B, int ldb, mpcg_cmat C, int ldc,
-            int prec, int mode, int acc, bool real_operands = false) {
-  const mpcg_options bound{MPCG_SLICE_INT8, 0, 0, 0, 1};
-  return run(m, n, k, &A, lda, &B, ldb, &C, ldc, prec, mode, MPCG_EXACT, real_operands ? &bound : nullptr, nullptr,
-             acc, false);
+            int prec, int mode, int acc) {
+  return run(m, n, k, &A, lda, &B, ldb, &C, ldc, prec, mode, MPCG_EXACT, nullptr, nullptr, acc, false);
 }
 
-// Newton steps taking the seed's 60 correct bits past prec + 4.
-int lu_newton_steps(int prec) {
-  int it = 0;
-  for (long bits = 60; bits < prec + 4; bits *= 2) ++it;
-  return it;
-}
-
-// W[REC] := the reciprocal of the 1 x 1 view y: conj(y) x with x ~ 1/|y|^2
-// from the seed and Newton steps x := x + x (1 - d x), each step two rounded
-// calls.  A zero y gives zero.
-int lu_recip(LuScratch& W, const mpcg_cmat& y, int prec, int mode) {
+// W[REC .. REC + count) := the reciprocals of `count` entries of y, entry t
+// at t * stride, each component correctly rounded (one kernel launch).  A
+// zero entry gives zero.
+int lu_recip(LuScratch& W, const mpcg_cmat& y, int64_t stride, int count, int prec) {
   const int L = (prec + 63) / 64;
-  int st;
-  const mpcg_cmat yc = W.at(LuScratch::YC), d = W.at(LuScratch::D), e = W.at(LuScratch::E);
-  mpcg_cmat x = W.at(LuScratch::X0), xn = W.at(LuScratch::X1);
-  HIP_TRY(launch_lu_copy(dpart(y.re, 0), dpart(y.im, 0), 1, doutpart(yc.re, 0), doutpart(yc.im, 0), 1, 1, 1, L, 1,
-                         g_stream));
-  if ((st = lu_prod(1, 1, 1, y, 1, yc, 1, d, 1, prec, mode, 0))) return st;  // |y|^2 (+0 imaginary)
-  HIP_TRY(launch_lu_seed(dpart(d.re, 0), doutpart(x.re, 0), doutpart(x.im, 0), prec, L, 1, g_stream));
-  const mpcg_cmat one = W.at(LuScratch::ONE);
-  for (int it = lu_newton_steps(prec); it > 0; --it) {
-    HIP_TRY(launch_lu_copy(dpart(one.re, 0), dpart(one.im, 0), 1, doutpart(e.re, 0), doutpart(e.im, 0), 1, 1, 1, L,
-                           0, g_stream));
-    if ((st = lu_prod(1, 1, 1, d, 1, x, 1, e, 1, prec, mode, -1, true))) return st;  // e := 1 - d x
-    HIP_TRY(launch_lu_copy(dpart(x.re, 0), dpart(x.im, 0), 1, doutpart(xn.re, 0), doutpart(xn.im, 0), 1, 1, 1, L,
-                           0, g_stream));
-    if ((st = lu_prod(1, 1, 1, x, 1, e, 1, xn, 1, prec, mode, +1, true))) return st;  // x' := x + x e
-    std::swap(x, xn);
-  }
-  return lu_prod(1, 1, 1, yc, 1, x, 1, W.at(LuScratch::REC), 1, prec, mode, 0);
+  const mpcg_cmat rec = W.at(LuScratch::REC);
+  HIP_TRY(launch_lu_recip(dpart(y.re, 0), dpart(y.im, 0), stride, doutpart(rec.re, 0), doutpart(rec.im, 0), prec, L,
+                          count, g_stream));
+  return MPCG_OK;
 }
 
 int check_square(int n, const mpcg_cmat* A, int lda, int prec_bits, int mode, Region out[6]) {
@@ -1214,7 +1187,7 @@ int lu_factor(int n, mpcg_cmat* A, int lda, int* ipiv, int nb, int prec, int mod
       if ((st = lu_prod(mr, 1, 1, T, W.R, W.at(LuScratch::OMI), 1, K, W.R, prec, mode, 0))) return st;
       HIP_TRY(launch_lu_pivot(dpart(K.re, 0), mr, L, c, ipiv + c, W.info, c, g_stream));
       HIP_TRY(launch_lu_swap(are, aim, lda, n, L, c, ipiv + c, g_stream));
-      if ((st = lu_recip(W, col, prec, mode))) return st;
+      if ((st = lu_recip(W, col, 1, 1, prec))) return st;
       if (mr > 1) {
         // l := a r below the pivot, through the scratch column
         if ((st = lu_prod(mr - 1, 1, 1, at(c + 1, c), lda, W.at(LuScratch::REC), 1, tmp, W.R, prec, mode, 0)))
@@ -1273,42 +1246,8 @@ int lu_solve(int n, int nrhs, const mpcg_cmat* A, int lda, const int* ipiv, mpcg
   if ((st = lu_scratch(W, std::max(n, nrhs), L))) return st;
   auto a_at = [&](int r, int c) { return view_at(*A, lda, n, r, c); };
   auto b_at = [&](int r, int c) { return view_at(*B, ldb, nrhs, r, c); };
-  // the reciprocals of U's diagonal, all at once: for every entry the steps of
-  // lu_recip, each step one batched call over the n entries (1 x n rows of
-  // the scratch, leading dimension 1)
-  {
-    const mpcg_cmat dg = W.at(LuScratch::ABS), yc = W.at(LuScratch::YC), d = W.at(LuScratch::D),
-                    e = W.at(LuScratch::E), one = W.at(LuScratch::ONE), rec = W.at(LuScratch::REC);
-    mpcg_cmat x = W.at(LuScratch::X0), xn = W.at(LuScratch::X1);
-    const mpcg_cmat diag = a_at(0, 0);  // entry c of the diagonal at c (lda + 1)
-    HIP_TRY(launch_lu_copy(dpart(diag.re, 0), dpart(diag.im, 0), (int64_t)lda + 1, doutpart(dg.re, 0),
-                           doutpart(dg.im, 0), 1, 1, n, L, 0, g_stream));
-    HIP_TRY(launch_lu_copy(dpart(dg.re, 0), dpart(dg.im, 0), 1, doutpart(yc.re, 0), doutpart(yc.im, 0), 1, 1, n, L,
-                           1, g_stream));
-    std::vector<mpcg_cmat> va(n), vb(n), vc(n);
-    std::vector<mpcg_problem> probs(n);
-    auto batch = [&](const mpcg_cmat& X, const mpcg_cmat& Y, const mpcg_cmat& Z, int acc) -> int {
-      for (int i = 0; i < n; ++i) {
-        va[i] = view_at(X, 1, W.R * LuScratch::NCOL, 0, i);
-        vb[i] = view_at(Y, 1, W.R * LuScratch::NCOL, 0, i);
-        vc[i] = view_at(Z, 1, W.R * LuScratch::NCOL, 0, i);
-        probs[i] = mpcg_problem{1, 1, 1, &va[i], 1, &vb[i], 1, &vc[i], 1};
-      }
-      return run_batched(n, probs.data(), prec, mode, MPCG_EXACT, nullptr, nullptr, acc, false);
-    };
-    if ((st = batch(dg, yc, d, 0))) return st;  // |y|^2
-    HIP_TRY(launch_lu_seed(dpart(d.re, 0), doutpart(x.re, 0), doutpart(x.im, 0), prec, L, n, g_stream));
-    for (int it = lu_newton_steps(prec); it > 0; --it) {
-      HIP_TRY(launch_lu_copy(dpart(one.re, 0), dpart(one.im, 0), 0, doutpart(e.re, 0), doutpart(e.im, 0), 1, 1, n,
-                             L, 0, g_stream));
-      if ((st = batch(d, x, e, -1))) return st;  // e := 1 - d x
-      HIP_TRY(launch_lu_copy(dpart(x.re, 0), dpart(x.im, 0), 1, doutpart(xn.re, 0), doutpart(xn.im, 0), 1, 1, n, L,
-                             0, g_stream));
-      if ((st = batch(x, e, xn, +1))) return st;  // x' := x + x e
-      std::swap(x, xn);
-    }
-    if ((st = batch(yc, x, rec, 0))) return st;
-  }
+  // the reciprocals of U's diagonal, all at once (entry c at c (lda + 1))
+  if ((st = lu_recip(W, a_at(0, 0), (int64_t)lda + 1, n, prec))) return st;
   HIP_TRY(launch_lu_laswp(doutpart(B->re, (int64_t)ldb * nrhs), doutpart(B->im, (int64_t)ldb * nrhs), ldb, nrhs, n,
                           L, ipiv, g_stream));
   // forward: row c of Y := RNE(B_c - L(c, 0:c) Y(0:c, :)), unit diagonal

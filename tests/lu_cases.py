@@ -81,3 +81,61 @@ def to_cmat(vals, prec_bits: int):
 
 def column(vals):
     return [[v] for v in vals]
+
+
+def dominant_matrix(n: int, prec_bits: int, seed, exp_range: int = 2):
+    """The factorization workload: random entries (exponents on [-R, R]) plus
+    n (1 + i) on the diagonal, each shifted diagonal component rounded once to
+    prec_bits (nearest, ties to even) from its exact value."""
+    from mpgen import random_cmat
+    from oracle.fraction_ref import decode, round_rne
+    from tests.mp_util import encode
+    A = random_cmat(seed, 0, n, n, prec_bits, exp_range)
+    for part in (A.re, A.im):
+        for i in range(n):
+            s, e, q = round_rne(decode(part, i, i, prec_bits) + n, prec_bits)
+            sg, ex, limbs = encode((-q if s else q, e - prec_bits), prec_bits)
+            part.sign[i, i] = sg
+            part.exp[i, i] = ex
+            for l in range(part.L):
+                part.mant[l, i, i] = np.uint64(limbs[l])
+    return A
+
+
+def diagonal_pivots(n: int, prec_bits: int, seed):
+    """An n x n diagonal matrix of pivots of every kind the reciprocal meets:
+    random significands, real and imaginary parts close in exponent, far
+    apart (near the width at which the smaller square stops mattering, and
+    twice beyond it), one part zero, powers of two, all-ones significands."""
+    from mpgen import EXP_ZERO, random_cmat
+    A = random_cmat(seed, 0, n, n, prec_bits, 6)
+    rng = np.random.default_rng([int(s) for s in np.atleast_1d(seed)] + [99])
+    L = A.re.L
+    wide = (3 * prec_bits + 7) // 2
+    for part in (A.re, A.im):
+        off = ~np.eye(n, dtype=bool)
+        part.exp[off] = EXP_ZERO
+        part.mant[:, off] = 0
+        part.sign[off] = 0
+    for i in range(n):
+        kind = i % 8
+        if kind == 1:
+            A.im.exp[i, i] = A.re.exp[i, i] + int(rng.choice([-1, 1])) * (wide + int(rng.integers(-2, 3)))
+        elif kind == 2:
+            A.im.exp[i, i] = A.re.exp[i, i] + int(rng.integers(-3 * prec_bits, 3 * prec_bits + 1))
+        elif kind == 3:
+            part = A.re if rng.random() < 0.5 else A.im
+            part.exp[i, i] = EXP_ZERO
+            part.mant[:, i, i] = 0
+        elif kind == 4:
+            for part in (A.re, A.im):
+                part.mant[:, i, i] = 0
+                part.mant[L - 1, i, i] = np.uint64(1 << 63)
+        elif kind == 5:
+            for part in (A.re, A.im):
+                M = ((1 << prec_bits) - 1) << (64 * L - prec_bits)
+                for l in range(L):
+                    part.mant[l, i, i] = np.uint64((M >> (64 * l)) & ((1 << 64) - 1))
+        elif kind == 6:  # far beyond that width (the factorization's own products then need ~3p/7 more slices)
+            A.im.exp[i, i] = A.re.exp[i, i] + int(rng.choice([-1, 1])) * (3 * prec_bits + int(rng.integers(0, 200)))
+    return A

@@ -14,7 +14,7 @@ from mpgen import random_cmat
 from oracle import lu_ref
 from oracle.fraction_ref import decode
 from tests.gpu_util import device_result_to_host, mismatches
-from tests.lu_cases import column, exact_case, to_cmat
+from tests.lu_cases import column, diagonal_pivots, dominant_matrix, exact_case, to_cmat
 
 pytestmark = pytest.mark.gpu
 
@@ -39,7 +39,8 @@ def _factor(A, nb, p, mode):
 
 @pytest.mark.parametrize("n,nb,p,mode", [(1, 1, 64, 1), (2, 1, 64, 0), (5, 2, 128, 1), (17, 8, 256, 1),
                                          (40, 16, 256, 1), (33, 64, 128, 0), (24, 5, 1000, 1), (9, 4, 2, 1),
-                                         (6, 4, 4096, 1), (65, 64, 128, 1)])
+                                         (6, 4, 4096, 1), (65, 64, 128, 1), (200, 128, 256, 1),
+                                         (150, 128, 192, 0)])
 def test_getrf_parity(n, nb, p, mode):
     A = random_cmat([51, n, p], 0, n, n, p, 2)
     _say(f"getrf n={n} nb={nb} p={p} mode={mode}")
@@ -142,3 +143,71 @@ def test_reciprocal_chain_wide_exponents():
     assert info == ref_info and np.array_equal(ipiv.cpu().numpy(), ref_piv)
     bad, first = mismatches(device_result_to_host(dA, p), ref, n, n)
     assert bad == 0, (bad, first)
+
+
+def _rhs_ones(A, n, p):
+    """b = A (1 + i) ones, rounded once (the oracle's product)."""
+    import oracle
+    ones = to_cmat(column([(Fraction(1), Fraction(1))] * n), p)
+    return oracle.cgemm(A, ones, p)
+
+
+def test_dominant_n256_nb128():
+    """The factorization workload at the size the oracle checks: A random
+    (exponents on [-2, 2]) plus 256 (1 + i) on the diagonal, block width 128,
+    256 bits; b = A (1 + i) ones.  Factors, interchanges and solution are
+    bit-identical to the oracle's, and x is (1 + i) ones to a few units of
+    2^-256."""
+    import torch
+    import paper_2307_06072_amd as mp
+    n, nb, p = 256, 128, 256
+    A = dominant_matrix(n, p, [5, n])
+    b = _rhs_ones(A, n, p)
+    _say("getrf dominant n=256 nb=128 p=256")
+    dA, ipiv, info = _factor(A, nb, p, 1)
+    ref, ref_piv, ref_info = lu_ref.getrf(A, nb, p)
+    assert info == ref_info == 0
+    assert np.array_equal(ipiv.cpu().numpy()[:n], ref_piv)
+    bad, first = mismatches(device_result_to_host(dA, p), ref, n, n)
+    assert bad == 0, (bad, first)
+    _say("getrs dominant n=256")
+    dB = mp.to_device(b)
+    mp.mp_zgetrs(n, 1, dA, dA.ld, ipiv, dB, dB.ld, p, 1)
+    torch.cuda.synchronize()
+    assert mp.mpcg_stream_status() == 0
+    refx = lu_ref.getrs(ref, ref_piv, b, p)
+    X = device_result_to_host(dB, p)
+    bad, first = mismatches(X, refx, n, 1)
+    assert bad == 0, (bad, first)
+    err = max(abs(decode(X.re, k, 0, p) - 1) + abs(decode(X.im, k, 0, p) - 1) for k in range(n)) / 2
+    _say(f"max relative error {float(err):.3e}")
+    assert err < Fraction(2) ** (8 - p)
+
+
+@pytest.mark.parametrize("n,p", [(64, 256), (48, 53), (40, 1024), (16, 2), (24, 100), (8, 4096)])
+def test_reciprocals_correctly_rounded(n, p):
+    """The pivot reciprocals, read through the solve of a diagonal system
+    with b = 1 (x_c is then the reciprocal of the pivot c): every component
+    equals the exact rational 1/y rounded once, for pivots with parts close
+    together, far apart, one part zero, powers of two and all-ones
+    significands."""
+    import torch
+    import paper_2307_06072_amd as mp
+    A = diagonal_pivots(n, p, [56, n, p])
+    b = to_cmat(column([(Fraction(1), Fraction(0))] * n), p)
+    _say(f"reciprocals n={n} p={p}")
+    dA, ipiv, info = _factor(A, 16, p, 1)
+    assert info == 0
+    dB = mp.to_device(b)
+    mp.mp_zgetrs(n, 1, dA, dA.ld, ipiv, dB, dB.ld, p, 1)
+    torch.cuda.synchronize()
+    assert mp.mpcg_stream_status() == 0
+    X = device_result_to_host(dB, p)
+    for c in range(n):
+        R = lu_ref.reciprocal(lu_ref._sub(A, c, 1, c, 1), p)
+        for name in ("re", "im"):
+            got, want = getattr(X, name), getattr(R, name)
+            assert int(got.exp[0, c]) == int(want.exp[0, 0]), (c, name)
+            if int(want.exp[0, 0]) != -2 ** 31:
+                assert int(got.sign[0, c]) == int(want.sign[0, 0]), (c, name)
+                assert np.array_equal(got.mant[:, 0, c], want.mant[:, 0, 0]), (c, name)
