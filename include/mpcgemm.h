@@ -169,6 +169,43 @@ int mp_cgemm_ex(int m, int n, int k, const mpcg_cmat *A, int lda, const mpcg_cma
                 mpcg_cmat *C, int ldc, int prec_bits, int mode, int scheme,
                 const mpcg_options *opt, mpcg_info *info);
 
+/* Size in bytes of the fixed device buffer of mp_cgemm_ex_noalloc. */
+#define MPCG_NOALLOC_BYTES (128u << 20)
+
+/*
+ * mp_cgemm_ex_noalloc - mp_cgemm_ex for callers that cannot allocate memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, layout, results (bit for bit) and errors as
+ * mp_cgemm_ex, but every byte of device memory the call needs beyond A, B
+ * and C (status word, exponent scan, digit planes, diagonal digits) comes
+ * from a fixed buffer of MPCG_NOALLOC_BYTES inside the library, one per
+ * device, held until the process ends; the call makes no hipMalloc, hipFree,
+ * hipHostMalloc or event creation (timing is off for it).
+ *   - A product whose scan and workspace exceed the buffer is rejected with
+ *     MPCG_ENOMEM before any device work (mpcg_workspace_size with the same
+ *     arguments gives the workspace part; the scan adds 16 (m + n) bytes
+ *     plus 256, rounded up to 256).  About 256 x 256 x 256 at 256 bits, or
+ *     128^3 at 1024 bits, fit.
+ *   - adaptive slicing (opt->adaptive without max_spread) is rejected with
+ *     MPCG_EUNSUPPORTED.
+ *   - Without opt->max_spread the call reads its exponent scan back into host
+ *     stack memory and synchronizes the stream once, as mp_cgemm_ex does; with
+ *     max_spread > 0 it never synchronizes and may be captured into a HIP
+ *     graph.
+ *   - The buffer is shared by every call of this entry point on a device and
+ *     keeps the last call's contents; each call initializes what it reads.
+ *     Calls that overlap on one device (on different streams, or from
+ *     several host threads whose stream work overlaps) race on it: the caller
+ *     orders them.  mp_cgemm_ex and the other entry points do not use it.
+ *   - Device-detected conditions are reported by mpcg_stream_status as for
+ *     mp_cgemm_ex (the buffer's own status word is read and cleared too).
+ * The buffer is set up on a device's first call: its device address is looked
+ * up and its status word cleared (a kernel on the library stream).
+ */
+int mp_cgemm_ex_noalloc(int m, int n, int k, const mpcg_cmat *A, int lda, const mpcg_cmat *B, int ldb,
+                        mpcg_cmat *C, int ldc, int prec_bits, int mode, int scheme,
+                        const mpcg_options *opt, mpcg_info *info);
+
 /*
  * mp_cgemm_acc - the accumulating product C := C + sign * A B (sign = +1 or
  * -1), the trailing update of the blocked complex LU (Sec. IV-B: the update

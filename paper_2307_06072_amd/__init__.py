@@ -81,6 +81,9 @@ _lib.mp_cgemm.restype = _i
 _lib.mp_cgemm_ex.argtypes = [_i, _i, _i, _P(mpcg_cmat), _i, _P(mpcg_cmat), _i, _P(mpcg_cmat), _i, _i, _i, _i,
                              _P(mpcg_options), _P(mpcg_info)]
 _lib.mp_cgemm_ex.restype = _i
+_lib.mp_cgemm_ex_noalloc.argtypes = [_i, _i, _i, _P(mpcg_cmat), _i, _P(mpcg_cmat), _i, _P(mpcg_cmat), _i, _i, _i,
+                                     _i, _P(mpcg_options), _P(mpcg_info)]
+_lib.mp_cgemm_ex_noalloc.restype = _i
 _lib.mp_cgemm_acc.argtypes = [_i, _i, _i, _P(mpcg_cmat), _i, _P(mpcg_cmat), _i, _P(mpcg_cmat), _i, _i, _i, _i, _i,
                               _P(mpcg_options), _P(mpcg_info)]
 _lib.mp_cgemm_acc.restype = _i
@@ -113,7 +116,7 @@ _lib.mp_zgetrf.restype = _i
 _lib.mp_zgetrs.argtypes = [_i, _i, _P(mpcg_cmat), _i, _vp, _P(mpcg_cmat), _i, _i, _i]
 _lib.mp_zgetrs.restype = _i
 
-EXPORTS = ["mp_cgemm", "mp_cgemm_ex", "mp_cgemm_acc", "mp_cgemm_batched", "mp_cgemm_batched_acc", "mp_zgetrf", "mp_zgetrs", "mpcg_set_stream", "mpcg_set_workspace", "mpcg_workspace_size",
+EXPORTS = ["mp_cgemm", "mp_cgemm_ex", "mp_cgemm_ex_noalloc", "mp_cgemm_acc", "mp_cgemm_batched", "mp_cgemm_batched_acc", "mp_zgetrf", "mp_zgetrs", "mpcg_set_stream", "mpcg_set_workspace", "mpcg_workspace_size",
            "mpcg_stream_status", "mpcg_last_error", "mpcg_enable_timing", "mpcg_last_timing",
            "mpcg_timing_report", "mpcg_from_doubles", "mpcg_to_doubles"]
 
@@ -316,6 +319,24 @@ def mp_cgemm_ex(m, n, k, A: DeviceCMat, lda, B: DeviceCMat, ldb, C: DeviceCMat, 
     info = mpcg_info()
     _check(_lib.mp_cgemm_ex(m, n, k, ctypes.byref(a), lda, ctypes.byref(b), ldb, ctypes.byref(c), ldc,
                             prec_bits, mode, scheme, ctypes.byref(opt), ctypes.byref(info)))
+    return info.as_dict()
+
+
+def mp_cgemm_ex_noalloc_raw(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, mode, scheme, options=None,
+                            info=None) -> int:
+    return int(_lib.mp_cgemm_ex_noalloc(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, mode, scheme, options, info))
+
+
+def mp_cgemm_ex_noalloc(m, n, k, A: DeviceCMat, lda, B: DeviceCMat, ldb, C: DeviceCMat, ldc, prec_bits,
+                        mode=MPCG_3M, scheme=MPCG_EXACT, slice_type=MPCG_SLICE_INT8, cutoff_override=0,
+                        ksplit_override=0, block_override=0, max_spread=0) -> dict:
+    """mp_cgemm_ex with every scratch byte from the library's fixed device
+    buffer (MPCG_NOALLOC_BYTES per device); no allocation."""
+    a, b, c = A.struct(), B.struct(), C.struct()
+    opt = mpcg_options(slice_type, cutoff_override, ksplit_override, block_override, max_spread, 0)
+    info = mpcg_info()
+    _check(_lib.mp_cgemm_ex_noalloc(m, n, k, ctypes.byref(a), lda, ctypes.byref(b), ldb, ctypes.byref(c), ldc,
+                                    prec_bits, mode, scheme, ctypes.byref(opt), ctypes.byref(info)))
     return info.as_dict()
 
 

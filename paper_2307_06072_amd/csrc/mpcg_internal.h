@@ -145,6 +145,14 @@ struct RoundArgs {
 };
 hipError_t launch_round(const RoundArgs& a, hipStream_t stream);
 
+// The fixed buffer of mp_cgemm_ex_noalloc on the current device (set up on
+// first use: its device address looked up, its status word cleared on
+// `stream`): *ptr, *bytes = MPCG_NOALLOC_BYTES.  The first 256 bytes hold the
+// status word.
+hipError_t noalloc_scratch(hipStream_t stream, void** ptr, size_t* bytes);
+// That status word on the current device, or NULL if the buffer is not set up.
+int* noalloc_status_word();
+
 // bytes[0 .. n) := 0 (a kernel, so that the call stays capturable).
 hipError_t launch_fill_zero(void* p, size_t n, hipStream_t stream);
 

@@ -388,9 +388,17 @@ std::vector<int> adaptive_blocks(const std::vector<RowStat>& st, int p, int x, b
 
 // acc = 0: C := AB; acc = +1 / -1: C := C + AB / C - AB, one rounding of the
 // exact sum (C's current entries are the addend).
+// Device memory of a call that must not allocate: the status word and one
+// region that holds the exponent scan and then the workspace.
+struct FixedBuffers {
+  int* status;
+  char* base;
+  size_t bytes;
+};
+
 int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, int ldb, mpcg_cmat* C, int ldc,
         int prec_bits, int mode, int scheme, const mpcg_options* opt, mpcg_info* info, int acc = 0,
-        bool check_overlap = true) {
+        bool check_overlap = true, const FixedBuffers* fixed = nullptr) {
   g_err.clear();
   int st = validate(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, mode, scheme, opt, check_overlap);
   if (st) return st;
@@ -398,12 +406,17 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
   if (acc && opt && opt->slice_type == MPCG_SLICE_FP64)
     return set_err(MPCG_EUNSUPPORTED, "the accumulating form needs INT8 slices");
   if (info) memset(info, 0, sizeof(*info));
+  if (fixed && opt && opt->adaptive && opt->max_spread <= 0)
+    return set_err(MPCG_EUNSUPPORTED, "adaptive slicing runs a batch, which this entry point cannot");
   if (m == 0 || n == 0) return MPCG_OK;
   std::unique_lock<std::mutex> lock(g_mu);
   g_timing_valid = false;
   const int L = (prec_bits + 63) / 64;
   const DOutPart cre = doutpart(C->re, (int64_t)ldc * n), cim = doutpart(C->im, (int64_t)ldc * n);
-  if ((st = ensure_status_and_pinned())) return st;
+  if (!fixed && (st = ensure_status_and_pinned())) return st;
+  int* const status = fixed ? fixed->status : g_status;
+  // stage events need event objects: no timing without allocation
+  auto stage = [&](int idx) { return fixed ? (int)MPCG_OK : record(idx); };
   if (k == 0) {  // empty contraction: AB = 0
     if (!acc) HIP_TRY(launch_zero(cre, cim, m, n, ldc, L, g_stream));
     return MPCG_OK;
@@ -426,27 +439,48 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
     // planned from the caller's bound: no read-back, the scan lives in the workspace
     if ((st = plan_slices(P, bound, bound, bound, bound, opt))) return st;
     if ((st = plan_layout(P, opt))) return st;
-    if ((st = ensure_workspace(P.total, &ws))) return st;
+    if (fixed) {
+      if (P.total > fixed->bytes)
+        return set_err(MPCG_ENOMEM, "this product needs %zu bytes of workspace; the fixed buffer holds %zu",
+                       P.total, fixed->bytes);
+      ws = fixed->base;
+    } else if ((st = ensure_workspace(P.total, &ws))) {
+      return st;
+    }
     char* sc = static_cast<char*>(ws) + P.off_scan;
     statA = reinterpret_cast<RowStat*>(sc);
     statB = reinterpret_cast<RowStat*>(sc + sA);
     ScanSummary* summ = reinterpret_cast<ScanSummary*>(sc + sA + sB);
-    if ((st = record(0))) return st;
-    HIP_TRY(launch_scan(opA, statA, summ, bound, g_status, g_stream));
-    HIP_TRY(launch_scan(opB, statB, summ + 1, bound, g_status, g_stream));
-    if ((st = record(1))) return st;
+    if ((st = stage(0))) return st;
+    HIP_TRY(launch_scan(opA, statA, summ, bound, status, g_stream));
+    HIP_TRY(launch_scan(opB, statB, summ + 1, bound, status, g_stream));
+    if ((st = stage(1))) return st;
   } else {
-    if ((st = ensure_scan(sA + sB + 256))) return st;
-    statA = reinterpret_cast<RowStat*>(g_scan);
-    statB = reinterpret_cast<RowStat*>((char*)g_scan + sA);
-    ScanSummary* summ = reinterpret_cast<ScanSummary*>((char*)g_scan + sA + sB);
-    if ((st = record(0))) return st;
+    // the scan's statistics: library-owned, or at the start of the fixed
+    // buffer (the workspace then follows them)
+    const size_t scan_bytes = sA + sB + 256;
+    char* scan_base;
+    if (fixed) {
+      if (scan_bytes > fixed->bytes)
+        return set_err(MPCG_ENOMEM, "the exponent scan needs %zu bytes; the fixed buffer holds %zu", scan_bytes,
+                       fixed->bytes);
+      scan_base = fixed->base;
+    } else {
+      if ((st = ensure_scan(scan_bytes))) return st;
+      scan_base = static_cast<char*>(g_scan);
+    }
+    statA = reinterpret_cast<RowStat*>(scan_base);
+    statB = reinterpret_cast<RowStat*>(scan_base + sA);
+    ScanSummary* summ = reinterpret_cast<ScanSummary*>(scan_base + sA + sB);
+    ScanSummary local[2];  // pageable read-back for calls that allocate nothing
+    ScanSummary* host_summ = fixed ? local : g_host_summary;
+    if ((st = stage(0))) return st;
     HIP_TRY(launch_scan(opA, statA, summ, 0, nullptr, g_stream));
     HIP_TRY(launch_scan(opB, statB, summ + 1, 0, nullptr, g_stream));
-    HIP_TRY(hipMemcpyAsync(g_host_summary, summ, 2 * sizeof(ScanSummary), hipMemcpyDeviceToHost, g_stream));
-    if ((st = record(1))) return st;
+    HIP_TRY(hipMemcpyAsync(host_summ, summ, 2 * sizeof(ScanSummary), hipMemcpyDeviceToHost, g_stream));
+    if ((st = stage(1))) return st;
     HIP_TRY(hipStreamSynchronize(g_stream));
-    const ScanSummary sa = g_host_summary[0], sb = g_host_summary[1];
+    const ScanSummary sa = host_summ[0], sb = host_summ[1];
     if ((sa.status | sb.status) & ST_IN_RANGE)
       return set_err(MPCG_ERANGE, "input exponent outside [-2^30, 2^30]");
     if (sa.nonzero == 0 || sb.nonzero == 0) {  // AB = 0
@@ -483,7 +517,15 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
     }
     if ((st = plan_slices(P, sa.spread, sb.spread, sa.hat, sb.hat, opt))) return st;
     if ((st = plan_layout(P, opt))) return st;
-    if ((st = ensure_workspace(P.total, &ws))) return st;
+    if (fixed) {
+      const size_t off = align256(scan_bytes);
+      if (P.total > fixed->bytes - off)
+        return set_err(MPCG_ENOMEM, "this product needs %zu bytes of workspace; the fixed buffer holds %zu",
+                       P.total + off, fixed->bytes);
+      ws = fixed->base + off;
+    } else if ((st = ensure_workspace(P.total, &ws))) {
+      return st;
+    }
   }
   if (info) {
     info->S_A = P.SA; info->S_B = P.SB; info->w = P.w; info->cutoff = P.cutoff;
@@ -501,16 +543,16 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
   const Third thirdB = P.mode3m ? Third::SUM : Third::NEG_IM;
   if (!P.f64) {
     HIP_TRY(launch_split_i8(opA, prec_bits, L, P.SA, P.SAp, P.xs, P.xlo, thirdA, G, P.mpad, P.kpad,
-                            reinterpret_cast<int8_t*>(base + P.off_X), g_status, g_stream));
+                            reinterpret_cast<int8_t*>(base + P.off_X), status, g_stream));
     HIP_TRY(launch_split_i8(opB, prec_bits, L, P.SB, P.SBp, P.ys, P.ylo, thirdB, H, P.npad, P.kpad,
-                            reinterpret_cast<int8_t*>(base + P.off_Y), g_status, g_stream));
+                            reinterpret_cast<int8_t*>(base + P.off_Y), status, g_stream));
   } else {
     HIP_TRY(launch_split_f64(opA, prec_bits, L, P.SA, P.SAp, P.w, thirdA, G, P.mpad, P.kpad,
-                             reinterpret_cast<double*>(base + P.off_X), g_status, g_stream));
+                             reinterpret_cast<double*>(base + P.off_X), status, g_stream));
     HIP_TRY(launch_split_f64(opB, prec_bits, L, P.SB, P.SBp, P.w, thirdB, H, P.npad, P.kpad,
-                             reinterpret_cast<double*>(base + P.off_Y), g_status, g_stream));
+                             reinterpret_cast<double*>(base + P.off_Y), status, g_stream));
   }
-  if ((st = record(2))) return st;
+  if ((st = stage(2))) return st;
 
   // ---- slice GEMM + carry chain -------------------------------------------
   int64_t* top = reinterpret_cast<int64_t*>(base + P.off_top);
@@ -533,7 +575,7 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
     ga.digits = reinterpret_cast<uint32_t*>(base + P.off_dig); ga.top = top; ga.lnz = lnz;
     HIP_TRY(launch_gemm_f64(ga, g_stream));
   }
-  if ((st = record(3))) return st;
+  if ((st = stage(3))) return st;
 
   // ---- merge chunks, round, store -------------------------------------------
   RoundArgs ra{};
@@ -544,11 +586,11 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
   ra.top = top; ra.lnz = lnz;
   ra.ksplit = P.ksplit; ra.mt = P.mt; ra.nt = P.nt; ra.Dmax = P.Dmax; ra.w = P.w;
   ra.G = G; ra.H = H; ra.m = m; ra.n = n; ra.prec = prec_bits; ra.L = L;
-  ra.cre = cre; ra.cim = cim; ra.ldc = ldc; ra.status = g_status;
+  ra.cre = cre; ra.cim = cim; ra.ldc = ldc; ra.status = status;
   ra.acc = acc;
   HIP_TRY(launch_round(ra, g_stream));
-  if ((st = record(4))) return st;
-  g_timing_valid = g_timing;
+  if ((st = stage(4))) return st;
+  g_timing_valid = g_timing && !fixed;
   return MPCG_OK;
 }
 
@@ -1281,6 +1323,26 @@ int mp_cgemm_ex(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cma
   return run(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, mode, scheme, opt, info);
 }
 
+int mp_cgemm_ex_noalloc(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, int ldb,
+                        mpcg_cmat* C, int ldc, int prec_bits, int mode, int scheme, const mpcg_options* opt,
+                        mpcg_info* info) {
+  g_err.clear();
+  int st = validate(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, mode, scheme, opt);
+  if (st) return st;
+  if (m == 0 || n == 0) {
+    if (info) memset(info, 0, sizeof(*info));
+    return MPCG_OK;
+  }
+  void* base = nullptr;
+  size_t bytes = 0;
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    HIP_TRY(noalloc_scratch(g_stream, &base, &bytes));
+  }
+  const FixedBuffers fb{static_cast<int*>(base), static_cast<char*>(base) + 256, bytes - 256};
+  return run(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, mode, scheme, opt, info, 0, true, &fb);
+}
+
 int mp_cgemm_acc(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, int ldb, mpcg_cmat* C,
                  int ldc, int prec_bits, int mode, int scheme, int sign, const mpcg_options* opt, mpcg_info* info) {
   if (sign != 1 && sign != -1) {
@@ -1350,12 +1412,18 @@ size_t mpcg_workspace_size(int m, int n, int k, int prec_bits, int mode, int sch
 
 int mpcg_stream_status(void* hip_stream) {
   std::lock_guard<std::mutex> lock(g_mu);
-  if (!g_status) return MPCG_OK;
+  int* const fixed_status = noalloc_status_word();
+  if (!g_status && !fixed_status) return MPCG_OK;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   HIP_TRY(hipStreamSynchronize(s));
   int v = 0;
-  HIP_TRY(hipMemcpy(&v, g_status, sizeof(int), hipMemcpyDeviceToHost));
-  HIP_TRY(hipMemset(g_status, 0, sizeof(int)));
+  for (int* word : {g_status, fixed_status}) {
+    if (!word) continue;
+    int w = 0;
+    HIP_TRY(hipMemcpy(&w, word, sizeof(int), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemset(word, 0, sizeof(int)));
+    v |= w;
+  }
   if (v & ST_SPREAD) return set_err(MPCG_ESPREAD, "an operand's exponent spread exceeded max_spread");
   if (v & ST_IN_RANGE) return set_err(MPCG_ERANGE, "input exponent outside [-2^30, 2^30]");
   if (v & ST_OUT_RANGE) return set_err(MPCG_ERANGE, "output exponent outside int32 (or a double component beyond the largest double)");
