@@ -10,8 +10,9 @@ goes to stderr.
 Also reported in "extra": the 512^3 / 512-bit family (FP64-slice 4M vs
 INT8-slice 4M vs INT8-slice 3M, exact and truncated) with the INT8-3M over
 FP64-4M speedup, the truncated scheme on the default workload, a batch of
-256 products, the LU trailing-update stream, the paper's full LU problem
-(n = 1024, 256 bits, K = 128) and the multi-component codec.
+256 products, the LU trailing-update stream, the blocked LU of order 4096
+(block 128, 256 bits, A + n(1+i)I, b = A(1+i) ones) and the
+multi-component codec.
 """
 from __future__ import annotations
 
@@ -291,7 +292,89 @@ def adaptive_case(A, B, p):
     return {"cgemm2048_p1024_mixed_spread": out}
 
 
-def lu_full_case(widths=(128,), precs=(256,)):
+def lu_full_case(n=4096, nb=128, p=256):
+    """The blocked LU workload: A with random entries (exponents on [-2, 2])
+    plus n (1 + i) on the diagonal (each shifted component rounded once, by
+    one accumulating product on the diagonal viewed as a row with leading
+    dimension lda + 1), b = A (1 + i) ones rounded
+    once by mp_cgemm; mp_zgetrf with block width nb, then mp_zgetrs.  Reports
+    the seconds of each and the largest relative error of x against
+    (1 + i) ones (|Re| + |Im| norm)."""
+    from fractions import Fraction
+    import torch
+    import paper_2307_06072_amd as mp
+    from mpgen import EXP_ZERO, random_cmat
+    log(f"blocked LU n={n} nb={nb} p={p}: A + n(1+i)I, b = A (1+i) ones")
+    L = (p + 63) // 64
+    A = random_cmat([5, n], 0, n, n, p, 2)
+    dA = mp.to_device(A)
+    del A
+
+    def scalar(vre, vim):  # a 1 x 1 matrix holding vre + i vim, both powers of two or zero
+        M = mp.device_empty(1, 1, p)
+        for part, v in ((M.re, vre), (M.im, vim)):
+            if v:
+                e = v.bit_length()
+                assert v == 1 << (e - 1)
+                part.exp.fill_(e)
+                part.mant[L - 1].fill_(-(1 << 63))  # top bit only (uint64 pattern as int64)
+        return M
+
+    # the diagonal as a 1 x n row (leading dimension lda + 1) := itself + n(1+i) x (1 x n row of ones)
+    dn = scalar(n, n)
+    row1 = mp.device_empty(1, n, p)
+    for part in (row1.re,):
+        part.exp.fill_(1)
+        part.mant[L - 1].fill_(-(1 << 63))
+    diag = mp.DeviceCMat(1, n, dA.ld + 1, dA.L, dA.re, dA.im)
+    mp.mpcg_set_stream()
+    mp.mp_cgemm_acc(1, n, 1, dn, 1, row1, 1, diag, dA.ld + 1, p, +1)
+    ones = mp.device_empty(n, 1, p)
+    for part in (ones.re, ones.im):
+        part.exp.fill_(1)
+        part.mant[L - 1].fill_(-(1 << 63))
+    dB = mp.device_empty(n, 1, p)
+    mp.mp_cgemm(n, 1, n, dA, dA.ld, ones, ones.ld, dB, dB.ld, p)
+    # warm-up of every kernel on a small case
+    dW = mp.to_device(random_cmat([5, 16], 0, 16, 16, p, 2))
+    wp = torch.zeros(16, dtype=torch.int32, device="cuda")
+    mp.mp_zgetrf(16, dW, dW.ld, wp, 8, p, mp.MPCG_3M)
+    ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = mp.mp_zgetrf(n, dA, dA.ld, ipiv, nb, p, mp.MPCG_3M)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    log(f"  getrf {t1 - t0:.2f} s")
+    mp.mp_zgetrs(n, 1, dA, dA.ld, ipiv, dB, dB.ld, p, mp.MPCG_3M)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    if info != 0 or mp.mpcg_stream_status() != 0:
+        raise RuntimeError(f"LU failed: info {info}, {mp.mpcg_last_error()}")
+    h = mp.to_numpy(dB)
+    err = Fraction(0)
+    for k in range(n):
+        comps = []
+        for name in ("re", "im"):
+            sg, ex, mt = h[name]
+            if ex[0, k] == EXP_ZERO:
+                comps.append(Fraction(0))
+                continue
+            M = 0
+            for l in range(L - 1, -1, -1):
+                M = (M << 64) | int(mt[l, 0, k])
+            v = Fraction(M) * Fraction(2) ** (int(ex[0, k]) - 64 * L)
+            comps.append(-v if sg[0, k] else v)
+        err = max(err, (abs(comps[0] - 1) + abs(comps[1] - 1)) / 2)
+    log(f"  getrs {t2 - t1:.2f} s, max relative error {float(err):.2e}")
+    pivots_moved = int((ipiv.cpu() != torch.arange(n, dtype=torch.int32)).sum())
+    return {f"lu_full_n{n}_b{nb}_p{p}": {"getrf_s": t1 - t0, "getrs_s": t2 - t1, "max_rel_err": float(err),
+                                         "rows_exchanged": pivots_moved,
+                                         "matrix": "random (e in [-2, 2]) + n(1+i) I",
+                                         "rhs": "b = A (1+i) ones"}}
+
+
+def lu_paper_case(widths=(128,), precs=(256,)):
     """The paper's LU experiment (Sec. IV-B) at n = 1024 and 256 (512, 768)
     bits: A with random entries (exponents on [-2, 2]), x_k = k + k i, b = A x
     rounded once by mp_cgemm; mp_zgetrf with block width K, then mp_zgetrs.
@@ -299,7 +382,7 @@ def lu_full_case(widths=(128,), precs=(256,)):
     |Im| norm)."""
     rec = {}
     for p in precs:
-        rec[f"lu_full_n1024_p{p}"] = _lu_full_one(widths, p)
+        rec[f"lu_paper_n1024_p{p}"] = _lu_full_one(widths, p)
     return rec
 
 
@@ -452,10 +535,10 @@ def main() -> int:
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration)")
     ap.add_argument("--lu-widths", default="64,128,352",
-                    help="block widths K of the full-LU family (comma-separated)")
+                    help="block widths K of the paper-LU family (comma-separated)")
     ap.add_argument("--lu-precs", default="256",
-                    help="precisions of the full-LU family (comma-separated bits)")
-    ap.add_argument("--family", choices=["batched", "lu", "codec", "lufull", "adaptive"], default=None,
+                    help="precisions of the paper-LU family (comma-separated bits)")
+    ap.add_argument("--family", choices=["batched", "lu", "codec", "lufull", "lupaper", "adaptive"], default=None,
                     help="only run one comparison family (for profiling) and print its record")
     args = ap.parse_args()
 
@@ -482,8 +565,9 @@ def main() -> int:
         return 0
     if args.family:
         rec = {"batched": batched_case, "lu": lu_update_stream, "codec": codec_case,
-               "lufull": lambda: lu_full_case(tuple(int(v) for v in args.lu_widths.split(",")),
-                                              tuple(int(v) for v in args.lu_precs.split(","))),
+               "lufull": lambda: lu_full_case(),
+               "lupaper": lambda: lu_paper_case(tuple(int(v) for v in args.lu_widths.split(",")),
+                                                tuple(int(v) for v in args.lu_precs.split(","))),
                "adaptive": lambda: adaptive_case(*workload_inputs("cgemm2048_p1024")[4:], 1024)}[args.family]()
         print(json.dumps({"family": args.family, **rec}), flush=True)
         return 0

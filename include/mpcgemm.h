@@ -26,7 +26,10 @@
  *                   paper's F_bM, Section II).  Only the top prec_bits bits are
  *                   read; the lower bits of limb 0 are ignored on input and
  *                   written as zero on output.
- *   limb_stride >= ld*cols; 0 means exactly ld*cols.
+ *   limb_stride >= (cols-1)*ld + rows (the entries addressed, so the limb
+ *                   planes never share an entry); 0 means exactly ld*cols.
+ *                   A strided view such as the diagonal of an n x n matrix
+ *                   as a 1 x n row with ld = lda + 1 is therefore valid.
  * Outputs: each component of each entry of C is the exact value rounded to
  * prec_bits, round to nearest, ties to even.  An exact zero is written as
  * sign 0, exp MPCG_EXP_ZERO, limbs 0.

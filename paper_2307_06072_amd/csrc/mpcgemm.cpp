@@ -88,10 +88,12 @@ bool overlap(Region a, Region b) { return a.lo < b.hi && b.lo < a.hi; }
 
 int check_part(const mpcg_part& p, int rows, int cols, int ld, int L, const char* name, Region out[3]) {
   if (!p.sign || !p.exp || !p.mant) return set_err(MPCG_EINVAL, "%s: NULL pointer", name);
-  const int64_t n = (int64_t)ld * cols;
-  const int64_t ls = p.limb_stride ? p.limb_stride : n;
-  if (ls < n) return set_err(MPCG_EINVAL, "%s: limb_stride %lld < ld*cols %lld", name, (long long)ls, (long long)n);
-  (void)rows;
+  // the entries addressed: columns 0 .. cols-2 whole (ld each), `rows` of the last
+  const int64_t n = cols > 0 ? (int64_t)ld * (cols - 1) + rows : 0;
+  const int64_t ls = p.limb_stride ? p.limb_stride : (int64_t)ld * cols;
+  if (ls < n)
+    return set_err(MPCG_EINVAL, "%s: limb_stride %lld < (cols-1)*ld + rows = %lld", name, (long long)ls,
+                   (long long)n);
   out[0] = {(uintptr_t)p.sign, (uintptr_t)p.sign + (uintptr_t)n};
   out[1] = {(uintptr_t)p.exp, (uintptr_t)p.exp + (uintptr_t)(4 * n)};
   out[2] = {(uintptr_t)p.mant, (uintptr_t)p.mant + (uintptr_t)(8 * (ls * (L - 1) + n))};

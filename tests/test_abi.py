@@ -88,6 +88,20 @@ def test_limb_stride_too_small():
     assert _call(B=B) == mp.MPCG_EINVAL
 
 
+def test_limb_stride_covers_only_the_addressed_entries():
+    """A strided row view (the diagonal of a 4 x 4 matrix as a 1 x 4 row with
+    ld = 5) addresses entries 0, 5, 10, 15: a limb stride of 16 keeps the limb
+    planes apart and passes validation (the call then fails only at its
+    first device call on a host without a GPU); 15 is rejected."""
+    import paper_2307_06072_amd as mp
+    for ls, bad in ((16, False), (15, True)):
+        C = _fake_cmat(3 << 40)
+        C.re.limb_stride = ls
+        C.im.limb_stride = ls
+        rc = _call(m=1, n=4, k=4, ldc=5, C=C)
+        assert (rc == mp.MPCG_EINVAL) == bad, (ls, rc, mp.mpcg_last_error())
+
+
 def test_output_aliasing_input_rejected():
     import paper_2307_06072_amd as mp
     A = _fake_cmat(1 << 40)

@@ -211,3 +211,29 @@ def test_reciprocals_correctly_rounded(n, p):
             if int(want.exp[0, 0]) != -2 ** 31:
                 assert int(got.sign[0, c]) == int(want.sign[0, 0]), (c, name)
                 assert np.array_equal(got.mant[:, 0, c], want.mant[:, 0, 0]), (c, name)
+
+
+def test_diagonal_shift_as_row_update():
+    """The factorization workload's diagonal shift done on the device as the
+    benchmark does it (the diagonal viewed as a 1 x n row with leading
+    dimension lda + 1, plus n (1 + i) times a row of ones, one rounding)
+    equals the host recipe bit for bit."""
+    import torch
+    import paper_2307_06072_amd as mp
+    n, p = 128, 256  # n a power of two: n (1 + i) is written as 2^(e-1), e = bit length of n
+    L = (p + 63) // 64
+    A = random_cmat([5, n], 0, n, n, p, 2)
+    want = dominant_matrix(n, p, [5, n])
+    dA = mp.to_device(A)
+    dn = mp.device_empty(1, 1, p)
+    row1 = mp.device_empty(1, n, p)
+    for part, e in ((dn.re, n.bit_length()), (dn.im, n.bit_length()), (row1.re, 1)):
+        part.exp.fill_(e)
+        part.mant[L - 1].fill_(-(1 << 63))
+    diag = mp.DeviceCMat(1, n, dA.ld + 1, dA.L, dA.re, dA.im)
+    mp.mpcg_set_stream()
+    mp.mp_cgemm_acc(1, n, 1, dn, 1, row1, 1, diag, dA.ld + 1, p, +1)
+    torch.cuda.synchronize()
+    assert mp.mpcg_stream_status() == 0
+    bad, first = mismatches(device_result_to_host(dA, p), want, n, n)
+    assert bad == 0, (bad, first)
