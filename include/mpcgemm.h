@@ -256,11 +256,31 @@ typedef struct {
  * Every problem is validated as for mp_cgemm, and C_i must not overlap any
  * A_j, B_j or another C_j.  info (may be NULL) receives the largest S_A, S_B,
  * cutoff, ksplit and band width and the summed pairs and algo_ops.
+ * Graph capture: with opt->max_spread > 0 and a workspace from
+ * mpcg_set_workspace of at least mpcg_workspace_size_batched bytes, the
+ * batch's job tables (problem descriptors and work items) live in that
+ * workspace and, while the stream is capturing, are written by kernels that
+ * carry them in their arguments, so a captured graph owns everything it
+ * replays; later calls, batched or not, do not disturb it (the graph keeps
+ * using the workspace, which the caller must not hand to other work the
+ * replays overlap).  Capturing a batch without max_spread, without a caller
+ * workspace, or before any batched call has run on the library (which sets
+ * up its status word) returns MPCG_EUNSUPPORTED.
  * Returns MPCG_OK, MPCG_EINVAL, MPCG_ENOMEM, MPCG_ERANGE, MPCG_EHIP,
- * MPCG_EUNSUPPORTED (FP64 slices).
+ * MPCG_EUNSUPPORTED (FP64 slices; capture as above).
  */
 int mp_cgemm_batched(int count, const mpcg_problem *problems, int prec_bits, int mode, int scheme,
                      const mpcg_options *opt, mpcg_info *info);
+
+/*
+ * mpcg_workspace_size_batched - bytes of workspace a batch planned from
+ * opt->max_spread (> 0, required) needs: every problem's slice planes and
+ * digits, the exponent scans and the job tables (the same planning as
+ * mp_cgemm_batched / mp_cgemm_batched_acc with these arguments; no device
+ * work).  Returns 0 for invalid arguments or a batch with nothing to compute.
+ */
+size_t mpcg_workspace_size_batched(int count, const mpcg_problem *problems, int prec_bits, int mode, int scheme,
+                                   const mpcg_options *opt);
 
 /*
  * mp_cgemm_batched_acc - the batched accumulating product: C_i := C_i +

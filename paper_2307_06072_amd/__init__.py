@@ -97,6 +97,8 @@ _lib.mpcg_set_workspace.argtypes = [_vp, ctypes.c_size_t]
 _lib.mpcg_set_workspace.restype = _i
 _lib.mpcg_workspace_size.argtypes = [_i, _i, _i, _i, _i, _i, _P(mpcg_options), _i]
 _lib.mpcg_workspace_size.restype = ctypes.c_size_t
+_lib.mpcg_workspace_size_batched.argtypes = [_i, _P(mpcg_problem), _i, _i, _i, _P(mpcg_options)]
+_lib.mpcg_workspace_size_batched.restype = ctypes.c_size_t
 _lib.mpcg_stream_status.argtypes = [_vp]
 _lib.mpcg_stream_status.restype = _i
 _lib.mpcg_last_error.argtypes = []
@@ -116,7 +118,7 @@ _lib.mp_zgetrf.restype = _i
 _lib.mp_zgetrs.argtypes = [_i, _i, _P(mpcg_cmat), _i, _vp, _P(mpcg_cmat), _i, _i, _i]
 _lib.mp_zgetrs.restype = _i
 
-EXPORTS = ["mp_cgemm", "mp_cgemm_ex", "mp_cgemm_ex_noalloc", "mp_cgemm_acc", "mp_cgemm_batched", "mp_cgemm_batched_acc", "mp_zgetrf", "mp_zgetrs", "mpcg_set_stream", "mpcg_set_workspace", "mpcg_workspace_size",
+EXPORTS = ["mp_cgemm", "mp_cgemm_ex", "mp_cgemm_ex_noalloc", "mp_cgemm_acc", "mp_cgemm_batched", "mp_cgemm_batched_acc", "mp_zgetrf", "mp_zgetrs", "mpcg_set_stream", "mpcg_set_workspace", "mpcg_workspace_size", "mpcg_workspace_size_batched",
            "mpcg_stream_status", "mpcg_last_error", "mpcg_enable_timing", "mpcg_last_timing",
            "mpcg_timing_report", "mpcg_from_doubles", "mpcg_to_doubles"]
 
@@ -359,6 +361,25 @@ def mp_cgemm_acc(m, n, k, A: DeviceCMat, lda, B: DeviceCMat, ldb, C: DeviceCMat,
 
 def mp_cgemm_batched_raw(count, problems, prec_bits, mode, scheme, options=None, info=None) -> int:
     return int(_lib.mp_cgemm_batched(count, problems, prec_bits, mode, scheme, options, info))
+
+
+def _problem_array(problems):
+    keep = []
+    arr = (mpcg_problem * max(1, len(problems)))()
+    for t, (A, B, C) in enumerate(problems):
+        a, b, c = A.struct(), B.struct(), C.struct()
+        keep += [a, b, c]
+        arr[t] = mpcg_problem(A.rows, B.cols, A.cols, ctypes.pointer(a), A.ld, ctypes.pointer(b), B.ld,
+                              ctypes.pointer(c), C.ld)
+    return arr, keep
+
+
+def mpcg_workspace_size_batched(problems, prec_bits, mode=MPCG_3M, scheme=MPCG_EXACT, max_spread=0,
+                                block_override=0, ksplit_override=0) -> int:
+    """Workspace bytes of a batch planned from max_spread (> 0)."""
+    arr, keep = _problem_array(problems)
+    opt = mpcg_options(MPCG_SLICE_INT8, 0, ksplit_override, block_override, max_spread)
+    return int(_lib.mpcg_workspace_size_batched(len(problems), arr, prec_bits, mode, scheme, ctypes.byref(opt)))
 
 
 def mp_cgemm_batched(problems, prec_bits, mode=MPCG_3M, scheme=MPCG_EXACT, cutoff_override=0,

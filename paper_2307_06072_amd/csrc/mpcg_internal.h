@@ -153,6 +153,16 @@ hipError_t noalloc_scratch(hipStream_t stream, void** ptr, size_t* bytes);
 // That status word on the current device, or NULL if the buffer is not set up.
 int* noalloc_status_word();
 
+// dst[0, bytes) := src[0, bytes) by kernels that carry the data in their
+// arguments (StoreWords::N words per launch): a captured graph replays its
+// own copy, whatever becomes of src.
+struct StoreWords {
+  static constexpr uint32_t N = 760;
+  uint32_t n;
+  uint32_t v[N];
+};
+hipError_t launch_store_words(void* dst, const void* src, size_t bytes, hipStream_t stream);
+
 // bytes[0 .. n) := 0 (a kernel, so that the call stays capturable).
 hipError_t launch_fill_zero(void* p, size_t n, hipStream_t stream);
 

@@ -358,7 +358,8 @@ int validate(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* 
 }
 
 int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, int scheme,
-                const mpcg_options* opt, mpcg_info* info, int acc, bool check_overlap);
+                const mpcg_options* opt, mpcg_info* info, int acc, bool check_overlap,
+                size_t* size_query = nullptr);
 mpcg_cmat view_at(const mpcg_cmat& M, int ld, int cols, int r, int c);
 
 // Contiguous blocks of rows (of A) or columns (of B) for adaptive slicing:
@@ -514,7 +515,7 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
         mpcg_options o = *opt;
         o.adaptive = 0;
         lock.unlock();
-        return run_batched((int)probs.size(), probs.data(), prec_bits, mode, scheme, &o, info, acc, false);
+        return run_batched((int)probs.size(), probs.data(), prec_bits, mode, scheme, &o, info, acc, false, nullptr);
       }
     }
     if ((st = plan_slices(P, sa.spread, sb.spread, sa.hat, sb.hat, opt))) return st;
@@ -616,18 +617,29 @@ int g_num_cu = 0;
 
 struct Tables {
   std::vector<char> bytes;
+  // room for `count` entries of T (at least one), 256-byte aligned
+  template <typename T>
+  size_t reserve(size_t count) {
+    const size_t off = align256(bytes.size());
+    bytes.resize(off + std::max<size_t>(1, count) * sizeof(T));
+    return off;
+  }
+  template <typename T>
+  void put(size_t off, const std::vector<T>& v) {
+    if (!v.empty()) memcpy(bytes.data() + off, v.data(), v.size() * sizeof(T));
+  }
   template <typename T>
   size_t add(const std::vector<T>& v) {
-    const size_t off = align256(bytes.size());
-    bytes.resize(off + std::max<size_t>(1, v.size()) * sizeof(T));
-    if (!v.empty()) memcpy(bytes.data() + off, v.data(), v.size() * sizeof(T));
+    const size_t off = reserve<T>(v.size());
+    put(off, v);
     return off;
   }
 };
 
-// Copy the tables to the device (asynchronously on the library stream);
-// returns the device base address.
-int upload_tables(const Tables& t, char** dev) {
+// Copy the tables to the device (asynchronously on the library stream), to
+// `dst` if given, else to the library's table buffer; returns the device
+// base address.
+int upload_tables(const Tables& t, char** dev, char* dst = nullptr) {
   const size_t n = align256(t.bytes.size());
   if (g_stage_pending) {
     HIP_TRY(hipEventSynchronize(g_stage_ev));
@@ -640,7 +652,7 @@ int upload_tables(const Tables& t, char** dev) {
     HIP_TRY(hipHostMalloc(&g_stage, n, 0));
     g_stage_bytes = n;
   }
-  if (n > g_tab_bytes) {
+  if (!dst && n > g_tab_bytes) {
     if (g_tab) {
       HIP_TRY(hipStreamSynchronize(g_stream));
       HIP_TRY(hipFree(g_tab));
@@ -650,12 +662,13 @@ int upload_tables(const Tables& t, char** dev) {
     HIP_TRY(hipMalloc(&g_tab, n));
     g_tab_bytes = n;
   }
+  if (!dst) dst = static_cast<char*>(g_tab);
   if (!g_stage_ev) HIP_TRY(hipEventCreateWithFlags(&g_stage_ev, hipEventDisableTiming));
   memcpy(g_stage, t.bytes.data(), t.bytes.size());
-  HIP_TRY(hipMemcpyAsync(g_tab, g_stage, t.bytes.size(), hipMemcpyHostToDevice, g_stream));
+  HIP_TRY(hipMemcpyAsync(dst, g_stage, t.bytes.size(), hipMemcpyHostToDevice, g_stream));
   HIP_TRY(hipEventRecord(g_stage_ev, g_stream));
   g_stage_pending = true;
-  *dev = static_cast<char*>(g_tab);
+  *dev = dst;
   return MPCG_OK;
 }
 
@@ -698,8 +711,10 @@ struct BatchProblem {
 };
 
 // acc = 0: C_i := A_i B_i; +1 / -1: C_i := C_i +- A_i B_i in place, one rounding.
+// size_query != NULL (bound-planned batches only): plan, store the workspace
+// the batch needs in *size_query and return before any device work.
 int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, int scheme,
-                const mpcg_options* opt, mpcg_info* info, int acc, bool check_overlap) {
+                const mpcg_options* opt, mpcg_info* info, int acc, bool check_overlap, size_t* size_query) {
   g_err.clear();
   if (count < 0) return set_err(MPCG_EINVAL, "negative batch count %d", count);
   if (acc != 0 && acc != 1 && acc != -1) return set_err(MPCG_EINVAL, "accumulate sign must be +1 or -1");
@@ -750,10 +765,22 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
   std::lock_guard<std::mutex> lock(g_mu);
   g_timing_valid = false;
   int st;
-  if ((st = ensure_status_and_pinned())) return st;
+  const int bound = opt ? opt->max_spread : 0;
+  bool capturing = false;
+  if (size_query) {
+    if (bound <= 0) return set_err(MPCG_EINVAL, "the batch workspace query needs max_spread > 0");
+  } else {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(g_stream, &cap));
+    capturing = cap != hipStreamCaptureStatusNone;
+    if (capturing && (bound <= 0 || !g_user_ws || !g_status || !g_host_summary || !g_num_cu))
+      return set_err(MPCG_EUNSUPPORTED,
+                     "a batch captured into a graph needs max_spread > 0, a workspace set by mpcg_set_workspace "
+                     "and one batched call made before the capture");
+    if ((st = ensure_status_and_pinned())) return st;
+  }
   if ((st = num_cu())) return st;
   const int L = (prec_bits + 63) / 64;
-  const int bound = opt ? opt->max_spread : 0;
 
   std::vector<BatchProblem> bp;
   size_t scan_total = 0;
@@ -762,7 +789,7 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
     if (q.m == 0 || q.n == 0) continue;
     const DOutPart cre = doutpart(q.C->re, (int64_t)q.ldc * q.n), cim = doutpart(q.C->im, (int64_t)q.ldc * q.n);
     if (q.k == 0) {  // A B = 0: C := 0, or C unchanged when accumulating
-      if (!acc) HIP_TRY(launch_zero(cre, cim, q.m, q.n, q.ldc, L, g_stream));
+      if (!acc && !size_query) HIP_TRY(launch_zero(cre, cim, q.m, q.n, q.ldc, L, g_stream));
       continue;
     }
     BatchProblem b{};
@@ -775,7 +802,10 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
     scan_total += scan_bytes(q.m, q.n);
     bp.push_back(b);
   }
-  if (bp.empty()) return MPCG_OK;
+  if (bp.empty()) {
+    if (size_query) *size_query = 0;
+    return MPCG_OK;
+  }
   const int np = (int)bp.size();
 
   // ---- plans (from the bound, or after the scan read-back) ------------------
@@ -866,14 +896,12 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
   };
   char* scan_base = nullptr;
   if (bound > 0) {
+    // the workspace (problems, scan area, job tables) is sized once the
+    // tables are laid out, below
     for (auto& b : bp)
       if ((st = make_plan(b, bound, bound, bound, bound, 1))) return st;
     if ((st = balance_chunks())) return st;
     layout_workspace();
-    const size_t scan_at = ws_total;
-    if ((st = ensure_workspace(ws_total + align256(scan_total), &ws))) return st;
-    scan_base = static_cast<char*>(ws) + scan_at;
-    fill_scan_jobs(scan_base);
   } else {
     if ((st = ensure_scan(align256(scan_total) + 256))) return st;
     scan_base = static_cast<char*>(g_scan);
@@ -914,64 +942,13 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
     if ((st = ensure_workspace(ws_total, &ws))) return st;
   }
   const int nl = (int)bp.size();
-  char* base = static_cast<char*>(ws);
-  (void)base;
 
-  // ---- job tables of the remaining stages ------------------------------------
-  std::vector<ScaleJob> scj;
-  std::vector<int> fsc(1, 0);
-  std::vector<SplitJob> spA, spB;
-  std::vector<int> fspA(1, 0), fspB(1, 0);
-  std::vector<GemmArgs> gargs(nl);
-  std::vector<RoundArgs> rargs(nl);
-  std::vector<int> frd(1, 0);
-  const Third thirdA = mode == MPCG_3M ? Third::SUM : Third::NONE;
-  const Third thirdB = mode == MPCG_3M ? Third::SUM : Third::NEG_IM;
-  // work items come in groups of equal cost: the 2 x 2 tile groups of one
-  // contraction chunk of one problem
+  // ---- work items: every 2x2 tile group of every contraction chunk ----------
+  // (groups of equal cost: the tile groups of one chunk of one problem)
   struct Group { long long cost; int band, t, sp, gm, gn; };
   std::vector<Group> groups;
   for (int t = 0; t < nl; ++t) {
-    BatchProblem& b = bp[t];
-    const Plan& P = b.P;
-    char* pb = base + b.ws_off;
-    int32_t* G = reinterpret_cast<int32_t*>(pb + P.off_G);
-    int32_t* H = reinterpret_cast<int32_t*>(pb + P.off_H);
-    char* sc = scan_base + b.scan_off;
-    const size_t sA = align256(sizeof(RowStat) * (size_t)P.m);
-    scj.push_back(ScaleJob{reinterpret_cast<RowStat*>(sc), P.m, P.mpad, P.x, G});
-    fsc.push_back(fsc.back() + ceil_div(P.mpad, 256));
-    scj.push_back(ScaleJob{reinterpret_cast<RowStat*>(sc + sA), P.n, P.npad, P.x, H});
-    fsc.push_back(fsc.back() + ceil_div(P.npad, 256));
-    spA.push_back(SplitJob{b.opA, P.SA, P.SAp, P.xs, P.xlo, (int)thirdA, P.mpad, P.kpad, G,
-                           reinterpret_cast<int8_t*>(pb + P.off_X)});
-    fspA.push_back(fspA.back() + (P.kpad / 64) * (P.mpad / 16));
-    spB.push_back(SplitJob{b.opB, P.SB, P.SBp, P.ys, P.ylo, (int)thirdB, P.npad, P.kpad, H,
-                           reinterpret_cast<int8_t*>(pb + P.off_Y)});
-    fspB.push_back(fspB.back() + (P.kpad / 64) * (P.npad / 16));
-    GemmArgs& ga = gargs[t];
-    ga = GemmArgs{};
-    ga.X = reinterpret_cast<const int8_t*>(pb + P.off_X);
-    ga.Y = reinterpret_cast<const int8_t*>(pb + P.off_Y);
-    ga.mt = P.mt; ga.nt = P.nt; ga.kblocks = P.kblocks; ga.ksplit = P.ksplit;
-    ga.SAp = P.SAp; ga.SBp = P.SBp; ga.Dmax = P.Dmax; ga.mode3m = P.mode3m;
-    ga.digits = pb + P.off_dig;
-    ga.top = reinterpret_cast<int64_t*>(pb + P.off_top);
-    ga.lnz = reinterpret_cast<int32_t*>(pb + P.off_lnz);
-    ga.xs = P.xs; ga.ys = P.ys; ga.xlo = P.xlo; ga.ylo = P.ylo;
-    RoundArgs& ra = rargs[t];
-    ra = RoundArgs{};
-    ra.digits = pb + P.off_dig;
-    ra.digit_bytes = 1;
-    ra.nchunk = P.nchunk;
-    ra.f64_layout = 0;
-    ra.top = ga.top; ra.lnz = ga.lnz;
-    ra.ksplit = P.ksplit; ra.mt = P.mt; ra.nt = P.nt; ra.Dmax = P.Dmax; ra.w = P.w;
-    ra.G = G; ra.H = H; ra.m = P.m; ra.n = P.n; ra.prec = prec_bits; ra.L = L;
-    ra.cre = b.cre; ra.cim = b.cim; ra.ldc = probs[b.idx].ldc; ra.status = g_status;
-    ra.acc = acc;
-    frd.push_back(frd.back() + P.mt * P.nt * 2);
-    // work items: every 2x2 tile group of every contraction chunk
+    const Plan& P = bp[t].P;
     const long long steps = band_steps(P.block, P.SAp, P.SBp, P.Dmax);
     const int kbps = ceil_div(P.kblocks, P.ksplit);
     const int passes = P.mode3m ? 3 : 2;
@@ -1065,17 +1042,102 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
     a = e;
   }
 
+  // ---- job tables: layout, then the workspace, then their contents ----------
   Tables T;
-  if (bound > 0) add_scan_tables(T);
-  const size_t o_scj = T.add(scj), o_fsc = T.add(fsc);
-  const size_t o_spA = T.add(spA), o_fspA = T.add(fspA), o_spB = T.add(spB), o_fspB = T.add(fspB);
-  const size_t o_ga = T.add(gargs), o_ra = T.add(rargs), o_frd = T.add(frd);
+  if (bound > 0) {
+    o_sjA = T.reserve<ScanJob>(np); o_sjB = T.reserve<ScanJob>(np);
+    o_fiA = T.reserve<int>(np + 1); o_fsA = T.reserve<int>(np + 1);
+    o_fiB = T.reserve<int>(np + 1); o_fsB = T.reserve<int>(np + 1);
+  }
+  const size_t o_scj = T.reserve<ScaleJob>(2 * (size_t)nl), o_fsc = T.reserve<int>(2 * (size_t)nl + 1);
+  const size_t o_spA = T.reserve<SplitJob>(nl), o_fspA = T.reserve<int>(nl + 1);
+  const size_t o_spB = T.reserve<SplitJob>(nl), o_fspB = T.reserve<int>(nl + 1);
+  const size_t o_ga = T.reserve<GemmArgs>(nl), o_ra = T.reserve<RoundArgs>(nl), o_frd = T.reserve<int>(nl + 1);
   for (size_t l = 0; l < launches.size(); ++l) {
-    launches[l].o_items = T.add(litems[l]);
-    launches[l].o_first = T.add(lfirst[l]);
+    launches[l].o_items = T.reserve<int4>(litems[l].size());
+    launches[l].o_first = T.reserve<int>(lfirst[l].size());
+  }
+  T.bytes.resize(align256(T.bytes.size()));
+  char* tab_dev = nullptr;  // bound-planned batches keep their tables in the workspace
+  if (bound > 0) {
+    const size_t scan_at = ws_total, tab_at = ws_total + align256(scan_total);
+    if (size_query) {
+      *size_query = tab_at + T.bytes.size();
+      return MPCG_OK;
+    }
+    if ((st = ensure_workspace(tab_at + T.bytes.size(), &ws))) return st;
+    scan_base = static_cast<char*>(ws) + scan_at;
+    tab_dev = static_cast<char*>(ws) + tab_at;
+    fill_scan_jobs(scan_base);
+    T.put(o_sjA, sjA); T.put(o_sjB, sjB);
+    T.put(o_fiA, fiA); T.put(o_fsA, fsA); T.put(o_fiB, fiB); T.put(o_fsB, fsB);
+  }
+  char* base = static_cast<char*>(ws);
+  std::vector<ScaleJob> scj;
+  std::vector<int> fsc(1, 0);
+  std::vector<SplitJob> spA, spB;
+  std::vector<int> fspA(1, 0), fspB(1, 0);
+  std::vector<GemmArgs> gargs(nl);
+  std::vector<RoundArgs> rargs(nl);
+  std::vector<int> frd(1, 0);
+  const Third thirdA = mode == MPCG_3M ? Third::SUM : Third::NONE;
+  const Third thirdB = mode == MPCG_3M ? Third::SUM : Third::NEG_IM;
+  for (int t = 0; t < nl; ++t) {
+    BatchProblem& b = bp[t];
+    const Plan& P = b.P;
+    char* pb = base + b.ws_off;
+    int32_t* G = reinterpret_cast<int32_t*>(pb + P.off_G);
+    int32_t* H = reinterpret_cast<int32_t*>(pb + P.off_H);
+    char* sc = scan_base + b.scan_off;
+    const size_t sA = align256(sizeof(RowStat) * (size_t)P.m);
+    scj.push_back(ScaleJob{reinterpret_cast<RowStat*>(sc), P.m, P.mpad, P.x, G});
+    fsc.push_back(fsc.back() + ceil_div(P.mpad, 256));
+    scj.push_back(ScaleJob{reinterpret_cast<RowStat*>(sc + sA), P.n, P.npad, P.x, H});
+    fsc.push_back(fsc.back() + ceil_div(P.npad, 256));
+    spA.push_back(SplitJob{b.opA, P.SA, P.SAp, P.xs, P.xlo, (int)thirdA, P.mpad, P.kpad, G,
+                           reinterpret_cast<int8_t*>(pb + P.off_X)});
+    fspA.push_back(fspA.back() + (P.kpad / 64) * (P.mpad / 16));
+    spB.push_back(SplitJob{b.opB, P.SB, P.SBp, P.ys, P.ylo, (int)thirdB, P.npad, P.kpad, H,
+                           reinterpret_cast<int8_t*>(pb + P.off_Y)});
+    fspB.push_back(fspB.back() + (P.kpad / 64) * (P.npad / 16));
+    GemmArgs& ga = gargs[t];
+    ga = GemmArgs{};
+    ga.X = reinterpret_cast<const int8_t*>(pb + P.off_X);
+    ga.Y = reinterpret_cast<const int8_t*>(pb + P.off_Y);
+    ga.mt = P.mt; ga.nt = P.nt; ga.kblocks = P.kblocks; ga.ksplit = P.ksplit;
+    ga.SAp = P.SAp; ga.SBp = P.SBp; ga.Dmax = P.Dmax; ga.mode3m = P.mode3m;
+    ga.digits = pb + P.off_dig;
+    ga.top = reinterpret_cast<int64_t*>(pb + P.off_top);
+    ga.lnz = reinterpret_cast<int32_t*>(pb + P.off_lnz);
+    ga.xs = P.xs; ga.ys = P.ys; ga.xlo = P.xlo; ga.ylo = P.ylo;
+    RoundArgs& ra = rargs[t];
+    ra = RoundArgs{};
+    ra.digits = pb + P.off_dig;
+    ra.digit_bytes = 1;
+    ra.nchunk = P.nchunk;
+    ra.f64_layout = 0;
+    ra.top = ga.top; ra.lnz = ga.lnz;
+    ra.ksplit = P.ksplit; ra.mt = P.mt; ra.nt = P.nt; ra.Dmax = P.Dmax; ra.w = P.w;
+    ra.G = G; ra.H = H; ra.m = P.m; ra.n = P.n; ra.prec = prec_bits; ra.L = L;
+    ra.cre = b.cre; ra.cim = b.cim; ra.ldc = probs[b.idx].ldc; ra.status = g_status;
+    ra.acc = acc;
+    frd.push_back(frd.back() + P.mt * P.nt * 2);
+  }
+  T.put(o_scj, scj); T.put(o_fsc, fsc);
+  T.put(o_spA, spA); T.put(o_fspA, fspA); T.put(o_spB, spB); T.put(o_fspB, fspB);
+  T.put(o_ga, gargs); T.put(o_ra, rargs); T.put(o_frd, frd);
+  for (size_t l = 0; l < launches.size(); ++l) {
+    T.put(launches[l].o_items, litems[l]);
+    T.put(launches[l].o_first, lfirst[l]);
   }
   char* dev = nullptr;
-  if ((st = upload_tables(T, &dev))) return st;
+  if (capturing) {
+    // the data travels in kernel arguments, which the graph keeps
+    HIP_TRY(launch_store_words(tab_dev, T.bytes.data(), T.bytes.size(), g_stream));
+    dev = tab_dev;
+  } else if ((st = upload_tables(T, &dev, tab_dev))) {
+    return st;
+  }
   if (bound > 0) {
     if ((st = record(0))) return st;
     // the scan's status bits go to the status word; spreads are checked against the bound
@@ -1357,6 +1419,13 @@ int mp_cgemm_acc(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cm
 int mp_cgemm_batched(int count, const mpcg_problem* problems, int prec_bits, int mode, int scheme,
                      const mpcg_options* opt, mpcg_info* info) {
   return run_batched(count, problems, prec_bits, mode, scheme, opt, info, 0, true);
+}
+
+size_t mpcg_workspace_size_batched(int count, const mpcg_problem* problems, int prec_bits, int mode, int scheme,
+                                   const mpcg_options* opt) {
+  size_t bytes = 0;
+  if (run_batched(count, problems, prec_bits, mode, scheme, opt, nullptr, 0, true, &bytes)) return 0;
+  return bytes;
 }
 
 int mp_cgemm_batched_acc(int count, const mpcg_problem* problems, int prec_bits, int mode, int scheme, int sign,

@@ -16,6 +16,9 @@
 // and top part -T - 1 (or -T when all digits are zero).
 // Sticky information needs only the position of the lowest set bit of X,
 // which is the same for X and |X|.
+#include <algorithm>
+#include <cstring>
+
 #include "mpcg_internal.h"
 
 namespace mpcg {
@@ -232,6 +235,12 @@ __global__ void zero_kernel(DOutPart cre, DOutPart cim, int m, int n, int64_t ld
 __global__ void fill_zero_kernel(uint32_t* p, size_t n32) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n32) p[i] = 0;
+}
+
+// dst[0, w.n) := w.v[0, w.n): host data carried in the kernel's arguments
+// (a graph keeps its own copy of them at capture).
+__global__ void store_words_kernel(uint32_t* dst, StoreWords w) {
+  for (uint32_t i = threadIdx.x; i < w.n; i += blockDim.x) dst[i] = w.v[i];
 }
 
 // ---- INT8 digits: chunked per component --------------------------------------
@@ -991,6 +1000,24 @@ __global__ __launch_bounds__(256) void round_i8_batched(const RoundArgs* __restr
 }
 
 }  // namespace
+
+hipError_t launch_store_words(void* dst, const void* src, size_t bytes, hipStream_t stream) {
+  const uint32_t* w = static_cast<const uint32_t*>(src);
+  uint32_t* d = static_cast<uint32_t*>(dst);
+  size_t n32 = (bytes + 3) / 4;  // callers pass 256-byte multiples
+  while (n32 > 0) {
+    StoreWords a;
+    a.n = (uint32_t)std::min<size_t>(n32, StoreWords::N);
+    memcpy(a.v, w, 4 * (size_t)a.n);
+    store_words_kernel<<<1, 256, 0, stream>>>(d, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    w += a.n;
+    d += a.n;
+    n32 -= a.n;
+  }
+  return hipSuccess;
+}
 
 hipError_t launch_fill_zero(void* p, size_t n, hipStream_t stream) {
   const size_t n32 = (n + 3) / 4;  // caller allocations are 256-byte aligned and rounded

@@ -164,3 +164,57 @@ def test_single_call_spread_bound_graph_replay():
     finally:
         mp.mpcg_set_workspace(None, 0)
         mp.mpcg_set_stream()
+
+
+def test_batched_spread_bound_graph_replay():
+    """A batch planned from a spread bound with a caller workspace of
+    mpcg_workspace_size_batched bytes, captured once, replayed three times
+    with other batched and single calls in between (they rewrite and regrow
+    the library's own staging and table buffers): every replay gives the
+    oracle's bits."""
+    import torch
+    import paper_2307_06072_amd as mp
+    p, R, bound = 256, 6, 12
+    shapes = [(37, 45, 71), (16, 48, 130), (50, 3, 200), (64, 64, 64), (5, 90, 17), (100, 70, 9), (1, 1, 1)]
+    batch = _uneven_batch(95, p, R, shapes)
+    refs = [oracle.cgemm(A, B, p) for (m, n, k, A, B) in batch]
+    devs = [(mp.to_device(A), mp.to_device(B), mp.device_empty(m, n, p)) for (m, n, k, A, B) in batch]
+    mp.mpcg_set_stream()
+    mp.mp_cgemm_batched(devs, p, M3, EXACT, max_spread=bound)  # eager, also sets up the library
+    torch.cuda.synchronize()
+    assert mp.mpcg_stream_status() == 0
+    wsz = mp.mpcg_workspace_size_batched(devs, p, M3, EXACT, max_spread=bound)
+    assert wsz > 0
+    ws = torch.empty(wsz, dtype=torch.uint8, device="cuda")
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    _say("batched capture")
+    mp.mpcg_set_workspace(ws.data_ptr(), wsz)
+    try:
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side, capture_error_mode="thread_local"):
+                mp.mpcg_set_stream(side.cuda_stream)
+                mp.mp_cgemm_batched(devs, p, M3, EXACT, max_spread=bound)
+    finally:
+        mp.mpcg_set_workspace(None, 0)
+        mp.mpcg_set_stream()
+    torch.cuda.synchronize()
+    other = _uneven_batch(96, 200, 4, [(70, 80, 90), (120, 33, 60), (9, 9, 300)])
+    for rep in range(3):
+        for (_, _, C) in devs:
+            for part in (C.re, C.im):
+                part.exp.fill_(7)
+                part.mant.fill_(0)
+        res, _, st = _run_batch(other[: 1 + rep], 200, M3)  # library tables rewritten (and grown)
+        assert st == 0
+        for (m, n, k, A, B), C in zip(other[: 1 + rep], res):
+            assert mismatches(C, oracle.cgemm(A, B, 200), m, n)[0] == 0
+        torch.cuda.synchronize()
+        _say(f"batched replay {rep}")
+        g.replay()
+        torch.cuda.synchronize()
+        assert mp.mpcg_stream_status() == 0
+        for t, ((m, n, k, A, B), (_, _, C)) in enumerate(zip(batch, devs)):
+            bad, first = mismatches(device_result_to_host(C, p), refs[t], m, n)
+            assert bad == 0, (rep, t, first)
