@@ -21,7 +21,8 @@
 // Re(A)Re(B) - Im(A)Im(B) accumulates as a sum (eq. 5).
 //
 // One block handles a 16 x 64 tile (16 rows of the operand, 64 contraction
-// indices).  Digits go to LDS in the matrix-core operand order and leave as
+// indices), two entries per thread; each thread reads the limbs of its
+// entries once, in order, as the windows move up the significands.  Digits go to LDS in the matrix-core operand order and leave as
 // contiguous fragments:
 //   INT8: fragment = 16 rows x 64 k, lane l holds row l%16, k = 16*(l/16)..+16
 //         (16 bytes), tile-major [R/16][op][pad_lo + s][K/64][1024 B] with
@@ -34,24 +35,47 @@ namespace mpcg {
 
 namespace {
 
-// Bits [pos, pos + nbits) of the significand M (nbits <= 56); bits below the
-// precision (mask on limb 0) and outside [0, 64L) read as zero.
-__device__ inline uint64_t window_bits(const uint64_t* mant, int64_t ls, int64_t idx, int L,
-                                       uint64_t low_mask, int64_t pos, int nbits) {
-  const int64_t li = pos >> 6;  // floor
-  const int off = (int)(pos & 63);
-  uint64_t a = 0, b = 0;
-  if (li >= 0 && li < L) {
-    a = mant[li * ls + idx];
-    if (li == 0) a &= low_mask;
-  }
-  if (li + 1 >= 0 && li + 1 < L) {
-    b = mant[(li + 1) * ls + idx];
-    if (li + 1 == 0) b &= low_mask;
-  }
-  const uint64_t r = off ? ((a >> off) | (b << (64 - off))) : a;
-  return r & ((1ull << nbits) - 1ull);
+// A block splits one 16 x 64 tile, EPT entries per thread.
+constexpr int SPLIT_THREADS = 1024;
+constexpr int EPT = 1024 / SPLIT_THREADS;
+
+// Limb li of one significand (0 outside [0, L); limb 0 masked to the
+// precision); `denorm` collects a clear top bit of limb L-1.
+__device__ inline uint64_t limb_at(const uint64_t* m, int64_t ls, int64_t li, int L, uint64_t low_mask,
+                                   int& denorm) {
+  if (!m || li < 0 || li >= L) return 0;
+  uint64_t v = m[li * ls];
+  if (li == L - 1) denorm |= !(v >> 63);
+  return li == 0 ? (v & low_mask) : v;
 }
+
+// Bits [pos, pos + 56) of one significand for pos rising by at most 64 per
+// call: limbs li, li + 1 and (loaded a window ahead) li + 2, so every limb is
+// read once.
+struct LimbStream {
+  const uint64_t* m;  // mant + entry index, NULL for a zero entry
+  int64_t li;
+  uint64_t a, b, c;
+  __device__ inline void start(const uint64_t* mp, int64_t ls, int64_t pos, int L, uint64_t low_mask,
+                               int& denorm) {
+    m = mp;
+    li = pos >> 6;  // floor
+    a = limb_at(m, ls, li, L, low_mask, denorm);
+    b = limb_at(m, ls, li + 1, L, low_mask, denorm);
+    c = limb_at(m, ls, li + 2, L, low_mask, denorm);
+  }
+  __device__ inline uint64_t window56(int64_t ls, int64_t pos, int L, uint64_t low_mask, int& denorm) {
+    if ((pos >> 6) > li) {
+      ++li;
+      a = b;
+      b = c;
+      c = limb_at(m, ls, li + 2, L, low_mask, denorm);
+    }
+    const int off = (int)(pos - 64 * li);
+    const uint64_t r = off ? ((a >> off) | (b << (64 - off))) : a;
+    return r & ((1ull << 56) - 1ull);
+  }
+};
 
 struct Entry {
   int64_t idx;
@@ -85,31 +109,39 @@ struct Layout<double> {
   }
 };
 
-template <typename DT, bool ROWCONTIG>
+// WC: the digit width when known at compile time (7 for INT8), else 0 (w);
+// TH: the third plane (Third) when known at compile time, else -1 (third).
+// INT8 tiles alternate between two LDS buffers, so one barrier per chunk
+// separates the digit writes of a chunk from their stores, and the stores of
+// a chunk from the writes two chunks later.
+template <typename DT, bool ROWCONTIG, int WC, int TH>
 __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, int Sp, int Sstride, int pad_lo,
-                                  int w, int third, const int32_t* __restrict__ G, int Rpad, int Kpad,
+                                  int w_rt, int third_rt, const int32_t* __restrict__ G, int Rpad, int Kpad,
                                   DT* __restrict__ out, int* status, int kt, int rt, unsigned char* lds_raw) {
-  DT* lds = reinterpret_cast<DT*>(lds_raw);
   constexpr int FRAG = Layout<DT>::FRAG_BYTES / (int)sizeof(DT);  // elements per (op, digit) tile
+  constexpr int NBUF = sizeof(DT) == 1 ? 2 : 1;
 
+  const int w = WC ? WC : w_rt;
+  const int third = TH >= 0 ? TH : third_rt;
   const int g = 56 / w;  // digits per window
   const int nops = third ? 3 : 2;
   const int t = threadIdx.x;
   const uint64_t low_mask = ~((1ull << (64 * L - prec)) - 1ull) | (64 * L - prec == 0 ? ~0ull : 0ull);
   const int64_t wS = (int64_t)w * S;
 
-  Entry e[4];
-  int lofs[4];
+  Entry e[EPT];
+  int lofs[EPT];
   int bad = 0;
+  LimbStream sre[EPT], sim[EPT];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < EPT; ++q) {
     int rl, kl;
     if (ROWCONTIG) {
       rl = t & 15;
-      kl = (t >> 4) + 16 * q;
+      kl = (t >> 4) + (SPLIT_THREADS / 16) * q;
     } else {
       kl = t & 63;
-      rl = (t >> 6) + 4 * q;
+      rl = (t >> 6) + (SPLIT_THREADS / 64) * q;
     }
     lofs[q] = Layout<DT>::offset(rl, kl);
     const int r = rt * 16 + rl, kk = kt * 64 + kl;
@@ -126,49 +158,56 @@ __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, in
         e[q].z_re = 0;
         e[q].neg_re = op.re.sign[idx] ? 1 : 0;
         e[q].sh_re = (int64_t)er - base;
-        bad |= !(op.re.mant[(int64_t)(L - 1) * op.re.ls + idx] >> 63);
       }
       if (ei != EXP_ZERO) {
         e[q].z_im = 0;
         e[q].neg_im = op.im.sign[idx] ? 1 : 0;
         e[q].sh_im = (int64_t)ei - base;
-        bad |= !(op.im.mant[(int64_t)(L - 1) * op.im.ls + idx] >> 63);
       }
     }
   }
-  if (bad) atomicOr(status, ST_DENORM);
 
   const int64_t half = 1ll << (w - 1);
   const int64_t dmask = (1ll << w) - 1;
-  int64_t carry[4][3];
+  int64_t carry[EPT][3];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) carry[q][0] = carry[q][1] = carry[q][2] = 0;
+  for (int q = 0; q < EPT; ++q) carry[q][0] = carry[q][1] = carry[q][2] = 0;
 
   const int nchunks = (Sp + g - 1) / g;
-  for (int c = nchunks - 1; c >= 0; --c) {
-    const int64_t fstart = (int64_t)w * (S - g * c - g);  // F bit of the window's lowest digit
-    const int nbits = g * w;
+  const int nbits = g * w;  // <= 56
+  const uint64_t wmask = (1ull << nbits) - 1ull;
+  {
+    const int64_t f0 = (int64_t)w * (S - g * (nchunks - 1) - g);  // lowest window's first F bit
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int64_t fre = 0, fim = 0;
-      if (!e[q].z_re)
-        fre = (int64_t)window_bits(op.re.mant, op.re.ls, e[q].idx, L, low_mask, fstart - e[q].sh_re, nbits);
-      if (!e[q].z_im)
-        fim = (int64_t)window_bits(op.im.mant, op.im.ls, e[q].idx, L, low_mask, fstart - e[q].sh_im, nbits);
+    for (int q = 0; q < EPT; ++q) {
+      sre[q].start(e[q].z_re ? nullptr : op.re.mant + e[q].idx, op.re.ls, f0 - e[q].sh_re, L, low_mask, bad);
+      sim[q].start(e[q].z_im ? nullptr : op.im.mant + e[q].idx, op.im.ls, f0 - e[q].sh_im, L, low_mask, bad);
+    }
+  }
+  const int buf_bytes = nops * g * Layout<DT>::FRAG_BYTES;
+  for (int c = nchunks - 1; c >= 0; --c) {
+    unsigned char* buf = lds_raw + (NBUF == 2 ? (c & 1) * buf_bytes : 0);
+    DT* lds = reinterpret_cast<DT*>(buf);
+    const int64_t fstart = (int64_t)w * (S - g * c - g);  // F bit of the window's lowest digit
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      int64_t fre = (int64_t)(sre[q].window56(op.re.ls, fstart - e[q].sh_re, L, low_mask, bad) & wmask);
+      int64_t fim = (int64_t)(sim[q].window56(op.im.ls, fstart - e[q].sh_im, L, low_mask, bad) & wmask);
       if (e[q].neg_re) fre = -fre;
       if (e[q].neg_im) fim = -fim;
       int64_t v[3];
       v[0] = fre + carry[q][0];
       v[1] = fim + carry[q][1];
       v[2] = (third == (int)Third::SUM) ? fre + fim + carry[q][2] : 0;
+      const bool top = c == 0;  // the chunk holding digit 0, which keeps the remaining value
+#pragma unroll
       for (int j = g - 1; j >= 0; --j) {
-        const int s = g * c + j;
         DT dig[3];
 #pragma unroll
         for (int o = 0; o < 3; ++o) {
           int64_t d;
-          if (s == 0) {
-            d = v[o];  // topmost digit keeps the remaining value
+          if (top && j == 0) {
+            d = v[o];
           } else {
             d = ((v[o] + half) & dmask) - half;
             v[o] = (v[o] - d) >> w;
@@ -187,25 +226,26 @@ __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, in
     __syncthreads();
     // write the chunk's digit tiles: contiguous (op, digit) fragments of FRAG_BYTES
     constexpr int units = Layout<DT>::FRAG_BYTES / 16;
-    for (int idx = t; idx < nops * g * units; idx += 256) {
+    for (int idx = t; idx < nops * g * units; idx += SPLIT_THREADS) {
       const int u = idx % units;
       const int oj = idx / units;  // = o * g + j
       const int o = oj / g, j = oj % g;
       const int s = g * c + j;
       if (s >= Sp) continue;
-      const uint4* src = reinterpret_cast<const uint4*>(lds_raw + (size_t)oj * Layout<DT>::FRAG_BYTES);
+      const uint4* src = reinterpret_cast<const uint4*>(buf + (size_t)oj * Layout<DT>::FRAG_BYTES);
       uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<unsigned char*>(out) +
                                             Layout<DT>::tile_base((int64_t)o * Sstride + pad_lo + s, rt, kt,
                                                                   Rpad / 16, Kpad, (int64_t)nops * Sstride));
       dst[u] = src[u];
     }
-    __syncthreads();
+    if (NBUF == 1) __syncthreads();
   }
+  if (bad) atomicOr(status, ST_DENORM);
   // zero slices around the digits (this tile of every plane)
   const int npad = Sstride - Sp;
   if (npad > 0) {
     constexpr int units = Layout<DT>::FRAG_BYTES / 16;
-    for (int idx = t; idx < nops * npad * units; idx += 256) {
+    for (int idx = t; idx < nops * npad * units; idx += SPLIT_THREADS) {
       const int u = idx % units;
       const int oj = idx / units;
       const int o = oj / npad, j = oj % npad;
@@ -218,19 +258,19 @@ __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, in
   }
 }
 
-template <typename DT, bool ROWCONTIG>
-__global__ __launch_bounds__(256) void split_kernel(DOperand op, int prec, int L, int S, int Sp, int Sstride,
+template <typename DT, bool ROWCONTIG, int WC, int TH>
+__global__ __launch_bounds__(SPLIT_THREADS) void split_kernel(DOperand op, int prec, int L, int S, int Sp, int Sstride,
                                                     int pad_lo, int w, int third,
                                                     const int32_t* __restrict__ G, int Rpad, int Kpad,
                                                     DT* __restrict__ out, int* status) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  split_tile<DT, ROWCONTIG>(op, prec, L, S, Sp, Sstride, pad_lo, w, third, G, Rpad, Kpad, out, status, blockIdx.x,
-                            blockIdx.y, lds_raw);
+  split_tile<DT, ROWCONTIG, WC, TH>(op, prec, L, S, Sp, Sstride, pad_lo, w, third, G, Rpad, Kpad, out, status,
+                                    blockIdx.x, blockIdx.y, lds_raw);
 }
 
 // Batched INT8 form: job j owns (Kpad/64) * (Rpad/16) blocks.
 template <bool ROWCONTIG>
-__global__ __launch_bounds__(256) void split_i8_batched(const SplitJob* __restrict__ jobs, int njobs,
+__global__ __launch_bounds__(SPLIT_THREADS) void split_i8_batched(const SplitJob* __restrict__ jobs, int njobs,
                                                         const int* __restrict__ first, int prec, int L,
                                                         int* status) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -238,24 +278,26 @@ __global__ __launch_bounds__(256) void split_i8_batched(const SplitJob* __restri
   const SplitJob& J = jobs[j];
   const int local = blockIdx.x - first[j];
   const int kts = J.Kpad / 64;
-  split_tile<int8_t, ROWCONTIG>(J.op, prec, L, J.S, J.Sp, J.Sstride, J.pad_lo, 7, J.third, J.G, J.Rpad, J.Kpad,
-                                J.out, status, local % kts, local / kts, lds_raw);
+  split_tile<int8_t, ROWCONTIG, 7, -1>(J.op, prec, L, J.S, J.Sp, J.Sstride, J.pad_lo, 7, J.third, J.G, J.Rpad,
+                                       J.Kpad, J.out, status, local % kts, local / kts, lds_raw);
 }
 
-template <typename DT>
+template <typename DT, int WC, int TH>
 hipError_t launch_split_t(const DOperand& op, int prec, int L, int S, int Sp, int Sstride, int pad_lo, int w,
                           Third third, const int32_t* G, int Rpad, int Kpad, DT* out, int* status,
                           hipStream_t stream) {
   const int g = 56 / w;
   const int nops = third == Third::NONE ? 2 : 3;
-  const size_t lds = (size_t)nops * g * Layout<DT>::FRAG_BYTES;
+  const size_t lds = (size_t)(sizeof(DT) == 1 ? 2 : 1) * nops * g * Layout<DT>::FRAG_BYTES;
   dim3 grid(Kpad / 64, Rpad / 16);
   if (op.rs == 1)
-    split_kernel<DT, true><<<grid, dim3(256), lds, stream>>>(op, prec, L, S, Sp, Sstride, pad_lo, w, (int)third, G, Rpad, Kpad,
-                                                             out, status);
+    split_kernel<DT, true, WC, TH><<<grid, dim3(SPLIT_THREADS), lds, stream>>>(op, prec, L, S, Sp, Sstride, pad_lo,
+                                                                                w, (int)third, G, Rpad, Kpad, out,
+                                                                                status);
   else
-    split_kernel<DT, false><<<grid, dim3(256), lds, stream>>>(op, prec, L, S, Sp, Sstride, pad_lo, w, (int)third, G, Rpad, Kpad,
-                                                              out, status);
+    split_kernel<DT, false, WC, TH><<<grid, dim3(SPLIT_THREADS), lds, stream>>>(op, prec, L, S, Sp, Sstride, pad_lo,
+                                                                                 w, (int)third, G, Rpad, Kpad, out,
+                                                                                 status);
   return hipGetLastError();
 }
 
@@ -264,22 +306,32 @@ hipError_t launch_split_t(const DOperand& op, int prec, int L, int S, int Sp, in
 hipError_t launch_split_i8(const DOperand& op, int prec, int L, int S, int Sp, int Sstride, int pad_lo,
                            Third third, const int32_t* G, int Rpad, int Kpad, int8_t* out, int* status,
                            hipStream_t stream) {
-  return launch_split_t<int8_t>(op, prec, L, S, Sp, Sstride, pad_lo, 7, third, G, Rpad, Kpad, out, status, stream);
+  switch (third) {
+    case Third::NONE:
+      return launch_split_t<int8_t, 7, 0>(op, prec, L, S, Sp, Sstride, pad_lo, 7, third, G, Rpad, Kpad, out, status,
+                                          stream);
+    case Third::SUM:
+      return launch_split_t<int8_t, 7, 1>(op, prec, L, S, Sp, Sstride, pad_lo, 7, third, G, Rpad, Kpad, out, status,
+                                          stream);
+    default:
+      return launch_split_t<int8_t, 7, 2>(op, prec, L, S, Sp, Sstride, pad_lo, 7, third, G, Rpad, Kpad, out, status,
+                                          stream);
+  }
 }
 
 hipError_t launch_split_f64(const DOperand& op, int prec, int L, int S, int Sp, int w, Third third,
                             const int32_t* G, int Rpad, int Kpad, double* out, int* status, hipStream_t stream) {
-  return launch_split_t<double>(op, prec, L, S, Sp, Sp, 0, w, third, G, Rpad, Kpad, out, status, stream);
+  return launch_split_t<double, 0, -1>(op, prec, L, S, Sp, Sp, 0, w, third, G, Rpad, Kpad, out, status, stream);
 }
 
 hipError_t launch_split_i8_batched(const SplitJob* jobs, int njobs, const int* first, int blocks, int prec, int L,
                                    bool rows_contiguous, int* status, hipStream_t stream) {
   if (njobs <= 0 || blocks <= 0) return hipSuccess;
-  const size_t lds = (size_t)3 * (56 / 7) * Layout<int8_t>::FRAG_BYTES;  // up to three planes
+  const size_t lds = (size_t)2 * 3 * (56 / 7) * Layout<int8_t>::FRAG_BYTES;  // two buffers of up to three planes
   if (rows_contiguous)
-    split_i8_batched<true><<<dim3(blocks), dim3(256), lds, stream>>>(jobs, njobs, first, prec, L, status);
+    split_i8_batched<true><<<dim3(blocks), dim3(SPLIT_THREADS), lds, stream>>>(jobs, njobs, first, prec, L, status);
   else
-    split_i8_batched<false><<<dim3(blocks), dim3(256), lds, stream>>>(jobs, njobs, first, prec, L, status);
+    split_i8_batched<false><<<dim3(blocks), dim3(SPLIT_THREADS), lds, stream>>>(jobs, njobs, first, prec, L, status);
   return hipGetLastError();
 }
 
