@@ -98,7 +98,7 @@ typedef struct {
     mpcg_part re, im;
 } mpcg_cmat;
 
-typedef enum { MPCG_4M = 0, MPCG_3M = 1 } mpcg_mode;
+typedef enum { MPCG_4M = 0, MPCG_3M = 1, MPCG_AUTO = 2 } mpcg_mode;
 typedef enum { MPCG_EXACT = 0, MPCG_TRUNCATED = 1 } mpcg_scheme;
 typedef enum { MPCG_SLICE_INT8 = 0, MPCG_SLICE_FP64 = 1 } mpcg_slice;
 
@@ -107,6 +107,9 @@ typedef enum { MPCG_SLICE_INT8 = 0, MPCG_SLICE_FP64 = 1 } mpcg_slice;
  *   mode   MPCG_4M: eq. (5), four real slice products per slice pair.
  *          MPCG_3M: eq. (6), three; (Re A + Im A) and (Re B + Im B) are formed
  *          exactly in fixed point, so no accuracy is lost.
+ *          MPCG_AUTO: the form mpcg_autotune found faster for this size class
+ *          (3M when the tuning cache has no entry); exact-scheme bits are the
+ *          same either way.
  *   scheme MPCG_EXACT: every slice pair is kept; the result is the exact sum
  *          rounded once (bit-identical for 4M/3M and for both slice types).
  *          MPCG_TRUNCATED: slice pairs (s, t) with s + t above a cutoff are
@@ -171,6 +174,7 @@ typedef struct {
 int mp_cgemm_ex(int m, int n, int k, const mpcg_cmat *A, int lda, const mpcg_cmat *B, int ldb,
                 mpcg_cmat *C, int ldc, int prec_bits, int mode, int scheme,
                 const mpcg_options *opt, mpcg_info *info);
+
 
 /* Size in bytes of the fixed device buffer of mp_cgemm_ex_noalloc. */
 #define MPCG_NOALLOC_BYTES (128u << 20)
@@ -281,6 +285,69 @@ int mp_cgemm_batched(int count, const mpcg_problem *problems, int prec_bits, int
  */
 size_t mpcg_workspace_size_batched(int count, const mpcg_problem *problems, int prec_bits, int mode, int scheme,
                                    const mpcg_options *opt);
+
+/*
+ * Size-class tuning (the planner's choices per size class, measured).  A size
+ * class is (device architecture, scheme, requested form, ceil(log2 m),
+ * ceil(log2 n), ceil(log2 k), ceil(S / 8)) with S the larger slice count of
+ * the two operands.  For a class in the cache the planner takes its INT8
+ * band width, its work-item target (which sets the contraction chunks of a
+ * single product; batches keep balancing their chunks over the compute
+ * units) and, for MPCG_AUTO, its form, unless the options override them.
+ * None of these choices changes a bit of an exact-scheme result.  The cache
+ * starts empty; if the environment variable MPCG_TUNE_CACHE names a file,
+ * the first planning call reads it (a missing or malformed file is skipped).
+ */
+typedef struct {
+    int band;         /* chosen band width (8, 12, 16 or 20) */
+    int groups;       /* chosen work-item target (256 ... 2048) */
+    int mode;         /* chosen form: MPCG_4M or MPCG_3M */
+    int S;            /* slice count of the size class key */
+    int candidates;   /* plans measured */
+    float us;         /* time of one call with the chosen plan */
+    float untuned_us; /* time of one call with the fixed rule's plan */
+} mpcg_tune_report;
+
+/*
+ * mpcg_autotune - measures the plans of one product (the caller's operands:
+ * A, B and C as for mp_cgemm, C overwritten) and stores the fastest in the
+ * cache under the product's size class: band widths 8, 12, 16, 20 (4M: up to
+ * 16), work-item targets 256, 512, 1024, 2048, and for mode MPCG_AUTO both
+ * forms; reps timed calls per plan (at least 1) after one untimed call, on
+ * the library stream, synchronously.  report (may be NULL) receives the
+ * choice.  INT8 slices, no spread bound.  Returns MPCG_OK, MPCG_EINVAL (also
+ * for an empty product), MPCG_ENOMEM, MPCG_ERANGE, MPCG_EHIP.
+ */
+int mpcg_autotune(int m, int n, int k, const mpcg_cmat *A, int lda, const mpcg_cmat *B, int ldb,
+                  mpcg_cmat *C, int ldc, int prec_bits, int mode, int scheme, int reps,
+                  mpcg_tune_report *report);
+
+/*
+ * mpcg_autotune_batched - the same for a batch (as for mp_cgemm_batched;
+ * outputs overwritten): measures the whole batch with each problem's own
+ * band width and 3M (4M if asked for), then with one band width (8, 12, 16,
+ * 20; 4M up to 16) and form (both for MPCG_AUTO) for every problem, reps
+ * timed calls each after one untimed call.  The winner is stored for the
+ * size class of every problem of the batch (work-item target 512): the
+ * uniform plan, or, if none beat the first, each problem's own band in the
+ * first form (report->band is then 0).  opt may carry max_spread and ksplit_override (no block or adaptive
+ * option).  Returns as mp_cgemm_batched, MPCG_EINVAL also for a bad option.
+ */
+int mpcg_autotune_batched(int count, const mpcg_problem *problems, int prec_bits, int mode, int scheme, int reps,
+                          const mpcg_options *opt, mpcg_tune_report *report);
+
+/*
+ * mpcg_tune_load / mpcg_tune_save - read (merging the entries of this
+ * device's architecture into the cache) or write the cache as JSON at path
+ * (NULL: the path in MPCG_TUNE_CACHE).  Return the number of entries read or
+ * written, or MPCG_EINVAL (no path, an unreadable or malformed file, a
+ * failed write; the file is written whole or not at all).
+ * mpcg_tune_clear empties the cache (and keeps MPCG_TUNE_CACHE from being
+ * read later).
+ */
+int mpcg_tune_load(const char *path);
+int mpcg_tune_save(const char *path);
+int mpcg_tune_clear(void);
 
 /*
  * mp_cgemm_batched_acc - the batched accumulating product: C_i := C_i +

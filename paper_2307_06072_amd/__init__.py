@@ -28,6 +28,7 @@ MPCG_ESPREAD = -7
 
 MPCG_4M = 0
 MPCG_3M = 1
+MPCG_AUTO = 2
 MPCG_EXACT = 0
 MPCG_TRUNCATED = 1
 MPCG_SLICE_INT8 = 0
@@ -66,6 +67,14 @@ class mpcg_info(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
+class mpcg_tune_report(ctypes.Structure):
+    _fields_ = [("band", ctypes.c_int), ("groups", ctypes.c_int), ("mode", ctypes.c_int), ("S", ctypes.c_int),
+                ("candidates", ctypes.c_int), ("us", ctypes.c_float), ("untuned_us", ctypes.c_float)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class mpcg_problem(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int), ("n", ctypes.c_int), ("k", ctypes.c_int),
                 ("A", ctypes.POINTER(mpcg_cmat)), ("lda", ctypes.c_int),
@@ -99,6 +108,17 @@ _lib.mpcg_workspace_size.argtypes = [_i, _i, _i, _i, _i, _i, _P(mpcg_options), _
 _lib.mpcg_workspace_size.restype = ctypes.c_size_t
 _lib.mpcg_workspace_size_batched.argtypes = [_i, _P(mpcg_problem), _i, _i, _i, _P(mpcg_options)]
 _lib.mpcg_workspace_size_batched.restype = ctypes.c_size_t
+_lib.mpcg_autotune.argtypes = [_i, _i, _i, _P(mpcg_cmat), _i, _P(mpcg_cmat), _i, _P(mpcg_cmat), _i, _i, _i, _i, _i,
+                               _P(mpcg_tune_report)]
+_lib.mpcg_autotune.restype = _i
+_lib.mpcg_autotune_batched.argtypes = [_i, _P(mpcg_problem), _i, _i, _i, _i, _P(mpcg_options), _P(mpcg_tune_report)]
+_lib.mpcg_autotune_batched.restype = _i
+_lib.mpcg_tune_load.argtypes = [ctypes.c_char_p]
+_lib.mpcg_tune_load.restype = _i
+_lib.mpcg_tune_save.argtypes = [ctypes.c_char_p]
+_lib.mpcg_tune_save.restype = _i
+_lib.mpcg_tune_clear.argtypes = []
+_lib.mpcg_tune_clear.restype = _i
 _lib.mpcg_stream_status.argtypes = [_vp]
 _lib.mpcg_stream_status.restype = _i
 _lib.mpcg_last_error.argtypes = []
@@ -118,7 +138,8 @@ _lib.mp_zgetrf.restype = _i
 _lib.mp_zgetrs.argtypes = [_i, _i, _P(mpcg_cmat), _i, _vp, _P(mpcg_cmat), _i, _i, _i]
 _lib.mp_zgetrs.restype = _i
 
-EXPORTS = ["mp_cgemm", "mp_cgemm_ex", "mp_cgemm_ex_noalloc", "mp_cgemm_acc", "mp_cgemm_batched", "mp_cgemm_batched_acc", "mp_zgetrf", "mp_zgetrs", "mpcg_set_stream", "mpcg_set_workspace", "mpcg_workspace_size", "mpcg_workspace_size_batched",
+EXPORTS = ["mp_cgemm", "mp_cgemm_ex", "mp_cgemm_ex_noalloc", "mp_cgemm_acc", "mp_cgemm_batched", "mp_cgemm_batched_acc", "mp_zgetrf", "mp_zgetrs", "mpcg_set_stream", "mpcg_set_workspace", "mpcg_workspace_size", "mpcg_workspace_size_batched", "mpcg_autotune", "mpcg_autotune_batched", "mpcg_tune_load",
+           "mpcg_tune_save", "mpcg_tune_clear",
            "mpcg_stream_status", "mpcg_last_error", "mpcg_enable_timing", "mpcg_last_timing",
            "mpcg_timing_report", "mpcg_from_doubles", "mpcg_to_doubles"]
 
@@ -340,6 +361,49 @@ def mp_cgemm_ex_noalloc(m, n, k, A: DeviceCMat, lda, B: DeviceCMat, ldb, C: Devi
     _check(_lib.mp_cgemm_ex_noalloc(m, n, k, ctypes.byref(a), lda, ctypes.byref(b), ldb, ctypes.byref(c), ldc,
                                     prec_bits, mode, scheme, ctypes.byref(opt), ctypes.byref(info)))
     return info.as_dict()
+
+
+def mpcg_autotune(m, n, k, A: DeviceCMat, lda, B: DeviceCMat, ldb, C: DeviceCMat, ldc, prec_bits, mode=MPCG_AUTO,
+                  scheme=MPCG_EXACT, reps=2) -> dict:
+    """Measure the plans of this product and store the fastest for its size
+    class; returns the choice (band, groups, mode, S, candidates, us,
+    untuned_us).  C is overwritten."""
+    a, b, c = A.struct(), B.struct(), C.struct()
+    rep = mpcg_tune_report()
+    _check(_lib.mpcg_autotune(m, n, k, ctypes.byref(a), lda, ctypes.byref(b), ldb, ctypes.byref(c), ldc, prec_bits,
+                              mode, scheme, reps, ctypes.byref(rep)))
+    return rep.as_dict()
+
+
+def mpcg_autotune_batched(problems, prec_bits, mode=MPCG_AUTO, scheme=MPCG_EXACT, reps=1, max_spread=0) -> dict:
+    """Tune a batch of (A, B, C) triples: one band width and form for the whole
+    batch if that beats each problem's own; stored per size class."""
+    arr, keep = _problem_array(problems)
+    opt = mpcg_options(MPCG_SLICE_INT8, 0, 0, 0, max_spread)
+    rep = mpcg_tune_report()
+    _check(_lib.mpcg_autotune_batched(len(problems), arr, prec_bits, mode, scheme, reps, ctypes.byref(opt),
+                                      ctypes.byref(rep)))
+    return rep.as_dict()
+
+
+def _count(code: int) -> int:
+    if code < 0:
+        raise MPCGError(code, mpcg_last_error())
+    return code
+
+
+def mpcg_tune_load(path=None) -> int:
+    """Merge a tuning cache file (None: $MPCG_TUNE_CACHE); returns entries read."""
+    return _count(_lib.mpcg_tune_load(path.encode() if path else None))
+
+
+def mpcg_tune_save(path=None) -> int:
+    """Write the tuning cache (None: $MPCG_TUNE_CACHE); returns entries written."""
+    return _count(_lib.mpcg_tune_save(path.encode() if path else None))
+
+
+def mpcg_tune_clear() -> int:
+    return _check(_lib.mpcg_tune_clear())
 
 
 def mp_cgemm_acc_raw(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, mode, scheme, sign, options=None,

@@ -11,7 +11,7 @@ REPO = os.path.dirname(HERE)
 BUILD = os.path.join(REPO, "_build")
 LIB = os.path.join(HERE, "libmpcgemm.so")
 
-SOURCES = ["mpcgemm.cpp", "scan.hip", "split.hip", "gemm_i8.hip", "gemm_f64.hip", "round.hip", "codec.hip", "lu.hip", "recip.hip", "noalloc.hip"]
+SOURCES = ["mpcgemm.cpp", "tune.cpp", "scan.hip", "split.hip", "gemm_i8.hip", "gemm_f64.hip", "round.hip", "codec.hip", "lu.hip", "recip.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for every device compile.

@@ -163,6 +163,28 @@ struct StoreWords {
 };
 hipError_t launch_store_words(void* dst, const void* src, size_t bytes, hipStream_t stream);
 
+// Size-class tuning cache (tune.cpp).
+struct TuneKey {
+  int scheme, mode;  // scheme, requested form (MPCG_4M, MPCG_3M or MPCG_AUTO)
+  int lm, ln, lk;    // ceil(log2) of m, n, k
+  int sb;            // ceil(S / 8), S the larger slice count of the two operands
+};
+struct TuneChoice {
+  int band;    // INT8 slice GEMM band width
+  int groups;  // work-item target that sets the contraction chunks
+  int mode3m;  // the form chosen (for requests of MPCG_AUTO)
+  float us;    // measured time of the class's tuning problem
+};
+bool operator<(const TuneKey& a, const TuneKey& b);
+TuneKey tune_key(int scheme, int mode, int m, int n, int k, int S);
+const char* tune_arch();
+bool tune_find(const TuneKey& key, TuneChoice* out);
+void tune_put(const TuneKey& key, const TuneChoice& c);
+int tune_count();
+void tune_clear();
+int tune_load(const char* path);  // entries loaded, -1 on a read or parse error
+int tune_save(const char* path);  // entries written, -1 on a write error
+
 // bytes[0 .. n) := 0 (a kernel, so that the call stays capturable).
 hipError_t launch_fill_zero(void* p, size_t n, hipStream_t stream);
 

@@ -36,6 +36,14 @@ size_t g_scan_bytes = 0;
 int* g_status = nullptr;  // persistent device status word
 ScanSummary* g_host_summary = nullptr;  // pinned
 int g_fault_inject = -1;  // test hook: MPCG_FAULT_INJECT=hip makes HIP calls fail
+// size-class tuning: the cache of MPCG_TUNE_CACHE is read on first use; while
+// mpcg_autotune measures a candidate, g_tune_forced_groups sets the work-item
+// target and the cache is not consulted
+bool g_tune_env_done = false;
+int g_tune_forced_groups = 0;
+bool g_tune_bypass = false;                 // plans ignore the cache (tuning measures its candidates)
+// when set, a batch records its problems' size classes and band widths
+std::vector<std::pair<TuneKey, int>>* g_tune_keys = nullptr;
 
 // per-call stage events: [call][boundary], boundaries = start, after scan,
 // after split, after slice GEMM, after round
@@ -119,6 +127,8 @@ struct Plan {
   long long pairs;
   double algo_ops, bound_bits;
   int want_groups;   // contraction chunks are added until this many work items exist
+  int mode_req;      // the caller's form (MPCG_AUTO resolved into mode3m), the tuning cache's key
+  int tune_S;        // MPCG_AUTO: the 3M slice count the cache is keyed by (else the plan's own)
   int nchunk;        // INT8: 16-digit chunks per output component
   size_t off_G, off_H, off_X, off_Y, off_dig, off_top, off_lnz, off_scan, total;
 };
@@ -184,8 +194,21 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
   P.nopsB = 3;
   const int groups = (P.mpad / 32) * (P.npad / 32);
   if (!P.f64) {
-    // band width: diagonals accumulated together by one wavefront
-    P.block = (opt && opt->block_override) ? opt->block_override : pick_band(P);
+    // band width: diagonals accumulated together by one wavefront; from the
+    // tuning cache for this size class if it has an entry
+    TuneChoice tc;
+    if (opt && opt->block_override) {
+      P.block = opt->block_override;
+    } else if (!g_tune_bypass && !(opt && opt->ksplit_override) &&
+               tune_find(tune_key(P.trunc, P.mode_req, P.m, P.n, P.k, P.tune_S ? P.tune_S : std::max(P.SA, P.SB)),
+                         &tc) &&
+               tc.mode3m == P.mode3m) {
+      P.block = tc.band;
+      P.want_groups = tc.groups;
+    } else {
+      P.block = pick_band(P);
+    }
+    if (g_tune_forced_groups) P.want_groups = g_tune_forced_groups;
     if (P.block != 8 && P.block != 12 && P.block != 16 && P.block != 20)
       return set_err(MPCG_EINVAL, "block_override (band width) must be 8, 12, 16 or 20");
     P.SAp = P.SA;
@@ -320,7 +343,7 @@ int validate(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* 
   if (m < 0 || n < 0 || k < 0) return set_err(MPCG_EINVAL, "negative dimension (m=%d n=%d k=%d)", m, n, k);
   if (prec_bits < MPCG_MIN_PREC || prec_bits > MPCG_MAX_PREC)
     return set_err(MPCG_EINVAL, "prec_bits %d outside [%d, %d]", prec_bits, MPCG_MIN_PREC, MPCG_MAX_PREC);
-  if (mode != MPCG_4M && mode != MPCG_3M) return set_err(MPCG_EINVAL, "bad mode %d", mode);
+  if (mode != MPCG_4M && mode != MPCG_3M && mode != MPCG_AUTO) return set_err(MPCG_EINVAL, "bad mode %d", mode);
   if (scheme != MPCG_EXACT && scheme != MPCG_TRUNCATED) return set_err(MPCG_EINVAL, "bad scheme %d", scheme);
   if (opt) {
     if (opt->slice_type != MPCG_SLICE_INT8 && opt->slice_type != MPCG_SLICE_FP64)
@@ -391,6 +414,28 @@ std::vector<int> adaptive_blocks(const std::vector<RowStat>& st, int p, int x, b
 
 // acc = 0: C := AB; acc = +1 / -1: C := C + AB / C - AB, one rounding of the
 // exact sum (C's current entries are the addend).
+// Reads the tuning cache named by MPCG_TUNE_CACHE once per process (a
+// missing file is not an error; a malformed one is ignored).
+void tune_env_load() {
+  if (g_tune_env_done) return;
+  g_tune_env_done = true;
+  const char* path = getenv("MPCG_TUNE_CACHE");
+  if (path && *path) (void)tune_load(path);
+}
+
+// The slice count a request of MPCG_AUTO is keyed by: the 3M form's.
+int auto_key_S(int p, int spreadA, int spreadB) { return ceil_div(p + 2 + std::max(spreadA, spreadB), 7); }
+
+// The form for a request of MPCG_AUTO: the tuning cache's choice for the size
+// class, else 3M.
+int resolve_mode(int mode, int scheme, int m, int n, int k, int p, int spreadA, int spreadB) {
+  if (mode != MPCG_AUTO) return mode;
+  const int S = auto_key_S(p, spreadA, spreadB);
+  TuneChoice tc;
+  if (!g_tune_bypass && tune_find(tune_key(scheme, MPCG_AUTO, m, n, k, S), &tc)) return tc.mode3m ? MPCG_3M : MPCG_4M;
+  return MPCG_3M;
+}
+
 // Device memory of a call that must not allocate: the status word and one
 // region that holds the exponent scan and then the workspace.
 struct FixedBuffers {
@@ -430,16 +475,20 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
   DOperand opB{dpart(B->re, (int64_t)ldb * n), dpart(B->im, (int64_t)ldb * n), n, k, ldb, 1};
   Plan P{};
   P.m = m; P.n = n; P.k = k; P.p = prec_bits;
-  P.mode3m = mode == MPCG_3M;
+  P.mode_req = mode;
+  P.mode3m = mode != MPCG_4M;  // MPCG_AUTO is resolved once the spreads are known
   P.trunc = scheme == MPCG_TRUNCATED;
   P.f64 = opt && opt->slice_type == MPCG_SLICE_FP64;
   P.want_groups = 512;
   const int bound = opt ? opt->max_spread : 0;
+  tune_env_load();
   const size_t sA = align256(sizeof(RowStat) * (size_t)m), sB = align256(sizeof(RowStat) * (size_t)n);
   void* ws = nullptr;
   RowStat *statA, *statB;
   if (bound > 0) {
     // planned from the caller's bound: no read-back, the scan lives in the workspace
+    P.mode3m = resolve_mode(mode, scheme, m, n, k, prec_bits, bound, bound) == MPCG_3M;
+    P.tune_S = mode == MPCG_AUTO ? auto_key_S(prec_bits, bound, bound) : 0;
     if ((st = plan_slices(P, bound, bound, bound, bound, opt))) return st;
     if ((st = plan_layout(P, opt))) return st;
     if (fixed) {
@@ -518,6 +567,8 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
         return run_batched((int)probs.size(), probs.data(), prec_bits, mode, scheme, &o, info, acc, false, nullptr);
       }
     }
+    P.mode3m = resolve_mode(mode, scheme, m, n, k, prec_bits, sa.spread, sb.spread) == MPCG_3M;
+    P.tune_S = mode == MPCG_AUTO ? auto_key_S(prec_bits, sa.spread, sb.spread) : 0;
     if ((st = plan_slices(P, sa.spread, sb.spread, sa.hat, sb.hat, opt))) return st;
     if ((st = plan_layout(P, opt))) return st;
     if (fixed) {
@@ -780,6 +831,7 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
     if ((st = ensure_status_and_pinned())) return st;
   }
   if ((st = num_cu())) return st;
+  tune_env_load();
   const int L = (prec_bits + 63) / 64;
 
   std::vector<BatchProblem> bp;
@@ -813,7 +865,9 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
     Plan& P = b.P;
     P = Plan{};
     P.m = b.opA.R; P.n = b.opB.R; P.k = b.opA.K; P.p = prec_bits;
-    P.mode3m = mode == MPCG_3M;
+    P.mode_req = mode;
+    P.mode3m = resolve_mode(mode, scheme, P.m, P.n, P.k, prec_bits, spA, spB) == MPCG_3M;
+    P.tune_S = mode == MPCG_AUTO ? auto_key_S(prec_bits, spA, spB) : 0;
     P.trunc = scheme == MPCG_TRUNCATED;
     P.f64 = 0;
     P.want_groups = want;
@@ -822,8 +876,17 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
     if (r) return r;
     mpcg_options o = opt ? *opt : mpcg_options{};
     if (!o.block_override) {
-      // the band width from the size class (needs S, which plan_slices set)
-      o.block_override = pick_band(P);
+      // the band width from the size class (needs S, which plan_slices set):
+      // the tuning cache's, else the fixed rule; the contraction chunks stay
+      // the batch's (balanced over the compute units below)
+      TuneChoice tc;
+      o.block_override = (!g_tune_bypass &&
+                          tune_find(tune_key(P.trunc, mode, P.m, P.n, P.k,
+                                             P.tune_S ? P.tune_S : std::max(P.SA, P.SB)),
+                                    &tc) &&
+                          tc.mode3m == P.mode3m)
+                             ? tc.band
+                             : pick_band(P);
     }
     return plan_layout(P, &o);
   };
@@ -942,10 +1005,15 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
     if ((st = ensure_workspace(ws_total, &ws))) return st;
   }
   const int nl = (int)bp.size();
+  if (g_tune_keys)
+    for (const auto& b : bp)
+      g_tune_keys->push_back({tune_key(scheme, mode, b.P.m, b.P.n, b.P.k,
+                                       b.P.tune_S ? b.P.tune_S : std::max(b.P.SA, b.P.SB)),
+                              b.P.block});
 
   // ---- work items: every 2x2 tile group of every contraction chunk ----------
   // (groups of equal cost: the tile groups of one chunk of one problem)
-  struct Group { long long cost; int band, t, sp, gm, gn; };
+  struct Group { long long cost; int band, m3, t, sp, gm, gn; };
   std::vector<Group> groups;
   for (int t = 0; t < nl; ++t) {
     const Plan& P = bp[t].P;
@@ -956,7 +1024,7 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
     for (int sp = 0; sp < P.ksplit; ++sp) {
       const int kb = std::min(P.kblocks, (sp + 1) * kbps) - sp * kbps;
       const long long cost = steps * passes * kb * (P.mode3m ? 1 : 2) * P.block + 64;
-      groups.push_back(Group{cost, P.block, t, sp, gm, gn});
+      groups.push_back(Group{cost, P.block, P.mode3m, t, sp, gm, gn});
     }
     if (info) {
       info->S_A = std::max(info->S_A, P.SA); info->S_B = std::max(info->S_B, P.SB); info->w = P.w;
@@ -967,18 +1035,21 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
     }
   }
   // longest processing time first onto one workgroup per compute unit, per
-  // band class (sorting the groups orders their items the same way)
+  // class of band width and form (sorting the groups orders their items the
+  // same way)
   std::stable_sort(groups.begin(), groups.end(), [](const Group& a, const Group& b) {
-    return a.band != b.band ? a.band > b.band : a.cost > b.cost;
+    if (a.band != b.band) return a.band > b.band;
+    if (a.m3 != b.m3) return a.m3 > b.m3;
+    return a.cost > b.cost;
   });
-  struct Launch { int band, blocks; size_t o_items, o_first; };
+  struct Launch { int band, m3, blocks; size_t o_items, o_first; };
   std::vector<Launch> launches;
   std::vector<std::vector<int4>> litems;
   std::vector<std::vector<int>> lfirst;
   for (size_t a = 0; a < groups.size();) {
     size_t e = a;
     long long nitems = 0;
-    while (e < groups.size() && groups[e].band == groups[a].band) {
+    while (e < groups.size() && groups[e].band == groups[a].band && groups[e].m3 == groups[a].m3) {
       nitems += (long long)groups[e].gm * groups[e].gn;
       ++e;
     }
@@ -1036,7 +1107,7 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
       flat.insert(flat.end(), by_block[bk].begin(), by_block[bk].end());
       first.push_back((int)flat.size());
     }
-    launches.push_back(Launch{groups[a].band, nbins, 0, 0});
+    launches.push_back(Launch{groups[a].band, groups[a].m3, nbins, 0, 0});
     litems.push_back(std::move(flat));
     lfirst.push_back(std::move(first));
     a = e;
@@ -1080,11 +1151,11 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
   std::vector<GemmArgs> gargs(nl);
   std::vector<RoundArgs> rargs(nl);
   std::vector<int> frd(1, 0);
-  const Third thirdA = mode == MPCG_3M ? Third::SUM : Third::NONE;
-  const Third thirdB = mode == MPCG_3M ? Third::SUM : Third::NEG_IM;
   for (int t = 0; t < nl; ++t) {
     BatchProblem& b = bp[t];
     const Plan& P = b.P;
+    const Third thirdA = P.mode3m ? Third::SUM : Third::NONE;
+    const Third thirdB = P.mode3m ? Third::SUM : Third::NEG_IM;
     char* pb = base + b.ws_off;
     int32_t* G = reinterpret_cast<int32_t*>(pb + P.off_G);
     int32_t* H = reinterpret_cast<int32_t*>(pb + P.off_H);
@@ -1153,7 +1224,7 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
   if ((st = record(2))) return st;
   for (const Launch& l : launches)
     HIP_TRY(launch_gemm_i8_batched(reinterpret_cast<GemmArgs*>(dev + o_ga), reinterpret_cast<int4*>(dev + l.o_items),
-                                   reinterpret_cast<int*>(dev + l.o_first), l.blocks, l.band, mode == MPCG_3M,
+                                   reinterpret_cast<int*>(dev + l.o_first), l.blocks, l.band, l.m3,
                                    g_stream));
   if ((st = record(3))) return st;
   HIP_TRY(launch_round_batched(reinterpret_cast<RoundArgs*>(dev + o_ra), nl, reinterpret_cast<int*>(dev + o_frd),
@@ -1248,7 +1319,7 @@ int check_square(int n, const mpcg_cmat* A, int lda, int prec_bits, int mode, Re
   if (n < 0) return set_err(MPCG_EINVAL, "negative dimension n=%d", n);
   if (prec_bits < MPCG_MIN_PREC || prec_bits > MPCG_MAX_PREC)
     return set_err(MPCG_EINVAL, "prec_bits %d outside [%d, %d]", prec_bits, MPCG_MIN_PREC, MPCG_MAX_PREC);
-  if (mode != MPCG_4M && mode != MPCG_3M) return set_err(MPCG_EINVAL, "bad mode %d", mode);
+  if (mode != MPCG_4M && mode != MPCG_3M && mode != MPCG_AUTO) return set_err(MPCG_EINVAL, "bad mode %d", mode);
   if (lda < std::max(1, n)) return set_err(MPCG_EINVAL, "lda %d < max(1, n=%d)", lda, n);
   if (!A) return set_err(MPCG_EINVAL, "A is NULL");
   const int L = (prec_bits + 63) / 64;
@@ -1407,6 +1478,211 @@ int mp_cgemm_ex_noalloc(int m, int n, int k, const mpcg_cmat* A, int lda, const 
   return run(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, mode, scheme, opt, info, 0, true, &fb);
 }
 
+int mpcg_autotune(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, int ldb, mpcg_cmat* C,
+                  int ldc, int prec_bits, int mode, int scheme, int reps, mpcg_tune_report* report) {
+  g_err.clear();
+  int st = validate(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, mode, scheme, nullptr);
+  if (st) return st;
+  if (report) memset(report, 0, sizeof(*report));
+  if (m == 0 || n == 0 || k == 0) return set_err(MPCG_EINVAL, "nothing to tune for an empty product");
+  reps = std::max(1, reps);
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    tune_env_load();
+  }
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  HIP_TRY(hipEventCreate(&ev[0]));
+  hipError_t e = hipEventCreate(&ev[1]);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return set_err(MPCG_EHIP, "hipEventCreate failed: %s", hipGetErrorString(e));
+  }
+  struct Cand { int mode, band, groups; };
+  std::vector<Cand> cands;
+  const int forms[2] = {MPCG_3M, MPCG_4M};
+  for (int f = 0; f < 2; ++f) {
+    const int fm = forms[f];
+    if (mode != MPCG_AUTO && fm != mode) continue;
+    for (int band : {8, 12, 16, 20}) {
+      if (fm == MPCG_4M && band > 16) continue;  // two rings per diagonal: 16 is the widest that fits registers
+      for (int groups : {256, 512, 1024, 2048}) cands.push_back(Cand{fm, band, groups});
+    }
+  }
+  // time `reps` calls of one plan (after one untimed call); -1 if it fails
+  auto time_plan = [&](int fm, int band, int groups, mpcg_info* info) -> float {
+    mpcg_options o{MPCG_SLICE_INT8, 0, 0, band, 0, 0};
+    g_tune_forced_groups = groups;
+    g_tune_bypass = true;
+    int r = run(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, fm, scheme, band ? &o : nullptr, info);
+    float ms = -1.f;
+    if (!r && hipEventRecord(ev[0], g_stream) == hipSuccess) {
+      for (int i = 0; i < reps && !r; ++i) r = run(m, n, k, A, lda, B, ldb, C, ldc, prec_bits, fm, scheme,
+                                                 band ? &o : nullptr, nullptr);
+      if (!r && hipEventRecord(ev[1], g_stream) == hipSuccess && hipEventSynchronize(ev[1]) == hipSuccess &&
+          hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess)
+        ms /= reps;
+      else
+        ms = -1.f;
+    }
+    g_tune_forced_groups = 0;
+    g_tune_bypass = false;
+    return ms;
+  };
+  // the fixed rule's plan (3M unless 4M was asked for), which also gives S
+  mpcg_info info{};
+  const int base_mode = mode == MPCG_4M ? MPCG_4M : MPCG_3M;
+  const float base_ms = time_plan(base_mode, 0, 512, &info);
+  if (base_ms < 0) {
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    return g_err.empty() ? set_err(MPCG_EHIP, "timing the untuned plan failed") : MPCG_EHIP;
+  }
+  float best_ms = base_ms;
+  Cand best{base_mode, info.block, 512};
+  int tried = 0;
+  for (const Cand& c : cands) {
+    const float ms = time_plan(c.mode, c.band, c.groups, nullptr);
+    if (ms < 0) continue;  // a plan the limits reject (int32 headroom), or a failed call
+    ++tried;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  g_err.clear();
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  const int S = std::max(info.S_A, info.S_B);  // of the 3M plan for MPCG_AUTO and 3M requests
+  tune_put(tune_key(scheme, mode, m, n, k, S), TuneChoice{best.band, best.groups, best.mode == MPCG_3M ? 1 : 0,
+                                                          1000.f * best_ms});
+  if (report) {
+    report->band = best.band;
+    report->groups = best.groups;
+    report->mode = best.mode;
+    report->S = S;
+    report->candidates = tried;
+    report->us = 1000.f * best_ms;
+    report->untuned_us = 1000.f * base_ms;
+  }
+  return MPCG_OK;
+}
+
+int mpcg_autotune_batched(int count, const mpcg_problem* problems, int prec_bits, int mode, int scheme, int reps,
+                          const mpcg_options* opt, mpcg_tune_report* report) {
+  g_err.clear();
+  if (report) memset(report, 0, sizeof(*report));
+  if (mode != MPCG_4M && mode != MPCG_3M && mode != MPCG_AUTO) return set_err(MPCG_EINVAL, "bad mode %d", mode);
+  if (opt && (opt->block_override || opt->slice_type != MPCG_SLICE_INT8 || opt->adaptive))
+    return set_err(MPCG_EINVAL, "tuning a batch measures band widths itself (INT8 slices, no block or adaptive option)");
+  reps = std::max(1, reps);
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    tune_env_load();
+  }
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  HIP_TRY(hipEventCreate(&ev[0]));
+  hipError_t e = hipEventCreate(&ev[1]);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return set_err(MPCG_EHIP, "hipEventCreate failed: %s", hipGetErrorString(e));
+  }
+  std::vector<std::pair<TuneKey, int>> keys;
+  auto time_batch = [&](int fm, int band, bool record_keys) -> float {
+    mpcg_options o = opt ? *opt : mpcg_options{};
+    o.block_override = band;
+    g_tune_bypass = true;
+    g_tune_keys = record_keys ? &keys : nullptr;
+    int r = run_batched(count, problems, prec_bits, fm, scheme, &o, nullptr, 0, true);
+    g_tune_keys = nullptr;
+    float ms = -1.f;
+    if (!r && hipEventRecord(ev[0], g_stream) == hipSuccess) {
+      for (int i = 0; i < reps && !r; ++i) r = run_batched(count, problems, prec_bits, fm, scheme, &o, nullptr, 0, true);
+      if (!r && hipEventRecord(ev[1], g_stream) == hipSuccess && hipEventSynchronize(ev[1]) == hipSuccess &&
+          hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess)
+        ms /= reps;
+      else
+        ms = -1.f;
+    }
+    g_tune_bypass = false;
+    return ms;
+  };
+  // the fixed rule: 3M (unless 4M was asked for) with each problem's own band
+  const int base_mode = mode == MPCG_4M ? MPCG_4M : MPCG_3M;
+  const float base_ms = time_batch(base_mode, 0, true);
+  if (base_ms < 0) {
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    return g_err.empty() ? set_err(MPCG_EHIP, "timing the untuned batch failed") : MPCG_EHIP;
+  }
+  float best_ms = base_ms;
+  int best_mode = -1, best_band = 0, tried = 0;  // -1: keep the fixed rule
+  for (int fm : {MPCG_3M, MPCG_4M}) {
+    if (mode != MPCG_AUTO && fm != mode) continue;
+    for (int band : {8, 12, 16, 20}) {
+      if (fm == MPCG_4M && band > 16) continue;
+      const float ms = time_batch(fm, band, false);
+      if (ms < 0) continue;
+      ++tried;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_mode = fm;
+        best_band = band;
+      }
+    }
+  }
+  g_err.clear();
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  // every size class of the batch takes the winner: a uniform plan, or each
+  // problem's own band in the base form.  Keyed by the requested form (the
+  // classes were recorded by the base run, whose 3M or 4M slice counts are
+  // the ones such requests are keyed by).
+  for (auto kb : keys) {
+    TuneKey k = kb.first;
+    k.mode = mode;
+    const int fm = best_mode >= 0 ? best_mode : base_mode;
+    tune_put(k, TuneChoice{best_mode >= 0 ? best_band : kb.second, 512, fm == MPCG_3M ? 1 : 0, 1000.f * best_ms});
+  }
+  if (report) {
+    report->band = best_mode >= 0 ? best_band : 0;
+    report->groups = 512;
+    report->mode = best_mode >= 0 ? best_mode : base_mode;
+    report->S = 0;
+    report->candidates = tried;
+    report->us = 1000.f * best_ms;
+    report->untuned_us = 1000.f * base_ms;
+  }
+  return MPCG_OK;
+}
+
+int mpcg_tune_load(const char* path) {
+  g_err.clear();
+  if (!path) path = getenv("MPCG_TUNE_CACHE");
+  if (!path || !*path) return set_err(MPCG_EINVAL, "no tuning cache path (argument NULL and MPCG_TUNE_CACHE unset)");
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_tune_env_done = true;
+  const int r = tune_load(path);
+  if (r < 0) return set_err(MPCG_EINVAL, "cannot read tuning cache %s (missing or malformed)", path);
+  return r;
+}
+
+int mpcg_tune_save(const char* path) {
+  g_err.clear();
+  if (!path) path = getenv("MPCG_TUNE_CACHE");
+  if (!path || !*path) return set_err(MPCG_EINVAL, "no tuning cache path (argument NULL and MPCG_TUNE_CACHE unset)");
+  std::lock_guard<std::mutex> lock(g_mu);
+  const int r = tune_save(path);
+  if (r < 0) return set_err(MPCG_EINVAL, "cannot write tuning cache %s", path);
+  return r;
+}
+
+int mpcg_tune_clear(void) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  tune_clear();
+  g_tune_env_done = true;  // an explicit clear also stops the environment's cache from loading later
+  return MPCG_OK;
+}
+
 int mp_cgemm_acc(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, int ldb, mpcg_cmat* C,
                  int ldc, int prec_bits, int mode, int scheme, int sign, const mpcg_options* opt, mpcg_info* info) {
   if (sign != 1 && sign != -1) {
@@ -1470,9 +1746,13 @@ size_t mpcg_workspace_size(int m, int n, int k, int prec_bits, int mode, int sch
                            int max_spread) {
   if (m <= 0 || n <= 0 || k <= 0 || prec_bits < MPCG_MIN_PREC || prec_bits > MPCG_MAX_PREC || max_spread < 0)
     return 0;
+  if (mode != MPCG_4M && mode != MPCG_3M && mode != MPCG_AUTO) return 0;
+  tune_env_load();  // the same plan as the call's, tuned size classes included
   Plan P{};
   P.m = m; P.n = n; P.k = k; P.p = prec_bits;
-  P.mode3m = mode == MPCG_3M;
+  P.mode_req = mode;
+  P.mode3m = resolve_mode(mode, scheme, m, n, k, prec_bits, max_spread, max_spread) == MPCG_3M;
+  P.tune_S = mode == MPCG_AUTO ? auto_key_S(prec_bits, max_spread, max_spread) : 0;
   P.trunc = scheme == MPCG_TRUNCATED;
   P.f64 = opt && opt->slice_type == MPCG_SLICE_FP64;
   P.want_groups = 512;

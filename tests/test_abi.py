@@ -65,7 +65,7 @@ def _call(m=4, n=4, k=4, lda=4, ldb=4, ldc=4, p=256, mode=1, scheme=0, A=None, B
 
 
 @pytest.mark.parametrize("kw", [dict(m=-1), dict(n=-2), dict(k=-3), dict(lda=3), dict(ldb=3), dict(ldc=2),
-                                dict(p=1), dict(p=4097), dict(mode=2), dict(scheme=5), dict(A=False),
+                                dict(p=1), dict(p=4097), dict(mode=3), dict(scheme=5), dict(A=False),
                                 dict(B=False), dict(C=False)])
 def test_invalid_arguments(kw):
     import paper_2307_06072_amd as mp
@@ -268,7 +268,7 @@ def _getrf(n=4, lda=4, ipiv=9 << 40, nb=2, p=256, mode=1, A=None):
 
 
 @pytest.mark.parametrize("kw", [dict(n=-1), dict(lda=3), dict(ipiv=0), dict(nb=-1), dict(p=1), dict(p=4097),
-                                dict(mode=2), dict(A=False)])
+                                dict(mode=3), dict(A=False)])
 def test_getrf_rejects_bad_arguments(kw):
     import paper_2307_06072_amd as mp
     assert _getrf(**kw) == mp.MPCG_EINVAL
@@ -314,3 +314,54 @@ def test_adaptive_option_validated():
     for bad in (2, -1, 48, 1 << 21):
         assert _call(opt=mp.mpcg_options(0, 0, 0, 0, 0, bad)) == mp.MPCG_EINVAL
         assert "adaptive" in mp.mpcg_last_error()
+
+
+# ---------------------------------------------------------------------------
+# size-class tuning cache (file side; no GPU needed)
+# ---------------------------------------------------------------------------
+def test_tune_cache_file_round_trip(tmp_path, monkeypatch):
+    """A cache file is read back entry for entry after a save; a malformed or
+    missing file and a missing path are rejected with MPCG_EINVAL.  Without a
+    GPU the device's architecture reads as "unknown", so the file is written
+    for that name here."""
+    import json
+    import torch
+    import paper_2307_06072_amd as mp
+    if torch.cuda.is_available():
+        pytest.skip("the file names this host's architecture only when there is no GPU (the GPU tuning test covers it)")
+    monkeypatch.delenv("MPCG_TUNE_CACHE", raising=False)
+    mp.mpcg_tune_clear()
+    entries = [{"arch": "unknown", "scheme": 0, "mode": 2, "log2_m": 9, "log2_n": 8, "log2_k": 10, "s_bucket": 5,
+                "band": 12, "groups": 1024, "mode3m": 0, "us": 123.5},
+               {"arch": "unknown", "scheme": 1, "mode": 1, "log2_m": 11, "log2_n": 11, "log2_k": 11,
+                "s_bucket": 20, "band": 20, "groups": 512, "mode3m": 1, "us": 240000.0},
+               {"arch": "gfx000", "scheme": 0, "mode": 1, "log2_m": 4, "log2_n": 4, "log2_k": 4, "s_bucket": 5,
+                "band": 8, "groups": 256, "mode3m": 1, "us": 5.0}]
+    src = tmp_path / "cache.json"
+    src.write_text(json.dumps({"mpcg_tune_cache": 1, "entries": entries}))
+    assert mp.mpcg_tune_load(str(src)) == 2  # the other architecture's entry is skipped
+    out = tmp_path / "out.json"
+    assert mp.mpcg_tune_save(str(out)) == 2
+    got = json.loads(out.read_text())
+    assert got["mpcg_tune_cache"] == 1
+    key = lambda e: (e["scheme"], e["mode"], e["log2_m"], e["log2_n"], e["log2_k"], e["s_bucket"])
+    assert sorted(got["entries"], key=key) == sorted(entries[:2], key=key)
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"mpcg_tune_cache": 1, "entries": [{"arch": "unknown", "band": 7}]}')
+    for path in (str(bad), str(tmp_path / "missing.json")):
+        with pytest.raises(mp.MPCGError) as ei:
+            mp.mpcg_tune_load(path)
+        assert ei.value.code == mp.MPCG_EINVAL
+    with pytest.raises(mp.MPCGError) as ei:
+        mp.mpcg_tune_load(None)
+    assert ei.value.code == mp.MPCG_EINVAL
+    monkeypatch.setenv("MPCG_TUNE_CACHE", str(out))
+    mp.mpcg_tune_clear()
+    assert mp.mpcg_tune_load(None) == 2
+    mp.mpcg_tune_clear()
+
+
+def test_auto_mode_accepted_bad_mode_rejected():
+    import paper_2307_06072_amd as mp
+    assert _call(mode=3) == mp.MPCG_EINVAL
+    assert _call(mode=mp.MPCG_AUTO) != mp.MPCG_EINVAL  # passes validation; fails later without a GPU
