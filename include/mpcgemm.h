@@ -117,7 +117,7 @@ typedef enum { MPCG_SLICE_INT8 = 0, MPCG_SLICE_FP64 = 1 } mpcg_slice;
  *          component then satisfies
  *            |C~ - C*| <= 2^-(prec_bits-4) * sum_k |a_ik|_max |b_kj|_max,
  *          with C* the exact product and |z|_max = max(|Re z|, |Im z|).
- *   Slices are signed 7-bit integers on INT8 matrix cores.
+ *   Slices are signed 8-bit digits (balanced base 2^8) on INT8 matrix cores.
  * Quick returns: m == 0 or n == 0 does nothing; k == 0 writes +0 to C.
  * Returns MPCG_OK, MPCG_EINVAL, MPCG_ENOMEM, MPCG_ERANGE (input exponents),
  * MPCG_EHIP.  Output exponent overflow and non-normalized inputs are reported

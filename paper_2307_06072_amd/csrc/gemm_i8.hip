@@ -2,11 +2,11 @@
 // combination of the real products and the carry chain.
 //
 // With A = diag(2^G) sum_s X_s 2^(-w(s+1)) and B = sum_t Y_t 2^(-w(t+1)) diag(2^H)
-// (balanced 7-bit digits, |digit| <= 64), every real product is
+// (balanced base-2^8 digits in [-128, 127]), every real product is
 //     X Y = diag(2^G) [ sum_d D_d 2^(-w(d+2)) ] diag(2^H),   D_d = sum_{s+t=d} X_s Y_t,
 // i.e. the slice-pair products C_{alpha beta} of Algorithm 2 grouped by
 // anti-diagonal d = s + t.  Each D_d is an exact integer matrix: products of
-// digits are at most 2^12 in magnitude and the planner limits the terms per
+// digits are at most 2^14 in magnitude and the planner limits the terms per
 // diagonal so that int32 accumulation cannot overflow.
 //
 // Work of one wavefront: a 16 x 16 output tile (v_mfma_i32_16x16x64_i8) and a
@@ -41,7 +41,7 @@
 // (4M, eq. 5: the accumulators hold Re and Im directly, the B side supplying
 // -Im B; 3M, eq. 6: T1, T2, T3 with Re = T1 - T2, Im = T3 - T1 - T2) and pushed,
 // least significant first, through a per-element int64 carry chain that emits
-// one normalised base-2^7 digit per diagonal, stored contiguously per output
+// one normalised base-2^8 digit per diagonal, stored contiguously per output
 // component; the final carry is the signed top of the exact result.
 //
 // Workgroups are 2 x 2 tiles; their order is XCD-aware so that the workgroups
@@ -489,10 +489,10 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
         if (d >= 0) {  // diagonals below 0 (the last band's overhang) are empty
           cre[r] += vre;
           cim[r] += vim;
-          dre = (uint32_t)(cre[r] & 127);
-          dim = (uint32_t)(cim[r] & 127);
-          cre[r] >>= 7;
-          cim[r] >>= 7;
+          dre = (uint32_t)(cre[r] & ((1 << I8_W) - 1));
+          dim = (uint32_t)(cim[r] & ((1 << I8_W) - 1));
+          cre[r] >>= I8_W;
+          cim[r] >>= I8_W;
           if (dre && lre[r] < 0) lre[r] = d;
           if (dim && lim[r] < 0) lim[r] = d;
         }

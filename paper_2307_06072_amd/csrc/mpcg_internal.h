@@ -7,6 +7,9 @@
 namespace mpcg {
 
 constexpr int32_t EXP_ZERO = INT32_MIN;
+// Bits per digit of the INT8 slices: balanced base-2^8 digits in [-128, 127],
+// the full range of an int8 matrix-core operand.
+constexpr int I8_W = 8;
 constexpr int32_t EXP_LIMIT = 1 << 30;  // |exp| of a nonzero input
 
 // Device status bits (OR-ed into a word in the workspace).

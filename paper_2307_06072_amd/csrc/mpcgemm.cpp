@@ -135,8 +135,11 @@ struct Plan {
 
 int plan_slices(Plan& P, int spreadA, int spreadB, int hatA, int hatB, const mpcg_options* opt) {
   P.L = (P.p + 63) / 64;
-  P.x = P.mode3m ? 2 : 1;
-  P.w = P.f64 ? std::max(1, (53 - ceil_log2(std::max(1, P.k))) / 2) : 7;
+  // headroom bits above the row maximum: the top digit keeps the remaining
+  // value, at most 2^(w - x) (twice that for Re + Im in 3M), which must fit
+  // an int8 for the INT8 slices (|d| <= 64 with w = 8 and x = 2 or 3)
+  P.x = P.f64 ? (P.mode3m ? 2 : 1) : (P.mode3m ? 3 : 2);
+  P.w = P.f64 ? std::max(1, (53 - ceil_log2(std::max(1, P.k))) / 2) : I8_W;
   if (P.w > 31) P.w = 31;
   P.SA = ceil_div(P.p + P.x + spreadA, P.w);
   P.SB = ceil_div(P.p + P.x + spreadB, P.w);
@@ -218,9 +221,10 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
     P.xs = P.xlo + P.SA + ahi;
     P.ys = P.ylo + P.SB + bhi;
     P.kblocks = P.kpad / 64;
-    // int32 accumulators: terms per diagonal * 64*64 must stay below 2^31
+    // int32 accumulators: terms per diagonal * 128^2 (the largest digit product)
+    // must stay below 2^31
     const long long terms_per_k = (long long)(P.mode3m ? 1 : 2) * std::min(P.SA, P.SB);
-    const long long kc_max = ((1ll << 31) - 1) / (4096ll * terms_per_k);
+    const long long kc_max = ((1ll << 31) - 1) / ((1ll << (2 * I8_W - 2)) * terms_per_k);
     const long long kb_max = kc_max / 64;
     if (kb_max < 1) return set_err(MPCG_EUNSUPPORTED, "precision/spread too large for int32 slice accumulation");
     int ks = (int)((P.kblocks + kb_max - 1) / kb_max);
@@ -241,7 +245,7 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
   if (opt && opt->ksplit_override > 0) {
     if (!P.f64) {
       const long long terms_per_k = (long long)(P.mode3m ? 1 : 2) * std::min(P.SA, P.SB);
-      const long long kc_max = ((1ll << 31) - 1) / (4096ll * terms_per_k);
+      const long long kc_max = ((1ll << 31) - 1) / ((1ll << (2 * I8_W - 2)) * terms_per_k);
       const long long kc = (long long)ceil_div(P.kblocks, opt->ksplit_override) * 64;
       if (kc > kc_max) return set_err(MPCG_EINVAL, "ksplit_override too small for exact int32 accumulation");
     }
@@ -399,7 +403,8 @@ std::vector<int> adaptive_blocks(const std::vector<RowStat>& st, int p, int x, b
         spread = std::max(spread, st[r].emax - st[r].emin);
         hat = std::max(hat, st[r].emax - st[r].ehat);
       }
-    std::pair<int, int> key{spread < 0 ? -1 : ceil_div(p + x + spread, 7), trunc && hat >= 0 ? ceil_div(hat, 7) : 0};
+    std::pair<int, int> key{spread < 0 ? -1 : ceil_div(p + x + spread, I8_W),
+                            trunc && hat >= 0 ? ceil_div(hat, I8_W) : 0};
     if (!starts.empty() && (key.first < 0 || keys.back() == key)) continue;  // all-zero blocks join a neighbour
     if (!starts.empty() && keys.back().first < 0) {
       keys.back() = key;  // a leading all-zero block takes the next block's key
@@ -424,7 +429,7 @@ void tune_env_load() {
 }
 
 // The slice count a request of MPCG_AUTO is keyed by: the 3M form's.
-int auto_key_S(int p, int spreadA, int spreadB) { return ceil_div(p + 2 + std::max(spreadA, spreadB), 7); }
+int auto_key_S(int p, int spreadA, int spreadB) { return ceil_div(p + 3 + std::max(spreadA, spreadB), I8_W); }
 
 // The form for a request of MPCG_AUTO: the tuning cache's choice for the size
 // class, else 3M.
@@ -545,7 +550,7 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
       HIP_TRY(hipMemcpyAsync(hA.data(), statA, sizeof(RowStat) * m, hipMemcpyDeviceToHost, g_stream));
       HIP_TRY(hipMemcpyAsync(hB.data(), statB, sizeof(RowStat) * n, hipMemcpyDeviceToHost, g_stream));
       HIP_TRY(hipStreamSynchronize(g_stream));
-      const int xb = P.mode3m ? 2 : 1;
+      const int xb = P.mode3m ? 3 : 2;  // the INT8 headroom of plan_slices
       const int blk = opt->adaptive == 1 ? 256 : opt->adaptive;
       const std::vector<int> rb = adaptive_blocks(hA, prec_bits, xb, P.trunc, blk);
       const std::vector<int> cb = adaptive_blocks(hB, prec_bits, xb, P.trunc, blk);

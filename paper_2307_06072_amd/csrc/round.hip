@@ -25,6 +25,8 @@ namespace mpcg {
 
 namespace {
 
+constexpr uint64_t DFULL = 1ull << I8_W;  // the INT8 digit base
+
 template <typename DIG>
 struct Stream {
   const DIG* base;  // digit d of this element: base[d * 512]
@@ -262,13 +264,13 @@ struct Win8 {
   // bits [pos, pos + 64) of |X| read from the digit stream (any position):
   // the at most 10 digits come from at most two 16-digit chunks, loaded whole
   __device__ uint64_t fieldg(int64_t pos) const {
-    const int64_t nbits = 7ll * (Dmax + 1);
+    const int64_t nbits = (int64_t)I8_W * (Dmax + 1);
     uint64_t r = 0;
     const int64_t lo = pos < 0 ? 0 : pos;
     const int64_t hi = pos + 64;
     if (lo < nbits) {
-      const int q0 = (int)(lo / 7);
-      const int q1 = (int)min((hi - 1) / 7, (int64_t)Dmax);
+      const int q0 = (int)(lo / I8_W);
+      const int q1 = (int)min((hi - 1) / I8_W, (int64_t)Dmax);
       const int c0 = q0 >> 4;
       const uint4 v0 = *reinterpret_cast<const uint4*>(glob + (size_t)c0 * 1024);
       const uint4 v1 = (q1 >> 4) != c0 ? *reinterpret_cast<const uint4*>(glob + (size_t)(c0 + 1) * 1024) : v0;
@@ -278,8 +280,8 @@ struct Win8 {
         const uint32_t w = b < 8 ? (b < 4 ? cv.x : cv.y) : (b < 12 ? cv.z : cv.w);
         const uint64_t raw = (w >> (8 * (b & 3))) & 255u;
         const int d = Dmax - q;
-        const uint64_t v = !neg ? raw : ((z < 0 || d > z) ? 0ull : (d == z ? 128 - raw : 127 - raw));
-        const int64_t sh = 7ll * q - pos;
+        const uint64_t v = !neg ? raw : ((z < 0 || d > z) ? 0ull : (d == z ? DFULL - raw : DFULL - 1 - raw));
+        const int64_t sh = (int64_t)I8_W * q - pos;
         if (sh >= 0) {
           if (sh < 64) r |= v << sh;
         } else if (-sh < 64) {
@@ -303,15 +305,15 @@ __device__ inline uint64_t lowmask(int64_t n) { return n <= 0 ? 0ull : (n >= 64 
 __device__ inline uint64_t rangemask(int64_t a, int64_t b) { return lowmask(b) & ~lowmask(a); }  // bits [a, b)
 
 // Bits [xw0, xw0 + 64 nx) of |X| in binary, as the words Xw[0 .. nx).  One
-// pass over the 16-digit chunks of the stream: four 7-bit digits (one 32-bit
-// word of a chunk) are packed to 28 bits at a time and collected in a
+// pass over the 16-digit chunks of the stream: four digits (one 32-bit word
+// of a chunk, already packed since a digit fills its byte) at a time are collected in a
 // two-word register window, and each word is stored once, low to high.  For
 // negative X the digit bits of the range are the two's complement of the
 // digit integer: inverted, plus the +1 carried up from below its lowest set
 // bit (low_x), which enters here when low_x lies in or above the range.  The
 // top U lies above the digits.
 __device__ __attribute__((always_inline)) inline void build_xwin(const Win8 st, int64_t xw0, int nx, int64_t low_x, uint64_t* Xw) {
-  const int64_t nbits = 7ll * (st.Dmax + 1);
+  const int64_t nbits = (int64_t)I8_W * (st.Dmax + 1);
   const int64_t wlo = max(xw0, (int64_t)0), whi = min(xw0 + 64ll * nx, nbits);
   const bool digits = wlo < whi && !(st.neg && st.z < 0);
   const bool inv = digits && st.neg;
@@ -335,7 +337,7 @@ __device__ __attribute__((always_inline)) inline void build_xwin(const Win8 st, 
     ++w;
   };
   if (digits) {
-    const int q0 = (int)(wlo / 7) & ~3, q1 = (int)((whi - 1) / 7);
+    const int q0 = (int)(wlo / I8_W) & ~3, q1 = (int)((whi - 1) / I8_W);
     for (int c = q0 >> 4; c <= (q1 >> 4); ++c) {
       const uint4 cv = *reinterpret_cast<const uint4*>(st.glob + (size_t)c * 1024);
       const uint32_t words[4] = {cv.x, cv.y, cv.z, cv.w};
@@ -344,10 +346,10 @@ __device__ __attribute__((always_inline)) inline void build_xwin(const Win8 st, 
         const int qq = 16 * c + 4 * k;
         if (qq + 3 < q0 || qq > q1) continue;
         const uint32_t wd = words[k];
-        uint64_t v = (wd & 0x7Fu) | ((wd >> 1) & 0x3F80u) | ((wd >> 2) & 0x1FC000u) | ((wd >> 3) & 0xFE00000u);
+        uint64_t v = wd;  // four digits of I8_W = 8 bits: the word is their binary value
         const int nvalid = st.Dmax - qq + 1;  // digits beyond Dmax are not part of X
-        if (nvalid < 4) v &= lowmask(7ll * (nvalid < 0 ? 0 : nvalid));
-        int64_t bp = 7ll * qq - xw0;  // >= -27
+        if (nvalid < 4) v &= lowmask((int64_t)I8_W * (nvalid < 0 ? 0 : nvalid));
+        int64_t bp = (int64_t)I8_W * qq - xw0;  // >= -(4 I8_W - 1)
         if (bp < 0) {
           v >>= -bp;
           bp = 0;
@@ -355,7 +357,7 @@ __device__ __attribute__((always_inline)) inline void build_xwin(const Win8 st, 
         while (bp >= 64ll * (w + 1)) flush();  // bp < 64 nx
         const int rr = (int)(bp - 64ll * w);
         lo |= v << rr;
-        if (rr > 36) hi |= v >> (64 - rr);
+        if (rr > 64 - 4 * I8_W) hi |= v >> (64 - rr);
       }
     }
   }
@@ -476,7 +478,7 @@ struct AccSum {
 __device__ __attribute__((always_inline)) inline void round_acc_general(const Win8& st, int64_t lead_x, int64_t low_x, int sx, const AccC& C, int sc,
                                   int64_t gbase, int p, int L, DOutPart out, int64_t o, uint64_t* Y, uint64_t* Xw,
                                   int nx, int* status) {
-  const int64_t nbits = 7ll * (st.Dmax + 1);
+  const int64_t nbits = (int64_t)I8_W * (st.Dmax + 1);
   const int64_t lead_c = 64ll * L - 1 + C.sh;
   const int64_t cb = C.lowest();
   const int64_t ct1 = lead_c + 2;
@@ -851,8 +853,8 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
         const int qq = ch * 16 + b;
         if (qq < nq) {
           const int64_t sv = c + sum[b];
-          const uint32_t dg = (uint32_t)(sv & 127);
-          c = sv >> 7;
+          const uint32_t dg = (uint32_t)(sv & (DFULL - 1));
+          c = sv >> I8_W;
           out[b >> 2] |= dg << (8 * (b & 3));
           if (dg && qz < 0) qz = qq;
         }
@@ -885,7 +887,7 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
   st.neg = T < 0;
   st.z = z;
   st.U = !st.neg ? (uint64_t)T : (z < 0 ? (uint64_t)(-T) : (uint64_t)(-T - 1));
-  const int64_t nbits = 7ll * (Dmax + 1);
+  const int64_t nbits = (int64_t)I8_W * (Dmax + 1);
   // leading bit of |X|: in the top, else in the highest nonzero magnitude
   // digit, found a 16-digit chunk (one load) at a time
   int64_t lead = -1;
@@ -900,19 +902,19 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
         const int q = 16 * c + b;
         const uint64_t raw = (words[b >> 2] >> (8 * (b & 3))) & 255u;
         const int d = Dmax - q;
-        const uint64_t v = q > Dmax ? 0ull : !st.neg ? raw : ((z < 0 || d > z) ? 0ull : (d == z ? 128 - raw : 127 - raw));
-        if (lead < 0 && v) lead = 7ll * q + 63 - __builtin_clzll(v);
+        const uint64_t v = q > Dmax ? 0ull : !st.neg ? raw : ((z < 0 || d > z) ? 0ull : (d == z ? DFULL - raw : DFULL - 1 - raw));
+        if (lead < 0 && v) lead = (int64_t)I8_W * q + 63 - __builtin_clzll(v);
       }
     }
   }
   // lowest set bit of X (= of |X|)
   int64_t lowset;
   if (z >= 0)
-    lowset = 7ll * (Dmax - z) + __builtin_ctzll(st.gn(Dmax - z));
+    lowset = (int64_t)I8_W * (Dmax - z) + __builtin_ctzll(st.gn(Dmax - z));
   else
     lowset = nbits + __builtin_ctzll((uint64_t)T);
 
-  const int64_t gbase = (int64_t)a.G[i] + (int64_t)a.H[j] - 7ll * (Dmax + 2);
+  const int64_t gbase = (int64_t)a.G[i] + (int64_t)a.H[j] - (int64_t)I8_W * (Dmax + 2);
   const int sx = st.neg ^ negp;  // sign of the product term
   int tie = -1;                   // >= 0: a negligible addend breaks the tie
   if (cnz) {

@@ -16,8 +16,9 @@
 // |x| < 2^(G-1)).
 //
 // In the 3M form (eq. 6) a third plane holds the digits of Re x + Im x, formed
-// exactly from the two signed windows with one shared carry; in the 4M form
-// the B side's third plane holds the digits of -Im x so that
+// exactly from the two signed windows with a carry of its own; in the 4M form
+// the B side's third plane holds the digits of -Im x (its own carry too: the
+// digit range [-2^(w-1), 2^(w-1)) is not symmetric) so that
 // Re(A)Re(B) - Im(A)Im(B) accumulates as a sum (eq. 5).
 //
 // One block handles a 16 x 64 tile (16 rows of the operand, 64 contraction
@@ -109,7 +110,7 @@ struct Layout<double> {
   }
 };
 
-// WC: the digit width when known at compile time (7 for INT8), else 0 (w);
+// WC: the digit width when known at compile time (I8_W for INT8), else 0 (w);
 // TH: the third plane (Third) when known at compile time, else -1 (third).
 // INT8 tiles alternate between two LDS buffers, so one barrier per chunk
 // separates the digit writes of a chunk from their stores, and the stores of
@@ -198,7 +199,10 @@ __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, in
       int64_t v[3];
       v[0] = fre + carry[q][0];
       v[1] = fim + carry[q][1];
-      v[2] = (third == (int)Third::SUM) ? fre + fim + carry[q][2] : 0;
+      // the third plane: Re + Im (3M), or -Im (4M B side) with a carry chain
+      // of its own, since negating a digit of -2^(w-1) would leave the range
+      v[2] = (third == (int)Third::SUM) ? fre + fim + carry[q][2]
+                                        : (third == (int)Third::NEG_IM ? carry[q][2] - fim : 0);
       const bool top = c == 0;  // the chunk holding digit 0, which keeps the remaining value
 #pragma unroll
       for (int j = g - 1; j >= 0; --j) {
@@ -214,7 +218,6 @@ __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, in
           }
           dig[o] = (DT)d;
         }
-        if (third == (int)Third::NEG_IM) dig[2] = (DT)(-dig[1]);
         lds[(0 * g + j) * FRAG + lofs[q]] = dig[0];
         lds[(1 * g + j) * FRAG + lofs[q]] = dig[1];
         if (nops == 3) lds[(2 * g + j) * FRAG + lofs[q]] = dig[2];
@@ -278,7 +281,7 @@ __global__ __launch_bounds__(SPLIT_THREADS) void split_i8_batched(const SplitJob
   const SplitJob& J = jobs[j];
   const int local = blockIdx.x - first[j];
   const int kts = J.Kpad / 64;
-  split_tile<int8_t, ROWCONTIG, 7, -1>(J.op, prec, L, J.S, J.Sp, J.Sstride, J.pad_lo, 7, J.third, J.G, J.Rpad,
+  split_tile<int8_t, ROWCONTIG, I8_W, -1>(J.op, prec, L, J.S, J.Sp, J.Sstride, J.pad_lo, I8_W, J.third, J.G, J.Rpad,
                                        J.Kpad, J.out, status, local % kts, local / kts, lds_raw);
 }
 
@@ -308,13 +311,13 @@ hipError_t launch_split_i8(const DOperand& op, int prec, int L, int S, int Sp, i
                            hipStream_t stream) {
   switch (third) {
     case Third::NONE:
-      return launch_split_t<int8_t, 7, 0>(op, prec, L, S, Sp, Sstride, pad_lo, 7, third, G, Rpad, Kpad, out, status,
+      return launch_split_t<int8_t, I8_W, 0>(op, prec, L, S, Sp, Sstride, pad_lo, I8_W, third, G, Rpad, Kpad, out, status,
                                           stream);
     case Third::SUM:
-      return launch_split_t<int8_t, 7, 1>(op, prec, L, S, Sp, Sstride, pad_lo, 7, third, G, Rpad, Kpad, out, status,
+      return launch_split_t<int8_t, I8_W, 1>(op, prec, L, S, Sp, Sstride, pad_lo, I8_W, third, G, Rpad, Kpad, out, status,
                                           stream);
     default:
-      return launch_split_t<int8_t, 7, 2>(op, prec, L, S, Sp, Sstride, pad_lo, 7, third, G, Rpad, Kpad, out, status,
+      return launch_split_t<int8_t, I8_W, 2>(op, prec, L, S, Sp, Sstride, pad_lo, I8_W, third, G, Rpad, Kpad, out, status,
                                           stream);
   }
 }
@@ -327,7 +330,7 @@ hipError_t launch_split_f64(const DOperand& op, int prec, int L, int S, int Sp, 
 hipError_t launch_split_i8_batched(const SplitJob* jobs, int njobs, const int* first, int blocks, int prec, int L,
                                    bool rows_contiguous, int* status, hipStream_t stream) {
   if (njobs <= 0 || blocks <= 0) return hipSuccess;
-  const size_t lds = (size_t)2 * 3 * (56 / 7) * Layout<int8_t>::FRAG_BYTES;  // two buffers of up to three planes
+  const size_t lds = (size_t)2 * 3 * (56 / I8_W) * Layout<int8_t>::FRAG_BYTES;  // two buffers of up to three planes
   if (rows_contiguous)
     split_i8_batched<true><<<dim3(blocks), dim3(SPLIT_THREADS), lds, stream>>>(jobs, njobs, first, prec, L, status);
   else

@@ -69,7 +69,9 @@ def test_config_2048_p1024_sampled(workload, rows, cols):
     _say(f"  S_A={info['S_A']} S_B={info['S_B']} pairs={info['pairs']} ksplit={info['ksplit']} block={info['block']}")
     _check_sampled(C, ri, ci, s, e, mm, workload)
     if workload == "cgemm2048_p1024_contract60":
-        assert info["S_A"] > 156  # the scaled contraction index widens every row's spread
+        # the scaled contraction index widens every row's spread by 60 bits:
+        # more slices than the 1024 + 3 + 64 bits of the unscaled workload need
+        assert info["S_A"] * info["w"] > 1024 + 3 + 64 + 48
 
 
 def test_config_2048_p1024_4m_and_truncated():
