@@ -154,6 +154,20 @@ typedef struct {
                              batched call, each planned from its own spreads (mp_cgemm_batched).
                              Exact-scheme bits are unchanged; the truncated bound holds per
                              block.  INT8 slices; ignored with max_spread > 0; 0 = off. */
+    int strassen;         /* 1: one level of Strassen's recursion over the slice products
+                             (Algorithm 1 applied to the exactly split operands): the seven
+                             half-size products M1..M7 of the operand quadrants' sums and
+                             differences, each sum formed exactly as it is split into digits,
+                             and the quadrants of C recombined from the products' exact digit
+                             streams before the one rounding, so the bits are those of the
+                             plain product with 7/8 of its slice-pair work at equal slice
+                             counts (the operand sums take one more bit of headroom, and the
+                             rows folded together share a scale, which can add a slice).
+                             Applies to C := AB in the exact scheme with INT8 slices, m, n and k
+                             even, and no max_spread or adaptive option; elsewhere, in batches
+                             and in mp_cgemm_ex_noalloc the plain product runs, as it does when
+                             the half-size product would take more than 4 contraction chunks.
+                             mpcg_info.strassen reports which ran.  0 = off. */
 } mpcg_options;
 
 /* Plan and timing report of one multiplication. */
@@ -164,9 +178,11 @@ typedef struct {
     int nprod;            /* real slice products per slice pair: 4 (4M) or 3 (3M) */
     int ksplit;           /* contraction chunks */
     int block;            /* band width of the INT8 slice GEMM (2 for FP64: pair block) */
-    int reserved;
+    int strassen;         /* levels of Strassen's recursion run: 0 or 1 (the plan fields then
+                             describe each of the seven half-size products) */
     long long pairs;      /* kept slice pairs (s, t) */
-    double algo_ops;      /* 2*m*n*k*pairs*nprod: slice-product operations */
+    double algo_ops;      /* 2*m*n*k*pairs*nprod: slice-product operations (all seven products
+                             with Strassen's recursion) */
     double bound_bits;    /* truncated: error bound exponent (error <= 2^-bound_bits * sum|a||b|) */
 } mpcg_info;
 

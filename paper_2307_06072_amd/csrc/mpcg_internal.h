@@ -87,10 +87,19 @@ enum class Third { NONE = 0, SUM = 1, NEG_IM = 2 };
 hipError_t launch_split_i8(const DOperand& op, int prec, int L, int S, int Sp, int Sstride, int pad_lo,
                            Third third, const int32_t* G, int Rpad, int Kpad, int8_t* out, int* status,
                            hipStream_t stream);
+// The split of op + sign2 * op2 (sign2 = +1 or -1; the same shape and
+// strides), each entry's exact sum digitized with the row scales G, which must
+// leave room for the sum (one more bit than either operand).
+hipError_t launch_split2_i8(const DOperand& op, const DOperand& op2, int sign2, int prec, int L, int S, int Sp,
+                            int Sstride, int pad_lo, Third third, const int32_t* G, int Rpad, int Kpad, int8_t* out,
+                            int* status, hipStream_t stream);
 hipError_t launch_split_f64(const DOperand& op, int prec, int L, int S, int Sp, int w, Third third,
                             const int32_t* G, int Rpad, int Kpad, double* out, int* status,
                             hipStream_t stream);
 
+// Scales of the rows r < half of a one-level Strassen split: G[r] = max(emax
+// of rows r and r + half) + x (0 where both are zero), G[r] = 0 up to Rpad.
+hipError_t launch_fold_scales(const RowStat* stats, int half, int Rpad, int x, int32_t* G, hipStream_t stream);
 // Scale exponents G[r] = emax + x (0 for all-zero rows), r < Rpad.
 hipError_t launch_scales(const RowStat* stats, int R, int Rpad, int x, int32_t* G, hipStream_t stream);
 
@@ -129,8 +138,14 @@ struct GemmF64Args {
 hipError_t launch_gemm_f64(const GemmF64Args& a, hipStream_t stream);
 
 // Merge chunk streams (if ksplit > 1), round to prec, write C.
+constexpr int MAX_MERGE = 16;
+struct MergeSrc {       // one signed digit stream of a merge
+  const uint8_t* dig;   // one contraction chunk's digits, laid out like `digits`
+  const int64_t* top;   // its tops
+  int64_t sign;         // +1 or -1
+};
 struct RoundArgs {
-  const void* digits;  // uint8 (w = 7, INT8 chunked layout) or uint32 (FP64 form) digits
+  const void* digits;  // uint8 (w = 8, INT8 chunked layout) or uint32 (FP64 form) digits
   int digit_bytes;     // 1 or 4
   int nchunk;          // INT8: 16-digit chunks per component
   int f64_layout;      // 1: element (i, j) of a 16x16 tile sits in lane j + 16*(i%4), slot i/4
@@ -145,6 +160,11 @@ struct RoundArgs {
   int64_t ldc;
   int* status;
   int acc;  // 0: C := AB; +1 / -1: C := C + AB / C - AB (INT8 layout only), rounded once
+  // INT8 only, nsrc > 0: the exact integer to round is the signed sum of the
+  // nsrc (<= MAX_MERGE) streams of the device table src, formed into
+  // `digits` (ksplit must be 1): the recombination of Strassen's products
+  int nsrc;
+  const MergeSrc* src;
 };
 hipError_t launch_round(const RoundArgs& a, hipStream_t stream);
 

@@ -129,6 +129,7 @@ struct Plan {
   int want_groups;   // contraction chunks are added until this many work items exist
   int mode_req;      // the caller's form (MPCG_AUTO resolved into mode3m), the tuning cache's key
   int tune_S;        // MPCG_AUTO: the 3M slice count the cache is keyed by (else the plan's own)
+  int extra_x;       // more headroom bits (1 for the operand sums of Strassen's recursion)
   int nchunk;        // INT8: 16-digit chunks per output component
   size_t off_G, off_H, off_X, off_Y, off_dig, off_top, off_lnz, off_scan, total;
 };
@@ -138,7 +139,7 @@ int plan_slices(Plan& P, int spreadA, int spreadB, int hatA, int hatB, const mpc
   // headroom bits above the row maximum: the top digit keeps the remaining
   // value, at most 2^(w - x) (twice that for Re + Im in 3M), which must fit
   // an int8 for the INT8 slices (|d| <= 64 with w = 8 and x = 2 or 3)
-  P.x = P.f64 ? (P.mode3m ? 2 : 1) : (P.mode3m ? 3 : 2);
+  P.x = (P.f64 ? (P.mode3m ? 2 : 1) : (P.mode3m ? 3 : 2)) + P.extra_x;
   P.w = P.f64 ? std::max(1, (53 - ceil_log2(std::max(1, P.k))) / 2) : I8_W;
   if (P.w > 31) P.w = 31;
   P.SA = ceil_div(P.p + P.x + spreadA, P.w);
@@ -441,6 +442,182 @@ int resolve_mode(int mode, int scheme, int m, int n, int k, int p, int spreadA, 
   return MPCG_3M;
 }
 
+// ---------------------------------------------------------------------------
+// One level of Strassen's recursion (Algorithm 1) over the slice products.
+// The operand quadrants' sums and differences are split exactly (one more
+// bit of headroom in the folded row scales), the seven half-size products
+// run as ordinary slice GEMMs, and each quadrant of C is the signed sum of
+// two or four products' exact digit streams, formed in the rounding kernel
+// before the single rounding: the same bits as the plain product.
+// ---------------------------------------------------------------------------
+constexpr int STRASSEN_DECLINED = 1;  // not applicable here: the plain product runs
+
+DOperand quad(const DOperand& op, int br, int bk, int hR, int hK) {
+  DOperand q = op;
+  const int64_t off = (int64_t)br * hR * op.rs + (int64_t)bk * hK * op.ks;
+  q.re.sign += off; q.re.exp += off; q.re.mant += off;
+  q.im.sign += off; q.im.exp += off; q.im.mant += off;
+  q.R = hR;
+  q.K = hK;
+  return q;
+}
+
+DOutPart quad_out(const DOutPart& c, int64_t off) {
+  DOutPart q = c;
+  q.sign += off; q.exp += off; q.mant += off;
+  return q;
+}
+
+// Largest spread of the folded rows (r with r + half): -1 if all are zero.
+int folded_spread(const std::vector<RowStat>& st, int half) {
+  int spread = -1;
+  for (int r = 0; r < half; ++r) {
+    int32_t hi = INT32_MIN, lo = INT32_MAX;
+    for (const RowStat& x : {st[r], st[r + half]})
+      if (x.emax != EXP_ZERO) {
+        hi = std::max(hi, x.emax);
+        lo = std::min(lo, x.emin);
+      }
+    if (hi != INT32_MIN) spread = std::max(spread, hi - lo);
+  }
+  return spread;
+}
+
+int run_strassen(int m, int n, int k, const DOperand& opA, const DOperand& opB, int prec_bits, int mode3m,
+                 int mode_req, const mpcg_options* opt, mpcg_info* info, const RowStat* statA, const RowStat* statB,
+                 const DOutPart& cre, const DOutPart& cim, int64_t ldc) {
+  const int hm = m / 2, hn = n / 2, hk = k / 2;
+  const int L = (prec_bits + 63) / 64;
+  std::vector<RowStat> hA(m), hB(n);
+  HIP_TRY(hipMemcpyAsync(hA.data(), statA, sizeof(RowStat) * m, hipMemcpyDeviceToHost, g_stream));
+  HIP_TRY(hipMemcpyAsync(hB.data(), statB, sizeof(RowStat) * n, hipMemcpyDeviceToHost, g_stream));
+  HIP_TRY(hipStreamSynchronize(g_stream));
+  const int spA = folded_spread(hA, hm), spB = folded_spread(hB, hn);
+  if (spA < 0 || spB < 0) return STRASSEN_DECLINED;
+  Plan Q{};
+  Q.m = hm; Q.n = hn; Q.k = hk; Q.p = prec_bits;
+  Q.mode_req = mode_req;
+  Q.mode3m = mode3m;
+  Q.trunc = 0;
+  Q.f64 = 0;
+  Q.want_groups = 512;
+  Q.extra_x = 1;
+  int st;
+  if ((st = plan_slices(Q, spA, spB, spA, spB, opt))) return st;
+  if ((st = plan_layout(Q, opt))) return st;
+  if (4 * Q.ksplit > MAX_MERGE) return STRASSEN_DECLINED;
+  const size_t stride = align256(Q.total);
+  const size_t tiles = (size_t)Q.mt * Q.nt;
+  const size_t qbytes = align256(tiles * 8 * Q.nchunk * 1024);  // one quadrant's recombined digits
+  void* ws = nullptr;
+  if ((st = ensure_workspace(7 * stride + 4 * qbytes + align256(sizeof(MergeSrc) * 4 * MAX_MERGE), &ws))) return st;
+  char* base = static_cast<char*>(ws);
+  int32_t* G = reinterpret_cast<int32_t*>(base + Q.off_G);
+  int32_t* H = reinterpret_cast<int32_t*>(base + Q.off_H);
+  HIP_TRY(launch_fold_scales(statA, hm, Q.mpad, Q.x, G, g_stream));
+  HIP_TRY(launch_fold_scales(statB, hn, Q.npad, Q.x, H, g_stream));
+  // quadrants: A_ij = rows block i, k block j; B_ij = k block i, column block j
+  auto Aq = [&](int i, int j) { return quad(opA, i, j, hm, hk); };
+  auto Bq = [&](int i, int j) { return quad(opB, j, i, hn, hk); };
+  struct Side { DOperand x, y; int sign; };
+  struct Prod { Side a, b; };
+  const Prod prods[7] = {
+      {{Aq(0, 0), Aq(1, 1), +1}, {Bq(0, 0), Bq(1, 1), +1}},  // M1 = (A11 + A22)(B11 + B22)
+      {{Aq(1, 0), Aq(1, 1), +1}, {Bq(0, 0), Bq(0, 0), 0}},   // M2 = (A21 + A22) B11
+      {{Aq(0, 0), Aq(0, 0), 0}, {Bq(0, 1), Bq(1, 1), -1}},   // M3 = A11 (B12 - B22)
+      {{Aq(1, 1), Aq(1, 1), 0}, {Bq(1, 0), Bq(0, 0), -1}},   // M4 = A22 (B21 - B11)
+      {{Aq(0, 0), Aq(0, 1), +1}, {Bq(1, 1), Bq(1, 1), 0}},   // M5 = (A11 + A12) B22
+      {{Aq(1, 0), Aq(0, 0), -1}, {Bq(0, 0), Bq(0, 1), +1}},  // M6 = (A21 - A11)(B11 + B12)
+      {{Aq(0, 1), Aq(1, 1), -1}, {Bq(1, 0), Bq(1, 1), +1}},  // M7 = (A12 - A22)(B21 + B22)
+  };
+  const Third thirdA = Q.mode3m ? Third::SUM : Third::NONE;
+  const Third thirdB = Q.mode3m ? Third::SUM : Third::NEG_IM;
+  for (int j = 0; j < 7; ++j) {
+    char* pb = base + j * stride;
+    int8_t* X = reinterpret_cast<int8_t*>(pb + Q.off_X);
+    int8_t* Y = reinterpret_cast<int8_t*>(pb + Q.off_Y);
+    const Prod& P = prods[j];
+    if (P.a.sign)
+      HIP_TRY(launch_split2_i8(P.a.x, P.a.y, P.a.sign, prec_bits, L, Q.SA, Q.SAp, Q.xs, Q.xlo, thirdA, G, Q.mpad,
+                               Q.kpad, X, g_status, g_stream));
+    else
+      HIP_TRY(launch_split_i8(P.a.x, prec_bits, L, Q.SA, Q.SAp, Q.xs, Q.xlo, thirdA, G, Q.mpad, Q.kpad, X, g_status,
+                              g_stream));
+    if (P.b.sign)
+      HIP_TRY(launch_split2_i8(P.b.x, P.b.y, P.b.sign, prec_bits, L, Q.SB, Q.SBp, Q.ys, Q.ylo, thirdB, H, Q.npad,
+                               Q.kpad, Y, g_status, g_stream));
+    else
+      HIP_TRY(launch_split_i8(P.b.x, prec_bits, L, Q.SB, Q.SBp, Q.ys, Q.ylo, thirdB, H, Q.npad, Q.kpad, Y, g_status,
+                              g_stream));
+  }
+  if ((st = record(2))) return st;
+  for (int j = 0; j < 7; ++j) {
+    char* pb = base + j * stride;
+    GemmArgs ga{};
+    ga.X = reinterpret_cast<const int8_t*>(pb + Q.off_X);
+    ga.Y = reinterpret_cast<const int8_t*>(pb + Q.off_Y);
+    ga.mt = Q.mt; ga.nt = Q.nt; ga.kblocks = Q.kblocks; ga.ksplit = Q.ksplit;
+    ga.SAp = Q.SAp; ga.SBp = Q.SBp; ga.Dmax = Q.Dmax; ga.mode3m = Q.mode3m;
+    ga.digits = pb + Q.off_dig;
+    ga.top = reinterpret_cast<int64_t*>(pb + Q.off_top);
+    ga.lnz = reinterpret_cast<int32_t*>(pb + Q.off_lnz);
+    ga.xs = Q.xs; ga.ys = Q.ys; ga.xlo = Q.xlo; ga.ylo = Q.ylo;
+    HIP_TRY(launch_gemm_i8(ga, Q.block, g_stream));
+  }
+  if ((st = record(3))) return st;
+  // C11 = M1 + M4 - M5 + M7, C12 = M3 + M5, C21 = M2 + M4, C22 = M1 - M2 + M3 + M6
+  struct Term { int prod, sign; };
+  const std::vector<Term> terms[4] = {{{0, +1}, {3, +1}, {4, -1}, {6, +1}},
+                                      {{2, +1}, {4, +1}},
+                                      {{1, +1}, {3, +1}},
+                                      {{0, +1}, {1, -1}, {2, +1}, {5, +1}}};
+  const size_t sstride = tiles * 8 * Q.nchunk * 1024;  // one contraction chunk's digits
+  char* merged = base + 7 * stride;
+  MergeSrc* srcdev = reinterpret_cast<MergeSrc*>(base + 7 * stride + 4 * qbytes);
+  MergeSrc srcs[4][MAX_MERGE] = {};
+  int nsrc[4] = {0, 0, 0, 0};
+  for (int qd = 0; qd < 4; ++qd)
+    for (const Term& t : terms[qd])
+      for (int c = 0; c < Q.ksplit; ++c) {
+        char* pb = base + t.prod * stride;
+        MergeSrc& ms = srcs[qd][nsrc[qd]++];
+        ms.dig = reinterpret_cast<const uint8_t*>(pb + Q.off_dig) + c * sstride;
+        ms.top = reinterpret_cast<const int64_t*>(pb + Q.off_top) + (size_t)c * tiles * 512;
+        ms.sign = t.sign;
+      }
+  HIP_TRY(launch_store_words(srcdev, srcs, sizeof(srcs), g_stream));
+  for (int qd = 0; qd < 4; ++qd) {
+    const int qr = qd >> 1, qc = qd & 1;
+    RoundArgs ra{};
+    ra.digits = merged + qd * qbytes;
+    ra.digit_bytes = 1;
+    ra.nchunk = Q.nchunk;
+    ra.f64_layout = 0;
+    ra.ksplit = 1; ra.mt = Q.mt; ra.nt = Q.nt; ra.Dmax = Q.Dmax; ra.w = Q.w;
+    ra.G = G; ra.H = H; ra.m = hm; ra.n = hn; ra.prec = prec_bits; ra.L = L;
+    const int64_t off = (int64_t)qc * hn * ldc + (int64_t)qr * hm;
+    ra.cre = quad_out(cre, off);
+    ra.cim = quad_out(cim, off);
+    ra.ldc = ldc;
+    ra.status = g_status;
+    ra.acc = 0;
+    ra.nsrc = nsrc[qd];
+    ra.src = srcdev + qd * MAX_MERGE;
+    ra.top = srcs[qd][0].top;  // not read when nsrc > 0
+    ra.lnz = reinterpret_cast<const int32_t*>(base + Q.off_lnz);
+    HIP_TRY(launch_round(ra, g_stream));
+  }
+  if ((st = record(4))) return st;
+  if (info) {
+    info->S_A = Q.SA; info->S_B = Q.SB; info->w = Q.w; info->cutoff = Q.cutoff;
+    info->nprod = Q.mode3m ? 3 : 4; info->ksplit = Q.ksplit; info->block = Q.block;
+    info->pairs = Q.pairs; info->algo_ops = 7 * Q.algo_ops; info->bound_bits = 0;
+    info->strassen = 1;
+  }
+  g_timing_valid = g_timing;
+  return MPCG_OK;
+}
+
 // Device memory of a call that must not allocate: the status word and one
 // region that holds the exponent scan and then the workspace.
 struct FixedBuffers {
@@ -574,6 +751,10 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
     }
     P.mode3m = resolve_mode(mode, scheme, m, n, k, prec_bits, sa.spread, sb.spread) == MPCG_3M;
     P.tune_S = mode == MPCG_AUTO ? auto_key_S(prec_bits, sa.spread, sb.spread) : 0;
+    if (opt && opt->strassen && !P.f64 && !acc && !P.trunc && !fixed && m % 2 == 0 && n % 2 == 0 && k % 2 == 0) {
+      st = run_strassen(m, n, k, opA, opB, prec_bits, P.mode3m, mode, opt, info, statA, statB, cre, cim, ldc);
+      if (st != STRASSEN_DECLINED) return st;
+    }
     if ((st = plan_slices(P, sa.spread, sb.spread, sa.hat, sb.hat, opt))) return st;
     if ((st = plan_layout(P, opt))) return st;
     if (fixed) {

@@ -827,7 +827,42 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
 
   int64_t T;
   int z;
-  if (a.ksplit == 1) {
+  if (a.nsrc > 0) {
+    // the signed sum of the source streams, least significant digit first, 16
+    // digits at a time, written to this element's digits
+    const size_t eo = ((size_t)tile * 8 + slot) * a.nchunk * 1024 + (size_t)lane * 16;
+    int64_t c = 0;
+    int qz = -1;
+    const int nq = Dmax + 1;
+    for (int ch = 0; ch * 16 < nq; ++ch) {
+      uint32_t out[4] = {0, 0, 0, 0};
+      int32_t sum[16];
+#pragma unroll
+      for (int b = 0; b < 16; ++b) sum[b] = 0;
+      for (int q = 0; q < a.nsrc; ++q) {
+        const uint4 v = *reinterpret_cast<const uint4*>(a.src[q].dig + eo + (size_t)ch * 1024);
+        const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+        const int sg = (int)a.src[q].sign;
+#pragma unroll
+        for (int b = 0; b < 16; ++b) sum[b] += sg * (int32_t)((wv[b >> 2] >> (8 * (b & 3))) & 255u);
+      }
+#pragma unroll
+      for (int b = 0; b < 16; ++b) {
+        const int qq = ch * 16 + b;
+        if (qq < nq) {
+          const int64_t sv = c + sum[b];
+          const uint32_t dg = (uint32_t)(sv & (DFULL - 1));
+          c = sv >> I8_W;
+          out[b >> 2] |= dg << (8 * (b & 3));
+          if (dg && qz < 0) qz = qq;
+        }
+      }
+      *reinterpret_cast<uint4*>(g0 + (size_t)ch * 1024) = make_uint4(out[0], out[1], out[2], out[3]);
+    }
+    z = qz < 0 ? -1 : Dmax - qz;
+    T = c;
+    for (int q = 0; q < a.nsrc; ++q) T += a.src[q].sign * a.src[q].top[tb0];
+  } else if (a.ksplit == 1) {
     T = a.top[tb0];
     z = a.lnz[tb0];
   } else {

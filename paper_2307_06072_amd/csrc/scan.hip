@@ -187,6 +187,22 @@ __global__ __launch_bounds__(256) void scales_kernel(const RowStat* stats, int R
   scales_body(stats, R, Rpad, x, G, blockIdx.x);
 }
 
+// Scales of the folded rows of one level of Strassen's recursion: row r < half
+// of every operand combination mixes rows r and r + half, whose exponents all
+// lie below max(emax) (one bit more for a sum); 0 where both are zero.
+__global__ __launch_bounds__(256) void fold_scales_kernel(const RowStat* stats, int half, int Rpad, int x,
+                                                          int32_t* G) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= Rpad) return;
+  int32_t g = 0;
+  if (r < half) {
+    const int32_t a = stats[r].emax, b = stats[r + half].emax;
+    const int32_t e = a == INT32_MIN ? b : (b == INT32_MIN ? a : (a > b ? a : b));
+    g = e == INT32_MIN ? 0 : e + x;
+  }
+  G[r] = g;
+}
+
 // ---- batched forms ----------------------------------------------------------
 __global__ __launch_bounds__(256) void stats_init_batched(const ScanJob* __restrict__ jobs, int njobs,
                                                           const int* __restrict__ first) {
@@ -276,6 +292,11 @@ hipError_t launch_scan_batched(const ScanJob* jobs, int njobs, const int* first_
       scan_batched<false><<<dim3(scan_blocks_total), dim3(256), 0, stream>>>(jobs, njobs, first_scan);
   }
   summary_batched<<<dim3(njobs), dim3(256), 0, stream>>>(jobs, limit, status_word);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_scales(const RowStat* stats, int half, int Rpad, int x, int32_t* G, hipStream_t stream) {
+  fold_scales_kernel<<<dim3((Rpad + 255) / 256), dim3(256), 0, stream>>>(stats, half, Rpad, x, G);
   return hipGetLastError();
 }
 

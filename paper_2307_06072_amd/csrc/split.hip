@@ -115,10 +115,13 @@ struct Layout<double> {
 // INT8 tiles alternate between two LDS buffers, so one barrier per chunk
 // separates the digit writes of a chunk from their stores, and the stores of
 // a chunk from the writes two chunks later.
-template <typename DT, bool ROWCONTIG, int WC, int TH>
+// TWO: the operand split is op + sign2 * op2 (two operands of the same shape,
+// each entry's exact sum formed in the windows; the scales G must cover it).
+template <typename DT, bool ROWCONTIG, int WC, int TH, bool TWO = false>
 __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, int Sp, int Sstride, int pad_lo,
                                   int w_rt, int third_rt, const int32_t* __restrict__ G, int Rpad, int Kpad,
-                                  DT* __restrict__ out, int* status, int kt, int rt, unsigned char* lds_raw) {
+                                  DT* __restrict__ out, int* status, int kt, int rt, unsigned char* lds_raw,
+                                  const DOperand* op2 = nullptr, int sign2 = 0) {
   constexpr int FRAG = Layout<DT>::FRAG_BYTES / (int)sizeof(DT);  // elements per (op, digit) tile
   constexpr int NBUF = sizeof(DT) == 1 ? 2 : 1;
 
@@ -130,10 +133,10 @@ __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, in
   const uint64_t low_mask = ~((1ull << (64 * L - prec)) - 1ull) | (64 * L - prec == 0 ? ~0ull : 0ull);
   const int64_t wS = (int64_t)w * S;
 
-  Entry e[EPT];
+  Entry e[EPT], e2[TWO ? EPT : 1];
   int lofs[EPT];
   int bad = 0;
-  LimbStream sre[EPT], sim[EPT];
+  LimbStream sre[EPT], sim[EPT], sre2[TWO ? EPT : 1], sim2[TWO ? EPT : 1];
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
     int rl, kl;
@@ -150,22 +153,30 @@ __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, in
     e[q].neg_re = e[q].neg_im = 0;
     e[q].sh_re = e[q].sh_im = 0;
     e[q].idx = 0;
-    if (r < op.R && kk < op.K) {
-      const int64_t idx = (int64_t)r * op.rs + (int64_t)kk * op.ks;
-      e[q].idx = idx;
-      const int64_t base = (int64_t)G[r] - wS + 64 * (int64_t)L;  // sh = exp - base
-      const int32_t er = op.re.exp[idx], ei = op.im.exp[idx];
-      if (er != EXP_ZERO) {
-        e[q].z_re = 0;
-        e[q].neg_re = op.re.sign[idx] ? 1 : 0;
-        e[q].sh_re = (int64_t)er - base;
+    auto fill = [&](const DOperand& o, Entry& en, int flip) {
+      en.z_re = en.z_im = 1;
+      en.neg_re = en.neg_im = 0;
+      en.sh_re = en.sh_im = 0;
+      en.idx = 0;
+      if (r < o.R && kk < o.K) {
+        const int64_t idx = (int64_t)r * o.rs + (int64_t)kk * o.ks;
+        en.idx = idx;
+        const int64_t base = (int64_t)G[r] - wS + 64 * (int64_t)L;  // sh = exp - base
+        const int32_t er = o.re.exp[idx], ei = o.im.exp[idx];
+        if (er != EXP_ZERO) {
+          en.z_re = 0;
+          en.neg_re = (o.re.sign[idx] ? 1 : 0) ^ flip;
+          en.sh_re = (int64_t)er - base;
+        }
+        if (ei != EXP_ZERO) {
+          en.z_im = 0;
+          en.neg_im = (o.im.sign[idx] ? 1 : 0) ^ flip;
+          en.sh_im = (int64_t)ei - base;
+        }
       }
-      if (ei != EXP_ZERO) {
-        e[q].z_im = 0;
-        e[q].neg_im = op.im.sign[idx] ? 1 : 0;
-        e[q].sh_im = (int64_t)ei - base;
-      }
-    }
+    };
+    fill(op, e[q], 0);
+    if (TWO) fill(*op2, e2[q], sign2 < 0 ? 1 : 0);
   }
 
   const int64_t half = 1ll << (w - 1);
@@ -183,6 +194,12 @@ __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, in
     for (int q = 0; q < EPT; ++q) {
       sre[q].start(e[q].z_re ? nullptr : op.re.mant + e[q].idx, op.re.ls, f0 - e[q].sh_re, L, low_mask, bad);
       sim[q].start(e[q].z_im ? nullptr : op.im.mant + e[q].idx, op.im.ls, f0 - e[q].sh_im, L, low_mask, bad);
+      if (TWO) {
+        sre2[q].start(e2[q].z_re ? nullptr : op2->re.mant + e2[q].idx, op2->re.ls, f0 - e2[q].sh_re, L, low_mask,
+                      bad);
+        sim2[q].start(e2[q].z_im ? nullptr : op2->im.mant + e2[q].idx, op2->im.ls, f0 - e2[q].sh_im, L, low_mask,
+                      bad);
+      }
     }
   }
   const int buf_bytes = nops * g * Layout<DT>::FRAG_BYTES;
@@ -196,6 +213,12 @@ __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, in
       int64_t fim = (int64_t)(sim[q].window56(op.im.ls, fstart - e[q].sh_im, L, low_mask, bad) & wmask);
       if (e[q].neg_re) fre = -fre;
       if (e[q].neg_im) fim = -fim;
+      if (TWO) {  // the second operand's windows, signed (sign2 folded into neg)
+        int64_t gre = (int64_t)(sre2[q].window56(op2->re.ls, fstart - e2[q].sh_re, L, low_mask, bad) & wmask);
+        int64_t gim = (int64_t)(sim2[q].window56(op2->im.ls, fstart - e2[q].sh_im, L, low_mask, bad) & wmask);
+        fre += e2[q].neg_re ? -gre : gre;
+        fim += e2[q].neg_im ? -gim : gim;
+      }
       int64_t v[3];
       v[0] = fre + carry[q][0];
       v[1] = fim + carry[q][1];
@@ -271,6 +294,17 @@ __global__ __launch_bounds__(SPLIT_THREADS) void split_kernel(DOperand op, int p
                                     blockIdx.x, blockIdx.y, lds_raw);
 }
 
+// INT8 split of op + sign2 * op2.
+template <bool ROWCONTIG, int TH>
+__global__ __launch_bounds__(SPLIT_THREADS) void split2_kernel(DOperand op, DOperand op2, int sign2, int prec, int L,
+                                                     int S, int Sp, int Sstride, int pad_lo,
+                                                     const int32_t* __restrict__ G, int Rpad, int Kpad,
+                                                     int8_t* __restrict__ out, int* status) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  split_tile<int8_t, ROWCONTIG, I8_W, TH, true>(op, prec, L, S, Sp, Sstride, pad_lo, I8_W, TH, G, Rpad, Kpad, out,
+                                                 status, blockIdx.x, blockIdx.y, lds_raw, &op2, sign2);
+}
+
 // Batched INT8 form: job j owns (Kpad/64) * (Rpad/16) blocks.
 template <bool ROWCONTIG>
 __global__ __launch_bounds__(SPLIT_THREADS) void split_i8_batched(const SplitJob* __restrict__ jobs, int njobs,
@@ -320,6 +354,31 @@ hipError_t launch_split_i8(const DOperand& op, int prec, int L, int S, int Sp, i
       return launch_split_t<int8_t, I8_W, 2>(op, prec, L, S, Sp, Sstride, pad_lo, I8_W, third, G, Rpad, Kpad, out, status,
                                           stream);
   }
+}
+
+hipError_t launch_split2_i8(const DOperand& op, const DOperand& op2, int sign2, int prec, int L, int S, int Sp,
+                            int Sstride, int pad_lo, Third third, const int32_t* G, int Rpad, int Kpad, int8_t* out,
+                            int* status, hipStream_t stream) {
+  const int nops = third == Third::NONE ? 2 : 3;
+  const size_t lds = (size_t)2 * nops * (56 / I8_W) * Layout<int8_t>::FRAG_BYTES;
+  dim3 grid(Kpad / 64, Rpad / 16);
+  const bool rc = op.rs == 1;
+#define MPCG_SPLIT2(RC, T)                                                                                      \
+  split2_kernel<RC, T><<<grid, dim3(SPLIT_THREADS), lds, stream>>>(op, op2, sign2, prec, L, S, Sp, Sstride, pad_lo, \
+                                                                   G, Rpad, Kpad, out, status)
+  switch (third) {
+    case Third::NONE:
+      if (rc) MPCG_SPLIT2(true, 0); else MPCG_SPLIT2(false, 0);
+      break;
+    case Third::SUM:
+      if (rc) MPCG_SPLIT2(true, 1); else MPCG_SPLIT2(false, 1);
+      break;
+    default:
+      if (rc) MPCG_SPLIT2(true, 2); else MPCG_SPLIT2(false, 2);
+      break;
+  }
+#undef MPCG_SPLIT2
+  return hipGetLastError();
 }
 
 hipError_t launch_split_f64(const DOperand& op, int prec, int L, int S, int Sp, int w, Third third,
