@@ -31,6 +31,7 @@ METRIC = "MP complex GEMM 8mnk/s at 256/1024-bit; INT8-3M vs FP64-4M Ozaki speed
 PEAK_INT8_TOPS = 5000.0   # MI355X dense INT8 matrix peak, TOP/s
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 matrix peak, TFLOP/s
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E, GB/s
+M3_MODE = 1
 
 
 def log(msg: str) -> None:
@@ -52,21 +53,23 @@ def _slice(s):
     return {"int8": mp.MPCG_SLICE_INT8, "fp64": mp.MPCG_SLICE_FP64}[s]
 
 
-def time_calls(dA, dB, dC, m, n, k, p, mode, scheme, slice_type, steps, warmup):
+def time_calls(dA, dB, dC, m, n, k, p, mode, scheme, slice_type, steps, warmup, strassen=0):
     """Warm up, then time `steps` whole calls; returns (seconds, info, avg stage us)."""
     import torch
     import paper_2307_06072_amd as mp
     mp.mpcg_set_stream()
     info = None
     for _ in range(warmup):
-        info = mp.mp_cgemm_ex(m, n, k, dA, dA.ld, dB, dB.ld, dC, dC.ld, p, mode, scheme, slice_type=slice_type)
+        info = mp.mp_cgemm_ex(m, n, k, dA, dA.ld, dB, dB.ld, dC, dC.ld, p, mode, scheme, slice_type=slice_type,
+                              strassen=strassen)
     torch.cuda.synchronize()
     mp.mpcg_enable_timing(True)
     mp.mpcg_timing_report()  # start a fresh collection
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        info = mp.mp_cgemm_ex(m, n, k, dA, dA.ld, dB, dB.ld, dC, dC.ld, p, mode, scheme, slice_type=slice_type)
+        info = mp.mp_cgemm_ex(m, n, k, dA, dA.ld, dB, dB.ld, dC, dC.ld, p, mode, scheme, slice_type=slice_type,
+                              strassen=strassen)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     us_sum, ncalls = mp.mpcg_timing_report()
@@ -79,30 +82,36 @@ def time_calls(dA, dB, dC, m, n, k, p, mode, scheme, slice_type, steps, warmup):
 
 
 def stage_bytes(m, n, k, p, info, mode3m, slice_fp64):
-    """Algorithmic HBM bytes of the split and round stages (per call)."""
+    """Algorithmic HBM bytes of the split and round stages (per call).  With
+    one level of Strassen's recursion the split reads 12 operand quadrants per
+    side (three whole operands) and writes 7 quarter-size slice sets, and the
+    rounding reads 12 quarter-size product streams (three whole ones) per
+    contraction chunk."""
     L = (p + 63) // 64
     esz = 8 if slice_fp64 else 1
     ent_in = 2 * (8 * L + 5)  # Re + Im: limbs, exponent, sign
     nops_a = 3 if mode3m else 2
     nops_b = 3
-    split = (m * k + k * n) * ent_in + (m * k * nops_a * info["S_A"] + k * n * nops_b * info["S_B"]) * esz
+    rd, wr = (3.0, 7.0 / 4.0) if info.get("strassen") else (1.0, 1.0)
+    split = (m * k + k * n) * ent_in * rd + (m * k * nops_a * info["S_A"] + k * n * nops_b * info["S_B"]) * esz * wr
     nd = info["cutoff"] + 1
     dig = 4 if slice_fp64 else 1
-    rnd = m * n * 2 * (nd * dig * info["ksplit"] + 12) + m * n * ent_in
+    rnd = m * n * 2 * (nd * dig * info["ksplit"] + 12) * rd + m * n * ent_in
     return split, rnd
 
 
-def traffic_record(kernel_src: str):
-    """HBM traffic of the slice GEMM from committed rocprofv3 counters, if they
-    were taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "gemm_i8_traffic.json")
+def traffic_record(kernel_src: str, form: str):
+    """HBM traffic per launch of the slice GEMM from committed rocprofv3
+    counters, if they were taken on the current kernel source in this form
+    ("plain" or "strassen1", whose launches are half-size products), else None."""
+    path = os.path.join(ROOT, "profiles", f"gemm_i8_traffic_{form}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
     with open(kernel_src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
-    if rec.get("source_sha256") != sha:
+    if rec.get("source_sha256") != sha or rec.get("form") != form:
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -617,6 +626,8 @@ def main() -> int:
     ap.add_argument("--mode", default="3M", choices=["3M", "4M"])
     ap.add_argument("--scheme", default="exact", choices=["exact", "truncated"])
     ap.add_argument("--slice", default="int8", choices=["int8", "fp64"])
+    ap.add_argument("--strassen", type=int, default=1, choices=[0, 1],
+                    help="one level of Strassen's recursion over the slice products (same bits; INT8 exact)")
     ap.add_argument("--no-extras", action="store_true", help="skip the comparison family")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -666,7 +677,9 @@ def main() -> int:
     torch.cuda.synchronize()
     mode, scheme, sl = _mode(args.mode), _scheme(args.scheme), _slice(args.slice)
     log(f"timing {args.steps} steps after {args.warmup} warmup ({args.slice} {args.mode} {args.scheme})")
-    dt, info, stages = time_calls(dA, dB, dC, m, n, k, p, mode, scheme, sl, args.steps, args.warmup)
+    dt, info, stages = time_calls(dA, dB, dC, m, n, k, p, mode, scheme, sl, args.steps, args.warmup,
+                                  strassen=args.strassen)
+    launches = 7 if info["strassen"] else 1  # slice GEMM launches per call
     ms = 1000.0 * dt / args.steps
     value = 8.0 * m * n * k * args.steps / dt
     log(f"{ms:.3f} ms/step, {value:.4e} 8mnk/s; stages us {['%.1f' % s for s in stages]}")
@@ -680,9 +693,11 @@ def main() -> int:
         peak, unit = PEAK_FP64_TFLOPS, "TFLOP/s"
     src = os.path.join(ROOT, "paper_2307_06072_amd", "csrc", "gemm_i8.hip")
     roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
-            "traffic": traffic_record(src) if args.slice == "int8" else None,
+            "traffic": (traffic_record(src, "strassen1" if info["strassen"] else "plain")
+                        if args.slice == "int8" else None),
             "kernel": "gemm_i8_kernel (slice-pair GEMM + carry chain)" if args.slice == "int8"
-            else "gemm_f64_kernel", "algo_ops_per_launch": info["algo_ops"], "avg_launch_us": gemm_us}
+            else "gemm_f64_kernel", "launches_per_step": launches,
+            "algo_ops_per_launch": info["algo_ops"] / launches, "avg_launch_us": gemm_us / launches}
     split_b, round_b = stage_bytes(m, n, k, p, info, args.mode == "3M", args.slice == "fp64")
     stage_report = {
         "scan_us": stages[0], "split_us": stages[1], "gemm_us": stages[2], "round_us": stages[3],
@@ -710,18 +725,46 @@ def main() -> int:
                         "gemm_us": st2[2], "gemm_frac_of_peak": info2["algo_ops"] / (st2[2] * 1e-6) / 1e12 / peak2,
                         "S_A": info2["S_A"], "cutoff": info2["cutoff"], "pairs": info2["pairs"]}
             log(f"  {key}: {fam[key]['ms_per_call']:.3f} ms")
+        dt2, info2, st2 = time_calls(dA2, dB2, dC2, m2, n2, k2, p2, M3_MODE, 0, 0, steps=5, warmup=1, strassen=1)
+        fam["int8_3M_exact_strassen"] = {"ms_per_call": 1000 * dt2 / 5, "8mnk_per_s": 8.0 * m2 * n2 * k2 * 5 / dt2,
+                                         "gemm_us": st2[2], "strassen": info2["strassen"],
+                                         "gemm_frac_of_peak": info2["algo_ops"] / (st2[2] * 1e-6) / 1e12 /
+                                         PEAK_INT8_TOPS}
+        log(f"  int8_3M_exact_strassen: {fam['int8_3M_exact_strassen']['ms_per_call']:.3f} ms")
         fam["speedup_int8_3m_over_fp64_4m_exact"] = fam["fp64_4M_exact"]["ms_per_call"] / fam["int8_3M_exact"]["ms_per_call"]
         fam["speedup_int8_3m_over_fp64_4m_truncated"] = (fam["fp64_4M_truncated"]["ms_per_call"] /
                                                          fam["int8_3M_truncated"]["ms_per_call"])
         extra["cgemm512_p512"] = fam
         del dA2, dB2, dC2
         if args.workload == "cgemm2048_p1024" and args.scheme == "exact":
+            other = 1 - args.strassen
+            log(f"default workload, strassen={other}")
+            dto, infoo, sto = time_calls(dA, dB, dC, m, n, k, p, mode, scheme, sl, steps=2, warmup=1, strassen=other)
+            extra[f"cgemm2048_p1024_strassen{other}"] = {
+                "ms_per_call": 1000 * dto / 2, "8mnk_per_s": 8.0 * m * n * k * 2 / dto, "strassen": infoo["strassen"],
+                "stage_us": sto, "ksplit": infoo["ksplit"], "block": infoo["block"],
+                "gemm_frac_of_peak": infoo["algo_ops"] / (sto[2] * 1e-6) / 1e12 / PEAK_INT8_TOPS}
             extra.update(adaptive_case(A, B, p))
             log("default workload, truncated scheme")
             dtt, infot, stt = time_calls(dA, dB, dC, m, n, k, p, mode, _scheme("truncated"), sl, steps=2, warmup=1)
             extra["cgemm2048_p1024_truncated"] = {"ms_per_call": 1000 * dtt / 2, "8mnk_per_s": 8.0 * m * n * k * 2 / dtt,
                                                   "cutoff": infot["cutoff"], "pairs": infot["pairs"],
                                                   "gemm_frac_of_peak": infot["algo_ops"] / (stt[2] * 1e-6) / 1e12 / PEAK_INT8_TOPS}
+
+    if not args.no_extras and args.workload == "cgemm2048_p1024":
+        del dA, dB, dC
+        for variant in ("cgemm2048_p1024_rowcol60", "cgemm2048_p1024_contract60"):
+            log(f"{variant}: generating and timing")
+            mv, nv, kv, pv, Av, Bv = workload_inputs(variant)
+            dAv, dBv = mp.to_device(Av), mp.to_device(Bv)
+            dCv = mp.device_empty(mv, nv, pv)
+            dtv, infov, stv = time_calls(dAv, dBv, dCv, mv, nv, kv, pv, mode, scheme, sl, steps=2, warmup=1,
+                                         strassen=args.strassen)
+            extra[variant] = {"ms_per_call": 1000 * dtv / 2, "8mnk_per_s": 8.0 * mv * nv * kv * 2 / dtv,
+                              "S_A": infov["S_A"], "S_B": infov["S_B"], "pairs": infov["pairs"],
+                              "strassen": infov["strassen"], "stage_us": stv,
+                              "gemm_frac_of_peak": infov["algo_ops"] / (stv[2] * 1e-6) / 1e12 / PEAK_INT8_TOPS}
+            del dAv, dBv, dCv, Av, Bv
 
     if not args.no_extras:
         extra.update(small_latency_case())
@@ -741,7 +784,7 @@ def main() -> int:
         "config": {"workload": f"{args.workload} {args.slice.upper()}-{args.mode} {args.scheme}", "m": m, "n": n,
                    "k": k, "prec_bits": p, "mode": args.mode, "scheme": args.scheme, "slice": args.slice,
                    "S_A": info["S_A"], "S_B": info["S_B"], "cutoff": info["cutoff"], "pairs": info["pairs"],
-                   "ksplit": info["ksplit"], "block": info["block"]},
+                   "ksplit": info["ksplit"], "block": info["block"], "strassen_levels": info["strassen"]},
         "roofline": roof,
         "cpu_baseline": cpu,
         "stages": stage_report,
