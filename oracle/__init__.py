@@ -54,9 +54,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        override = os.environ.get("ORACLE_LIBRARY")  # another build, e.g. one with sanitizers
+        if not override and (not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
             build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(override or _LIB)
         vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
         L.oracle_cgemm.argtypes = [i32, i32, i32, vp, i64, vp, i64, vp, i64, i32, i32, i32]
         L.oracle_cgemm.restype = i32

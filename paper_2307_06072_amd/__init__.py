@@ -15,7 +15,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmpcgemm.so")
+LIB_PATH = os.environ.get("MPCG_LIBRARY") or os.path.join(_HERE, "libmpcgemm.so")  # another build of the same sources
 
 MPCG_OK = 0
 MPCG_EINVAL = -1

@@ -24,6 +24,21 @@ def _say(msg):
     sys.stdout.flush()
 
 
+def _oracle_sampled(C, A, B, p, rows, cols, Cin=None, sign=1):
+    """C's entries (rows[t], cols[t]) against the oracle's, bit for bit (the
+    accumulating form's when Cin is given)."""
+    if Cin is None:
+        sg, ex, mt = oracle.cgemm_entries(A, B, rows, cols, p)
+    else:
+        sg, ex, mt = oracle.cgemm_acc_entries(A, B, Cin, rows, cols, p, sign)
+    for t, (i, j) in enumerate(zip(rows, cols)):
+        for comp, part in enumerate((C.re, C.im)):
+            assert part.exp[j, i] == ex[t, comp], (i, j, comp)
+            if ex[t, comp] != EXP_ZERO:
+                assert part.sign[j, i] == sg[t, comp] and np.array_equal(part.mant[:, j, i], mt[t, comp]), \
+                    (i, j, comp)
+
+
 def _mixed(m, n, k, p, shift, seed=61):
     """Random A (m x k) and B (k x n); rows 256..511 of A and columns 256.. of B
     get one entry each raised by 2^shift, so those rows' and columns' exponent
@@ -67,6 +82,8 @@ def test_adaptive_uniform_input_is_one_plan():
     C1, info1 = run_device(A, B, p, M3, EXACT, I8, adaptive=1)
     assert info0 == info1
     assert mismatches(C1, C0, m, n)[0] == 0
+    rng = np.random.default_rng(62)
+    _oracle_sampled(C1, A, B, p, rng.integers(0, m, 150), rng.integers(0, n, 150))
 
 
 def test_adaptive_truncated_bound():
@@ -93,6 +110,10 @@ def test_adaptive_accumulate_matches_single_plan():
         from tests.gpu_util import device_result_to_host
         outs.append(device_result_to_host(dC, p))
     assert mismatches(outs[1], outs[0], m, n)[0] == 0
+    rng = np.random.default_rng(64)
+    rows = np.concatenate([rng.integers(0, m, 150), [0, 255, 256, 511, 529]])
+    cols = np.concatenate([rng.integers(0, n, 150), [0, 255, 256, 289, 289]])
+    _oracle_sampled(outs[1], A, B, p, rows, cols, Cin=Cin, sign=-1)
 
 
 def test_adaptive_block_size():
@@ -109,3 +130,7 @@ def test_adaptive_block_size():
     C2, info2 = run_device(A, B, p, M3, EXACT, I8, adaptive=64)
     assert mismatches(C1, C0, m, n)[0] == 0 and mismatches(C2, C0, m, n)[0] == 0
     assert info2["algo_ops"] < info1["algo_ops"] < info0["algo_ops"], (info0, info1, info2)
+    rng = np.random.default_rng(65)
+    rows = np.concatenate([rng.integers(0, m, 120), np.arange(60, 132, 4)])
+    cols = np.concatenate([rng.integers(0, n, 120), rng.integers(0, n, 18)])
+    _oracle_sampled(C2, A, B, p, rows, cols)
