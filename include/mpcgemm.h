@@ -168,6 +168,18 @@ typedef struct {
                              and in mp_cgemm_ex_noalloc the plain product runs, as it does when
                              the half-size product would take more than 4 contraction chunks.
                              mpcg_info.strassen reports which ran.  0 = off. */
+    int part_scales;      /* 1: separate scales for the Re and Im parts (MPCG_4M, exact scheme,
+                             INT8 slices, C := AB; the adaptive numbers of divisions of the
+                             paper's concluding section, per component).  Each part of a row of
+                             A (column of B) is scaled by its own largest exponent, so a part far
+                             below the other costs no slices; the four real products run as two
+                             slice GEMMs and each component of C is the exact sum of its two
+                             products, shifted by the whole digits between their scales, rounded
+                             once: the bits of the one-scale product.  Runs only where it needs
+                             fewer slice pairs than one scale per row (and the scales of a
+                             component's two products lie within 4096 digits); otherwise, in
+                             batches and in mp_cgemm_ex_noalloc the one-scale product runs.
+                             mpcg_info.part_scales reports which ran.  0 = off. */
 } mpcg_options;
 
 /* Plan and timing report of one multiplication. */
@@ -184,6 +196,8 @@ typedef struct {
     double algo_ops;      /* 2*m*n*k*pairs*nprod: slice-product operations (all seven products
                              with Strassen's recursion) */
     double bound_bits;    /* truncated: error bound exponent (error <= 2^-bound_bits * sum|a||b|) */
+    int part_scales;      /* 1 if the Re and Im parts were scaled separately (S_A, S_B then cover
+                             each part's own spread) */
 } mpcg_info;
 
 /* mp_cgemm with options; info (may be NULL) receives the plan. */

@@ -159,6 +159,14 @@ def workload_inputs(name: str):
         A = random_cmat(seed, 0, m, k, p, R)
         B = random_cmat(seed, 1, k, n, p, R)
         return m, n, k, p, A, B
+    if name == "cgemm2048_p1024_im200":
+        # every imaginary part 2^200 below the real parts (exponents in [-232, -168])
+        m, n, k, p, R, _ = WORKLOADS["cgemm2048_p1024"]
+        A = random_cmat(33, 0, m, k, p, R)
+        B = random_cmat(33, 1, k, n, p, R)
+        scale_exponents(A.im, rows=list(range(m)), shift=-200)
+        scale_exponents(B.im, rows=list(range(k)), shift=-200)
+        return m, n, k, p, A, B
     if name in ("cgemm2048_p1024_rowcol60", "cgemm2048_p1024_contract60"):
         m, n, k, p, R, _ = WORKLOADS["cgemm2048_p1024"]
         seed = 31 if name.endswith("rowcol60") else 32

@@ -54,14 +54,15 @@ class mpcg_cmat(ctypes.Structure):
 class mpcg_options(ctypes.Structure):
     _fields_ = [("slice_type", ctypes.c_int), ("cutoff_override", ctypes.c_int),
                 ("ksplit_override", ctypes.c_int), ("block_override", ctypes.c_int),
-                ("max_spread", ctypes.c_int), ("adaptive", ctypes.c_int), ("strassen", ctypes.c_int)]
+                ("max_spread", ctypes.c_int), ("adaptive", ctypes.c_int), ("strassen", ctypes.c_int),
+                ("part_scales", ctypes.c_int)]
 
 
 class mpcg_info(ctypes.Structure):
     _fields_ = [("S_A", ctypes.c_int), ("S_B", ctypes.c_int), ("w", ctypes.c_int), ("cutoff", ctypes.c_int),
                 ("nprod", ctypes.c_int), ("ksplit", ctypes.c_int), ("block", ctypes.c_int),
                 ("strassen", ctypes.c_int), ("pairs", ctypes.c_longlong), ("algo_ops", ctypes.c_double),
-                ("bound_bits", ctypes.c_double)]
+                ("bound_bits", ctypes.c_double), ("part_scales", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -336,9 +337,10 @@ def mp_cgemm(m, n, k, A: DeviceCMat, lda, B: DeviceCMat, ldb, C: DeviceCMat, ldc
 
 def mp_cgemm_ex(m, n, k, A: DeviceCMat, lda, B: DeviceCMat, ldb, C: DeviceCMat, ldc, prec_bits,
                 mode=MPCG_3M, scheme=MPCG_EXACT, slice_type=MPCG_SLICE_INT8, cutoff_override=0,
-                ksplit_override=0, block_override=0, max_spread=0, adaptive=0, strassen=0) -> dict:
+                ksplit_override=0, block_override=0, max_spread=0, adaptive=0, strassen=0, part_scales=0) -> dict:
     a, b, c = A.struct(), B.struct(), C.struct()
-    opt = mpcg_options(slice_type, cutoff_override, ksplit_override, block_override, max_spread, adaptive, strassen)
+    opt = mpcg_options(slice_type, cutoff_override, ksplit_override, block_override, max_spread, adaptive, strassen,
+                       part_scales)
     info = mpcg_info()
     _check(_lib.mp_cgemm_ex(m, n, k, ctypes.byref(a), lda, ctypes.byref(b), ldb, ctypes.byref(c), ldc,
                             prec_bits, mode, scheme, ctypes.byref(opt), ctypes.byref(info)))

@@ -121,18 +121,18 @@ __host__ __device__ inline int digit_chunks(int Dmax, int W) {
 // Compile-time shape of the fragment queue.  An entry holds NS consecutive
 // steps; per step: the A fragment X_s of the workgroup's two row tiles and the
 // B fragments Y_{d0-s} of its two column tiles for each B plane.
-template <int W, bool M3>
+template <int W, int F>
 struct Q {
   static constexpr int NS = (W % 8 == 0) ? 4 : 2;  // steps per entry (a ring turn is an even number of entries)
-  static constexpr int NB = M3 ? 1 : 2;     // B planes per step
+  static constexpr int NB = F == F4M ? 2 : 1;  // B planes per step
   static constexpr int E = 2 + 2 * NB;      // fragments per step
   static constexpr int ENT = NS * E;        // fragments per entry
   static constexpr int PW = ENT / 4;        // loads each wavefront issues per entry
   static constexpr int QS = 160 / ENT;      // entries in the queue (at most 160 KB of LDS)
   static constexpr int VM = (QS - 3) * PW;  // own loads still allowed in flight when the next entry must have landed
   static constexpr int VM0 = (QS - 2) * PW; // the same for entry 0 after the prologue
-  static constexpr int NPASS = M3 ? 3 : 2;
-  static constexpr int NACC = M3 ? 3 : 2;
+  static constexpr int NPASS = F == F3M ? 3 : 2;
+  static constexpr int NACC = F == F3M ? 3 : 2;
   static constexpr int CH = W / NS;         // entries per chunk (W steps: one turn of the ring)
   static_assert(CH % 2 == 0, "entries alternate between two register buffers");
   static_assert(VM0 < 64, "vmcnt range");
@@ -170,9 +170,9 @@ __host__ __device__ inline void pads_for(int W, int& alo, int& ahi, int& blo, in
 // entry.  Within a unit its (wave-uniform) source moves by a constant stride
 // per entry, so a load costs a 64-bit scalar add and the instruction itself;
 // only the end of a unit branches.
-template <int W, bool M3>
+template <int W, int F>
 struct Producer {
-  using G = Q<W, M3>;
+  using G = Q<W, F>;
   static constexpr int PW = G::PW;
   size_t xplane, yplane;  // bytes between consecutive slices of a tile's plane
   int SA, SB, Dmax, nbands, kb0, kb1;
@@ -212,7 +212,7 @@ struct Producer {
     const int s0 = g.down ? g.s_hi : (g.s_lo > 0 ? g.s_lo : g.s_lo - W);
     const int t0 = g.down ? g.d0 + W - 1 - g.s_hi : g.d0 - s0;
     int pa, pb0, pb1;
-    if (M3) {
+    if (F != F4M) {  // X plane p with Y plane p
       pa = pass; pb0 = pass; pb1 = 0;
     } else {  // Re A with (Re B, Im B); Im A with (-Im B, Re B)
       pa = pass; pb0 = pass == 0 ? 0 : 2; pb1 = pass == 0 ? 1 : 0;
@@ -273,9 +273,9 @@ struct Producer {
   }
 };
 
-template <int W, bool M3>
+template <int W, int F>
 struct Consumer {
-  using G = Q<W, M3>;
+  using G = Q<W, F>;
   static_assert(W % 4 == 0, "a ring turn is an even number of entries");
   static constexpr int NB = G::NB, E = G::E, QS = G::QS, NACC = G::NACC, PW = G::PW;
   int8_t* q;  // the workgroup's queue: QS entries of ENT KB
@@ -284,7 +284,7 @@ struct Consumer {
   static constexpr int NS = G::NS;
   // fragments of the current entry (parity p) and of the next one (parity 1 - p)
   v4i abuf[2][NS], bbuf[2][NS][NB];
-  v4i ring0[W], ring1[M3 ? 1 : W];
+  v4i ring0[W], ring1[F == F4M ? W : 1];
 
   template <int P>
   __device__ inline void read(int sl) {
@@ -307,7 +307,7 @@ struct Consumer {
   // zeros), so those MFMAs are skipped.  DOWN: a downward unit, whose ring
   // slot jj steps old holds the B fragment of diagonal d0 + W - 1 - jj.
   template <int C, bool MF, int Q0, int Q1, bool RAMP = false, bool DOWN = false>
-  __device__ inline void entry(v4i (&acc)[NACC][W], Producer<W, M3>& P) {
+  __device__ inline void entry(v4i (&acc)[NACC][W], Producer<W, F>& P) {
     constexpr int PAR = C & 1;
     wait_vmcnt<G::VM>();
     __builtin_amdgcn_s_barrier();
@@ -318,7 +318,7 @@ struct Consumer {
       constexpr int V0 = NS * C;
       const int V = V0 + h;
       ring0[V % W] = bbuf[PAR][h][0];
-      if (!M3) ring1[V % W] = bbuf[PAR][h][NB - 1];
+      if (F == F4M) ring1[V % W] = bbuf[PAR][h][NB - 1];
       // in accumulator order: the same accumulator recurs only W MFMAs later,
       // also across steps
 #pragma unroll
@@ -327,7 +327,7 @@ struct Consumer {
           const int r = (V - j + W) % W;      // ring slot of the fragment loaded j steps ago
           const int ja = DOWN ? W - 1 - j : j;  // its diagonal d0 + ja
           acc[Q0][ja] = mfma(abuf[PAR][h], ring0[r], acc[Q0][ja]);
-          if (!M3) acc[Q1][ja] = mfma(abuf[PAR][h], ring1[r], acc[Q1][ja]);
+          if (F == F4M) acc[Q1][ja] = mfma(abuf[PAR][h], ring1[r], acc[Q1][ja]);
         }
         // spread this wavefront's loads over the entry
         constexpr int per = (PW + NS - 1) / NS;
@@ -341,7 +341,7 @@ struct Consumer {
   }
 
   template <int C, bool MF, int Q0, int Q1, bool RAMP = false, bool DOWN = false>
-  __device__ inline void chunk(v4i (&acc)[NACC][W], Producer<W, M3>& P, int left) {
+  __device__ inline void chunk(v4i (&acc)[NACC][W], Producer<W, F>& P, int left) {
     if constexpr (C < G::CH) {
       if (MF && left <= C) return;
       entry<C, MF, Q0, Q1, RAMP, DOWN>(acc, P);
@@ -354,7 +354,7 @@ struct Consumer {
   // ring-filling entries first; 2: downward, a ramped first turn (pairs with
   // t < 0).  Then chunks with MFMAs.
   template <int Q0, int Q1, int KIND>
-  __device__ inline void unit(v4i (&acc)[NACC][W], Producer<W, M3>& P, const Band& g) {
+  __device__ inline void unit(v4i (&acc)[NACC][W], Producer<W, F>& P, const Band& g) {
     const int ne = unit_entries(g, W, NS);
     if constexpr (KIND == 1) {
       chunk<0, false, Q0, Q1>(acc, P, G::CH);
@@ -366,11 +366,11 @@ struct Consumer {
 };
 
 // One work item: the 2 x 2 tile group (gi, gj) of contraction chunk `split`.
-template <int W, bool M3>
+template <int W, int F>
 __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& a, int split, int gi, int gj,
                                                                  int8_t* lds_queue) {
-  using G = Q<W, M3>;
-  using C = Consumer<W, M3>;
+  using G = Q<W, F>;
+  using C = Consumer<W, F>;
   constexpr int NACC = G::NACC;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -383,7 +383,7 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
   const int kb0 = split * kbps;
   const int kb1 = min(a.kblocks, kb0 + kbps);
 
-  Producer<W, M3> P;
+  Producer<W, F> P;
   // tile-major planes: consecutive slices of one tile and plane are a k-row
   // (kblocks fragments) apart, so a unit's loads stay within a few pages
   P.xplane = (size_t)a.kblocks * 1024;
@@ -400,7 +400,7 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
   P.kb0 = kb0;
   P.kb1 = kb1;
   {
-    const size_t xtile = (size_t)(M3 ? 3 : 2) * a.xs * a.kblocks * 1024;  // bytes of one row tile
+    const size_t xtile = (size_t)(F == F3M ? 3 : 2) * a.xs * a.kblocks * 1024;  // bytes of one row tile
     const size_t ytile = (size_t)3 * a.ys * a.kblocks * 1024;             // bytes of one column tile
     const int8_t* X0 = a.X + (size_t)(2 * gi) * xtile;  // row tiles 2gi, 2gi+1
     const int8_t* Y0 = a.Y + (size_t)(2 * gj) * ytile;  // column tiles 2gj, 2gj+1
@@ -452,13 +452,18 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
 #pragma unroll
       for (int j = 0; j < W; ++j) acc[p][j] = v4i{0, 0, 0, 0};
 
-    if constexpr (M3) {  // T1 = Re Re, T2 = Im Im, T3 = (Re+Im)(Re+Im)
+    if constexpr (F == F3M) {  // T1 = Re Re, T2 = Im Im, T3 = (Re+Im)(Re+Im)
 #pragma unroll 1
       for (int kb = kb0; kb < kb1; ++kb) c.template unit<0, 0, KIND>(acc, P, g);
 #pragma unroll 1
       for (int kb = kb0; kb < kb1; ++kb) c.template unit<1, 1, KIND>(acc, P, g);
 #pragma unroll 1
       for (int kb = kb0; kb < kb1; ++kb) c.template unit<2, 2, KIND>(acc, P, g);
+    } else if constexpr (F == FSEP) {  // T1 = X0 Y0 and T2 = X1 Y1, kept apart
+#pragma unroll 1
+      for (int kb = kb0; kb < kb1; ++kb) c.template unit<0, 0, KIND>(acc, P, g);
+#pragma unroll 1
+      for (int kb = kb0; kb < kb1; ++kb) c.template unit<1, 1, KIND>(acc, P, g);
     } else {  // Re += ReA ReB + ImA (-ImB),  Im += ReA ImB + ImA ReB
 #pragma unroll 1
       for (int pass = 0; pass < 2; ++pass)
@@ -477,7 +482,7 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         int64_t vre, vim;
-        if constexpr (M3) {
+        if constexpr (F == F3M) {
           const int64_t t1 = acc[0][j][r], t2 = acc[1][j][r], t3 = acc[2][j][r];
           vre = t1 - t2;
           vim = t3 - t1 - t2;
@@ -541,12 +546,12 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
   }
 }
 
-template <int W, bool M3>
+template <int W, int F>
 __global__ __launch_bounds__(256) void gemm_i8_kernel(GemmArgs a) {
   extern __shared__ __attribute__((aligned(1024))) int8_t lds_queue[];
   int split, gi, gj;
   map_block(blockIdx.x, gridDim.x, a.mt >> 1, a.nt >> 1, split, gi, gj);
-  gemm_item<W, M3>(a, split, gi, gj, lds_queue);
+  gemm_item<W, F>(a, split, gi, gj, lds_queue);
 }
 
 // Persistent form for a batch of products: block b works through its list of
@@ -554,7 +559,7 @@ __global__ __launch_bounds__(256) void gemm_i8_kernel(GemmArgs a) {
 // (longest-processing-time first).  The queue is drained at the end of an
 // item; the barrier keeps a fast wavefront from refilling it while another
 // still reads the previous item's last entry.
-template <int W, bool M3>
+template <int W, int F>
 __global__ __launch_bounds__(256) void gemm_i8_batched_kernel(const GemmArgs* __restrict__ probs,
                                                               const int4* __restrict__ items,
                                                               const int* __restrict__ first) {
@@ -563,45 +568,50 @@ __global__ __launch_bounds__(256) void gemm_i8_batched_kernel(const GemmArgs* __
   for (int i = i0; i < i1; ++i) {
     const int4 it = items[i];
     const GemmArgs a = probs[it.x];
-    gemm_item<W, M3>(a, it.w, it.y, it.z, lds_queue);
+    gemm_item<W, F>(a, it.w, it.y, it.z, lds_queue);
     __syncthreads();
   }
 }
 
-template <int W, bool M3>
+template <int W, int F>
 hipError_t launch_wm(const GemmArgs& a, hipStream_t stream) {
-  using G = Q<W, M3>;
+  using G = Q<W, F>;
   const int blocks = (a.mt / 2) * (a.nt / 2) * a.ksplit;
   const size_t lds = (size_t)G::QS * G::ENT * 1024;
-  hipError_t e = hipFuncSetAttribute((const void*)gemm_i8_kernel<W, M3>,
+  hipError_t e = hipFuncSetAttribute((const void*)gemm_i8_kernel<W, F>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  gemm_i8_kernel<W, M3><<<dim3(blocks), dim3(256), lds, stream>>>(a);
+  gemm_i8_kernel<W, F><<<dim3(blocks), dim3(256), lds, stream>>>(a);
   return hipGetLastError();
 }
 
 template <int W>
 hipError_t launch_w(const GemmArgs& a, hipStream_t stream) {
-  return a.mode3m ? launch_wm<W, true>(a, stream) : launch_wm<W, false>(a, stream);
+  switch (a.form) {
+    case F4M: return launch_wm<W, F4M>(a, stream);
+    case F3M: return launch_wm<W, F3M>(a, stream);
+    case FSEP: return launch_wm<W, FSEP>(a, stream);
+    default: return hipErrorInvalidValue;
+  }
 }
 
-template <int W, bool M3>
+template <int W, int F>
 hipError_t launch_batched_wm(const GemmArgs* probs, const int4* items, const int* first, int blocks,
                              hipStream_t stream) {
-  using G = Q<W, M3>;
+  using G = Q<W, F>;
   const size_t lds = (size_t)G::QS * G::ENT * 1024;
-  hipError_t e = hipFuncSetAttribute((const void*)gemm_i8_batched_kernel<W, M3>,
+  hipError_t e = hipFuncSetAttribute((const void*)gemm_i8_batched_kernel<W, F>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  gemm_i8_batched_kernel<W, M3><<<dim3(blocks), dim3(256), lds, stream>>>(probs, items, first);
+  gemm_i8_batched_kernel<W, F><<<dim3(blocks), dim3(256), lds, stream>>>(probs, items, first);
   return hipGetLastError();
 }
 
 template <int W>
 hipError_t launch_batched_w(const GemmArgs* probs, const int4* items, const int* first, int blocks, int mode3m,
                             hipStream_t stream) {
-  return mode3m ? launch_batched_wm<W, true>(probs, items, first, blocks, stream)
-                : launch_batched_wm<W, false>(probs, items, first, blocks, stream);
+  return mode3m ? launch_batched_wm<W, F3M>(probs, items, first, blocks, stream)
+                : launch_batched_wm<W, F4M>(probs, items, first, blocks, stream);
 }
 
 }  // namespace

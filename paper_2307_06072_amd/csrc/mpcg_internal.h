@@ -81,7 +81,7 @@ hipError_t launch_scan(const DOperand& op, RowStat* stats, ScanSummary* summary,
 //              |x| / 2^G[r] = sum_s d_s 2^(-w(s+1)).
 //   out        INT8: int8 planes [nops][Sp][Rpad/16][Kpad/64][64][16];
 //              FP64: double planes [nops][Sp][Rpad/16][Kpad/4][64].
-enum class Third { NONE = 0, SUM = 1, NEG_IM = 2 };
+enum class Third { NONE = 0, SUM = 1, NEG_IM = 2, RE = 3 };
 // INT8 planes hold Sstride slices each: pad_lo zero slices, the Sp digit
 // slices, then zero slices up to Sstride (all written by the split).
 hipError_t launch_split_i8(const DOperand& op, int prec, int L, int S, int Sp, int Sstride, int pad_lo,
@@ -93,6 +93,11 @@ hipError_t launch_split_i8(const DOperand& op, int prec, int L, int S, int Sp, i
 hipError_t launch_split2_i8(const DOperand& op, const DOperand& op2, int sign2, int prec, int L, int S, int Sp,
                             int Sstride, int pad_lo, Third third, const int32_t* G, int Rpad, int Kpad, int8_t* out,
                             int* status, hipStream_t stream);
+// The split with separate row scales for the Re parts (G) and the Im parts
+// (Gim); third NONE or RE (the Re plane again, as the third plane).
+hipError_t launch_split_parts_i8(const DOperand& op, int prec, int L, int S, int Sp, int Sstride, int pad_lo,
+                                 Third third, const int32_t* G, const int32_t* Gim, int Rpad, int Kpad, int8_t* out,
+                                 int* status, hipStream_t stream);
 hipError_t launch_split_f64(const DOperand& op, int prec, int L, int S, int Sp, int w, Third third,
                             const int32_t* G, int Rpad, int Kpad, double* out, int* status,
                             hipStream_t stream);
@@ -104,6 +109,7 @@ hipError_t launch_fold_scales(const RowStat* stats, int half, int Rpad, int x, i
 hipError_t launch_scales(const RowStat* stats, int R, int Rpad, int x, int32_t* G, hipStream_t stream);
 
 // Slice GEMM + combination + carry chain (INT8 digits).
+enum GemmForm { F4M = 0, F3M = 1, FSEP = 2 };
 struct GemmArgs {
   const int8_t* X;   // A-side planes
   const int8_t* Y;   // B-side planes
@@ -114,7 +120,10 @@ struct GemmArgs {
   int xs, ys;        // slices per A / B plane including the zero pads
   int xlo, ylo;      // zero slices below slice 0 of an A / B plane
   int Dmax;          // highest emitted diagonal
-  int mode3m;        // 1: planes are (Re, Im, Re+Im) on both sides; 0: A (Re, Im), B (Re, Im, -Im)
+  int form;          // F4M: A planes (Re, Im), B (Re, Im, -Im), Re and Im of C out;
+                     // F3M: planes (Re, Im, Re+Im) on both sides, Re and Im of C out;
+                     // FSEP: A planes (X0, X1), B (Y0, Y1, ...), the two real products
+                     //       X0 Y0 and X1 Y1 out in place of Re and Im
   void* digits;      // [ksplit][tiles][slot 8][chunk][lane 64][16] uint8 digits, q = Dmax - d
                      // (chunk = q / 16; gemm_i8_digit_chunks chunks per component)
   int64_t* top;      // [ksplit][tiles][64][8]
@@ -165,8 +174,32 @@ struct RoundArgs {
   // `digits` (ksplit must be 1): the recombination of Strassen's products
   int nsrc;
   const MergeSrc* src;
+  // INT8 only, non-null: the four real products of separately scaled parts
+  // (device pointer), merged into `digits` (nchunk chunks per component;
+  // Dmax is the products' own)
+  const struct PartsMerge* parts;
 };
 hipError_t launch_round(const RoundArgs& a, hipStream_t stream);
+
+// Separately scaled Re and Im parts (4M): the real products P_rr = Re A Re B,
+// P_ii = Im A Im B, P_ri = Re A Im B and P_ir = Im A Re B are exact digit
+// streams of one layout, each at the scale of its own parts, and
+// Re C = P_rr - P_ii, Im C = P_ri + P_ir.  The scales of the two parts of a
+// row (column) agree modulo 8, so the streams of one component are merged
+// shifted by whole digits.
+struct PartsMerge {
+  const uint8_t* dig[2];  // streams of the pair (P_rr, P_ii) and (P_ri, P_ir): the first in the
+                          // Re slots, the second in the Im slots of a GEMM digit layout
+  const int64_t* top[2];  // their tops
+  int nchunk;             // 16-digit chunks per component of those layouts
+  int ksplit;             // contraction chunks of those layouts
+  const int32_t* Gre;     // [m] row scales of Re A
+  const int32_t* Gim;     // [m] row scales of Im A
+  const int32_t* Hre;     // [n] column scales of Re B
+  const int32_t* Him;     // [n] column scales of Im B
+  char pad[256 - 2 * 8 - 2 * 8 - 2 * 4 - 4 * 8];  // a 256-byte record
+};
+static_assert(sizeof(PartsMerge) == 256, "PartsMerge is stored as 256 bytes");
 
 // The fixed buffer of mp_cgemm_ex_noalloc on the current device (set up on
 // first use: its device address looked up, its status word cleared on

@@ -130,6 +130,7 @@ struct Plan {
   int mode_req;      // the caller's form (MPCG_AUTO resolved into mode3m), the tuning cache's key
   int tune_S;        // MPCG_AUTO: the 3M slice count the cache is keyed by (else the plan's own)
   int extra_x;       // more headroom bits (1 for the operand sums of Strassen's recursion)
+  int sep;           // the four real products of separately scaled parts (FSEP GEMM form)
   int nchunk;        // INT8: 16-digit chunks per output component
   size_t off_G, off_H, off_X, off_Y, off_dig, off_top, off_lnz, off_scan, total;
 };
@@ -185,7 +186,7 @@ size_t scan_bytes(int m, int n) {
 // cost more.  The 4M form keeps two accumulators and two rings per diagonal,
 // for which 16 is the widest band that fits the registers.
 int pick_band(const Plan& P) {
-  return (P.mode3m && std::min(P.SA, P.SB) >= 64) ? 20 : 16;
+  return ((P.mode3m || P.sep) && std::min(P.SA, P.SB) >= 64) ? 20 : 16;
 }
 
 int plan_layout(Plan& P, const mpcg_options* opt) {
@@ -203,7 +204,7 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
     TuneChoice tc;
     if (opt && opt->block_override) {
       P.block = opt->block_override;
-    } else if (!g_tune_bypass && !(opt && opt->ksplit_override) &&
+    } else if (!g_tune_bypass && !P.sep && !(opt && opt->ksplit_override) &&
                tune_find(tune_key(P.trunc, P.mode_req, P.m, P.n, P.k, P.tune_S ? P.tune_S : std::max(P.SA, P.SB)),
                          &tc) &&
                tc.mode3m == P.mode3m) {
@@ -224,7 +225,7 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
     P.kblocks = P.kpad / 64;
     // int32 accumulators: terms per diagonal * 128^2 (the largest digit product)
     // must stay below 2^31
-    const long long terms_per_k = (long long)(P.mode3m ? 1 : 2) * std::min(P.SA, P.SB);
+    const long long terms_per_k = (long long)(P.mode3m || P.sep ? 1 : 2) * std::min(P.SA, P.SB);
     const long long kc_max = ((1ll << 31) - 1) / ((1ll << (2 * I8_W - 2)) * terms_per_k);
     const long long kb_max = kc_max / 64;
     if (kb_max < 1) return set_err(MPCG_EUNSUPPORTED, "precision/spread too large for int32 slice accumulation");
@@ -245,7 +246,7 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
   }
   if (opt && opt->ksplit_override > 0) {
     if (!P.f64) {
-      const long long terms_per_k = (long long)(P.mode3m ? 1 : 2) * std::min(P.SA, P.SB);
+      const long long terms_per_k = (long long)(P.mode3m || P.sep ? 1 : 2) * std::min(P.SA, P.SB);
       const long long kc_max = ((1ll << 31) - 1) / ((1ll << (2 * I8_W - 2)) * terms_per_k);
       const long long kc = (long long)ceil_div(P.kblocks, opt->ksplit_override) * 64;
       if (kc > kc_max) return set_err(MPCG_EINVAL, "ksplit_override too small for exact int32 accumulation");
@@ -557,7 +558,7 @@ int run_strassen(int m, int n, int k, const DOperand& opA, const DOperand& opB, 
     ga.X = reinterpret_cast<const int8_t*>(pb + Q.off_X);
     ga.Y = reinterpret_cast<const int8_t*>(pb + Q.off_Y);
     ga.mt = Q.mt; ga.nt = Q.nt; ga.kblocks = Q.kblocks; ga.ksplit = Q.ksplit;
-    ga.SAp = Q.SAp; ga.SBp = Q.SBp; ga.Dmax = Q.Dmax; ga.mode3m = Q.mode3m;
+    ga.SAp = Q.SAp; ga.SBp = Q.SBp; ga.Dmax = Q.Dmax; ga.form = Q.mode3m ? F3M : F4M;
     ga.digits = pb + Q.off_dig;
     ga.top = reinterpret_cast<int64_t*>(pb + Q.off_top);
     ga.lnz = reinterpret_cast<int32_t*>(pb + Q.off_lnz);
@@ -613,6 +614,192 @@ int run_strassen(int m, int n, int k, const DOperand& opA, const DOperand& opB, 
     info->nprod = Q.mode3m ? 3 : 4; info->ksplit = Q.ksplit; info->block = Q.block;
     info->pairs = Q.pairs; info->algo_ops = 7 * Q.algo_ops; info->bound_bits = 0;
     info->strassen = 1;
+  }
+  g_timing_valid = g_timing;
+  return MPCG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Separate scales for the Re and Im parts (4M, exact): each part of a row of
+// A (column of B) is scaled by its own maximum, so a part far below the
+// other costs no slices; the four real products run as two GEMMs of two
+// separate products each, and the rounding kernel merges each component's
+// two streams, shifted by the whole digits between their scales, before the
+// one rounding.  The scales of a row's two parts are made to agree modulo 8
+// (at most 7 bits more headroom for one of them).
+// ---------------------------------------------------------------------------
+constexpr int PARTS_DECLINED = 1;  // no fewer slice pairs than one scale: the plain product runs
+constexpr int PARTS_MAX_SHIFT = 4096;  // digits between the scales of one component's products
+
+struct PartScales {
+  std::vector<int32_t> Gre, Gim;  // scales of the Re and Im parts per row (column)
+  int need = 0;                   // bits the slices must hold: max over parts of G - emin + p
+  int maxq = 0;                   // max |G_re - G_im| / 8
+  bool any = false;
+};
+
+PartScales part_scales(const std::vector<RowStat>& re, const std::vector<RowStat>& im, int x, int p) {
+  PartScales ps;
+  const size_t R = re.size();
+  ps.Gre.assign(R, 0);
+  ps.Gim.assign(R, 0);
+  for (size_t r = 0; r < R; ++r) {
+    const bool zr = re[r].emax == EXP_ZERO, zi = im[r].emax == EXP_ZERO;
+    int64_t gr = 0, gi = 0;
+    if (!zr && !zi) {
+      gr = (int64_t)re[r].emax + x;
+      const int64_t gi_nat = (int64_t)im[r].emax + x;
+      const int64_t d = gr - gi_nat;
+      const int64_t fl = d >= 0 ? d / I8_W : -((-d + I8_W - 1) / I8_W);  // floor(d / 8)
+      gi = gr - (int64_t)I8_W * fl;  // >= gi_nat, within 7 bits of it
+    } else if (!zr) {
+      gr = gi = (int64_t)re[r].emax + x;
+    } else if (!zi) {
+      gr = gi = (int64_t)im[r].emax + x;
+    }
+    ps.Gre[r] = (int32_t)gr;
+    ps.Gim[r] = (int32_t)gi;
+    if (!zr) ps.need = std::max<int64_t>(ps.need, gr - re[r].emin + p);
+    if (!zi) ps.need = std::max<int64_t>(ps.need, gi - im[r].emin + p);
+    ps.any = ps.any || !zr || !zi;
+    ps.maxq = std::max<int64_t>(ps.maxq, std::llabs(gr - gi) / I8_W);
+  }
+  return ps;
+}
+
+int run_parts(int m, int n, int k, const DOperand& opA, const DOperand& opB, int prec_bits,
+              const mpcg_options* opt, mpcg_info* info, int SA_common, int SB_common, const DOutPart& cre,
+              const DOutPart& cim, int64_t ldc) {
+  const int L = (prec_bits + 63) / 64;
+  // per-part statistics: the scan of a view whose two parts are the same part
+  DOperand vAr = opA, vAi = opA, vBr = opB, vBi = opB;
+  vAr.im = opA.re;
+  vAi.re = opA.im;
+  vBr.im = opB.re;
+  vBi.re = opB.im;
+  const size_t sA = align256(sizeof(RowStat) * (size_t)m), sB = align256(sizeof(RowStat) * (size_t)n);
+  void* ws = nullptr;
+  int st;
+  if ((st = ensure_workspace(2 * sA + 2 * sB + 256, &ws))) return st;
+  {
+    char* b = static_cast<char*>(ws);
+    RowStat* s0 = reinterpret_cast<RowStat*>(b);
+    RowStat* s1 = reinterpret_cast<RowStat*>(b + sA);
+    RowStat* s2 = reinterpret_cast<RowStat*>(b + 2 * sA);
+    RowStat* s3 = reinterpret_cast<RowStat*>(b + 2 * sA + sB);
+    ScanSummary* summ = reinterpret_cast<ScanSummary*>(b + 2 * sA + 2 * sB);
+    HIP_TRY(launch_scan(vAr, s0, summ, 0, nullptr, g_stream));
+    HIP_TRY(launch_scan(vAi, s1, summ + 1, 0, nullptr, g_stream));
+    HIP_TRY(launch_scan(vBr, s2, summ + 2, 0, nullptr, g_stream));
+    HIP_TRY(launch_scan(vBi, s3, summ + 3, 0, nullptr, g_stream));
+  }
+  std::vector<RowStat> aR(m), aI(m), bR(n), bI(n);
+  {
+    char* b = static_cast<char*>(ws);
+    HIP_TRY(hipMemcpyAsync(aR.data(), b, sizeof(RowStat) * m, hipMemcpyDeviceToHost, g_stream));
+    HIP_TRY(hipMemcpyAsync(aI.data(), b + sA, sizeof(RowStat) * m, hipMemcpyDeviceToHost, g_stream));
+    HIP_TRY(hipMemcpyAsync(bR.data(), b + 2 * sA, sizeof(RowStat) * n, hipMemcpyDeviceToHost, g_stream));
+    HIP_TRY(hipMemcpyAsync(bI.data(), b + 2 * sA + sB, sizeof(RowStat) * n, hipMemcpyDeviceToHost, g_stream));
+    HIP_TRY(hipStreamSynchronize(g_stream));
+  }
+  const int x = 2;  // the 4M headroom of plan_slices
+  const PartScales pa = part_scales(aR, aI, x, prec_bits), pb = part_scales(bR, bI, x, prec_bits);
+  if (!pa.any || !pb.any) return PARTS_DECLINED;
+  const int qmax = pa.maxq + pb.maxq;
+  Plan Q{};
+  Q.m = m; Q.n = n; Q.k = k; Q.p = prec_bits;
+  Q.mode_req = MPCG_4M;
+  Q.mode3m = 0;
+  Q.sep = 1;
+  Q.want_groups = 512;
+  // plan_slices takes S = ceil((p + x + spread) / 8): pass the spread that gives `need` bits
+  int spA = pa.need - prec_bits - x, spB = pb.need - prec_bits - x;
+  if ((st = plan_slices(Q, spA, spB, spA, spB, opt))) return st;
+  if ((long long)Q.SA * Q.SB >= (long long)SA_common * SB_common || qmax > PARTS_MAX_SHIFT)
+    return PARTS_DECLINED;
+  if ((st = plan_layout(Q, opt))) return st;
+  const size_t tiles = (size_t)Q.mt * Q.nt;
+  const size_t dig_b = align256((size_t)Q.ksplit * tiles * 8 * Q.nchunk * 1024);
+  const size_t top_b = align256((size_t)Q.ksplit * tiles * 512 * 8);
+  const size_t lnz_b = align256((size_t)Q.ksplit * tiles * 512 * 4);
+  const int nchunk_m = (Q.Dmax + 1 + qmax + 15) / 16;
+  const size_t mer_b = align256(tiles * 8 * (size_t)nchunk_m * 1024);
+  const size_t sc_b = 2 * align256(4 * (size_t)Q.mpad) + 2 * align256(4 * (size_t)Q.npad);
+  const size_t total = align256(Q.total) + dig_b + top_b + lnz_b + mer_b + sc_b + 256;
+  if ((st = ensure_workspace(total, &ws))) return st;
+  char* base = static_cast<char*>(ws);
+  char* p2 = base + align256(Q.total);
+  uint8_t* dig2 = reinterpret_cast<uint8_t*>(p2);
+  int64_t* top2 = reinterpret_cast<int64_t*>(p2 + dig_b);
+  int32_t* lnz2 = reinterpret_cast<int32_t*>(p2 + dig_b + top_b);
+  uint8_t* merged = reinterpret_cast<uint8_t*>(p2 + dig_b + top_b + lnz_b);
+  char* scp = p2 + dig_b + top_b + lnz_b + mer_b;
+  int32_t* dGr = reinterpret_cast<int32_t*>(scp);
+  int32_t* dGi = reinterpret_cast<int32_t*>(scp + align256(4 * (size_t)Q.mpad));
+  int32_t* dHr = reinterpret_cast<int32_t*>(scp + 2 * align256(4 * (size_t)Q.mpad));
+  int32_t* dHi = reinterpret_cast<int32_t*>(scp + 2 * align256(4 * (size_t)Q.mpad) + align256(4 * (size_t)Q.npad));
+  PartsMerge* dpm = reinterpret_cast<PartsMerge*>(scp + sc_b);
+  // scales (padding rows take 0, as from the scale kernel)
+  std::vector<int32_t> hG(Q.mpad, 0), hGi(Q.mpad, 0), hH(Q.npad, 0), hHi(Q.npad, 0);
+  std::copy(pa.Gre.begin(), pa.Gre.end(), hG.begin());
+  std::copy(pa.Gim.begin(), pa.Gim.end(), hGi.begin());
+  std::copy(pb.Gre.begin(), pb.Gre.end(), hH.begin());
+  std::copy(pb.Gim.begin(), pb.Gim.end(), hHi.begin());
+  HIP_TRY(hipMemcpyAsync(dGr, hG.data(), 4 * (size_t)Q.mpad, hipMemcpyHostToDevice, g_stream));
+  HIP_TRY(hipMemcpyAsync(dGi, hGi.data(), 4 * (size_t)Q.mpad, hipMemcpyHostToDevice, g_stream));
+  HIP_TRY(hipMemcpyAsync(dHr, hH.data(), 4 * (size_t)Q.npad, hipMemcpyHostToDevice, g_stream));
+  HIP_TRY(hipMemcpyAsync(dHi, hHi.data(), 4 * (size_t)Q.npad, hipMemcpyHostToDevice, g_stream));
+  PartsMerge pm{};
+  pm.dig[0] = reinterpret_cast<const uint8_t*>(base + Q.off_dig);
+  pm.dig[1] = dig2;
+  pm.top[0] = reinterpret_cast<const int64_t*>(base + Q.off_top);
+  pm.top[1] = top2;
+  pm.nchunk = Q.nchunk;
+  pm.ksplit = Q.ksplit;
+  pm.Gre = dGr; pm.Gim = dGi; pm.Hre = dHr; pm.Him = dHi;
+  HIP_TRY(hipMemcpyAsync(dpm, &pm, sizeof(pm), hipMemcpyHostToDevice, g_stream));
+  // the host arrays are pageable: wait for the copies before they go away
+  HIP_TRY(hipStreamSynchronize(g_stream));
+  int8_t* X = reinterpret_cast<int8_t*>(base + Q.off_X);
+  int8_t* Y = reinterpret_cast<int8_t*>(base + Q.off_Y);
+  HIP_TRY(launch_split_parts_i8(opA, prec_bits, L, Q.SA, Q.SAp, Q.xs, Q.xlo, Third::NONE, dGr, dGi, Q.mpad, Q.kpad,
+                                X, g_status, g_stream));
+  // B planes (Re, Im, Re): from the second plane on they read (Im, Re)
+  HIP_TRY(launch_split_parts_i8(opB, prec_bits, L, Q.SB, Q.SBp, Q.ys, Q.ylo, Third::RE, dHr, dHi, Q.npad, Q.kpad, Y,
+                                g_status, g_stream));
+  if ((st = record(2))) return st;
+  for (int pass = 0; pass < 2; ++pass) {
+    GemmArgs ga{};
+    ga.X = X;
+    ga.Y = Y + (pass ? (size_t)Q.ys * Q.kblocks * 1024 : 0);
+    ga.mt = Q.mt; ga.nt = Q.nt; ga.kblocks = Q.kblocks; ga.ksplit = Q.ksplit;
+    ga.SAp = Q.SAp; ga.SBp = Q.SBp; ga.Dmax = Q.Dmax; ga.form = FSEP;
+    ga.digits = pass ? static_cast<void*>(dig2) : static_cast<void*>(base + Q.off_dig);
+    ga.top = pass ? top2 : reinterpret_cast<int64_t*>(base + Q.off_top);
+    ga.lnz = pass ? lnz2 : reinterpret_cast<int32_t*>(base + Q.off_lnz);
+    ga.xs = Q.xs; ga.ys = Q.ys; ga.xlo = Q.xlo; ga.ylo = Q.ylo;
+    HIP_TRY(launch_gemm_i8(ga, Q.block, g_stream));
+  }
+  if ((st = record(3))) return st;
+  RoundArgs ra{};
+  ra.digits = merged;
+  ra.digit_bytes = 1;
+  ra.nchunk = nchunk_m;
+  ra.f64_layout = 0;
+  ra.top = pm.top[0];
+  ra.lnz = reinterpret_cast<const int32_t*>(base + Q.off_lnz);
+  ra.ksplit = 1; ra.mt = Q.mt; ra.nt = Q.nt; ra.Dmax = Q.Dmax; ra.w = Q.w;
+  ra.G = dGr; ra.H = dHr; ra.m = m; ra.n = n; ra.prec = prec_bits; ra.L = L;
+  ra.cre = cre; ra.cim = cim; ra.ldc = ldc; ra.status = g_status;
+  ra.acc = 0;
+  ra.parts = dpm;
+  HIP_TRY(launch_round(ra, g_stream));
+  if ((st = record(4))) return st;
+  if (info) {
+    info->S_A = Q.SA; info->S_B = Q.SB; info->w = Q.w; info->cutoff = Q.cutoff;
+    info->nprod = 4; info->ksplit = Q.ksplit; info->block = Q.block;
+    info->pairs = Q.pairs; info->algo_ops = 2.0 * m * (double)n * k * (double)Q.pairs * 4; info->bound_bits = 0;
+    info->part_scales = 1;
   }
   g_timing_valid = g_timing;
   return MPCG_OK;
@@ -751,6 +938,13 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
     }
     P.mode3m = resolve_mode(mode, scheme, m, n, k, prec_bits, sa.spread, sb.spread) == MPCG_3M;
     P.tune_S = mode == MPCG_AUTO ? auto_key_S(prec_bits, sa.spread, sb.spread) : 0;
+    if (opt && opt->part_scales && mode == MPCG_4M && !P.f64 && !acc && !P.trunc && !fixed) {
+      // the one-scale plan's slice counts, to compare with
+      Plan C0 = P;
+      if ((st = plan_slices(C0, sa.spread, sb.spread, sa.hat, sb.hat, opt))) return st;
+      st = run_parts(m, n, k, opA, opB, prec_bits, opt, info, C0.SA, C0.SB, cre, cim, ldc);
+      if (st != PARTS_DECLINED) return st;
+    }
     if (opt && opt->strassen && !P.f64 && !acc && !P.trunc && !fixed && m % 2 == 0 && n % 2 == 0 && k % 2 == 0) {
       st = run_strassen(m, n, k, opA, opB, prec_bits, P.mode3m, mode, opt, info, statA, statB, cre, cim, ldc);
       if (st != STRASSEN_DECLINED) return st;
@@ -802,7 +996,7 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
     ga.X = reinterpret_cast<const int8_t*>(base + P.off_X);
     ga.Y = reinterpret_cast<const int8_t*>(base + P.off_Y);
     ga.mt = P.mt; ga.nt = P.nt; ga.kblocks = P.kblocks; ga.ksplit = P.ksplit;
-    ga.SAp = P.SAp; ga.SBp = P.SBp; ga.Dmax = P.Dmax; ga.mode3m = P.mode3m;
+    ga.SAp = P.SAp; ga.SBp = P.SBp; ga.Dmax = P.Dmax; ga.form = P.mode3m ? F3M : F4M;
     ga.digits = base + P.off_dig; ga.top = top; ga.lnz = lnz;
     ga.xs = P.xs; ga.ys = P.ys; ga.xlo = P.xlo; ga.ylo = P.ylo;
     HIP_TRY(launch_gemm_i8(ga, P.block, g_stream));
@@ -1362,7 +1556,7 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
     ga.X = reinterpret_cast<const int8_t*>(pb + P.off_X);
     ga.Y = reinterpret_cast<const int8_t*>(pb + P.off_Y);
     ga.mt = P.mt; ga.nt = P.nt; ga.kblocks = P.kblocks; ga.ksplit = P.ksplit;
-    ga.SAp = P.SAp; ga.SBp = P.SBp; ga.Dmax = P.Dmax; ga.mode3m = P.mode3m;
+    ga.SAp = P.SAp; ga.SBp = P.SBp; ga.Dmax = P.Dmax; ga.form = P.mode3m ? F3M : F4M;
     ga.digits = pb + P.off_dig;
     ga.top = reinterpret_cast<int64_t*>(pb + P.off_top);
     ga.lnz = reinterpret_cast<int32_t*>(pb + P.off_lnz);

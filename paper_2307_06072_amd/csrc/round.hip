@@ -823,11 +823,110 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
   uint8_t* g0 = reinterpret_cast<uint8_t*>(const_cast<void*>(a.digits)) +
                 ((size_t)tile * 8 + slot) * a.nchunk * 1024 + (size_t)lane * 16;
   const size_t tb0 = ((size_t)tile * 64 + lane) * 8 + slot;
-  const int Dmax = a.Dmax;
+  int Dmax = a.Dmax;  // digits of the integer rounded: more when shifted streams are merged
+  int64_t gbase = (int64_t)a.G[i] + (int64_t)a.H[j] - (int64_t)I8_W * (a.Dmax + 2);
 
   int64_t T;
   int z;
-  if (a.nsrc > 0) {
+  if (a.parts) {
+    // separately scaled parts: Re = P_rr - P_ii, Im = P_ri + P_ir, the stream
+    // at the larger scale shifted up by the whole digits between the scales
+    const PartsMerge& pm = *a.parts;
+    const int64_t Gr = pm.Gre[i], Gi = pm.Gim[i], Hr = pm.Hre[j], Hi = pm.Him[j];
+    const int64_t sU = comp ? Gr + Hi : Gr + Hr;
+    const int64_t sV = comp ? Gi + Hr : Gi + Hi;
+    const int sgV = comp ? 1 : -1;
+    const int64_t dq = (sU - sV) / I8_W;  // exact: the scales agree modulo 8
+    const int shU = dq > 0 ? (int)dq : 0, shV = dq < 0 ? (int)-dq : 0;
+    const int D0 = a.Dmax;
+    Dmax = D0 + shU + shV;
+    gbase = (sU < sV ? sU : sV) - (int64_t)I8_W * (D0 + 2);
+    const uint8_t* src = pm.dig[comp];
+    const size_t cstride = (size_t)tiles * 8 * pm.nchunk * 1024;  // one contraction chunk's layout
+    const size_t eoU = ((size_t)tile * 8 + (ii & 3)) * pm.nchunk * 1024 + (size_t)lane * 16;
+    const size_t eoV = ((size_t)tile * 8 + 4 + (ii & 3)) * pm.nchunk * 1024 + (size_t)lane * 16;
+    const size_t tU = ((size_t)tile * 64 + lane) * 8 + (ii & 3);
+    int64_t TU = 0, TV = 0;
+    for (int q = 0; q < pm.ksplit; ++q) {
+      TU += pm.top[comp][(size_t)q * tiles * 512 + tU];
+      TV += pm.top[comp][(size_t)q * tiles * 512 + tU + 4];
+    }
+    const int lastc = D0 >> 4;  // the sources' last chunk
+    // digits 16 ch .. 16 ch + 15 of one source shifted up by sh digits, as two
+    // 64-bit words (zero below the source's digit 0 and above digit D0)
+    auto window16 = [&](const uint8_t* base, int ch, int sh, uint64_t& r0, uint64_t& r1)
+                        __attribute__((always_inline)) {
+      const int i0 = 16 * ch - sh;  // source digit under output digit 16 ch
+      const int c0 = i0 >= 0 ? (i0 >> 4) : -((15 - i0) >> 4);
+      const int o = i0 - 16 * c0;   // 0 .. 15
+      // both chunks loaded from clamped (valid) positions, then zeroed where
+      // they lie outside the source
+      const int ca = min(max(c0, 0), lastc), cb = min(max(c0 + 1, 0), lastc);
+      const uint4 v0 = *reinterpret_cast<const uint4*>(base + (size_t)ca * 1024);
+      const uint4 v1 = *reinterpret_cast<const uint4*>(base + (size_t)cb * 1024);
+      const bool in0 = c0 >= 0 && c0 <= lastc, in1 = c0 + 1 >= 0 && c0 + 1 <= lastc;
+      // the 32-byte window as four 64-bit words; bytes o .. o + 15 of it
+      const uint64_t q0 = in0 ? v0.x | ((uint64_t)v0.y << 32) : 0, q1 = in0 ? v0.z | ((uint64_t)v0.w << 32) : 0;
+      const uint64_t q2 = in1 ? v1.x | ((uint64_t)v1.y << 32) : 0, q3 = in1 ? v1.z | ((uint64_t)v1.w << 32) : 0;
+      const bool hi8 = o >= 8;
+      const uint64_t a0 = hi8 ? q1 : q0, a1 = hi8 ? q2 : q1, a2 = hi8 ? q3 : q2;
+      const int sb = 8 * (o & 7);
+      r0 = sb ? (a0 >> sb) | (a1 << (64 - sb)) : a0;
+      r1 = sb ? (a1 >> sb) | (a2 << (64 - sb)) : a1;
+      // source digits above D0 (the unwritten end of the last chunk)
+      const int nv = D0 - i0 + 1;  // digits of the window at or below D0
+      if (nv < 16) {
+        if (nv <= 0) {
+          r0 = r1 = 0;
+        } else if (nv <= 8) {
+          r0 = nv == 8 ? r0 : (r0 & ((1ull << (8 * nv)) - 1));
+          r1 = 0;
+        } else {
+          r1 &= (1ull << (8 * (nv - 8))) - 1;
+        }
+      }
+    };
+    // tops enter at digit D0 + 1 + sh of the merged integer, above it when that
+    // is past the merged digits
+    const int posU = D0 + 1 + shU, posV = D0 + 1 + shV;
+    int64_t c = 0;
+    int qz = -1;
+    const int nq = Dmax + 1;
+    for (int ch = 0; ch * 16 < nq; ++ch) {
+      uint32_t out[4] = {0, 0, 0, 0};
+      int32_t sum[16];
+#pragma unroll
+      for (int b = 0; b < 16; ++b) sum[b] = 0;
+      for (int q = 0; q < pm.ksplit; ++q) {
+        uint64_t u0, u1, v0, v1;
+        window16(src + q * cstride + eoU, ch, shU, u0, u1);
+        window16(src + q * cstride + eoV, ch, shV, v0, v1);
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+          const int sh8 = 8 * (b & 7);
+          const int32_t du = (int32_t)(((b < 8 ? u0 : u1) >> sh8) & 255u);
+          const int32_t dv = (int32_t)(((b < 8 ? v0 : v1) >> sh8) & 255u);
+          sum[b] += du + sgV * dv;
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < 16; ++b) {
+        const int qq = ch * 16 + b;
+        if (qq < nq) {
+          int64_t sv = c + sum[b];
+          if (qq == posU) sv += TU;
+          if (qq == posV) sv += sgV * TV;
+          const uint32_t dg = (uint32_t)(sv & (DFULL - 1));
+          c = sv >> I8_W;
+          out[b >> 2] |= dg << (8 * (b & 3));
+          if (dg && qz < 0) qz = qq;
+        }
+      }
+      *reinterpret_cast<uint4*>(g0 + (size_t)ch * 1024) = make_uint4(out[0], out[1], out[2], out[3]);
+    }
+    z = qz < 0 ? -1 : Dmax - qz;
+    T = c + (posU > Dmax ? TU : 0) + (posV > Dmax ? sgV * TV : 0);
+  } else if (a.nsrc > 0) {
     // the signed sum of the source streams, least significant digit first, 16
     // digits at a time, written to this element's digits
     const size_t eo = ((size_t)tile * 8 + slot) * a.nchunk * 1024 + (size_t)lane * 16;
@@ -949,7 +1048,6 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
   else
     lowset = nbits + __builtin_ctzll((uint64_t)T);
 
-  const int64_t gbase = (int64_t)a.G[i] + (int64_t)a.H[j] - (int64_t)I8_W * (Dmax + 2);
   const int sx = st.neg ^ negp;  // sign of the product term
   int tie = -1;                   // >= 0: a negligible addend breaks the tie
   if (cnz) {

@@ -117,11 +117,13 @@ struct Layout<double> {
 // a chunk from the writes two chunks later.
 // TWO: the operand split is op + sign2 * op2 (two operands of the same shape,
 // each entry's exact sum formed in the windows; the scales G must cover it).
+// Gim (optional): the Im parts' own row scales (the Re parts take G).
 template <typename DT, bool ROWCONTIG, int WC, int TH, bool TWO = false>
 __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, int Sp, int Sstride, int pad_lo,
                                   int w_rt, int third_rt, const int32_t* __restrict__ G, int Rpad, int Kpad,
                                   DT* __restrict__ out, int* status, int kt, int rt, unsigned char* lds_raw,
-                                  const DOperand* op2 = nullptr, int sign2 = 0) {
+                                  const DOperand* op2 = nullptr, int sign2 = 0,
+                                  const int32_t* __restrict__ Gim = nullptr) {
   constexpr int FRAG = Layout<DT>::FRAG_BYTES / (int)sizeof(DT);  // elements per (op, digit) tile
   constexpr int NBUF = sizeof(DT) == 1 ? 2 : 1;
 
@@ -162,6 +164,7 @@ __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, in
         const int64_t idx = (int64_t)r * o.rs + (int64_t)kk * o.ks;
         en.idx = idx;
         const int64_t base = (int64_t)G[r] - wS + 64 * (int64_t)L;  // sh = exp - base
+        const int64_t base_im = Gim ? (int64_t)Gim[r] - wS + 64 * (int64_t)L : base;
         const int32_t er = o.re.exp[idx], ei = o.im.exp[idx];
         if (er != EXP_ZERO) {
           en.z_re = 0;
@@ -171,7 +174,7 @@ __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, in
         if (ei != EXP_ZERO) {
           en.z_im = 0;
           en.neg_im = (o.im.sign[idx] ? 1 : 0) ^ flip;
-          en.sh_im = (int64_t)ei - base;
+          en.sh_im = (int64_t)ei - base_im;
         }
       }
     };
@@ -222,10 +225,13 @@ __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, in
       int64_t v[3];
       v[0] = fre + carry[q][0];
       v[1] = fim + carry[q][1];
-      // the third plane: Re + Im (3M), or -Im (4M B side) with a carry chain
-      // of its own, since negating a digit of -2^(w-1) would leave the range
-      v[2] = (third == (int)Third::SUM) ? fre + fim + carry[q][2]
-                                        : (third == (int)Third::NEG_IM ? carry[q][2] - fim : 0);
+      // the third plane: Re + Im (3M), -Im (4M B side) with a carry chain
+      // of its own, since negating a digit of -2^(w-1) would leave the range,
+      // or Re again (the B side of separately scaled parts)
+      v[2] = (third == (int)Third::SUM)      ? fre + fim + carry[q][2]
+             : (third == (int)Third::NEG_IM) ? carry[q][2] - fim
+             : (third == (int)Third::RE)     ? fre + carry[q][2]
+                                             : 0;
       const bool top = c == 0;  // the chunk holding digit 0, which keeps the remaining value
 #pragma unroll
       for (int j = g - 1; j >= 0; --j) {
@@ -305,6 +311,17 @@ __global__ __launch_bounds__(SPLIT_THREADS) void split2_kernel(DOperand op, DOpe
                                                  status, blockIdx.x, blockIdx.y, lds_raw, &op2, sign2);
 }
 
+// INT8 split with separate row scales for the Re (G) and Im (Gim) parts.
+template <bool ROWCONTIG, int TH>
+__global__ __launch_bounds__(SPLIT_THREADS) void split_parts_kernel(DOperand op, int prec, int L, int S, int Sp,
+                                                          int Sstride, int pad_lo, const int32_t* __restrict__ G,
+                                                          const int32_t* __restrict__ Gim, int Rpad, int Kpad,
+                                                          int8_t* __restrict__ out, int* status) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  split_tile<int8_t, ROWCONTIG, I8_W, TH>(op, prec, L, S, Sp, Sstride, pad_lo, I8_W, TH, G, Rpad, Kpad, out, status,
+                                          blockIdx.x, blockIdx.y, lds_raw, nullptr, 0, Gim);
+}
+
 // Batched INT8 form: job j owns (Kpad/64) * (Rpad/16) blocks.
 template <bool ROWCONTIG>
 __global__ __launch_bounds__(SPLIT_THREADS) void split_i8_batched(const SplitJob* __restrict__ jobs, int njobs,
@@ -378,6 +395,26 @@ hipError_t launch_split2_i8(const DOperand& op, const DOperand& op2, int sign2, 
       break;
   }
 #undef MPCG_SPLIT2
+  return hipGetLastError();
+}
+
+hipError_t launch_split_parts_i8(const DOperand& op, int prec, int L, int S, int Sp, int Sstride, int pad_lo,
+                                 Third third, const int32_t* G, const int32_t* Gim, int Rpad, int Kpad, int8_t* out,
+                                 int* status, hipStream_t stream) {
+  if (third != Third::NONE && third != Third::RE) return hipErrorInvalidValue;
+  const int nops = third == Third::NONE ? 2 : 3;
+  const size_t lds = (size_t)2 * nops * (56 / I8_W) * Layout<int8_t>::FRAG_BYTES;
+  dim3 grid(Kpad / 64, Rpad / 16);
+  const bool rc = op.rs == 1;
+#define MPCG_SPLITP(RC, T)                                                                                        \
+  split_parts_kernel<RC, T><<<grid, dim3(SPLIT_THREADS), lds, stream>>>(op, prec, L, S, Sp, Sstride, pad_lo, G, Gim, \
+                                                                        Rpad, Kpad, out, status)
+  if (third == Third::NONE) {
+    if (rc) MPCG_SPLITP(true, 0); else MPCG_SPLITP(false, 0);
+  } else {
+    if (rc) MPCG_SPLITP(true, 3); else MPCG_SPLITP(false, 3);
+  }
+#undef MPCG_SPLITP
   return hipGetLastError();
 }
 
