@@ -389,6 +389,46 @@ def adaptive_case(A, B, p):
     return {"cgemm2048_p1024_mixed_spread": out}
 
 
+def parts_case():
+    """Separate Re/Im scales on the 2048 workload at 1024 bits with every
+    imaginary part 2^200 below the real parts: one scale per row in 4M and 3M
+    (the slices cover the 200-bit gap) against the part_scales option in 4M;
+    the bits are compared on the device."""
+    import torch
+    import paper_2307_06072_amd as mp
+    from mpgen import workload_inputs
+    log("separate Re/Im scales: 2048^3, 1024 bits, Im parts 2^-200 below Re")
+    m, n, k, p, A, B = workload_inputs("cgemm2048_p1024_im200")
+    dA, dB = mp.to_device(A), mp.to_device(B)
+    del A, B
+    out, res = {}, []
+    mp.mpcg_set_stream()
+    for key, mode, parts in (("one_scale_4M", mp.MPCG_4M, 0), ("one_scale_3M", mp.MPCG_3M, 0),
+                             ("part_scales_4M", mp.MPCG_4M, 1)):
+        dC = mp.device_empty(m, n, p)
+        info = mp.mp_cgemm_ex(m, n, k, dA, dA.ld, dB, dB.ld, dC, dC.ld, p, mode, mp.MPCG_EXACT, part_scales=parts)
+        torch.cuda.synchronize()
+        reps = 2
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            mp.mp_cgemm_ex(m, n, k, dA, dA.ld, dB, dB.ld, dC, dC.ld, p, mode, mp.MPCG_EXACT, part_scales=parts)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        if mp.mpcg_stream_status() != 0:
+            raise RuntimeError(mp.mpcg_last_error())
+        out[key] = {"ms_per_call": 1000 * dt, "8mnk_per_s": 8.0 * m * n * k / dt, "S_A": info["S_A"],
+                    "S_B": info["S_B"], "pairs": info["pairs"], "part_scales": info["part_scales"],
+                    "gemm_frac_of_peak_est": info["algo_ops"] / dt / 1e12 / PEAK_INT8_TOPS}
+        res.append(dC)
+        log(f"  {key}: {1000 * dt:.1f} ms (S = {info['S_A']})")
+    same = all(torch.equal(getattr(getattr(res[0], h), f), getattr(getattr(res[i], h), f))
+               for i in (1, 2) for h in ("re", "im") for f in ("sign", "exp", "mant"))
+    out["identical_bits"] = bool(same)
+    out["speedup_over_one_scale_4M"] = out["one_scale_4M"]["ms_per_call"] / out["part_scales_4M"]["ms_per_call"]
+    out["speedup_over_one_scale_3M"] = out["one_scale_3M"]["ms_per_call"] / out["part_scales_4M"]["ms_per_call"]
+    return {"cgemm2048_p1024_im200": out}
+
+
 def lu_full_case(n=4096, nb=128, p=256):
     """The blocked LU workload: A with random entries (exponents on [-2, 2])
     plus n (1 + i) on the diagonal (each shifted component rounded once, by
@@ -637,7 +677,8 @@ def main() -> int:
                     help="block widths K of the paper-LU family (comma-separated)")
     ap.add_argument("--lu-precs", default="256",
                     help="precisions of the paper-LU family (comma-separated bits)")
-    ap.add_argument("--family", choices=["batched", "lu", "codec", "lufull", "lupaper", "adaptive"], default=None,
+    ap.add_argument("--family", choices=["batched", "lu", "codec", "lufull", "lupaper", "adaptive", "parts"],
+                    default=None,
                     help="only run one comparison family (for profiling) and print its record")
     args = ap.parse_args()
 
@@ -667,7 +708,8 @@ def main() -> int:
                "lufull": lambda: lu_full_case(),
                "lupaper": lambda: lu_paper_case(tuple(int(v) for v in args.lu_widths.split(",")),
                                                 tuple(int(v) for v in args.lu_precs.split(","))),
-               "adaptive": lambda: adaptive_case(*workload_inputs("cgemm2048_p1024")[4:], 1024)}[args.family]()
+               "adaptive": lambda: adaptive_case(*workload_inputs("cgemm2048_p1024")[4:], 1024),
+               "parts": parts_case}[args.family]()
         print(json.dumps({"family": args.family, **rec}), flush=True)
         return 0
     log(f"generating {args.workload}")
@@ -765,6 +807,9 @@ def main() -> int:
                               "strassen": infov["strassen"], "stage_us": stv,
                               "gemm_frac_of_peak": infov["algo_ops"] / (stv[2] * 1e-6) / 1e12 / PEAK_INT8_TOPS}
             del dAv, dBv, dCv, Av, Bv
+
+    if not args.no_extras and args.workload == "cgemm2048_p1024":
+        extra.update(parts_case())
 
     if not args.no_extras:
         extra.update(small_latency_case())
