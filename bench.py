@@ -738,7 +738,7 @@ def main() -> int:
             "traffic": (traffic_record(src, "strassen1" if info["strassen"] else "plain")
                         if args.slice == "int8" else None),
             "kernel": "gemm_i8_kernel (slice-pair GEMM + carry chain)" if args.slice == "int8"
-            else "gemm_f64_kernel", "launches_per_step": launches,
+            else "rocblas_dgemm + f64_accumulate_kernel", "launches_per_step": launches,
             "algo_ops_per_launch": info["algo_ops"] / launches, "avg_launch_us": gemm_us / launches}
     split_b, round_b = stage_bytes(m, n, k, p, info, args.mode == "3M", args.slice == "fp64")
     stage_report = {

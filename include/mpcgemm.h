@@ -129,8 +129,9 @@ int mp_cgemm(int m, int n, int k, const mpcg_cmat *A, int lda, const mpcg_cmat *
 /* Options for mp_cgemm_ex (NULL = defaults, all fields 0). */
 typedef struct {
     int slice_type;       /* MPCG_SLICE_INT8 (default) or MPCG_SLICE_FP64: FP64 slices of
-                             floor((53 - ceil(log2 k)) / 2) bits on FP64 matrix cores, the
-                             slice width rule of Algorithm 2 */
+                             floor((53 - ceil(log2 k)) / 2) bits, the slice width rule of
+                             Algorithm 2, their plane products as rocBLAS DGEMMs on the FP64
+                             matrix cores, accumulated exactly */
     int cutoff_override;  /* truncated scheme: > 0 keeps pairs with s + t <= cutoff_override
                              (no error bound is then promised); 0 = derived cutoff */
     int ksplit_override;  /* > 0: number of contraction chunks; 0 = planner's choice */
@@ -223,7 +224,8 @@ int mp_cgemm_ex(int m, int n, int k, const mpcg_cmat *A, int lda, const mpcg_cma
  *     arguments gives the workspace part; the scan adds 16 (m + n) bytes
  *     plus 256, rounded up to 256).  About 256 x 256 x 256 at 256 bits, or
  *     128^3 at 1024 bits, fit.
- *   - adaptive slicing (opt->adaptive without max_spread) is rejected with
+ *   - adaptive slicing (opt->adaptive without max_spread) and FP64 slices
+ *     (whose DGEMMs run through rocBLAS, which allocates) are rejected with
  *     MPCG_EUNSUPPORTED.
  *   - Without opt->max_spread the call reads its exponent scan back into host
  *     stack memory and synchronizes the stream once, as mp_cgemm_ex does; with

@@ -80,7 +80,8 @@ hipError_t launch_scan(const DOperand& op, RowStat* stats, ScanSummary* summary,
 //   G          per-row scale exponents (int32 [Rpad]); digits represent
 //              |x| / 2^G[r] = sum_s d_s 2^(-w(s+1)).
 //   out        INT8: int8 planes [nops][Sp][Rpad/16][Kpad/64][64][16];
-//              FP64: double planes [nops][Sp][Rpad/16][Kpad/4][64].
+//              FP64: one column-major matrix of nops Sp Rpad rows (row
+//              (o Sp + s) Rpad + r) and Kpad columns.
 enum class Third { NONE = 0, SUM = 1, NEG_IM = 2, RE = 3 };
 // INT8 planes hold Sstride slices each: pad_lo zero slices, the Sp digit
 // slices, then zero slices up to Sstride (all written by the split).
@@ -136,15 +137,29 @@ void gemm_i8_pads(int band, int* alo, int* ahi, int* blo, int* bhi);
 int gemm_i8_digit_chunks(int Dmax, int band);
 hipError_t launch_gemm_i8(const GemmArgs& a, int band, hipStream_t stream);
 
-struct GemmF64Args {
-  const double* X;
-  const double* Y;
-  int mt, nt, kblocks, ksplit, SA, SB, Dmax, mode3m, w;
+// The FP64 form: the slice-plane products are DGEMMs (rocBLAS) of stacked
+// column-major slice planes; these kernels accumulate them exactly.
+// C[q]: the products of the block s0 .. s1 - 1 of A's slices with B's slices
+// t = 0 .. tcnt - 1, row (s - s0) mpad + i, column t npad + j, leading
+// dimension ldc: 4M (Re Re, Im Im, Re Im, Im Re), 3M (Re Re, Im Im,
+// (Re+Im)(Re+Im)).  acc: int64 [2][Dmax + 1][n][m] diagonal sums of Re and Im.
+struct F64AccArgs {
+  const double* C[4];
+  int64_t ldc;
+  int s0, s1, tcnt, mpad, npad, m, n, Dmax, mode3m;
+  int64_t* acc;
+};
+hipError_t launch_f64_accumulate(const F64AccArgs& a, hipStream_t stream);
+// acc into the rounding kernel's FP64-order digit streams, tops and lowest
+// nonzero digits (one contraction chunk).
+struct F64CarryArgs {
+  const int64_t* acc;
+  int m, n, mt, nt, Dmax, w;
   uint32_t* digits;
   int64_t* top;
   int32_t* lnz;
 };
-hipError_t launch_gemm_f64(const GemmF64Args& a, hipStream_t stream);
+hipError_t launch_f64_carry(const F64CarryArgs& a, hipStream_t stream);
 
 // Merge chunk streams (if ksplit > 1), round to prec, write C.
 constexpr int MAX_MERGE = 16;

@@ -14,6 +14,10 @@
 #include <array>
 #include <vector>
 
+#include <map>
+
+#include <rocblas/rocblas.h>
+
 #include "../../include/mpcgemm.h"
 #include "mpcg_internal.h"
 
@@ -133,6 +137,9 @@ struct Plan {
   int sep;           // the four real products of separately scaled parts (FSEP GEMM form)
   int nchunk;        // INT8: 16-digit chunks per output component
   size_t off_G, off_H, off_X, off_Y, off_dig, off_top, off_lnz, off_scan, total;
+  // FP64 form: slices of A per DGEMM block, the block's products and the diagonal sums
+  int schunk, tcnt, ncombo;
+  size_t off_C, off_acc;
 };
 
 int plan_slices(Plan& P, int spreadA, int spreadB, int hatA, int hatB, const mpcg_options* opt) {
@@ -189,6 +196,9 @@ int pick_band(const Plan& P) {
   return ((P.mode3m || P.sep) && std::min(P.SA, P.SB) >= 64) ? 20 : 16;
 }
 
+// Bytes of one block of FP64 slice-plane products (at least one slice of A).
+constexpr size_t F64_BLOCK_BYTES = size_t(4) << 30;
+
 int plan_layout(Plan& P, const mpcg_options* opt) {
   P.mpad = (int)round_up(P.m, 32);
   P.npad = (int)round_up(P.n, 32);
@@ -196,7 +206,7 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
   P.mt = P.mpad / 16;
   P.nt = P.npad / 16;
   P.nopsA = P.mode3m ? 3 : 2;
-  P.nopsB = 3;
+  P.nopsB = (P.f64 && !P.mode3m) ? 2 : 3;  // the FP64 4M products take Im B itself
   const int groups = (P.mpad / 32) * (P.npad / 32);
   if (!P.f64) {
     // band width: diagonals accumulated together by one wavefront; from the
@@ -234,17 +244,27 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
     ks = std::max(ks, std::min(want, P.kblocks));
     P.ksplit = ks;
   } else {
+    // DGEMMs of the stacked slice planes: A's slices in blocks of schunk
+    // against B's first tcnt slices, the block's products within
+    // F64_BLOCK_BYTES; one contraction chunk (the slice width keeps every
+    // product entry below 2^53 over the whole contraction)
     P.block = 2;
-    P.SAp = (int)round_up(P.SA, 2);
-    P.SBp = (int)round_up(P.SB, 2);
+    P.SAp = P.SA;
+    P.SBp = P.SB;
     P.xs = P.SAp;
     P.ys = P.SBp;
     P.xlo = P.ylo = 0;
-    P.kblocks = P.kpad / 4;
-    int want = std::max(1, ceil_div(P.want_groups, groups));
-    P.ksplit = std::min(want, std::max(1, P.kpad / 64));
+    P.kblocks = P.kpad / 64;
+    P.ksplit = 1;
+    P.ncombo = P.mode3m ? 3 : 4;
+    P.tcnt = std::min(P.SB, P.Dmax + 1);
+    const size_t per_s = (size_t)P.ncombo * P.mpad * (size_t)P.tcnt * P.npad * 8;
+    P.schunk = (int)std::max<size_t>(1, std::min<size_t>(P.SA, F64_BLOCK_BYTES / per_s));
+    // truncated: about five blocks, each against the B slices its first
+    // slice reaches, so that few dropped pairs are computed
+    if (P.trunc) P.schunk = std::min(P.schunk, std::max(1, ceil_div(std::min(P.SA, P.Dmax + 1), 5)));
   }
-  if (opt && opt->ksplit_override > 0) {
+  if (opt && opt->ksplit_override > 0 && !P.f64) {
     if (!P.f64) {
       const long long terms_per_k = (long long)(P.mode3m || P.sep ? 1 : 2) * std::min(P.SA, P.SB);
       const long long kc_max = ((1ll << 31) - 1) / ((1ll << (2 * I8_W - 2)) * terms_per_k);
@@ -268,6 +288,8 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
   P.off_X = o; o = align256(o + (size_t)P.nopsA * P.xs * P.mpad * (size_t)P.kpad * esz);
   P.off_Y = o; o = align256(o + (size_t)P.nopsB * P.ys * P.npad * (size_t)P.kpad * esz);
   if (P.f64) {
+    P.off_C = o; o = align256(o + (size_t)P.ncombo * P.schunk * P.mpad * (size_t)P.tcnt * P.npad * 8);
+    P.off_acc = o; o = align256(o + 2 * nd * (size_t)P.m * P.n * 8);
     P.off_dig = o; o = align256(o + (size_t)P.ksplit * tiles * nd * 512 * dig_bytes);
   } else {  // [ksplit][tiles][slot 8][chunk][lane 64][16] digit bytes
     P.nchunk = gemm_i8_digit_chunks(P.Dmax, P.block);
@@ -620,6 +642,78 @@ int run_strassen(int m, int n, int k, const DOperand& opA, const DOperand& opB, 
 }
 
 // ---------------------------------------------------------------------------
+// FP64 form: the slice-plane products as DGEMMs (rocBLAS), accumulated
+// exactly into the diagonals, then carried into digit streams.
+// ---------------------------------------------------------------------------
+std::map<int, rocblas_handle> g_blas;  // per device, created on first use
+
+int blas_handle(rocblas_handle* h) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  auto it = g_blas.find(dev);
+  if (it == g_blas.end()) {
+    rocblas_handle nh;
+    const rocblas_status bs = rocblas_create_handle(&nh);
+    if (bs != rocblas_status_success) return set_err(MPCG_EHIP, "rocblas_create_handle: %s", rocblas_status_to_string(bs));
+    it = g_blas.emplace(dev, nh).first;
+  }
+  const rocblas_status bs = rocblas_set_stream(it->second, g_stream);
+  if (bs != rocblas_status_success) return set_err(MPCG_EHIP, "rocblas_set_stream: %s", rocblas_status_to_string(bs));
+  *h = it->second;
+  return MPCG_OK;
+}
+
+// X: nopsA planes of SA slices of mpad rows, column-major with leading
+// dimension nopsA SA mpad; Y alike.  Products of plane pairs (4M: (0,0),
+// (1,1), (0,1), (1,0); 3M: (0,0), (1,1), (2,2)), A's slices in blocks.
+int f64_products(const Plan& P, char* base, int L) {
+  (void)L;
+  rocblas_handle h;
+  int st;
+  if ((st = blas_handle(&h))) return st;
+  const double* X = reinterpret_cast<const double*>(base + P.off_X);
+  const double* Y = reinterpret_cast<const double*>(base + P.off_Y);
+  double* C = reinterpret_cast<double*>(base + P.off_C);
+  int64_t* acc = reinterpret_cast<int64_t*>(base + P.off_acc);
+  const int64_t ldx = (int64_t)P.nopsA * P.SAp * P.mpad, ldy = (int64_t)P.nopsB * P.SBp * P.npad;
+  HIP_TRY(launch_fill_zero(acc, 2 * (size_t)(P.Dmax + 1) * P.m * P.n * 8, g_stream));
+  static const int pairs4[4][2] = {{0, 0}, {1, 1}, {0, 1}, {1, 0}};
+  static const int pairs3[3][2] = {{0, 0}, {1, 1}, {2, 2}};
+  const double one = 1.0, zero = 0.0;
+  const int smax = std::min(P.SA, P.Dmax + 1);  // slices of A that reach a kept diagonal
+  for (int s0 = 0; s0 < smax; s0 += P.schunk) {
+    const int s1 = std::min(smax, s0 + P.schunk);
+    const int tcnt = std::min(P.tcnt, P.Dmax - s0 + 1);  // B slices reaching a kept diagonal
+    const int M = (s1 - s0) * P.mpad, N = tcnt * P.npad;
+    F64AccArgs fa{};
+    for (int q = 0; q < P.ncombo; ++q) {
+      const int oa = P.mode3m ? pairs3[q][0] : pairs4[q][0], ob = P.mode3m ? pairs3[q][1] : pairs4[q][1];
+      double* Cq = C + (size_t)q * P.schunk * P.mpad * (size_t)P.tcnt * P.npad;
+      const double* Xq = X + ((int64_t)oa * P.SAp + s0) * P.mpad;
+      const double* Yq = Y + (int64_t)ob * P.SBp * P.npad;
+      const rocblas_status bs = rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, M, N, P.kpad,
+                                              &one, Xq, ldx, Yq, ldy, &zero, Cq, M);
+      if (bs != rocblas_status_success) return set_err(MPCG_EHIP, "rocblas_dgemm: %s", rocblas_status_to_string(bs));
+      fa.C[q] = Cq;
+    }
+    fa.ldc = M;
+    fa.s0 = s0; fa.s1 = s1; fa.tcnt = tcnt;
+    fa.mpad = P.mpad; fa.npad = P.npad; fa.m = P.m; fa.n = P.n;
+    fa.Dmax = P.Dmax; fa.mode3m = P.mode3m;
+    fa.acc = acc;
+    HIP_TRY(launch_f64_accumulate(fa, g_stream));
+  }
+  F64CarryArgs ca{};
+  ca.acc = acc;
+  ca.m = P.m; ca.n = P.n; ca.mt = P.mt; ca.nt = P.nt; ca.Dmax = P.Dmax; ca.w = P.w;
+  ca.digits = reinterpret_cast<uint32_t*>(base + P.off_dig);
+  ca.top = reinterpret_cast<int64_t*>(base + P.off_top);
+  ca.lnz = reinterpret_cast<int32_t*>(base + P.off_lnz);
+  HIP_TRY(launch_f64_carry(ca, g_stream));
+  return MPCG_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Separate scales for the Re and Im parts (4M, exact): each part of a row of
 // A (column of B) is scaled by its own maximum, so a part far below the
 // other costs no slices; the four real products run as two GEMMs of two
@@ -823,6 +917,8 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
   if (acc && opt && opt->slice_type == MPCG_SLICE_FP64)
     return set_err(MPCG_EUNSUPPORTED, "the accumulating form needs INT8 slices");
   if (info) memset(info, 0, sizeof(*info));
+  if (fixed && opt && opt->slice_type == MPCG_SLICE_FP64)
+    return set_err(MPCG_EUNSUPPORTED, "FP64 slices run their products through rocBLAS, which allocates");
   if (fixed && opt && opt->adaptive && opt->max_spread <= 0)
     return set_err(MPCG_EUNSUPPORTED, "adaptive slicing runs a batch, which this entry point cannot");
   if (m == 0 || n == 0) return MPCG_OK;
@@ -974,7 +1070,7 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
   HIP_TRY(launch_scales(statA, m, P.mpad, P.x, G, g_stream));
   HIP_TRY(launch_scales(statB, n, P.npad, P.x, H, g_stream));
   const Third thirdA = P.mode3m ? Third::SUM : Third::NONE;
-  const Third thirdB = P.mode3m ? Third::SUM : Third::NEG_IM;
+  const Third thirdB = P.mode3m ? Third::SUM : (P.f64 ? Third::NONE : Third::NEG_IM);
   if (!P.f64) {
     HIP_TRY(launch_split_i8(opA, prec_bits, L, P.SA, P.SAp, P.xs, P.xlo, thirdA, G, P.mpad, P.kpad,
                             reinterpret_cast<int8_t*>(base + P.off_X), status, g_stream));
@@ -1000,14 +1096,8 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
     ga.digits = base + P.off_dig; ga.top = top; ga.lnz = lnz;
     ga.xs = P.xs; ga.ys = P.ys; ga.xlo = P.xlo; ga.ylo = P.ylo;
     HIP_TRY(launch_gemm_i8(ga, P.block, g_stream));
-  } else {
-    GemmF64Args ga{};
-    ga.X = reinterpret_cast<const double*>(base + P.off_X);
-    ga.Y = reinterpret_cast<const double*>(base + P.off_Y);
-    ga.mt = P.mt; ga.nt = P.nt; ga.kblocks = P.kblocks; ga.ksplit = P.ksplit;
-    ga.SA = P.SAp; ga.SB = P.SBp; ga.Dmax = P.Dmax; ga.mode3m = P.mode3m; ga.w = P.w;
-    ga.digits = reinterpret_cast<uint32_t*>(base + P.off_dig); ga.top = top; ga.lnz = lnz;
-    HIP_TRY(launch_gemm_f64(ga, g_stream));
+  } else if ((st = f64_products(P, base, L))) {
+    return st;
   }
   if ((st = stage(3))) return st;
 

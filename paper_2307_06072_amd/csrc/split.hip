@@ -123,7 +123,7 @@ __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, in
                                   int w_rt, int third_rt, const int32_t* __restrict__ G, int Rpad, int Kpad,
                                   DT* __restrict__ out, int* status, int kt, int rt, unsigned char* lds_raw,
                                   const DOperand* op2 = nullptr, int sign2 = 0,
-                                  const int32_t* __restrict__ Gim = nullptr) {
+                                  const int32_t* __restrict__ Gim = nullptr, int64_t cm_ld = 0) {
   constexpr int FRAG = Layout<DT>::FRAG_BYTES / (int)sizeof(DT);  // elements per (op, digit) tile
   constexpr int NBUF = sizeof(DT) == 1 ? 2 : 1;
 
@@ -265,10 +265,20 @@ __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, in
       const int s = g * c + j;
       if (s >= Sp) continue;
       const uint4* src = reinterpret_cast<const uint4*>(buf + (size_t)oj * Layout<DT>::FRAG_BYTES);
-      uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<unsigned char*>(out) +
-                                            Layout<DT>::tile_base((int64_t)o * Sstride + pad_lo + s, rt, kt,
-                                                                  Rpad / 16, Kpad, (int64_t)nops * Sstride));
-      dst[u] = src[u];
+      if constexpr (sizeof(DT) == 8) {
+        // doubles: one column-major matrix of leading dimension cm_ld whose
+        // row (plane, slice, r) is (o Sstride + pad_lo + s) Rpad + r; the
+        // fragment holds 16 consecutive rows of each of its 64 columns
+        const int kl = u >> 3, q2 = u & 7;
+        const int64_t row0 = ((int64_t)o * Sstride + pad_lo + s) * Rpad + (int64_t)rt * 16;
+        double* dst = reinterpret_cast<double*>(out) + ((int64_t)kt * 64 + kl) * cm_ld + row0 + 2 * q2;
+        *reinterpret_cast<uint4*>(dst) = src[u];
+      } else {
+        uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<unsigned char*>(out) +
+                                              Layout<DT>::tile_base((int64_t)o * Sstride + pad_lo + s, rt, kt,
+                                                                    Rpad / 16, Kpad, (int64_t)nops * Sstride));
+        dst[u] = src[u];
+      }
     }
     if (NBUF == 1) __syncthreads();
   }
@@ -294,10 +304,10 @@ template <typename DT, bool ROWCONTIG, int WC, int TH>
 __global__ __launch_bounds__(SPLIT_THREADS) void split_kernel(DOperand op, int prec, int L, int S, int Sp, int Sstride,
                                                     int pad_lo, int w, int third,
                                                     const int32_t* __restrict__ G, int Rpad, int Kpad,
-                                                    DT* __restrict__ out, int* status) {
+                                                    DT* __restrict__ out, int* status, int64_t cm_ld) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   split_tile<DT, ROWCONTIG, WC, TH>(op, prec, L, S, Sp, Sstride, pad_lo, w, third, G, Rpad, Kpad, out, status,
-                                    blockIdx.x, blockIdx.y, lds_raw);
+                                    blockIdx.x, blockIdx.y, lds_raw, nullptr, 0, nullptr, cm_ld);
 }
 
 // INT8 split of op + sign2 * op2.
@@ -339,7 +349,7 @@ __global__ __launch_bounds__(SPLIT_THREADS) void split_i8_batched(const SplitJob
 template <typename DT, int WC, int TH>
 hipError_t launch_split_t(const DOperand& op, int prec, int L, int S, int Sp, int Sstride, int pad_lo, int w,
                           Third third, const int32_t* G, int Rpad, int Kpad, DT* out, int* status,
-                          hipStream_t stream) {
+                          hipStream_t stream, int64_t cm_ld = 0) {
   const int g = 56 / w;
   const int nops = third == Third::NONE ? 2 : 3;
   const size_t lds = (size_t)(sizeof(DT) == 1 ? 2 : 1) * nops * g * Layout<DT>::FRAG_BYTES;
@@ -347,11 +357,11 @@ hipError_t launch_split_t(const DOperand& op, int prec, int L, int S, int Sp, in
   if (op.rs == 1)
     split_kernel<DT, true, WC, TH><<<grid, dim3(SPLIT_THREADS), lds, stream>>>(op, prec, L, S, Sp, Sstride, pad_lo,
                                                                                 w, (int)third, G, Rpad, Kpad, out,
-                                                                                status);
+                                                                                status, cm_ld);
   else
     split_kernel<DT, false, WC, TH><<<grid, dim3(SPLIT_THREADS), lds, stream>>>(op, prec, L, S, Sp, Sstride, pad_lo,
                                                                                  w, (int)third, G, Rpad, Kpad, out,
-                                                                                 status);
+                                                                                 status, cm_ld);
   return hipGetLastError();
 }
 
@@ -420,7 +430,9 @@ hipError_t launch_split_parts_i8(const DOperand& op, int prec, int L, int S, int
 
 hipError_t launch_split_f64(const DOperand& op, int prec, int L, int S, int Sp, int w, Third third,
                             const int32_t* G, int Rpad, int Kpad, double* out, int* status, hipStream_t stream) {
-  return launch_split_t<double, 0, -1>(op, prec, L, S, Sp, Sp, 0, w, third, G, Rpad, Kpad, out, status, stream);
+  const int nops = third == Third::NONE ? 2 : 3;
+  return launch_split_t<double, 0, -1>(op, prec, L, S, Sp, Sp, 0, w, third, G, Rpad, Kpad, out, status, stream,
+                                       (int64_t)nops * Sp * Rpad);
 }
 
 hipError_t launch_split_i8_batched(const SplitJob* jobs, int njobs, const int* first, int blocks, int prec, int L,

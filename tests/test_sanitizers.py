@@ -88,7 +88,7 @@ def test_host_code_under_sanitizers(tmp_path):
         subprocess.run(cmd, check=True, capture_output=True)
         host_objs.append(obj)
     lib = str(tmp_path / "libmpcgemm_san.so")
-    subprocess.run([hipcc, "--offload-arch=gfx950", "-shared", "-o", lib, *host_objs, *dev_objs], check=True)
+    subprocess.run([hipcc, "--offload-arch=gfx950", "-shared", "-o", lib, *host_objs, *dev_objs, *b.LINK], check=True)
     env = {"LD_PRELOAD": asan, "MPCG_LIBRARY": lib}
     probe = _run_child(["-c", "import ctypes, paper_2307_06072_amd as mp; print(mp.LIB_PATH); "
                               "ctypes.CDLL(None).__asan_init"], env, timeout=300)
