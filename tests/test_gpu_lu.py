@@ -237,3 +237,35 @@ def test_diagonal_shift_as_row_update():
     assert mp.mpcg_stream_status() == 0
     bad, first = mismatches(device_result_to_host(dA, p), want, n, n)
     assert bad == 0, (bad, first)
+
+
+@pytest.mark.parametrize("nb", [4, 2])
+def test_pivot_with_parts_90_bits_apart(nb):
+    """Row 1 is row 0 plus 1 + 2^-90 i in column 1, and column 0's largest
+    entries sit in rows 0 and 1, so elimination leaves the pivot 1 + 2^-90 i,
+    whose parts are 90 bits apart although no entry of A has such a gap: the
+    pivot search, the reciprocal and the scaling by it see the wide spread.
+    Factors, interchanges and status equal the oracle's (U(1, 1) =
+    1 + 2^-90 i exactly)."""
+    import torch
+    import paper_2307_06072_amd as mp
+    F = Fraction
+    p = 256
+    e = F(2) ** -90
+    vals = [[(F(8), F(0)), (F(1, 2), F(3, 4)), (F(3, 8), F(-1, 4)), (F(-1, 2), F(1, 8))],
+            [(F(8), F(0)), (F(3, 2), F(3, 4) + e), (F(1, 4), F(1, 2)), (F(1, 8), F(-3, 8))],
+            [(F(0), F(0)), (F(1, 4), F(1, 4)), (F(1), F(1, 2)), (F(1, 2), F(0))],
+            [(F(0), F(0)), (F(-1, 4), F(1, 8)), (F(0), F(1, 2)), (F(1), F(-1, 4))]]
+    A = to_cmat(vals, p)
+    n = 4
+    _say(f"getrf pivot 1 + 2^-90 i nb={nb}")
+    dA, ipiv, info = _factor(A, nb, p, 1)
+    ref, ref_piv, ref_info = lu_ref.getrf(A, nb, p)
+    assert info == ref_info == 0
+    assert np.array_equal(ipiv.cpu().numpy()[:n], ref_piv)
+    F_dev = device_result_to_host(dA, p)
+    bad, first = mismatches(F_dev, ref, n, n)
+    assert bad == 0, (bad, first)
+    assert decode(F_dev.im, 1, 1, p) == e
+    torch.cuda.synchronize()
+    assert mp.mpcg_stream_status() == 0
