@@ -231,11 +231,11 @@ struct Producer {
       }
     }
   }
-  __device__ inline void start() {
-    band = 0;
+  __device__ inline void start(int band0) {
+    band = band0;
     pass = 0;
     kb = kb0;
-    g.set(0, W, Dmax, SA, SB);
+    g.set(band0, W, Dmax, SA, SB);
     done = false;
     unit_begin();
   }
@@ -379,9 +379,18 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
   const int ti = 2 * gi + wi;
   const int tj = 2 * gj + wj;
   const int tile = tj * a.mt + ti;
+  // stream `split`: contraction chunk split / bs and, when the bands are
+  // split over workgroups (bs > 1), the bands of group split % bs only
+  const int bs = a.bsplit > 1 ? a.bsplit : 1;
+  const int kchunk = split / bs;
+  const int nb_all = (a.Dmax + W) / W;
+  const int bpg = (nb_all + bs - 1) / bs;  // bands per group
+  const int band_lo = min(nb_all, (split - kchunk * bs) * bpg);
+  const int band_hi = min(nb_all, band_lo + bpg);
   const int kbps = (a.kblocks + a.ksplit - 1) / a.ksplit;
-  const int kb0 = split * kbps;
+  const int kb0 = kchunk * kbps;
   const int kb1 = min(a.kblocks, kb0 + kbps);
+  if (band_lo >= band_hi) return;  // no band in this group (the host plans none such)
 
   Producer<W, F> P;
   // tile-major planes: consecutive slices of one tile and plane are a k-row
@@ -396,7 +405,7 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
   P.SA = a.SAp;
   P.SB = a.SBp;
   P.Dmax = a.Dmax;
-  P.nbands = (a.Dmax + W) / W;
+  P.nbands = band_hi;
   P.kb0 = kb0;
   P.kb1 = kb1;
   {
@@ -406,7 +415,7 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
     const int8_t* Y0 = a.Y + (size_t)(2 * gj) * ytile;  // column tiles 2gj, 2gj+1
     P.share(wv, X0, X0 + xtile, Y0, Y0 + ytile);
   }
-  P.start();
+  P.start(band_lo);
 
   C c;
   c.q = lds_queue;
@@ -523,7 +532,16 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
   // least significant first: upward bands with s_lo > 0, the upward band(s)
   // from s_lo = 0 that stop short of d0 + W - 1, then the downward ones (each
   // class is a contiguous run of the band order)
-  int band = 0;
+  // a stream of one band: its less significant digits are zero
+  for (int q = 0; q < W * band_lo; q += 4) {
+    const uint32_t at = (uint32_t)(q >> 4) * 1024u + (uint32_t)(q & 15) + dig_lane;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      *reinterpret_cast<uint32_t*>(dig + ((uint32_t)r * (uint32_t)slot_stride + at)) = 0u;
+      *reinterpret_cast<uint32_t*>(dig + ((uint32_t)(4 + r) * (uint32_t)slot_stride + at)) = 0u;
+    }
+  }
+  int band = band_lo;
 #pragma unroll 1
   for (; band < P.nbands && a.Dmax + 1 - W * (band + 1) > a.SBp - 1 &&
          !band_down(a.Dmax + 1 - W * (band + 1), W, a.SAp, a.SBp); ++band)
@@ -533,6 +551,34 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
     band_body(band, std::integral_constant<int, 1>{});
 #pragma unroll 1
   for (; band < P.nbands; ++band) band_body(band, std::integral_constant<int, 2>{});
+  // a stream of one band: its carry runs on through the more significant digits
+  for (int q = W * band_hi; q < W * nb_all; q += 4) {
+    uint32_t wr[4], wi[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) wr[r] = wi[r] = 0u;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int d = a.Dmax - (q + b);
+      if (d >= 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const uint32_t dre = (uint32_t)(cre[r] & ((1 << I8_W) - 1)), dim = (uint32_t)(cim[r] & ((1 << I8_W) - 1));
+          cre[r] >>= I8_W;
+          cim[r] >>= I8_W;
+          if (dre && lre[r] < 0) lre[r] = d;
+          if (dim && lim[r] < 0) lim[r] = d;
+          wr[r] |= dre << (8 * b);
+          wi[r] |= dim << (8 * b);
+        }
+      }
+    }
+    const uint32_t at = (uint32_t)(q >> 4) * 1024u + (uint32_t)(q & 15) + dig_lane;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      *reinterpret_cast<uint32_t*>(dig + ((uint32_t)r * (uint32_t)slot_stride + at)) = wr[r];
+      *reinterpret_cast<uint32_t*>(dig + ((uint32_t)(4 + r) * (uint32_t)slot_stride + at)) = wi[r];
+    }
+  }
   // the producer ran past the end of the stream: drain its loads before the LDS is released
   wait_vmcnt<0>();
 
@@ -576,7 +622,7 @@ __global__ __launch_bounds__(256) void gemm_i8_batched_kernel(const GemmArgs* __
 template <int W, int F>
 hipError_t launch_wm(const GemmArgs& a, hipStream_t stream) {
   using G = Q<W, F>;
-  const int blocks = (a.mt / 2) * (a.nt / 2) * a.ksplit;
+  const int blocks = (a.mt / 2) * (a.nt / 2) * a.ksplit * (a.bsplit > 1 ? a.bsplit : 1);
   const size_t lds = (size_t)G::QS * G::ENT * 1024;
   hipError_t e = hipFuncSetAttribute((const void*)gemm_i8_kernel<W, F>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -117,6 +117,9 @@ struct GemmArgs {
   int mt, nt;        // 16-row tiles of A, 16-column tiles of B
   int kblocks;       // Kpad / 64 (INT8) or Kpad / 4 (FP64)
   int ksplit;        // contraction chunks
+  int bsplit;        // > 1: the bands run in bsplit groups of consecutive bands on separate
+                     // workgroups, one digit stream each; the streams of chunk c are
+                     // c bsplit .. c bsplit + bsplit - 1 (a group may be empty)
   int SAp, SBp;      // slice counts of the A and B operands
   int xs, ys;        // slices per A / B plane including the zero pads
   int xlo, ylo;      // zero slices below slice 0 of an A / B plane

@@ -135,6 +135,8 @@ struct Plan {
   int tune_S;        // MPCG_AUTO: the 3M slice count the cache is keyed by (else the plan's own)
   int extra_x;       // more headroom bits (1 for the operand sums of Strassen's recursion)
   int sep;           // the four real products of separately scaled parts (FSEP GEMM form)
+  int allow_bsplit;  // the plain path: a product of few work items may run its bands apart
+  int bsplit;        // bands on separate workgroups (1: all bands in one work item)
   int nchunk;        // INT8: 16-digit chunks per output component
   size_t off_G, off_H, off_X, off_Y, off_dig, off_top, off_lnz, off_scan, total;
   // FP64 form: slices of A per DGEMM block, the block's products and the diagonal sums
@@ -195,6 +197,11 @@ size_t scan_bytes(int m, int n) {
 int pick_band(const Plan& P) {
   return ((P.mode3m || P.sep) && std::min(P.SA, P.SB) >= 64) ? 20 : 16;
 }
+
+// Work items (2x2 tile groups x contraction chunks) below which the bands of
+// a product run on separate workgroups.
+constexpr long long BSPLIT_ITEMS = 128;
+constexpr int BSPLIT_STREAMS = 16;
 
 // Bytes of one block of FP64 slice-plane products (at least one slice of A).
 constexpr size_t F64_BLOCK_BYTES = size_t(4) << 30;
@@ -278,6 +285,17 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
     const int kbps = ceil_div(P.kblocks, P.ksplit);
     P.ksplit = ceil_div(P.kblocks, kbps);
   }
+  // a product of few work items runs its bands in groups on workgroups of
+  // their own (one digit stream per group, added up by the rounding kernel),
+  // so its latency is a group's rather than all bands in turn; at most
+  // BSPLIT_STREAMS streams in all
+  P.bsplit = 1;
+  if (P.allow_bsplit && !P.f64 && (long long)groups * P.ksplit < BSPLIT_ITEMS) {
+    const int nb = (P.Dmax + P.block) / P.block;
+    const int bs = std::max(1, std::min(nb, BSPLIT_STREAMS / P.ksplit));
+    P.bsplit = ceil_div(nb, ceil_div(nb, bs));  // no empty group
+  }
+  const int streams = P.ksplit * P.bsplit;
   const size_t esz = P.f64 ? 8 : 1;
   const size_t tiles = (size_t)P.mt * P.nt;
   const size_t nd = (size_t)P.Dmax + 1;
@@ -293,10 +311,10 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
     P.off_dig = o; o = align256(o + (size_t)P.ksplit * tiles * nd * 512 * dig_bytes);
   } else {  // [ksplit][tiles][slot 8][chunk][lane 64][16] digit bytes
     P.nchunk = gemm_i8_digit_chunks(P.Dmax, P.block);
-    P.off_dig = o; o = align256(o + (size_t)P.ksplit * tiles * 8 * P.nchunk * 1024);
+    P.off_dig = o; o = align256(o + (size_t)streams * tiles * 8 * P.nchunk * 1024);
   }
-  P.off_top = o; o = align256(o + (size_t)P.ksplit * tiles * 512 * 8);
-  P.off_lnz = o; o = align256(o + (size_t)P.ksplit * tiles * 512 * 4);
+  P.off_top = o; o = align256(o + (size_t)streams * tiles * 512 * 8);
+  P.off_lnz = o; o = align256(o + (size_t)streams * tiles * 512 * 4);
   P.off_scan = o; o = align256(o + scan_bytes(P.m, P.n));
   P.total = o;
   return MPCG_OK;
@@ -945,6 +963,7 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
   P.trunc = scheme == MPCG_TRUNCATED;
   P.f64 = opt && opt->slice_type == MPCG_SLICE_FP64;
   P.want_groups = 512;
+  P.allow_bsplit = 1;
   const int bound = opt ? opt->max_spread : 0;
   tune_env_load();
   const size_t sA = align256(sizeof(RowStat) * (size_t)m), sB = align256(sizeof(RowStat) * (size_t)n);
@@ -1091,7 +1110,7 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
     GemmArgs ga{};
     ga.X = reinterpret_cast<const int8_t*>(base + P.off_X);
     ga.Y = reinterpret_cast<const int8_t*>(base + P.off_Y);
-    ga.mt = P.mt; ga.nt = P.nt; ga.kblocks = P.kblocks; ga.ksplit = P.ksplit;
+    ga.mt = P.mt; ga.nt = P.nt; ga.kblocks = P.kblocks; ga.ksplit = P.ksplit; ga.bsplit = P.bsplit;
     ga.SAp = P.SAp; ga.SBp = P.SBp; ga.Dmax = P.Dmax; ga.form = P.mode3m ? F3M : F4M;
     ga.digits = base + P.off_dig; ga.top = top; ga.lnz = lnz;
     ga.xs = P.xs; ga.ys = P.ys; ga.xlo = P.xlo; ga.ylo = P.ylo;
@@ -1108,7 +1127,7 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
   ra.nchunk = P.nchunk;
   ra.f64_layout = P.f64;
   ra.top = top; ra.lnz = lnz;
-  ra.ksplit = P.ksplit; ra.mt = P.mt; ra.nt = P.nt; ra.Dmax = P.Dmax; ra.w = P.w;
+  ra.ksplit = P.ksplit * P.bsplit; ra.mt = P.mt; ra.nt = P.nt; ra.Dmax = P.Dmax; ra.w = P.w;
   ra.G = G; ra.H = H; ra.m = m; ra.n = n; ra.prec = prec_bits; ra.L = L;
   ra.cre = cre; ra.cim = cim; ra.ldc = ldc; ra.status = status;
   ra.acc = acc;
@@ -2226,6 +2245,7 @@ size_t mpcg_workspace_size(int m, int n, int k, int prec_bits, int mode, int sch
   P.trunc = scheme == MPCG_TRUNCATED;
   P.f64 = opt && opt->slice_type == MPCG_SLICE_FP64;
   P.want_groups = 512;
+  P.allow_bsplit = 1;  // as the call plans it
   if (plan_slices(P, max_spread, max_spread, max_spread, max_spread, opt)) return 0;
   if (plan_layout(P, opt)) return 0;
   return P.total;

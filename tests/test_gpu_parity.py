@@ -150,3 +150,16 @@ def test_rounding_bit_below_limb_zero(p):
     B = random_cmat(90 + p, 1, k, n, p, 12)
     _check_exact(A, B, p, M3)
     _check_exact(A, B, p, M4)
+
+
+@pytest.mark.parametrize("mode", [M4, M3])
+@pytest.mark.parametrize("shape,p", [((40, 36, 1), 256), ((17, 70, 2), 130), ((100, 3, 5), 512), ((33, 33, 8), 64),
+                                     ((20, 18, 9), 200), ((16, 16, 1), 4096), ((1, 40, 3), 1000)])
+def test_short_contraction(mode, shape, p):
+    """Contractions of 1 to 9 (one 64-wide block, mostly padding), at 64 to
+    4096 bits: few work items, so each band runs on a workgroup of its own
+    and the rounding adds the bands' streams.  Exact bits."""
+    m, n, k = shape
+    A = random_cmat([81, m, n, k], 0, m, k, p, 9, zero_frac=0.1)
+    B = random_cmat([81, m, n, k], 1, k, n, p, 9, zero_frac=0.1)
+    _check_exact(A, B, p, mode)
