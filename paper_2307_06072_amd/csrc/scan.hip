@@ -172,6 +172,80 @@ __global__ __launch_bounds__(256) void summary_kernel(const RowStat* stats, int 
   summary_body(stats, R, summary, limit, status_word);
 }
 
+// A small operand (at most 512 rows of at most 256, 2^16 entries) in one launch:
+// one workgroup scans 64 rows at a time with 16 lanes per row, then reduces
+// the summary (what stats_init, the scan and the summary kernels do in three
+// launches).
+constexpr int64_t SCAN_SMALL_ENTRIES = 1 << 16;
+
+__global__ __launch_bounds__(1024) void scan_small_kernel(DOperand op, RowStat* stats, ScanSummary* summary,
+                                                          int limit, int* status_word) {
+  // 64 rows at a time, 16 contraction lanes per row
+  __shared__ Acc part[16][64];
+  __shared__ int32_t s_sp[1024], s_hat[1024], s_nz[1024], s_bad[1024];
+  const int rl = threadIdx.x & 63, kl = threadIdx.x >> 6;
+  int32_t sp = 0, hat = 0, nz = 0, bad = 0;
+  for (int r0 = 0; r0 < op.R; r0 += 64) {
+    const int r = r0 + rl;
+    Acc a{INT32_MIN, INT32_MAX, INT32_MAX, 0};
+    if (r < op.R)
+      for (int kk = kl; kk < op.K; kk += 16) {
+        const int64_t idx = (int64_t)r * op.rs + (int64_t)kk * op.ks;
+        consume(a, op.re.exp[idx], op.im.exp[idx]);
+      }
+    part[kl][rl] = a;
+    __syncthreads();
+    if (kl == 0 && r < op.R) {
+      for (int q = 1; q < 16; ++q) {
+        a.emax = max(a.emax, part[q][rl].emax);
+        a.emin = min(a.emin, part[q][rl].emin);
+        a.ehat = min(a.ehat, part[q][rl].ehat);
+        a.bad |= part[q][rl].bad;
+      }
+      RowStat st;
+      st.emax = a.emax;
+      st.emin = a.emax == INT32_MIN ? INT32_MAX : a.emin;
+      st.ehat = a.emax == INT32_MIN ? INT32_MAX : a.ehat;
+      st.pad = 0;
+      stats[r] = st;
+      if (a.emax != INT32_MIN) {
+        sp = max(sp, a.emax - a.emin);
+        hat = max(hat, a.emax - a.ehat);
+        nz += 1;
+      }
+      bad |= a.bad;
+    }
+    __syncthreads();
+  }
+  s_sp[threadIdx.x] = sp;
+  s_hat[threadIdx.x] = hat;
+  s_nz[threadIdx.x] = nz;
+  s_bad[threadIdx.x] = bad;
+  __syncthreads();
+  for (int off = 512; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      s_sp[threadIdx.x] = max(s_sp[threadIdx.x], s_sp[threadIdx.x + off]);
+      s_hat[threadIdx.x] = max(s_hat[threadIdx.x], s_hat[threadIdx.x + off]);
+      s_nz[threadIdx.x] += s_nz[threadIdx.x + off];
+      s_bad[threadIdx.x] |= s_bad[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    ScanSummary z;
+    z.spread = s_sp[0];
+    z.hat = s_hat[0];
+    z.nonzero = s_nz[0];
+    z.status = s_bad[0] ? ST_IN_RANGE : 0;
+    *summary = z;
+    if (status_word) {
+      int bits = z.status;
+      if (z.spread > limit || z.hat > limit) bits |= ST_SPREAD;
+      if (bits) atomicOr(status_word, bits);
+    }
+  }
+}
+
 __device__ inline void scales_body(const RowStat* stats, int R, int Rpad, int x, int32_t* G, int blk) {
   const int r = blk * 256 + (int)threadIdx.x;
   if (r >= Rpad) return;
@@ -261,6 +335,10 @@ void scan_blocks(const DOperand& op, int* init_blocks, int* nblocks, int* kchunk
 
 hipError_t launch_scan(const DOperand& op, RowStat* stats, ScanSummary* summary, int limit, int* status_word,
                        hipStream_t stream) {
+  if ((int64_t)op.R * op.K <= SCAN_SMALL_ENTRIES && op.K <= 256 && op.R <= 512) {
+    scan_small_kernel<<<dim3(1), dim3(1024), 0, stream>>>(op, stats, summary, limit, status_word);
+    return hipGetLastError();
+  }
   int ib, nb, kchunk, rblocks;
   scan_blocks(op, &ib, &nb, &kchunk, &rblocks);
   stats_init_kernel<<<dim3(ib), dim3(256), 0, stream>>>(stats, op.R, summary);
