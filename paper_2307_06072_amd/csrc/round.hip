@@ -976,7 +976,20 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
       int32_t sum[16];
 #pragma unroll
       for (int b = 0; b < 16; ++b) sum[b] = 0;
-      for (int q = 0; q < a.ksplit; ++q) {
+      // four streams' loads in flight at a time
+      int q = 0;
+      for (; q + 4 <= a.ksplit; q += 4) {
+        uint4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = *reinterpret_cast<const uint4*>(g0 + (q + u) * sstride + (size_t)ch * 1024);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const uint32_t wv[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+          for (int b = 0; b < 16; ++b) sum[b] += (int32_t)((wv[b >> 2] >> (8 * (b & 3))) & 255u);
+        }
+      }
+      for (; q < a.ksplit; ++q) {
         acc[0] = *reinterpret_cast<const uint4*>(g0 + q * sstride + (size_t)ch * 1024);
         const uint32_t wv[4] = {acc[0].x, acc[0].y, acc[0].z, acc[0].w};
 #pragma unroll
