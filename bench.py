@@ -159,7 +159,45 @@ def small_latency_case():
         dt, info, st = time_calls(dA, dB, dC, m, n, k, p, _mode(md), _scheme("exact"), _slice(sl), steps=20, warmup=3)
         out[f"{sl}_{md}_exact"] = {"ms_per_call": 1000 * dt / 20, "8mnk_per_s": 8.0 * m * n * k * 20 / dt,
                                    "stage_us": st, "S_A": info["S_A"], "pairs": info["pairs"]}
+    # one-call latency of tiny products (timing events off)
+    lat = {}
+    for (mm, nn, kk) in ((1, 1, 1), (16, 16, 16), (64, 64, 64)):
+        from mpgen import random_cmat
+        A1 = random_cmat(3, 0, mm, kk, p, 4)
+        B1 = random_cmat(3, 1, kk, nn, p, 4)
+        d1, d2, d3 = mp.to_device(A1), mp.to_device(B1), mp.device_empty(mm, nn, p)
+        mp.mpcg_set_stream()
+        for _ in range(10):
+            mp.mp_cgemm_ex(mm, nn, kk, d1, d1.ld, d2, d2.ld, d3, d3.ld, p, mp.MPCG_3M, mp.MPCG_EXACT)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(50):
+            mp.mp_cgemm_ex(mm, nn, kk, d1, d1.ld, d2, d2.ld, d3, d3.ld, p, mp.MPCG_3M, mp.MPCG_EXACT)
+        torch.cuda.synchronize()
+        lat[f"{mm}x{nn}x{kk}"] = 1e6 * (time.perf_counter() - t0) / 50
+    out["int8_3M_exact_latency_us"] = lat
     return {"cgemm64_p256": out}
+
+
+def f64_case(calls=3):
+    """The FP64 plain form on the 512^3 / 512-bit workload (4M exact), `calls`
+    calls (for profiling the DGEMMs and the accumulation)."""
+    import torch
+    import paper_2307_06072_amd as mp
+    from mpgen import workload_inputs
+    m, n, k, p, A, B = workload_inputs("cgemm512_p512")
+    dA, dB, dC = mp.to_device(A), mp.to_device(B), mp.device_empty(m, n, p)
+    mp.mpcg_set_stream()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        info = mp.mp_cgemm_ex(m, n, k, dA, dA.ld, dB, dB.ld, dC, dC.ld, p, mp.MPCG_4M, mp.MPCG_EXACT,
+                              slice_type=mp.MPCG_SLICE_FP64)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / calls
+    if mp.mpcg_stream_status() != 0:
+        raise RuntimeError(mp.mpcg_last_error())
+    return {"fp64_4M_exact_512": {"calls": calls, "ms_per_call_incl_first": 1000 * dt, "S_A": info["S_A"],
+                                  "pairs": info["pairs"]}}
 
 
 def batched_case():
@@ -677,7 +715,8 @@ def main() -> int:
                     help="block widths K of the paper-LU family (comma-separated)")
     ap.add_argument("--lu-precs", default="256",
                     help="precisions of the paper-LU family (comma-separated bits)")
-    ap.add_argument("--family", choices=["batched", "lu", "codec", "lufull", "lupaper", "adaptive", "parts"],
+    ap.add_argument("--family", choices=["batched", "lu", "codec", "lufull", "lupaper", "adaptive", "parts", "small",
+                                         "f64"],
                     default=None,
                     help="only run one comparison family (for profiling) and print its record")
     args = ap.parse_args()
@@ -709,7 +748,7 @@ def main() -> int:
                "lupaper": lambda: lu_paper_case(tuple(int(v) for v in args.lu_widths.split(",")),
                                                 tuple(int(v) for v in args.lu_precs.split(","))),
                "adaptive": lambda: adaptive_case(*workload_inputs("cgemm2048_p1024")[4:], 1024),
-               "parts": parts_case}[args.family]()
+               "parts": parts_case, "small": small_latency_case, "f64": f64_case}[args.family]()
         print(json.dumps({"family": args.family, **rec}), flush=True)
         return 0
     log(f"generating {args.workload}")
