@@ -389,11 +389,12 @@ __device__ __attribute__((always_inline)) inline void build_xwin(const Win8 st, 
 
 struct AccC {
   const uint64_t* mant;
-  int64_t ls, o, sh;  // sh: grid position of significand bit 0
-  int L, drop;        // drop: bits below the precision in limb 0 (ignored)
+  const uint64_t* cl;  // the limbs copied to this thread's LDS, or NULL: read them from mant
+  int64_t ls, o, sh;   // sh: grid position of significand bit 0
+  int L, drop;         // drop: bits below the precision in limb 0 (ignored)
   __device__ inline uint64_t limb(int64_t l) const {
     if (l < 0 || l >= L) return 0;
-    uint64_t v = mant[l * ls + o];
+    uint64_t v = cl ? cl[l] : mant[l * ls + o];
     if (l == 0 && drop) v &= ~((1ull << drop) - 1ull);
     return v;
   }
@@ -796,12 +797,15 @@ __host__ __device__ inline int round_i8_window_bytes(int L) {
 // The accumulating form also keeps, per thread, the sum over the addend's
 // range (L + 2 words) and |X| in binary from two words below the addend's
 // lowest bit (L + 4 words), when 256 threads' worth fits the LDS (p <= 2304);
-// beyond that |X| is read from global memory directly.  Bits of |X| outside
-// the window, and the addend's limbs, are always read from global memory.
+// beyond that |X| is read from global memory directly; and then the addend's
+// L limbs, read once from global memory, when that fits too (p <= 1536).
+// Bits of |X| outside the window are always read from global memory.
 __host__ __device__ inline int round_i8_acc_words(int L) { return L + 4; }
 __host__ __device__ inline int round_i8_lds_bytes(int L, int acc) {
   const int wb = round_i8_window_bytes(L);
   if (!acc) return wb;
+  const int with_c = 16 * (((8 * ((L + 2) + round_i8_acc_words(L) + L) + 15) / 16) | 1);
+  if (256 * with_c <= 160 * 1024) return with_c > wb ? with_c : wb;
   const int need = 16 * (((8 * ((L + 2) + round_i8_acc_words(L)) + 15) / 16) | 1);
   const int b = need > wb ? need : wb;
   return 256 * b <= 160 * 1024 ? b : wb;
@@ -1066,6 +1070,12 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
   if (cnz) {
     AccC C;
     C.mant = out.mant;
+    C.cl = nullptr;
+    if (WB >= 8 * ((L + 2) + round_i8_acc_words(L) + L)) {
+      uint64_t* cl = reinterpret_cast<uint64_t*>(lds) + (L + 2) + round_i8_acc_words(L);
+      for (int l = 0; l < L; ++l) cl[l] = out.mant[(int64_t)l * out.ls + o];
+      C.cl = cl;
+    }
     C.ls = out.ls;
     C.o = o;
     C.L = L;
