@@ -357,7 +357,10 @@ int ensure_workspace(size_t bytes, void** ptr) {
       g_ws_bytes = 0;
     }
     hipError_t e = fault_injected() ? hipErrorNotReady : hipMalloc(&g_ws, bytes);
-    if (e == hipErrorOutOfMemory) return set_err(MPCG_ENOMEM, "hipMalloc(%zu) failed: out of memory", bytes);
+    if (e == hipErrorOutOfMemory) {
+      (void)hipGetLastError();  // the failed allocation is not an error of the next launch
+      return set_err(MPCG_ENOMEM, "hipMalloc(%zu) failed: out of memory", bytes);
+    }
     if (e != hipSuccess) return set_err(MPCG_EHIP, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
     g_ws_bytes = bytes;
   }
@@ -551,7 +554,11 @@ int run_strassen(int m, int n, int k, const DOperand& opA, const DOperand& opB, 
   const size_t tiles = (size_t)Q.mt * Q.nt;
   const size_t qbytes = align256(tiles * 8 * Q.nchunk * 1024);  // one quadrant's recombined digits
   void* ws = nullptr;
-  if ((st = ensure_workspace(7 * stride + 4 * qbytes + align256(sizeof(MergeSrc) * 4 * MAX_MERGE), &ws))) return st;
+  if ((st = ensure_workspace(7 * stride + 4 * qbytes + align256(sizeof(MergeSrc) * 4 * MAX_MERGE), &ws))) {
+    if (st != MPCG_ENOMEM) return st;
+    g_err.clear();  // seven plan layouts do not fit: the plain product runs
+    return STRASSEN_DECLINED;
+  }
   char* base = static_cast<char*>(ws);
   int32_t* G = reinterpret_cast<int32_t*>(base + Q.off_G);
   int32_t* H = reinterpret_cast<int32_t*>(base + Q.off_H);
@@ -838,7 +845,11 @@ int run_parts(int m, int n, int k, const DOperand& opA, const DOperand& opB, int
   const size_t mer_b = align256(tiles * 8 * (size_t)nchunk_m * 1024);
   const size_t sc_b = 2 * align256(4 * (size_t)Q.mpad) + 2 * align256(4 * (size_t)Q.npad);
   const size_t total = align256(Q.total) + dig_b + top_b + lnz_b + mer_b + sc_b + 256;
-  if ((st = ensure_workspace(total, &ws))) return st;
+  if ((st = ensure_workspace(total, &ws))) {
+    if (st != MPCG_ENOMEM) return st;
+    g_err.clear();  // the two product layouts do not fit: one scale runs
+    return PARTS_DECLINED;
+  }
   char* base = static_cast<char*>(ws);
   char* p2 = base + align256(Q.total);
   uint8_t* dig2 = reinterpret_cast<uint8_t*>(p2);

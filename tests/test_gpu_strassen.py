@@ -176,3 +176,27 @@ def test_config_2048_p1024_sampled(mode):
     _say(f"  S_A={info['S_A']} S_B={info['S_B']} ksplit={info['ksplit']} block={info['block']}")
     assert info["strassen"] == 1
     _check_sampled(C, ri, ci, s, e, mm, f"strassen {mode}")
+
+
+def test_falls_back_when_the_workspace_is_short():
+    """With a caller workspace sized for the plain product (the workspace
+    query at the largest spread the inputs can have), the recursion's seven
+    plan layouts do not fit: the plain product runs in it, with no error and
+    the oracle's bits."""
+    import torch
+    import paper_2307_06072_amd as mp
+    m = n = k = 256
+    p, R = 256, 6
+    A = random_cmat(68, 0, m, k, p, R)
+    B = random_cmat(68, 1, k, n, p, R)
+    wsz = mp.mpcg_workspace_size(m, n, k, p, M3, EXACT, None, 2 * R)
+    ws = torch.empty(wsz, dtype=torch.uint8, device="cuda")
+    mp.mpcg_set_workspace(ws.data_ptr(), wsz)
+    try:
+        _say("short workspace, strassen=1")
+        C, info = run_device(A, B, p, M3, EXACT, I8, strassen=1)
+        assert info["strassen"] == 0, info
+        bad, first = mismatches(C, oracle.cgemm(A, B, p), m, n)
+        assert bad == 0, (bad, first)
+    finally:
+        mp.mpcg_set_workspace(None, 0)
