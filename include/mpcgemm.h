@@ -167,7 +167,9 @@ typedef struct {
                              Applies to C := AB in the exact scheme with INT8 slices, m, n and k
                              even, and no max_spread or adaptive option; elsewhere, in batches
                              and in mp_cgemm_ex_noalloc the plain product runs, as it does when
-                             the half-size product would take more than 4 contraction chunks.
+                             the half-size product would take more than 4 contraction chunks
+                             or the seven products' workspace cannot be had (out of memory, or
+                             beyond a workspace set by mpcg_set_workspace).
                              mpcg_info.strassen reports which ran.  0 = off. */
     int part_scales;      /* 1: separate scales for the Re and Im parts (MPCG_4M, exact scheme,
                              INT8 slices, C := AB; the adaptive numbers of divisions of the
@@ -178,8 +180,9 @@ typedef struct {
                              products, shifted by the whole digits between their scales, rounded
                              once: the bits of the one-scale product.  Runs only where it needs
                              fewer slice pairs than one scale per row (and the scales of a
-                             component's two products lie within 4096 digits); otherwise, in
-                             batches and in mp_cgemm_ex_noalloc the one-scale product runs.
+                             component's two products lie within 4096 digits, and their
+                             workspace can be had); otherwise, in batches and in
+                             mp_cgemm_ex_noalloc the one-scale product runs.
                              mpcg_info.part_scales reports which ran.  0 = off. */
 } mpcg_options;
 
