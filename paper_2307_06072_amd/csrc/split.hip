@@ -40,40 +40,45 @@ namespace {
 constexpr int SPLIT_THREADS = 1024;
 constexpr int EPT = 1024 / SPLIT_THREADS;
 
-// Limb li of one significand (0 outside [0, L); limb 0 masked to the
-// precision); `denorm` collects a clear top bit of limb L-1.
-__device__ inline uint64_t limb_at(const uint64_t* m, int64_t ls, int64_t li, int L, uint64_t low_mask,
-                                   int& denorm) {
-  if (!m || li < 0 || li >= L) return 0;
-  uint64_t v = m[li * ls];
-  if (li == L - 1) denorm |= !(v >> 63);
-  return li == 0 ? (v & low_mask) : v;
-}
-
-// Bits [pos, pos + 56) of one significand for pos rising by at most 64 per
-// call: limbs li, li + 1 and (loaded a window ahead) li + 2, so every limb is
-// read once.
+// Bits [pos, pos + 56) of one significand, pos rising by `step` <= 56 per
+// window: limbs li and li + 1 (off: pos - 64 li), and limb li + 2 loaded one
+// window ahead, so that its load is in flight while the current window is
+// used; every limb is read once.  The limbs are kept as loaded and masked
+// where a window uses them (limb 0 to the precision; a clear top bit of limb
+// L-1 is noted in `denorm`), so that nothing waits for a load before the next
+// window.
 struct LimbStream {
-  const uint64_t* m;  // mant + entry index, NULL for a zero entry
+  const uint64_t* p;  // limb li + 2 (NULL for a zero entry)
   int64_t li;
+  int off;
   uint64_t a, b, c;
-  __device__ inline void start(const uint64_t* mp, int64_t ls, int64_t pos, int L, uint64_t low_mask,
-                               int& denorm) {
-    m = mp;
+  __device__ inline uint64_t load(int64_t li2, int L) const { return (p && li2 >= 0 && li2 < L) ? *p : 0; }
+  // pos: the first window's lowest bit
+  __device__ inline void start(const uint64_t* mp, int64_t ls, int64_t pos, int L) {
     li = pos >> 6;  // floor
-    a = limb_at(m, ls, li, L, low_mask, denorm);
-    b = limb_at(m, ls, li + 1, L, low_mask, denorm);
-    c = limb_at(m, ls, li + 2, L, low_mask, denorm);
+    off = (int)(pos & 63);
+    p = mp ? mp + li * ls : nullptr;
+    a = load(li, L);
+    if (p) p += ls;
+    b = load(li + 1, L);
+    if (p) p += ls;
+    c = load(li + 2, L);
   }
-  __device__ inline uint64_t window56(int64_t ls, int64_t pos, int L, uint64_t low_mask, int& denorm) {
-    if ((pos >> 6) > li) {
+  // the current window, then a move up by step bits
+  __device__ inline uint64_t window56(int64_t ls, int step, int L, uint64_t low_mask, int& denorm) {
+    const uint64_t x = li == 0 ? a & low_mask : a;
+    const uint64_t y = li == -1 ? b & low_mask : b;
+    if (p && (li == L - 1 || li == L - 2)) denorm |= !((li == L - 1 ? x : y) >> 63);
+    const uint64_t r = off ? ((x >> off) | (y << (64 - off))) : x;
+    off += step;
+    if (off >= 64) {
+      off -= 64;
       ++li;
       a = b;
       b = c;
-      c = limb_at(m, ls, li + 2, L, low_mask, denorm);
+      if (p) p += ls;
+      c = load(li + 2, L);
     }
-    const int off = (int)(pos - 64 * li);
-    const uint64_t r = off ? ((a >> off) | (b << (64 - off))) : a;
     return r & ((1ull << 56) - 1ull);
   }
 };
@@ -182,8 +187,10 @@ __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, in
     if (TWO) fill(*op2, e2[q], sign2 < 0 ? 1 : 0);
   }
 
+  static_assert(sizeof(DT) != 1 || WC == 8, "INT8 slices take 8-bit digits");
   const int64_t half = 1ll << (w - 1);
   const int64_t dmask = (1ll << w) - 1;
+  (void)dmask;
   int64_t carry[EPT][3];
 #pragma unroll
   for (int q = 0; q < EPT; ++q) carry[q][0] = carry[q][1] = carry[q][2] = 0;
@@ -191,34 +198,58 @@ __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, in
   const int nchunks = (Sp + g - 1) / g;
   const int nbits = g * w;  // <= 56
   const uint64_t wmask = (1ull << nbits) - 1ull;
+  // half in every digit field of a window: the balanced digits of v are the
+  // fields of v + kfield less half each, and the bits above the window are
+  // the carry into the next one
+  uint64_t kfield = 0;
+  for (int i = 0; i < g; ++i) kfield |= (uint64_t)half << (w * i);
   {
     const int64_t f0 = (int64_t)w * (S - g * (nchunks - 1) - g);  // lowest window's first F bit
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
-      sre[q].start(e[q].z_re ? nullptr : op.re.mant + e[q].idx, op.re.ls, f0 - e[q].sh_re, L, low_mask, bad);
-      sim[q].start(e[q].z_im ? nullptr : op.im.mant + e[q].idx, op.im.ls, f0 - e[q].sh_im, L, low_mask, bad);
+      sre[q].start(e[q].z_re ? nullptr : op.re.mant + e[q].idx, op.re.ls, f0 - e[q].sh_re, L);
+      sim[q].start(e[q].z_im ? nullptr : op.im.mant + e[q].idx, op.im.ls, f0 - e[q].sh_im, L);
       if (TWO) {
-        sre2[q].start(e2[q].z_re ? nullptr : op2->re.mant + e2[q].idx, op2->re.ls, f0 - e2[q].sh_re, L, low_mask,
-                      bad);
-        sim2[q].start(e2[q].z_im ? nullptr : op2->im.mant + e2[q].idx, op2->im.ls, f0 - e2[q].sh_im, L, low_mask,
-                      bad);
+        sre2[q].start(e2[q].z_re ? nullptr : op2->re.mant + e2[q].idx, op2->re.ls, f0 - e2[q].sh_re, L);
+        sim2[q].start(e2[q].z_im ? nullptr : op2->im.mant + e2[q].idx, op2->im.ls, f0 - e2[q].sh_im, L);
       }
     }
   }
   const int buf_bytes = nops * g * Layout<DT>::FRAG_BYTES;
+  // INT8 stores: thread t moves 16-byte units t and t + SPLIT_THREADS of the
+  // chunk's nops * g fragments; each unit's (plane, digit, offset) is the
+  // same in every chunk, and its destination moves g slices per chunk
+  constexpr int I8_UNITS = 1024 / 16;
+  constexpr int I8_ITEMS = (3 * (56 / 8) * I8_UNITS + SPLIT_THREADS - 1) / SPLIT_THREADS;
+  int8_t* st_dst[I8_ITEMS];
+  int st_src[I8_ITEMS], st_j[I8_ITEMS];
+  size_t st_step = 0;
+  if constexpr (sizeof(DT) == 1) {
+    const int64_t kb = Kpad / 64, per_tile = (int64_t)nops * Sstride;
+    st_step = (size_t)g * kb * 1024;
+#pragma unroll
+    for (int it = 0; it < I8_ITEMS; ++it) {
+      const int idx = t + it * SPLIT_THREADS;
+      const int u = idx % I8_UNITS, oj = idx / I8_UNITS;
+      const int o = oj / g, j = oj - o * g;
+      st_src[it] = oj * 1024 + u * 16;
+      st_j[it] = idx < nops * g * I8_UNITS ? j : Sp;  // Sp: never stored
+      st_dst[it] = reinterpret_cast<int8_t*>(out) +
+                   ((((int64_t)rt * per_tile + (int64_t)o * Sstride + pad_lo + j) * kb + kt) * 1024 + u * 16);
+    }
+  }
   for (int c = nchunks - 1; c >= 0; --c) {
     unsigned char* buf = lds_raw + (NBUF == 2 ? (c & 1) * buf_bytes : 0);
     DT* lds = reinterpret_cast<DT*>(buf);
-    const int64_t fstart = (int64_t)w * (S - g * c - g);  // F bit of the window's lowest digit
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
-      int64_t fre = (int64_t)(sre[q].window56(op.re.ls, fstart - e[q].sh_re, L, low_mask, bad) & wmask);
-      int64_t fim = (int64_t)(sim[q].window56(op.im.ls, fstart - e[q].sh_im, L, low_mask, bad) & wmask);
+      int64_t fre = (int64_t)(sre[q].window56(op.re.ls, nbits, L, low_mask, bad) & wmask);
+      int64_t fim = (int64_t)(sim[q].window56(op.im.ls, nbits, L, low_mask, bad) & wmask);
       if (e[q].neg_re) fre = -fre;
       if (e[q].neg_im) fim = -fim;
       if (TWO) {  // the second operand's windows, signed (sign2 folded into neg)
-        int64_t gre = (int64_t)(sre2[q].window56(op2->re.ls, fstart - e2[q].sh_re, L, low_mask, bad) & wmask);
-        int64_t gim = (int64_t)(sim2[q].window56(op2->im.ls, fstart - e2[q].sh_im, L, low_mask, bad) & wmask);
+        int64_t gre = (int64_t)(sre2[q].window56(op2->re.ls, nbits, L, low_mask, bad) & wmask);
+        int64_t gim = (int64_t)(sim2[q].window56(op2->im.ls, nbits, L, low_mask, bad) & wmask);
         fre += e2[q].neg_re ? -gre : gre;
         fim += e2[q].neg_im ? -gim : gim;
       }
@@ -233,39 +264,44 @@ __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, in
              : (third == (int)Third::RE)     ? fre + carry[q][2]
                                              : 0;
       const bool top = c == 0;  // the chunk holding digit 0, which keeps the remaining value
+      (void)top;
 #pragma unroll
-      for (int j = g - 1; j >= 0; --j) {
-        DT dig[3];
+      for (int o = 0; o < 3; ++o) {
+        if (o == 2 && nops == 2) break;
+        const int64_t u = v[o] + (int64_t)kfield;
+        carry[q][o] = u >> nbits;
+        if constexpr (sizeof(DT) == 1) {
+          // w = 8: each byte of u ^ kfield is a digit as int8 (the top digit
+          // of the top chunk, which fits, is the same byte as its full value)
+          const uint64_t b = (uint64_t)u ^ kfield;
 #pragma unroll
-        for (int o = 0; o < 3; ++o) {
-          int64_t d;
-          if (top && j == 0) {
-            d = v[o];
-          } else {
-            d = ((v[o] + half) & dmask) - half;
-            v[o] = (v[o] - d) >> w;
+          for (int i = 0; i < 56 / 8; ++i) lds[(o * g + (g - 1 - i)) * FRAG + lofs[q]] = (DT)(int8_t)(b >> (8 * i));
+        } else {
+          for (int i = 0; i < g; ++i) {
+            const int64_t d = (top && i == g - 1) ? (u >> (w * i)) - half : ((u >> (w * i)) & dmask) - half;
+            lds[(o * g + (g - 1 - i)) * FRAG + lofs[q]] = (DT)d;
           }
-          dig[o] = (DT)d;
         }
-        lds[(0 * g + j) * FRAG + lofs[q]] = dig[0];
-        lds[(1 * g + j) * FRAG + lofs[q]] = dig[1];
-        if (nops == 3) lds[(2 * g + j) * FRAG + lofs[q]] = dig[2];
       }
-      carry[q][0] = v[0];
-      carry[q][1] = v[1];
-      carry[q][2] = v[2];
     }
     __syncthreads();
     // write the chunk's digit tiles: contiguous (op, digit) fragments of FRAG_BYTES
-    constexpr int units = Layout<DT>::FRAG_BYTES / 16;
-    for (int idx = t; idx < nops * g * units; idx += SPLIT_THREADS) {
-      const int u = idx % units;
-      const int oj = idx / units;  // = o * g + j
-      const int o = oj / g, j = oj % g;
-      const int s = g * c + j;
-      if (s >= Sp) continue;
-      const uint4* src = reinterpret_cast<const uint4*>(buf + (size_t)oj * Layout<DT>::FRAG_BYTES);
-      if constexpr (sizeof(DT) == 8) {
+    if constexpr (sizeof(DT) == 1) {
+      const size_t adv = (size_t)c * st_step;
+#pragma unroll
+      for (int it = 0; it < I8_ITEMS; ++it) {
+        if (g * c + st_j[it] >= Sp) continue;
+        *reinterpret_cast<uint4*>(st_dst[it] + adv) = *reinterpret_cast<const uint4*>(buf + st_src[it]);
+      }
+    } else {
+      constexpr int units = Layout<DT>::FRAG_BYTES / 16;
+      for (int idx = t; idx < nops * g * units; idx += SPLIT_THREADS) {
+        const int u = idx % units;
+        const int oj = idx / units;  // = o * g + j
+        const int o = oj / g, j = oj % g;
+        const int s = g * c + j;
+        if (s >= Sp) continue;
+        const uint4* src = reinterpret_cast<const uint4*>(buf + (size_t)oj * Layout<DT>::FRAG_BYTES);
         // doubles: one column-major matrix of leading dimension cm_ld whose
         // row (plane, slice, r) is (o Sstride + pad_lo + s) Rpad + r; the
         // fragment holds 16 consecutive rows of each of its 64 columns
@@ -273,11 +309,6 @@ __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, in
         const int64_t row0 = ((int64_t)o * Sstride + pad_lo + s) * Rpad + (int64_t)rt * 16;
         double* dst = reinterpret_cast<double*>(out) + ((int64_t)kt * 64 + kl) * cm_ld + row0 + 2 * q2;
         *reinterpret_cast<uint4*>(dst) = src[u];
-      } else {
-        uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<unsigned char*>(out) +
-                                              Layout<DT>::tile_base((int64_t)o * Sstride + pad_lo + s, rt, kt,
-                                                                    Rpad / 16, Kpad, (int64_t)nops * Sstride));
-        dst[u] = src[u];
       }
     }
     if (NBUF == 1) __syncthreads();
