@@ -181,8 +181,8 @@ struct Producer {
   // per load (static index i)
   const int8_t* tb[PW];   // the tile's planes (wave-uniform)
   int isa[PW], hh[PW], sel[PW], foff[PW];
-  // walk state
-  int band, pass, kb, e, ne;
+  // walk state (the passes of a unit run over [pass_lo, pass_hi))
+  int band, pass, kb, e, ne, pass_lo, pass_hi;
   Band g;
   bool done;
   const int8_t* src[PW];
@@ -233,7 +233,7 @@ struct Producer {
   }
   __device__ inline void start(int band0) {
     band = band0;
-    pass = 0;
+    pass = pass_lo;
     kb = kb0;
     g.set(band0, W, Dmax, SA, SB);
     done = false;
@@ -242,8 +242,8 @@ struct Producer {
   __device__ inline void next_unit() {
     if (++kb >= kb1) {
       kb = kb0;
-      if (++pass >= G::NPASS) {
-        pass = 0;
+      if (++pass >= pass_hi) {
+        pass = pass_lo;
         if (++band >= nbands) {
           // past the end: keep reloading the tile's first fragment (never consumed)
           done = true;
@@ -382,11 +382,14 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
   // stream `split`: contraction chunk split / bs and, when the bands are
   // split over workgroups (bs > 1), the bands of group split % bs only
   const int bs = a.bsplit > 1 ? a.bsplit : 1;
-  const int kchunk = split / bs;
+  const int ps = a.psplit > 1 ? a.psplit : 1;
+  const int pass_sel = split % ps;
+  const int kchunk = split / ps / bs;
   const int nb_all = (a.Dmax + W) / W;
   const int bpg = (nb_all + bs - 1) / bs;  // bands per group
-  const int band_lo = min(nb_all, (split - kchunk * bs) * bpg);
+  const int band_lo = min(nb_all, (split / ps - kchunk * bs) * bpg);
   const int band_hi = min(nb_all, band_lo + bpg);
+  const int pass_lo = ps > 1 ? pass_sel : 0, pass_hi = ps > 1 ? pass_sel + 1 : G::NPASS;
   const int kbps = (a.kblocks + a.ksplit - 1) / a.ksplit;
   const int kb0 = kchunk * kbps;
   const int kb1 = min(a.kblocks, kb0 + kbps);
@@ -408,6 +411,8 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
   P.nbands = band_hi;
   P.kb0 = kb0;
   P.kb1 = kb1;
+  P.pass_lo = pass_lo;
+  P.pass_hi = pass_hi;
   {
     const size_t xtile = (size_t)(F == F3M ? 3 : 2) * a.xs * a.kblocks * 1024;  // bytes of one row tile
     const size_t ytile = (size_t)3 * a.ys * a.kblocks * 1024;             // bytes of one column tile
@@ -461,21 +466,29 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
 #pragma unroll
       for (int j = 0; j < W; ++j) acc[p][j] = v4i{0, 0, 0, 0};
 
+    // the passes [pass_lo, pass_hi) of this work item (all of them unless
+    // the real products run on workgroups of their own; the others' sums
+    // then stay zero, and the carry chain below emits this pass's share)
     if constexpr (F == F3M) {  // T1 = Re Re, T2 = Im Im, T3 = (Re+Im)(Re+Im)
+      if (pass_lo <= 0)
 #pragma unroll 1
-      for (int kb = kb0; kb < kb1; ++kb) c.template unit<0, 0, KIND>(acc, P, g);
+        for (int kb = kb0; kb < kb1; ++kb) c.template unit<0, 0, KIND>(acc, P, g);
+      if (pass_lo <= 1 && 1 < pass_hi)
 #pragma unroll 1
-      for (int kb = kb0; kb < kb1; ++kb) c.template unit<1, 1, KIND>(acc, P, g);
+        for (int kb = kb0; kb < kb1; ++kb) c.template unit<1, 1, KIND>(acc, P, g);
+      if (2 < pass_hi)
 #pragma unroll 1
-      for (int kb = kb0; kb < kb1; ++kb) c.template unit<2, 2, KIND>(acc, P, g);
+        for (int kb = kb0; kb < kb1; ++kb) c.template unit<2, 2, KIND>(acc, P, g);
     } else if constexpr (F == FSEP) {  // T1 = X0 Y0 and T2 = X1 Y1, kept apart
+      if (pass_lo <= 0)
 #pragma unroll 1
-      for (int kb = kb0; kb < kb1; ++kb) c.template unit<0, 0, KIND>(acc, P, g);
+        for (int kb = kb0; kb < kb1; ++kb) c.template unit<0, 0, KIND>(acc, P, g);
+      if (1 < pass_hi)
 #pragma unroll 1
-      for (int kb = kb0; kb < kb1; ++kb) c.template unit<1, 1, KIND>(acc, P, g);
+        for (int kb = kb0; kb < kb1; ++kb) c.template unit<1, 1, KIND>(acc, P, g);
     } else {  // Re += ReA ReB + ImA (-ImB),  Im += ReA ImB + ImA ReB
 #pragma unroll 1
-      for (int pass = 0; pass < 2; ++pass)
+      for (int pass = pass_lo; pass < pass_hi; ++pass)
 #pragma unroll 1
         for (int kb = kb0; kb < kb1; ++kb) c.template unit<0, 1, KIND>(acc, P, g);
     }
@@ -532,8 +545,9 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
   // least significant first: upward bands with s_lo > 0, the upward band(s)
   // from s_lo = 0 that stop short of d0 + W - 1, then the downward ones (each
   // class is a contiguous run of the band order)
-  // a stream of one band: its less significant digits are zero
-  for (int q = 0; q < W * band_lo; q += 4) {
+  // a band group's stream: zeros from the start of the 16-digit chunk holding
+  // its first digit (the other groups' digits are not in this stream)
+  for (int q = (W * band_lo) & ~15; q < W * band_lo; q += 4) {
     const uint32_t at = (uint32_t)(q >> 4) * 1024u + (uint32_t)(q & 15) + dig_lane;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -551,32 +565,14 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
     band_body(band, std::integral_constant<int, 1>{});
 #pragma unroll 1
   for (; band < P.nbands; ++band) band_body(band, std::integral_constant<int, 2>{});
-  // a stream of one band: its carry runs on through the more significant digits
-  for (int q = W * band_hi; q < W * nb_all; q += 4) {
-    uint32_t wr[4], wi[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) wr[r] = wi[r] = 0u;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int d = a.Dmax - (q + b);
-      if (d >= 0) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const uint32_t dre = (uint32_t)(cre[r] & ((1 << I8_W) - 1)), dim = (uint32_t)(cim[r] & ((1 << I8_W) - 1));
-          cre[r] >>= I8_W;
-          cim[r] >>= I8_W;
-          if (dre && lre[r] < 0) lre[r] = d;
-          if (dim && lim[r] < 0) lim[r] = d;
-          wr[r] |= dre << (8 * b);
-          wi[r] |= dim << (8 * b);
-        }
-      }
-    }
+  // a band group's stream: zeros to the end of the chunk holding its last
+  // digit; its carry into the next group's digits is left in `top`
+  for (int q = W * band_hi; q < ((W * band_hi + 15) & ~15); q += 4) {
     const uint32_t at = (uint32_t)(q >> 4) * 1024u + (uint32_t)(q & 15) + dig_lane;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      *reinterpret_cast<uint32_t*>(dig + ((uint32_t)r * (uint32_t)slot_stride + at)) = wr[r];
-      *reinterpret_cast<uint32_t*>(dig + ((uint32_t)(4 + r) * (uint32_t)slot_stride + at)) = wi[r];
+      *reinterpret_cast<uint32_t*>(dig + ((uint32_t)r * (uint32_t)slot_stride + at)) = 0u;
+      *reinterpret_cast<uint32_t*>(dig + ((uint32_t)(4 + r) * (uint32_t)slot_stride + at)) = 0u;
     }
   }
   // the producer ran past the end of the stream: drain its loads before the LDS is released
@@ -622,7 +618,7 @@ __global__ __launch_bounds__(256) void gemm_i8_batched_kernel(const GemmArgs* __
 template <int W, int F>
 hipError_t launch_wm(const GemmArgs& a, hipStream_t stream) {
   using G = Q<W, F>;
-  const int blocks = (a.mt / 2) * (a.nt / 2) * a.ksplit * (a.bsplit > 1 ? a.bsplit : 1);
+  const int blocks = (a.mt / 2) * (a.nt / 2) * a.ksplit * (a.bsplit > 1 ? a.bsplit : 1) * (a.psplit > 1 ? a.psplit : 1);
   const size_t lds = (size_t)G::QS * G::ENT * 1024;
   hipError_t e = hipFuncSetAttribute((const void*)gemm_i8_kernel<W, F>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -70,6 +70,9 @@ struct ScanSummary {
 // OR-ed into *status_word (for calls that do not read the summary back).
 hipError_t launch_scan(const DOperand& op, RowStat* stats, ScanSummary* summary, int limit, int* status_word,
                        hipStream_t stream);
+// Both operands' scans (summary[0] for A, summary[1] for B), in one launch when both are small.
+hipError_t launch_scan_pair(const DOperand& a, RowStat* sa, const DOperand& b, RowStat* sb, ScanSummary* summary,
+                            int limit, int* status_word, hipStream_t stream);
 
 // Digit planes of one operand.
 //   nops       planes per slice index: 2 (Re, Im), 3 (Re, Im, Re+Im) or
@@ -117,9 +120,14 @@ struct GemmArgs {
   int mt, nt;        // 16-row tiles of A, 16-column tiles of B
   int kblocks;       // Kpad / 64 (INT8) or Kpad / 4 (FP64)
   int ksplit;        // contraction chunks
-  int bsplit;        // > 1: the bands run in bsplit groups of consecutive bands on separate
-                     // workgroups, one digit stream each; the streams of chunk c are
-                     // c bsplit .. c bsplit + bsplit - 1 (a group may be empty)
+  int bsplit;        // > 1: the bands run in bsplit groups of ceil(bands / bsplit) consecutive
+                     // bands on separate workgroups, one digit stream each, which holds the
+                     // group's own digits only (zero to whole 16-digit chunks around them;
+                     // other chunks unwritten) and leaves its carry into the next group's
+                     // digits in `top`
+  int psplit;        // > 1 (with bsplit > 1; 3M: 3, 4M: 2): each real product (pass) of a band
+                     // group on a workgroup of its own, a stream each; stream
+                     // (chunk c, group g, pass p) is (c bsplit + g) psplit + p
   int SAp, SBp;      // slice counts of the A and B operands
   int xs, ys;        // slices per A / B plane including the zero pads
   int xlo, ylo;      // zero slices below slice 0 of an A / B plane
@@ -180,6 +188,10 @@ struct RoundArgs {
   const int64_t* top;
   const int32_t* lnz;
   int ksplit, mt, nt, Dmax, w;
+  // > 1: the streams are band groups (GemmArgs.bsplit, .psplit): stream
+  // (chunk c, group g, pass p) = (c seg_bs + g) seg_ps + p holds group g's
+  // digits, its top the carry into digit seg_w min(nbands, (g + 1) seg_bpg)
+  int seg_bs, seg_ps, seg_w, seg_bpg;
   const int32_t* G;  // [m]
   const int32_t* H;  // [n]
   int m, n, prec, L;
@@ -326,6 +338,23 @@ struct ScaleJob {
   int32_t* G;
 };
 hipError_t launch_scales_batched(const ScaleJob* jobs, int njobs, const int* first, int blocks, hipStream_t stream);
+
+// Both operands of one product split in one launch (INT8): each row's scale
+// is G = emax + x from the scan's statistics (0 for an empty or padding row),
+// stored to G and H (Rpad entries) for the rounding by the blocks of the
+// first contraction tile.
+struct SplitPair {
+  DOperand a, b;
+  const RowStat *sa, *sb;
+  int32_t *G, *H;
+  int8_t *X, *Y;
+  int SA, SAp, xs, xlo, mpad;
+  int SB, SBp, ys, ylo, npad;
+  int Kpad, x, prec, L;
+  int* status;
+};
+// 3M: both third planes Re + Im; 4M: none for A, -Im for B.
+hipError_t launch_split_pair_i8(const SplitPair& a, bool mode3m, hipStream_t stream);
 
 struct SplitJob {
   DOperand op;

@@ -137,6 +137,7 @@ struct Plan {
   int sep;           // the four real products of separately scaled parts (FSEP GEMM form)
   int allow_bsplit;  // the plain path: a product of few work items may run its bands apart
   int bsplit;        // bands on separate workgroups (1: all bands in one work item)
+  int psplit;        // with bsplit > 1: the real products of a band group on workgroups of their own
   int nchunk;        // INT8: 16-digit chunks per output component
   size_t off_G, off_H, off_X, off_Y, off_dig, off_top, off_lnz, off_scan, total;
   // FP64 form: slices of A per DGEMM block, the block's products and the diagonal sums
@@ -188,20 +189,26 @@ size_t scan_bytes(int m, int n) {
   return align256(sizeof(RowStat) * (size_t)m) + align256(sizeof(RowStat) * (size_t)n) + 256;
 }
 
+// Work items (2x2 tile groups x contraction chunks) below which the bands of
+// a product run on separate workgroups.
+constexpr long long BSPLIT_ITEMS = 128;
+constexpr int BSPLIT_STREAMS = 16;
+
 // Band width for a product of this form and slice count (measured on MI355X,
 // exact 3M and 4M from S = 40 (256 bits) to S = 156 (1024 bits)): in the 3M
 // form 20 diagonals per band cut the fragment traffic per MFMA and win from
 // S = 76 up; below that the wider band's extra pairs outside the slice square
 // cost more.  The 4M form keeps two accumulators and two rings per diagonal,
-// for which 16 is the widest band that fits the registers.
-int pick_band(const Plan& P) {
+// for which 16 is the widest band that fits the registers.  A product of few
+// work items (2 x 2 tile groups x contraction chunks) runs its bands in
+// groups on workgroups of their own, and its time follows the longest group:
+// narrower bands make more and shorter groups (at 256 bits, 1^3 to 64^3 run
+// fastest with 8 diagonals per band, 128^3 with 12).
+int pick_band(const Plan& P, long long items) {
+  if (P.allow_bsplit && items < BSPLIT_ITEMS && std::min(P.SA, P.SB) < 64) return items <= 4 ? 8 : 12;
   return ((P.mode3m || P.sep) && std::min(P.SA, P.SB) >= 64) ? 20 : 16;
 }
 
-// Work items (2x2 tile groups x contraction chunks) below which the bands of
-// a product run on separate workgroups.
-constexpr long long BSPLIT_ITEMS = 128;
-constexpr int BSPLIT_STREAMS = 16;
 
 // Bytes of one block of FP64 slice-plane products (at least one slice of A).
 constexpr size_t F64_BLOCK_BYTES = size_t(4) << 30;
@@ -228,17 +235,9 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
       P.block = tc.band;
       P.want_groups = tc.groups;
     } else {
-      P.block = pick_band(P);
+      P.block = 0;  // chosen once the work items are known
     }
     if (g_tune_forced_groups) P.want_groups = g_tune_forced_groups;
-    if (P.block != 8 && P.block != 12 && P.block != 16 && P.block != 20)
-      return set_err(MPCG_EINVAL, "block_override (band width) must be 8, 12, 16 or 20");
-    P.SAp = P.SA;
-    P.SBp = P.SB;
-    int ahi, bhi;
-    gemm_i8_pads(P.block, &P.xlo, &ahi, &P.ylo, &bhi);
-    P.xs = P.xlo + P.SA + ahi;
-    P.ys = P.ylo + P.SB + bhi;
     P.kblocks = P.kpad / 64;
     // int32 accumulators: terms per diagonal * 128^2 (the largest digit product)
     // must stay below 2^31
@@ -250,6 +249,15 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
     int want = std::max(1, ceil_div(P.want_groups, groups));
     ks = std::max(ks, std::min(want, P.kblocks));
     P.ksplit = ks;
+    if (P.block == 0) P.block = pick_band(P, (long long)groups * ks);
+    if (P.block != 8 && P.block != 12 && P.block != 16 && P.block != 20)
+      return set_err(MPCG_EINVAL, "block_override (band width) must be 8, 12, 16 or 20");
+    P.SAp = P.SA;
+    P.SBp = P.SB;
+    int ahi, bhi;
+    gemm_i8_pads(P.block, &P.xlo, &ahi, &P.ylo, &bhi);
+    P.xs = P.xlo + P.SA + ahi;
+    P.ys = P.ylo + P.SB + bhi;
   } else {
     // DGEMMs of the stacked slice planes: A's slices in blocks of schunk
     // against B's first tcnt slices, the block's products within
@@ -290,12 +298,17 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
   // so its latency is a group's rather than all bands in turn; at most
   // BSPLIT_STREAMS streams in all
   P.bsplit = 1;
+  P.psplit = 1;
   if (P.allow_bsplit && !P.f64 && (long long)groups * P.ksplit < BSPLIT_ITEMS) {
     const int nb = (P.Dmax + P.block) / P.block;
     const int bs = std::max(1, std::min(nb, BSPLIT_STREAMS / P.ksplit));
     P.bsplit = ceil_div(nb, ceil_div(nb, bs));  // no empty group
+    // and the real products of a band group apart, when the rounding then
+    // reads at most four streams per group and chunk
+    const int np = P.mode3m ? 3 : 2;
+    if (P.bsplit > 1 && !P.sep && P.ksplit * np <= 4) P.psplit = np;
   }
-  const int streams = P.ksplit * P.bsplit;
+  const int streams = P.ksplit * P.bsplit * P.psplit;
   const size_t esz = P.f64 ? 8 : 1;
   const size_t tiles = (size_t)P.mt * P.nt;
   const size_t nd = (size_t)P.Dmax + 1;
@@ -999,8 +1012,7 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
     statB = reinterpret_cast<RowStat*>(sc + sA);
     ScanSummary* summ = reinterpret_cast<ScanSummary*>(sc + sA + sB);
     if ((st = stage(0))) return st;
-    HIP_TRY(launch_scan(opA, statA, summ, bound, status, g_stream));
-    HIP_TRY(launch_scan(opB, statB, summ + 1, bound, status, g_stream));
+    HIP_TRY(launch_scan_pair(opA, statA, opB, statB, summ, bound, status, g_stream));
     if ((st = stage(1))) return st;
   } else {
     // the scan's statistics: library-owned, or at the start of the fixed
@@ -1022,8 +1034,7 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
     ScanSummary local[2];  // pageable read-back for calls that allocate nothing
     ScanSummary* host_summ = fixed ? local : g_host_summary;
     if ((st = stage(0))) return st;
-    HIP_TRY(launch_scan(opA, statA, summ, 0, nullptr, g_stream));
-    HIP_TRY(launch_scan(opB, statB, summ + 1, 0, nullptr, g_stream));
+    HIP_TRY(launch_scan_pair(opA, statA, opB, statB, summ, 0, nullptr, g_stream));
     HIP_TRY(hipMemcpyAsync(host_summ, summ, 2 * sizeof(ScanSummary), hipMemcpyDeviceToHost, g_stream));
     if ((st = stage(1))) return st;
     HIP_TRY(hipStreamSynchronize(g_stream));
@@ -1097,16 +1108,21 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
   int32_t* H = reinterpret_cast<int32_t*>(base + P.off_H);
 
   // ---- split ---------------------------------------------------------------
-  HIP_TRY(launch_scales(statA, m, P.mpad, P.x, G, g_stream));
-  HIP_TRY(launch_scales(statB, n, P.npad, P.x, H, g_stream));
   const Third thirdA = P.mode3m ? Third::SUM : Third::NONE;
   const Third thirdB = P.mode3m ? Third::SUM : (P.f64 ? Third::NONE : Third::NEG_IM);
   if (!P.f64) {
-    HIP_TRY(launch_split_i8(opA, prec_bits, L, P.SA, P.SAp, P.xs, P.xlo, thirdA, G, P.mpad, P.kpad,
-                            reinterpret_cast<int8_t*>(base + P.off_X), status, g_stream));
-    HIP_TRY(launch_split_i8(opB, prec_bits, L, P.SB, P.SBp, P.ys, P.ylo, thirdB, H, P.npad, P.kpad,
-                            reinterpret_cast<int8_t*>(base + P.off_Y), status, g_stream));
+    // both operands in one launch, which also stores the row scales G and H
+    SplitPair sp{};
+    sp.a = opA; sp.b = opB; sp.sa = statA; sp.sb = statB; sp.G = G; sp.H = H;
+    sp.X = reinterpret_cast<int8_t*>(base + P.off_X);
+    sp.Y = reinterpret_cast<int8_t*>(base + P.off_Y);
+    sp.SA = P.SA; sp.SAp = P.SAp; sp.xs = P.xs; sp.xlo = P.xlo; sp.mpad = P.mpad;
+    sp.SB = P.SB; sp.SBp = P.SBp; sp.ys = P.ys; sp.ylo = P.ylo; sp.npad = P.npad;
+    sp.Kpad = P.kpad; sp.x = P.x; sp.prec = prec_bits; sp.L = L; sp.status = status;
+    HIP_TRY(launch_split_pair_i8(sp, P.mode3m, g_stream));
   } else {
+    HIP_TRY(launch_scales(statA, m, P.mpad, P.x, G, g_stream));
+    HIP_TRY(launch_scales(statB, n, P.npad, P.x, H, g_stream));
     HIP_TRY(launch_split_f64(opA, prec_bits, L, P.SA, P.SAp, P.w, thirdA, G, P.mpad, P.kpad,
                              reinterpret_cast<double*>(base + P.off_X), status, g_stream));
     HIP_TRY(launch_split_f64(opB, prec_bits, L, P.SB, P.SBp, P.w, thirdB, H, P.npad, P.kpad,
@@ -1122,6 +1138,7 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
     ga.X = reinterpret_cast<const int8_t*>(base + P.off_X);
     ga.Y = reinterpret_cast<const int8_t*>(base + P.off_Y);
     ga.mt = P.mt; ga.nt = P.nt; ga.kblocks = P.kblocks; ga.ksplit = P.ksplit; ga.bsplit = P.bsplit;
+    ga.psplit = P.psplit;
     ga.SAp = P.SAp; ga.SBp = P.SBp; ga.Dmax = P.Dmax; ga.form = P.mode3m ? F3M : F4M;
     ga.digits = base + P.off_dig; ga.top = top; ga.lnz = lnz;
     ga.xs = P.xs; ga.ys = P.ys; ga.xlo = P.xlo; ga.ylo = P.ylo;
@@ -1138,7 +1155,13 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
   ra.nchunk = P.nchunk;
   ra.f64_layout = P.f64;
   ra.top = top; ra.lnz = lnz;
-  ra.ksplit = P.ksplit * P.bsplit; ra.mt = P.mt; ra.nt = P.nt; ra.Dmax = P.Dmax; ra.w = P.w;
+  ra.ksplit = P.ksplit; ra.mt = P.mt; ra.nt = P.nt; ra.Dmax = P.Dmax; ra.w = P.w;
+  if (P.bsplit > 1) {
+    ra.seg_bs = P.bsplit;
+    ra.seg_ps = P.psplit;
+    ra.seg_w = P.block;
+    ra.seg_bpg = ceil_div((P.Dmax + P.block) / P.block, P.bsplit);
+  }
   ra.G = G; ra.H = H; ra.m = m; ra.n = n; ra.prec = prec_bits; ra.L = L;
   ra.cre = cre; ra.cim = cim; ra.ldc = ldc; ra.status = status;
   ra.acc = acc;
@@ -1386,7 +1409,7 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
                                     &tc) &&
                           tc.mode3m == P.mode3m)
                              ? tc.band
-                             : pick_band(P);
+                             : pick_band(P, BSPLIT_ITEMS);  // the rule for many work items: a batch is one launch
     }
     return plan_layout(P, &o);
   };

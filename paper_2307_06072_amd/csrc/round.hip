@@ -965,6 +965,74 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
     z = qz < 0 ? -1 : Dmax - qz;
     T = c;
     for (int q = 0; q < a.nsrc; ++q) T += a.src[q].sign * a.src[q].top[tb0];
+  } else if (a.seg_bs > 1) {
+    // band-group streams: group g's stream holds its own digits (zero to the
+    // ends of its chunks) and its top the carry into group g + 1's first
+    // digit.  A 16-digit chunk lies in at most two groups (bands of 8 or more
+    // digits), so it takes two streams per contraction chunk and pass, and at
+    // most two carries.
+    const int bs = a.seg_bs, ps = a.seg_ps > 1 ? a.seg_ps : 1, W = a.seg_w, bpg = a.seg_bpg;
+    const int nb_all = (a.Dmax + W) / W;
+    const int nss = a.ksplit * ps;  // streams per group
+    const size_t tstride = (size_t)tiles * 512;
+    auto sidx = [&](int s2, int g) { return ((s2 / ps) * bs + g) * ps + s2 % ps; };
+    int64_t c = 0;
+    int qz = -1;
+    const int nq = Dmax + 1;
+    for (int ch = 0; ch * 16 < nq; ++ch) {
+      const int gA = min(nb_all - 1, (16 * ch) / W) / bpg;
+      const int gB = min(nb_all - 1, (16 * ch + 15) / W) / bpg;
+      const int pA = W * gA * bpg, pB = W * gB * bpg;  // the groups' first digits
+      const bool inA = gA > 0 && pA == 16 * ch;      // group gA starts at this chunk
+      const bool inB = gB != gA;                     // group gB starts inside it
+      uint32_t out[4] = {0, 0, 0, 0};
+      int32_t sum[16];
+#pragma unroll
+      for (int b = 0; b < 16; ++b) sum[b] = 0;
+      int64_t cA = 0, cB = 0;
+      for (int q = 0; q < nss; q += 4) {  // four streams' loads per group and their carries in flight
+        uint4 vA[4], vB[4];
+        int64_t tA[4], tB[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const bool ok = q + u < nss;
+          const size_t so = (size_t)ch * 1024;
+          vA[u] = ok ? *reinterpret_cast<const uint4*>(g0 + (size_t)sidx(q + u, gA) * sstride + so)
+                     : make_uint4(0u, 0u, 0u, 0u);
+          vB[u] = ok && inB ? *reinterpret_cast<const uint4*>(g0 + (size_t)sidx(q + u, gB) * sstride + so)
+                            : make_uint4(0u, 0u, 0u, 0u);
+          tA[u] = ok && inA ? a.top[(size_t)sidx(q + u, gA - 1) * tstride + tb0] : 0;
+          tB[u] = ok && inB ? a.top[(size_t)sidx(q + u, gA) * tstride + tb0] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const uint32_t wa[4] = {vA[u].x, vA[u].y, vA[u].z, vA[u].w};
+          const uint32_t wb[4] = {vB[u].x, vB[u].y, vB[u].z, vB[u].w};
+#pragma unroll
+          for (int b = 0; b < 16; ++b)
+            sum[b] += (int32_t)((wa[b >> 2] >> (8 * (b & 3))) & 255u) + (int32_t)((wb[b >> 2] >> (8 * (b & 3))) & 255u);
+          cA += tA[u];
+          cB += tB[u];
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < 16; ++b) {
+        const int qq = ch * 16 + b;
+        if (qq < nq) {
+          int64_t sv = c + sum[b];
+          if (inA && qq == pA) sv += cA;
+          if (inB && qq == pB) sv += cB;
+          const uint32_t dg = (uint32_t)(sv & (DFULL - 1));
+          c = sv >> I8_W;
+          out[b >> 2] |= dg << (8 * (b & 3));
+          if (dg && qz < 0) qz = qq;
+        }
+      }
+      *reinterpret_cast<uint4*>(g0 + (size_t)ch * 1024) = make_uint4(out[0], out[1], out[2], out[3]);
+    }
+    z = qz < 0 ? -1 : Dmax - qz;
+    T = c;  // the last group's carry lies above every digit
+    for (int q = 0; q < nss; ++q) T += a.top[(size_t)sidx(q, bs - 1) * tstride + tb0];
   } else if (a.ksplit == 1) {
     T = a.top[tb0];
     z = a.lnz[tb0];
@@ -975,29 +1043,25 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
     int qz = -1;
     const int nq = Dmax + 1;
     for (int ch = 0; ch * 16 < nq; ++ch) {
-      uint4 acc[1];
       uint32_t out[4] = {0, 0, 0, 0};
       int32_t sum[16];
 #pragma unroll
       for (int b = 0; b < 16; ++b) sum[b] = 0;
-      // four streams' loads in flight at a time
-      int q = 0;
-      for (; q + 4 <= a.ksplit; q += 4) {
-        uint4 v[4];
+      // up to eight streams' loads in flight before any is used (a product
+      // of few work items has one stream per band group and contraction
+      // chunk, and its rounding waits on these loads one batch after another)
+      for (int q = 0; q < a.ksplit; q += 8) {
+        uint4 v[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = *reinterpret_cast<const uint4*>(g0 + (q + u) * sstride + (size_t)ch * 1024);
+        for (int u = 0; u < 8; ++u)
+          v[u] = q + u < a.ksplit ? *reinterpret_cast<const uint4*>(g0 + (q + u) * sstride + (size_t)ch * 1024)
+                                  : make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
           const uint32_t wv[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
 #pragma unroll
           for (int b = 0; b < 16; ++b) sum[b] += (int32_t)((wv[b >> 2] >> (8 * (b & 3))) & 255u);
         }
-      }
-      for (; q < a.ksplit; ++q) {
-        acc[0] = *reinterpret_cast<const uint4*>(g0 + q * sstride + (size_t)ch * 1024);
-        const uint32_t wv[4] = {acc[0].x, acc[0].y, acc[0].z, acc[0].w};
-#pragma unroll
-        for (int b = 0; b < 16; ++b) sum[b] += (int32_t)((wv[b >> 2] >> (8 * (b & 3))) & 255u);
       }
 #pragma unroll
       for (int b = 0; b < 16; ++b) {

@@ -178,8 +178,9 @@ __global__ __launch_bounds__(256) void summary_kernel(const RowStat* stats, int 
 // launches).
 constexpr int64_t SCAN_SMALL_ENTRIES = 1 << 16;
 
-__global__ __launch_bounds__(1024) void scan_small_kernel(DOperand op, RowStat* stats, ScanSummary* summary,
-                                                          int limit, int* status_word) {
+__device__ __attribute__((always_inline)) inline void scan_small_body(const DOperand& op, RowStat* stats,
+                                                                      ScanSummary* summary, int limit,
+                                                                      int* status_word) {
   // 64 rows at a time, 16 contraction lanes per row
   __shared__ Acc part[16][64];
   __shared__ int32_t s_sp[1024], s_hat[1024], s_nz[1024], s_bad[1024];
@@ -244,6 +245,20 @@ __global__ __launch_bounds__(1024) void scan_small_kernel(DOperand op, RowStat* 
       if (bits) atomicOr(status_word, bits);
     }
   }
+}
+
+__global__ __launch_bounds__(1024) void scan_small_kernel(DOperand op, RowStat* stats, ScanSummary* summary,
+                                                          int limit, int* status_word) {
+  scan_small_body(op, stats, summary, limit, status_word);
+}
+
+// Both operands of a product in one launch: block 0 scans A, block 1 B.
+__global__ __launch_bounds__(1024) void scan_small_pair_kernel(DOperand a, RowStat* sa, DOperand b, RowStat* sb,
+                                                               ScanSummary* summary, int limit, int* status_word) {
+  if (blockIdx.x == 0)
+    scan_small_body(a, sa, summary, limit, status_word);
+  else
+    scan_small_body(b, sb, summary + 1, limit, status_word);
 }
 
 __device__ inline void scales_body(const RowStat* stats, int R, int Rpad, int x, int32_t* G, int blk) {
@@ -351,6 +366,20 @@ hipError_t launch_scan(const DOperand& op, RowStat* stats, ScanSummary* summary,
   }
   summary_kernel<<<dim3(1), dim3(256), 0, stream>>>(stats, op.R, summary, limit, status_word);
   return hipGetLastError();
+}
+
+hipError_t launch_scan_pair(const DOperand& a, RowStat* sa, const DOperand& b, RowStat* sb, ScanSummary* summary,
+                            int limit, int* status_word, hipStream_t stream) {
+  auto small = [](const DOperand& op) {
+    return (int64_t)op.R * op.K <= SCAN_SMALL_ENTRIES && op.K <= 256 && op.R <= 512;
+  };
+  if (small(a) && small(b)) {
+    scan_small_pair_kernel<<<dim3(2), dim3(1024), 0, stream>>>(a, sa, b, sb, summary, limit, status_word);
+    return hipGetLastError();
+  }
+  hipError_t e = launch_scan(a, sa, summary, limit, status_word, stream);
+  if (e != hipSuccess) return e;
+  return launch_scan(b, sb, summary + 1, limit, status_word, stream);
 }
 
 hipError_t launch_scales(const RowStat* stats, int R, int Rpad, int x, int32_t* G, hipStream_t stream) {

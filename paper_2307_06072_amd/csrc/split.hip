@@ -115,6 +115,13 @@ struct Layout<double> {
   }
 };
 
+// The scale of row r < R from the scan's statistics: the row's largest
+// exponent plus the headroom x, 0 for a row of zeros (as the scales kernel).
+__device__ inline int32_t row_scale(const RowStat* stats, int r, int x) {
+  const int32_t e = stats[r].emax;
+  return e == INT32_MIN ? 0 : e + x;
+}
+
 // WC: the digit width when known at compile time (I8_W for INT8), else 0 (w);
 // TH: the third plane (Third) when known at compile time, else -1 (third).
 // INT8 tiles alternate between two LDS buffers, so one barrier per chunk
@@ -128,7 +135,8 @@ __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, in
                                   int w_rt, int third_rt, const int32_t* __restrict__ G, int Rpad, int Kpad,
                                   DT* __restrict__ out, int* status, int kt, int rt, unsigned char* lds_raw,
                                   const DOperand* op2 = nullptr, int sign2 = 0,
-                                  const int32_t* __restrict__ Gim = nullptr, int64_t cm_ld = 0) {
+                                  const int32_t* __restrict__ Gim = nullptr, int64_t cm_ld = 0,
+                                  const RowStat* __restrict__ stats = nullptr, int sx = 0) {
   constexpr int FRAG = Layout<DT>::FRAG_BYTES / (int)sizeof(DT);  // elements per (op, digit) tile
   constexpr int NBUF = sizeof(DT) == 1 ? 2 : 1;
 
@@ -168,7 +176,7 @@ __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, in
       if (r < o.R && kk < o.K) {
         const int64_t idx = (int64_t)r * o.rs + (int64_t)kk * o.ks;
         en.idx = idx;
-        const int64_t base = (int64_t)G[r] - wS + 64 * (int64_t)L;  // sh = exp - base
+        const int64_t base = (int64_t)(stats ? row_scale(stats, r, sx) : G[r]) - wS + 64 * (int64_t)L;  // sh = exp - base
         const int64_t base_im = Gim ? (int64_t)Gim[r] - wS + 64 * (int64_t)L : base;
         const int32_t er = o.re.exp[idx], ei = o.im.exp[idx];
         if (er != EXP_ZERO) {
@@ -352,6 +360,35 @@ __global__ __launch_bounds__(SPLIT_THREADS) void split2_kernel(DOperand op, DOpe
                                                  status, blockIdx.x, blockIdx.y, lds_raw, &op2, sign2);
 }
 
+// Both operands of a product: blocks [0, nA) split A (rows contiguous), the
+// rest B (contraction contiguous); the first contraction tile's blocks store
+// their rows' scales.
+template <int THA, int THB>
+__global__ __launch_bounds__(SPLIT_THREADS) void split_pair_kernel(SplitPair a) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int kts = a.Kpad / 64;
+  const int nA = kts * (a.mpad / 16);
+  int blk = blockIdx.x;
+  if (blk < nA) {
+    const int kt = blk % kts, rt = blk / kts;
+    if (kt == 0 && threadIdx.x < 16) {
+      const int r = rt * 16 + threadIdx.x;
+      a.G[r] = r < a.a.R ? row_scale(a.sa, r, a.x) : 0;
+    }
+    split_tile<int8_t, true, I8_W, THA>(a.a, a.prec, a.L, a.SA, a.SAp, a.xs, a.xlo, I8_W, THA, nullptr, a.mpad,
+                                        a.Kpad, a.X, a.status, kt, rt, lds_raw, nullptr, 0, nullptr, 0, a.sa, a.x);
+  } else {
+    blk -= nA;
+    const int kt = blk % kts, rt = blk / kts;
+    if (kt == 0 && threadIdx.x < 16) {
+      const int r = rt * 16 + threadIdx.x;
+      a.H[r] = r < a.b.R ? row_scale(a.sb, r, a.x) : 0;
+    }
+    split_tile<int8_t, false, I8_W, THB>(a.b, a.prec, a.L, a.SB, a.SBp, a.ys, a.ylo, I8_W, THB, nullptr, a.npad,
+                                         a.Kpad, a.Y, a.status, kt, rt, lds_raw, nullptr, 0, nullptr, 0, a.sb, a.x);
+  }
+}
+
 // INT8 split with separate row scales for the Re (G) and Im (Gim) parts.
 template <bool ROWCONTIG, int TH>
 __global__ __launch_bounds__(SPLIT_THREADS) void split_parts_kernel(DOperand op, int prec, int L, int S, int Sp,
@@ -456,6 +493,17 @@ hipError_t launch_split_parts_i8(const DOperand& op, int prec, int L, int S, int
     if (rc) MPCG_SPLITP(true, 3); else MPCG_SPLITP(false, 3);
   }
 #undef MPCG_SPLITP
+  return hipGetLastError();
+}
+
+hipError_t launch_split_pair_i8(const SplitPair& a, bool mode3m, hipStream_t stream) {
+  const int kts = a.Kpad / 64;
+  const int blocks = kts * (a.mpad / 16) + kts * (a.npad / 16);
+  const size_t lds = (size_t)2 * 3 * (56 / I8_W) * Layout<int8_t>::FRAG_BYTES;  // two buffers of up to three planes
+  if (mode3m)
+    split_pair_kernel<1, 1><<<dim3(blocks), dim3(SPLIT_THREADS), lds, stream>>>(a);
+  else
+    split_pair_kernel<0, 2><<<dim3(blocks), dim3(SPLIT_THREADS), lds, stream>>>(a);
   return hipGetLastError();
 }
 
