@@ -66,6 +66,21 @@ def test_tiling_independent(block, ksplit):
     _check_exact(A, B, p, M4, I8, block_override=block, ksplit_override=ksplit)
 
 
+@pytest.mark.parametrize("mode", [M3, M4])
+@pytest.mark.parametrize("shape", [(1, 1, 320), (3, 5, 448), (17, 9, 500)])
+def test_band_groups_many_chunks(mode, shape):
+    """A tiny output with a long contraction: 5 to 8 contraction chunks, its
+    bands in groups on workgroups of their own, so the rounding merges more
+    than four streams per band group and adds every group's carry at the next
+    group's first digit."""
+    m, n, k = shape
+    p = 200
+    A = random_cmat([12, m, n, k], 0, m, k, p, 7, zero_frac=0.1)
+    B = random_cmat([12, m, n, k], 1, k, n, p, 7, zero_frac=0.1)
+    info = _check_exact(A, B, p, mode, I8)
+    assert info["ksplit"] >= 5, info
+
+
 @pytest.mark.parametrize("p", [2, 3, 53, 64, 65, 127, 512, 1024])
 def test_precisions(p):
     A = random_cmat(p, 0, 20, 33, p, 5)
