@@ -832,6 +832,9 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
 
   int64_t T;
   int z;
+  int zdig = 0;  // the lowest nonzero digit's value, when a merge found it
+  uint4 topc = make_uint4(0u, 0u, 0u, 0u);  // the merged top chunk, when a merge formed it
+  bool have_topc = false;
   if (a.parts) {
     // separately scaled parts: Re = P_rr - P_ii, Im = P_ri + P_ir, the stream
     // at the larger scale shifted up by the whole digits between the scales
@@ -923,10 +926,17 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
           const uint32_t dg = (uint32_t)(sv & (DFULL - 1));
           c = sv >> I8_W;
           out[b >> 2] |= dg << (8 * (b & 3));
-          if (dg && qz < 0) qz = qq;
+          if (dg && qz < 0) {
+            qz = qq;
+            zdig = (int)dg;
+          }
         }
       }
       *reinterpret_cast<uint4*>(g0 + (size_t)ch * 1024) = make_uint4(out[0], out[1], out[2], out[3]);
+      if (ch == (Dmax >> 4)) {
+        topc = make_uint4(out[0], out[1], out[2], out[3]);
+        have_topc = true;
+      }
     }
     z = qz < 0 ? -1 : Dmax - qz;
     T = c + (posU > Dmax ? TU : 0) + (posV > Dmax ? sgV * TV : 0);
@@ -957,10 +967,17 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
           const uint32_t dg = (uint32_t)(sv & (DFULL - 1));
           c = sv >> I8_W;
           out[b >> 2] |= dg << (8 * (b & 3));
-          if (dg && qz < 0) qz = qq;
+          if (dg && qz < 0) {
+            qz = qq;
+            zdig = (int)dg;
+          }
         }
       }
       *reinterpret_cast<uint4*>(g0 + (size_t)ch * 1024) = make_uint4(out[0], out[1], out[2], out[3]);
+      if (ch == (Dmax >> 4)) {
+        topc = make_uint4(out[0], out[1], out[2], out[3]);
+        have_topc = true;
+      }
     }
     z = qz < 0 ? -1 : Dmax - qz;
     T = c;
@@ -976,6 +993,8 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
     const int nss = a.ksplit * ps;  // streams per group
     const size_t tstride = (size_t)tiles * 512;
     auto sidx = [&](int s2, int g) { return ((s2 / ps) * bs + g) * ps + s2 % ps; };
+    int64_t Ttop = 0;  // the last group's carries, which lie above every digit (loaded first)
+    for (int q = 0; q < nss; ++q) Ttop += a.top[(size_t)sidx(q, bs - 1) * tstride + tb0];
     int64_t c = 0;
     int qz = -1;
     const int nq = Dmax + 1;
@@ -1025,20 +1044,28 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
           const uint32_t dg = (uint32_t)(sv & (DFULL - 1));
           c = sv >> I8_W;
           out[b >> 2] |= dg << (8 * (b & 3));
-          if (dg && qz < 0) qz = qq;
+          if (dg && qz < 0) {
+            qz = qq;
+            zdig = (int)dg;
+          }
         }
       }
       *reinterpret_cast<uint4*>(g0 + (size_t)ch * 1024) = make_uint4(out[0], out[1], out[2], out[3]);
+      if (ch == (Dmax >> 4)) {
+        topc = make_uint4(out[0], out[1], out[2], out[3]);
+        have_topc = true;
+      }
     }
     z = qz < 0 ? -1 : Dmax - qz;
-    T = c;  // the last group's carry lies above every digit
-    for (int q = 0; q < nss; ++q) T += a.top[(size_t)sidx(q, bs - 1) * tstride + tb0];
+    T = c + Ttop;
   } else if (a.ksplit == 1) {
     T = a.top[tb0];
     z = a.lnz[tb0];
   } else {
     // add the chunk streams exactly, least significant digit first, 16 digits
     // at a time; the sum replaces chunk 0's digits
+    int64_t Ttop = 0;  // the streams' tops (loaded first)
+    for (int q = 0; q < a.ksplit; ++q) Ttop += a.top[(size_t)q * tiles * 64 * 8 + tb0];
     int64_t c = 0;
     int qz = -1;
     const int nq = Dmax + 1;
@@ -1071,14 +1098,20 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
           const uint32_t dg = (uint32_t)(sv & (DFULL - 1));
           c = sv >> I8_W;
           out[b >> 2] |= dg << (8 * (b & 3));
-          if (dg && qz < 0) qz = qq;
+          if (dg && qz < 0) {
+            qz = qq;
+            zdig = (int)dg;
+          }
         }
       }
       *reinterpret_cast<uint4*>(g0 + (size_t)ch * 1024) = make_uint4(out[0], out[1], out[2], out[3]);
+      if (ch == (Dmax >> 4)) {
+        topc = make_uint4(out[0], out[1], out[2], out[3]);
+        have_topc = true;
+      }
     }
     z = qz < 0 ? -1 : Dmax - qz;
-    T = c;
-    for (int q = 0; q < a.ksplit; ++q) T += a.top[(size_t)q * tiles * 64 * 8 + tb0];
+    T = c + Ttop;
   }
 
   DOutPart out = comp ? a.cim : a.cre;
@@ -1110,7 +1143,8 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
     lead = nbits + 63 - __builtin_clzll(st.U);
   } else {
     for (int c = Dmax >> 4; c >= 0 && lead < 0; --c) {
-      const uint4 cv = *reinterpret_cast<const uint4*>(g0 + (size_t)c * 1024);
+      const uint4 cv =
+          (have_topc && c == (Dmax >> 4)) ? topc : *reinterpret_cast<const uint4*>(g0 + (size_t)c * 1024);
       const uint32_t words[4] = {cv.x, cv.y, cv.z, cv.w};
 #pragma unroll
       for (int b = 15; b >= 0; --b) {
@@ -1125,7 +1159,7 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
   // lowest set bit of X (= of |X|)
   int64_t lowset;
   if (z >= 0)
-    lowset = (int64_t)I8_W * (Dmax - z) + __builtin_ctzll(st.gn(Dmax - z));
+    lowset = (int64_t)I8_W * (Dmax - z) + __builtin_ctzll(zdig ? (uint64_t)zdig : st.gn(Dmax - z));
   else
     lowset = nbits + __builtin_ctzll((uint64_t)T);
 
