@@ -225,8 +225,10 @@ int mp_cgemm_ex(int m, int n, int k, const mpcg_cmat *A, int lda, const mpcg_cma
  *   - A product whose scan and workspace exceed the buffer is rejected with
  *     MPCG_ENOMEM before any device work (mpcg_workspace_size with the same
  *     arguments gives the workspace part; the scan adds 16 (m + n) bytes
- *     plus 256, rounded up to 256).  About 256 x 256 x 256 at 256 bits, or
- *     128^3 at 1024 bits, fit.
+ *     plus 256, rounded up to 256).  256 x 256 x 256 at 256 bits (about
+ *     70 MiB), 64^3 at 1024 bits (43-90 MiB) and 32^3 at 4096 bits fit;
+ *     128^3 at 1024 bits does not (140 MiB in 3M, 226 MiB in 4M, whose real
+ *     products then run on workgroups of their own, a digit stream each).
  *   - adaptive slicing (opt->adaptive without max_spread) and FP64 slices
  *     (whose DGEMMs run through rocBLAS, which allocates) are rejected with
  *     MPCG_EUNSUPPORTED.
