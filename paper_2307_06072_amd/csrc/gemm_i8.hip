@@ -152,10 +152,11 @@ __device__ inline int unit_entries(const Band& g, int W, int NS) {
 // Zero slices around each digit plane.  An upward unit reads X_s for s in
 // [s_lo - W, s_hi + 2 NS - 1] and Y_t for t = d0 - s, i.e. t in
 // [2 - W - 2 NS, S_B - 1 + W]; a downward unit reads X_s for s in
-// [1 - 2 NS, s_hi] and Y_t for t in [0, S_B + W + 2 NS - 3].  The planes
-// carry that many zero slices below and above their S digits so that every
-// load of a unit is unconditional and the pairs outside the operands
-// multiply zeros.
+// [1 - 2 NS, s_hi] and Y_t for t in [0, S_B + W + 2 NS - 3].  That many
+// zero slices lie below and above each plane's S digits (the host lays the
+// planes out so that one run of max(lo, hi) zero slices serves as a plane's
+// upper and the next plane's lower pad), so that every load of a unit is
+// unconditional and the pairs outside the operands multiply zeros.
 __host__ __device__ inline void pads_for(int W, int& alo, int& ahi, int& blo, int& bhi) {
   const int NS = (W % 8 == 0) ? 4 : 2;
   alo = W;

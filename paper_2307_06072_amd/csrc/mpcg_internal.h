@@ -87,7 +87,10 @@ hipError_t launch_scan_pair(const DOperand& a, RowStat* sa, const DOperand& b, R
 //              (o Sp + s) Rpad + r) and Kpad columns.
 enum class Third { NONE = 0, SUM = 1, NEG_IM = 2, RE = 3 };
 // INT8 planes hold Sstride slices each: pad_lo zero slices, the Sp digit
-// slices, then zero slices up to Sstride (all written by the split).
+// slices, then zero slices up to Sstride (all written by the split); with
+// Sstride = pad_lo + Sp the planes share their pads, and the last row tile's
+// blocks also zero the pad_lo slices after its last plane (the region holds
+// them).
 hipError_t launch_split_i8(const DOperand& op, int prec, int L, int S, int Sp, int Sstride, int pad_lo,
                            Third third, const int32_t* G, int Rpad, int Kpad, int8_t* out, int* status,
                            hipStream_t stream);

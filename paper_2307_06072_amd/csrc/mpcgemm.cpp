@@ -254,10 +254,15 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
       return set_err(MPCG_EINVAL, "block_override (band width) must be 8, 12, 16 or 20");
     P.SAp = P.SA;
     P.SBp = P.SB;
-    int ahi, bhi;
-    gemm_i8_pads(P.block, &P.xlo, &ahi, &P.ylo, &bhi);
-    P.xs = P.xlo + P.SA + ahi;
-    P.ys = P.ylo + P.SB + bhi;
+    // consecutive planes share their zero slices: a plane's upper pad is the
+    // next plane's lower pad (the next tile's first plane after a tile's
+    // last), and one more pad follows the last tile
+    int alo, ahi, blo, bhi;
+    gemm_i8_pads(P.block, &alo, &ahi, &blo, &bhi);
+    P.xlo = std::max(alo, ahi);
+    P.ylo = std::max(blo, bhi);
+    P.xs = P.xlo + P.SA;
+    P.ys = P.ylo + P.SB;
   } else {
     // DGEMMs of the stacked slice planes: A's slices in blocks of schunk
     // against B's first tcnt slices, the block's products within
@@ -316,8 +321,9 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
   size_t o = 0;
   P.off_G = o; o = align256(o + 4 * (size_t)P.mpad);
   P.off_H = o; o = align256(o + 4 * (size_t)P.npad);
-  P.off_X = o; o = align256(o + (size_t)P.nopsA * P.xs * P.mpad * (size_t)P.kpad * esz);
-  P.off_Y = o; o = align256(o + (size_t)P.nopsB * P.ys * P.npad * (size_t)P.kpad * esz);
+  // (INT8: a slice of one 16-row tile is 16 kpad bytes; the pad after the last tile)
+  P.off_X = o; o = align256(o + (size_t)P.nopsA * P.xs * P.mpad * (size_t)P.kpad * esz + (size_t)P.xlo * 16 * P.kpad);
+  P.off_Y = o; o = align256(o + (size_t)P.nopsB * P.ys * P.npad * (size_t)P.kpad * esz + (size_t)P.ylo * 16 * P.kpad);
   if (P.f64) {
     P.off_C = o; o = align256(o + (size_t)P.ncombo * P.schunk * P.mpad * (size_t)P.tcnt * P.npad * 8);
     P.off_acc = o; o = align256(o + 2 * nd * (size_t)P.m * P.n * 8);

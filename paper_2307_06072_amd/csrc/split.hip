@@ -27,7 +27,9 @@
 // contiguous fragments:
 //   INT8: fragment = 16 rows x 64 k, lane l holds row l%16, k = 16*(l/16)..+16
 //         (16 bytes), tile-major [R/16][op][pad_lo + s][K/64][1024 B] with
-//         zero slices around the digits (Sstride slices per plane).
+//         zero slices around the digits (Sstride slices per plane; with
+//         Sstride = pad_lo + S a plane's lower pad is also the upper pad of
+//         the plane before it, and one more pad follows the last tile).
 //   FP64: fragment = 16 rows x 4 k, lane l holds row l%16, k = l/16 (one
 //         double), planes [op][s][R/16][K/4][64 doubles].
 #include "mpcg_internal.h"
@@ -322,14 +324,17 @@ __device__ inline void split_tile(const DOperand& op, int prec, int L, int S, in
     if (NBUF == 1) __syncthreads();
   }
   if (bad) atomicOr(status, ST_DENORM);
-  // zero slices around the digits (this tile of every plane)
+  // zero slices around the digits (this tile of every plane); planes whose
+  // pads are shared (Sstride = pad_lo + Sp) have only lower ones, and the
+  // last row tile also writes the pad after its last plane
   const int npad = Sstride - Sp;
+  const int ntail = (sizeof(DT) == 1 && npad == pad_lo && rt == Rpad / 16 - 1) ? pad_lo : 0;
   if (npad > 0) {
     constexpr int units = Layout<DT>::FRAG_BYTES / 16;
-    for (int idx = t; idx < nops * npad * units; idx += SPLIT_THREADS) {
+    for (int idx = t; idx < (nops * npad + ntail) * units; idx += SPLIT_THREADS) {
       const int u = idx % units;
       const int oj = idx / units;
-      const int o = oj / npad, j = oj % npad;
+      const int o = oj / npad, j = oj % npad;  // o == nops: the pad after the last plane
       const int sl = j < pad_lo ? j : Sp + j;  // plane slice index
       uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<unsigned char*>(out) +
                                             Layout<DT>::tile_base((int64_t)o * Sstride + sl, rt, kt, Rpad / 16, Kpad,
