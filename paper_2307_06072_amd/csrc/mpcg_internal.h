@@ -366,8 +366,12 @@ struct SplitJob {
   int8_t* out;
 };
 // One block per 16 x 64 tile: job j has (Kpad/64) * (Rpad/16) blocks.
-hipError_t launch_split_i8_batched(const SplitJob* jobs, int njobs, const int* first, int blocks, int prec, int L,
-                                   bool rows_contiguous, int* status, hipStream_t stream);
+
+// Both sides of a batch in one launch: A's jobs (rows contiguous) in blocks
+// [0, blocks_a), B's (contraction contiguous) after them; njobs jobs each.
+hipError_t launch_split_i8_batched_pair(const SplitJob* ja, const int* fa, int blocks_a, const SplitJob* jb,
+                                        const int* fb, int blocks_b, int njobs, int prec, int L, int* status,
+                                        hipStream_t stream);
 
 // Persistent slice GEMM: block b runs items[first[b] .. first[b+1]) in order;
 // an item is (problem, tile-group row, tile-group column, contraction chunk).

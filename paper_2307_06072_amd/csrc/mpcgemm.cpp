@@ -1746,10 +1746,10 @@ int run_batched(int count, const mpcg_problem* probs, int prec_bits, int mode, i
   }
   HIP_TRY(launch_scales_batched(reinterpret_cast<ScaleJob*>(dev + o_scj), (int)scj.size(),
                                 reinterpret_cast<int*>(dev + o_fsc), fsc.back(), g_stream));
-  HIP_TRY(launch_split_i8_batched(reinterpret_cast<SplitJob*>(dev + o_spA), nl, reinterpret_cast<int*>(dev + o_fspA),
-                                  fspA.back(), prec_bits, L, true, g_status, g_stream));
-  HIP_TRY(launch_split_i8_batched(reinterpret_cast<SplitJob*>(dev + o_spB), nl, reinterpret_cast<int*>(dev + o_fspB),
-                                  fspB.back(), prec_bits, L, false, g_status, g_stream));
+  HIP_TRY(launch_split_i8_batched_pair(reinterpret_cast<SplitJob*>(dev + o_spA), reinterpret_cast<int*>(dev + o_fspA),
+                                       fspA.back(), reinterpret_cast<SplitJob*>(dev + o_spB),
+                                       reinterpret_cast<int*>(dev + o_fspB), fspB.back(), nl, prec_bits, L, g_status,
+                                       g_stream));
   if ((st = record(2))) return st;
   for (const Launch& l : launches)
     HIP_TRY(launch_gemm_i8_batched(reinterpret_cast<GemmArgs*>(dev + o_ga), reinterpret_cast<int4*>(dev + l.o_items),

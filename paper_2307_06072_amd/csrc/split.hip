@@ -405,18 +405,30 @@ __global__ __launch_bounds__(SPLIT_THREADS) void split_parts_kernel(DOperand op,
                                           blockIdx.x, blockIdx.y, lds_raw, nullptr, 0, Gim);
 }
 
-// Batched INT8 form: job j owns (Kpad/64) * (Rpad/16) blocks.
-template <bool ROWCONTIG>
-__global__ __launch_bounds__(SPLIT_THREADS) void split_i8_batched(const SplitJob* __restrict__ jobs, int njobs,
-                                                        const int* __restrict__ first, int prec, int L,
-                                                        int* status) {
+// The A sides (rows contiguous) and the B sides of a batch in one launch:
+// blocks [0, blocks_a) take A's jobs, the rest B's.
+__global__ __launch_bounds__(SPLIT_THREADS) void split_i8_batched_pair(const SplitJob* __restrict__ ja, int na,
+                                                             const int* __restrict__ fa, int blocks_a,
+                                                             const SplitJob* __restrict__ jb, int nb,
+                                                             const int* __restrict__ fb, int prec, int L,
+                                                             int* status) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  const int j = job_of_block(first, njobs, blockIdx.x);
-  const SplitJob& J = jobs[j];
-  const int local = blockIdx.x - first[j];
-  const int kts = J.Kpad / 64;
-  split_tile<int8_t, ROWCONTIG, I8_W, -1>(J.op, prec, L, J.S, J.Sp, J.Sstride, J.pad_lo, I8_W, J.third, J.G, J.Rpad,
+  if ((int)blockIdx.x < blocks_a) {
+    const int j = job_of_block(fa, na, blockIdx.x);
+    const SplitJob& J = ja[j];
+    const int local = blockIdx.x - fa[j];
+    const int kts = J.Kpad / 64;
+    split_tile<int8_t, true, I8_W, -1>(J.op, prec, L, J.S, J.Sp, J.Sstride, J.pad_lo, I8_W, J.third, J.G, J.Rpad,
                                        J.Kpad, J.out, status, local % kts, local / kts, lds_raw);
+  } else {
+    const int b = blockIdx.x - blocks_a;
+    const int j = job_of_block(fb, nb, b);
+    const SplitJob& J = jb[j];
+    const int local = b - fb[j];
+    const int kts = J.Kpad / 64;
+    split_tile<int8_t, false, I8_W, -1>(J.op, prec, L, J.S, J.Sp, J.Sstride, J.pad_lo, I8_W, J.third, J.G, J.Rpad,
+                                        J.Kpad, J.out, status, local % kts, local / kts, lds_raw);
+  }
 }
 
 template <typename DT, int WC, int TH>
@@ -519,14 +531,13 @@ hipError_t launch_split_f64(const DOperand& op, int prec, int L, int S, int Sp, 
                                        (int64_t)nops * Sp * Rpad);
 }
 
-hipError_t launch_split_i8_batched(const SplitJob* jobs, int njobs, const int* first, int blocks, int prec, int L,
-                                   bool rows_contiguous, int* status, hipStream_t stream) {
-  if (njobs <= 0 || blocks <= 0) return hipSuccess;
+hipError_t launch_split_i8_batched_pair(const SplitJob* ja, const int* fa, int blocks_a, const SplitJob* jb,
+                                        const int* fb, int blocks_b, int njobs, int prec, int L, int* status,
+                                        hipStream_t stream) {
+  if (njobs <= 0 || blocks_a + blocks_b <= 0) return hipSuccess;
   const size_t lds = (size_t)2 * 3 * (56 / I8_W) * Layout<int8_t>::FRAG_BYTES;  // two buffers of up to three planes
-  if (rows_contiguous)
-    split_i8_batched<true><<<dim3(blocks), dim3(SPLIT_THREADS), lds, stream>>>(jobs, njobs, first, prec, L, status);
-  else
-    split_i8_batched<false><<<dim3(blocks), dim3(SPLIT_THREADS), lds, stream>>>(jobs, njobs, first, prec, L, status);
+  split_i8_batched_pair<<<dim3(blocks_a + blocks_b), dim3(SPLIT_THREADS), lds, stream>>>(ja, njobs, fa, blocks_a, jb,
+                                                                                         njobs, fb, prec, L, status);
   return hipGetLastError();
 }
 
