@@ -199,13 +199,15 @@ constexpr int BSPLIT_STREAMS = 16;
 // form 20 diagonals per band cut the fragment traffic per MFMA and win from
 // S = 76 up; below that the wider band's extra pairs outside the slice square
 // cost more.  The 4M form keeps two accumulators and two rings per diagonal,
-// for which 16 is the widest band that fits the registers.  A product of few
-// work items (2 x 2 tile groups x contraction chunks) runs its bands in
-// groups on workgroups of their own, and its time follows the longest group:
-// narrower bands make more and shorter groups (at 256 bits, 1^3 to 64^3 run
-// fastest with 8 diagonals per band, 128^3 with 12).
+// for which 16 is the widest band that fits the registers.  A product of at
+// most four work items (2 x 2 tile groups x contraction chunks) runs its
+// bands in groups on workgroups of their own, and its time follows the
+// longest group: narrower bands make more and shorter groups (at 256 bits,
+// 1^3 to 64^3 run fastest with 8 diagonals per band; from 5 work items on,
+// 16 served the n = 1024 LU's products best, 12 and 8 giving 0.51 s against
+// 0.48 s).
 int pick_band(const Plan& P, long long items) {
-  if (P.allow_bsplit && items < BSPLIT_ITEMS && std::min(P.SA, P.SB) < 64) return items <= 4 ? 8 : 12;
+  if (P.allow_bsplit && items <= 4 && std::min(P.SA, P.SB) < 64) return 8;
   return ((P.mode3m || P.sep) && std::min(P.SA, P.SB) >= 64) ? 20 : 16;
 }
 
