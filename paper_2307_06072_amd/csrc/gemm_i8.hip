@@ -366,7 +366,7 @@ struct Consumer {
   }
 };
 
-// One work item: the 2 x 2 tile group (gi, gj) of contraction chunk `split`.
+// One work item: the 2 x 2 tile group (gi, gj) of stream `split`.
 template <int W, int F>
 __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& a, int split, int gi, int gj,
                                                                  int8_t* lds_queue) {
@@ -380,8 +380,10 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
   const int ti = 2 * gi + wi;
   const int tj = 2 * gj + wj;
   const int tile = tj * a.mt + ti;
-  // stream `split`: contraction chunk split / bs and, when the bands are
-  // split over workgroups (bs > 1), the bands of group split % bs only
+  // stream `split` = (contraction chunk c, band group g, pass p) as
+  // (c bs + g) ps + p: the bands of group g only when the bands are split
+  // over workgroups (bs > 1), the real product p only when the products are
+  // (ps > 1)
   const int bs = a.bsplit > 1 ? a.bsplit : 1;
   const int ps = a.psplit > 1 ? a.psplit : 1;
   const int pass_sel = split % ps;
