@@ -100,6 +100,26 @@ def stage_bytes(m, n, k, p, info, mode3m, slice_fp64):
     return split, rnd
 
 
+def mfma_probe(kind: int, target_ms: float = 30.0):
+    """Register-only rate of a slice product's matrix instruction (kind 0:
+    INT8 v_mfma_i32_16x16x64_i8, 1: FP64 v_mfma_f64_16x16x4_f64), 8
+    workgroups of 4 wavefronts per compute unit: the best of three runs of
+    about target_ms, in TOP/s (TFLOP/s for FP64), and the run's shape."""
+    import torch
+    import paper_2307_06072_amd as mp
+    sink = torch.zeros(4, dtype=torch.int32, device="cuda")
+    blocks, iters = 256 * 8, 256
+    mp.mpcg_set_stream()
+    mp.mpcg_probe_mfma(kind, blocks, iters, sink.data_ptr())  # warm-up
+    _, ms = mp.mpcg_probe_mfma(kind, blocks, iters, sink.data_ptr())
+    iters = max(1, min(1 << 24, int(iters * target_ms / max(ms, 1e-3))))
+    best = 0.0
+    for _ in range(3):
+        ops, ms = mp.mpcg_probe_mfma(kind, blocks, iters, sink.data_ptr())
+        best = max(best, ops / (ms * 1e-3) / 1e12)
+    return best, {"blocks": blocks, "workgroup_threads": 256, "iters": iters, "instructions_per_iter": 8}
+
+
 def traffic_record(kernel_src: str, form: str):
     """HBM traffic per launch of the slice GEMM from committed rocprofv3
     counters, if they were taken on the current kernel source in this form
@@ -779,6 +799,12 @@ def main() -> int:
             "kernel": "gemm_i8_kernel (slice-pair GEMM + carry chain)" if args.slice == "int8"
             else "rocblas_dgemm + f64_accumulate_kernel", "launches_per_step": launches,
             "algo_ops_per_launch": info["algo_ops"] / launches, "avg_launch_us": gemm_us / launches}
+    # the same instruction's rate with no memory traffic, beside the published peak
+    meas, probe_shape = mfma_probe(0 if args.slice == "int8" else 1)
+    roof["measured_peak"] = meas
+    roof["frac_of_measured"] = achieved / meas
+    roof["measured_peak_probe"] = probe_shape
+    log(f"matrix-core probe: {meas:.0f} {unit} measured, slice GEMM at {achieved / meas:.3f} of it")
     split_b, round_b = stage_bytes(m, n, k, p, info, args.mode == "3M", args.slice == "fp64")
     stage_report = {
         "scan_us": stages[0], "split_us": stages[1], "gemm_us": stages[2], "round_us": stages[3],
@@ -813,6 +839,16 @@ def main() -> int:
                                          PEAK_INT8_TOPS}
         log(f"  int8_3M_exact_strassen: {fam['int8_3M_exact_strassen']['ms_per_call']:.3f} ms")
         fam["speedup_int8_3m_over_fp64_4m_exact"] = fam["fp64_4M_exact"]["ms_per_call"] / fam["int8_3M_exact"]["ms_per_call"]
+        # each form's slice products against its instruction's measured register-only rate
+        meas8 = meas if args.slice == "int8" else mfma_probe(0)[0]
+        meas64 = mfma_probe(1)[0]
+        fam["measured_peak_int8_TOPs"] = meas8
+        fam["measured_peak_fp64_TFLOPs"] = meas64
+        for key2, rec2 in fam.items():
+            if isinstance(rec2, dict) and "gemm_frac_of_peak" in rec2:
+                pk2 = PEAK_FP64_TFLOPS if key2.startswith("fp64") else PEAK_INT8_TOPS
+                ms2 = meas64 if key2.startswith("fp64") else meas8
+                rec2["gemm_frac_of_measured"] = rec2["gemm_frac_of_peak"] * pk2 / ms2
         fam["speedup_int8_3m_over_fp64_4m_truncated"] = (fam["fp64_4M_truncated"]["ms_per_call"] /
                                                          fam["int8_3M_truncated"]["ms_per_call"])
         extra["cgemm512_p512"] = fam

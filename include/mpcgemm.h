@@ -526,6 +526,19 @@ int mpcg_last_timing(float us[4]);
  * synchronizes with the last recorded event and starts a new collection. */
 int mpcg_timing_report(float us_sum[4], int *ncalls);
 
+/*
+ * Matrix-core rate probe (measurement support, no step of the method):
+ * `blocks` workgroups of 4 wavefronts each issue `iters` x 8 back-to-back
+ * matrix instructions from registers, no memory traffic; kind 0 is the INT8
+ * slice products' v_mfma_i32_16x16x64_i8 (32768 integer ops each), kind 1
+ * the FP64 plain form's v_mfma_f64_16x16x4_f64 (2048 flops each).  On the
+ * library stream; synchronizes it.  `sink`: a device buffer of at least 4
+ * bytes (one word is written).  Returns the operations issued in *ops and
+ * the kernel time in *ms (HIP events).  MPCG_EINVAL for kind outside {0, 1},
+ * blocks outside [1, 2^20], iters outside [1, 2^24] or a NULL pointer.
+ */
+int mpcg_probe_mfma(int kind, int blocks, int iters, void *sink, double *ops, float *ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -130,6 +130,8 @@ _lib.mpcg_last_timing.argtypes = [_P(ctypes.c_float)]
 _lib.mpcg_last_timing.restype = _i
 _lib.mpcg_timing_report.argtypes = [_P(ctypes.c_float), _P(ctypes.c_int)]
 _lib.mpcg_timing_report.restype = _i
+_lib.mpcg_probe_mfma.argtypes = [_i, _i, _i, _vp, _P(ctypes.c_double), _P(ctypes.c_float)]
+_lib.mpcg_probe_mfma.restype = _i
 _lib.mpcg_from_doubles.argtypes = [_i, _i, _i, _vp, _i, ctypes.c_longlong, _P(mpcg_part), _i, _i]
 _lib.mpcg_from_doubles.restype = _i
 _lib.mpcg_to_doubles.argtypes = [_i, _i, _P(mpcg_part), _i, _i, _i, _vp, _i, ctypes.c_longlong]
@@ -142,7 +144,7 @@ _lib.mp_zgetrs.restype = _i
 EXPORTS = ["mp_cgemm", "mp_cgemm_ex", "mp_cgemm_ex_noalloc", "mp_cgemm_acc", "mp_cgemm_batched", "mp_cgemm_batched_acc", "mp_zgetrf", "mp_zgetrs", "mpcg_set_stream", "mpcg_set_workspace", "mpcg_workspace_size", "mpcg_workspace_size_batched", "mpcg_autotune", "mpcg_autotune_batched", "mpcg_tune_load",
            "mpcg_tune_save", "mpcg_tune_clear",
            "mpcg_stream_status", "mpcg_last_error", "mpcg_enable_timing", "mpcg_last_timing",
-           "mpcg_timing_report", "mpcg_from_doubles", "mpcg_to_doubles"]
+           "mpcg_timing_report", "mpcg_from_doubles", "mpcg_to_doubles", "mpcg_probe_mfma"]
 
 
 class MPCGError(RuntimeError):
@@ -309,6 +311,16 @@ def mpcg_last_timing():
     us = (ctypes.c_float * 4)()
     _check(_lib.mpcg_last_timing(us))
     return list(us)
+
+
+def mpcg_probe_mfma(kind: int, blocks: int, iters: int, sink_ptr: int):
+    """Matrix-core rate probe (kind 0: INT8 16x16x64, 1: FP64 16x16x4):
+    (operations issued, kernel milliseconds).  sink_ptr: a device buffer of
+    at least 4 bytes."""
+    ops = ctypes.c_double(0.0)
+    ms = ctypes.c_float(0.0)
+    _check(_lib.mpcg_probe_mfma(kind, blocks, iters, ctypes.c_void_p(sink_ptr), ctypes.byref(ops), ctypes.byref(ms)))
+    return ops.value, ms.value
 
 
 def mpcg_timing_report():

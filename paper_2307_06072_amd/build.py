@@ -11,12 +11,18 @@ REPO = os.path.dirname(HERE)
 BUILD = os.path.join(REPO, "_build")
 LIB = os.path.join(HERE, "libmpcgemm.so")
 
-SOURCES = ["mpcgemm.cpp", "tune.cpp", "scan.hip", "split.hip", "gemm_i8.hip", "gemm_f64.hip", "round.hip", "codec.hip", "lu.hip", "recip.hip", "noalloc.hip"]
+SOURCES = ["mpcgemm.cpp", "tune.cpp", "scan.hip", "split.hip", "gemm_i8.hip", "gemm_f64.hip", "round.hip", "codec.hip", "lu.hip", "recip.hip", "noalloc.hip", "probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for every device compile.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# The rate probe's accumulators are loop-carried values only; with the
+# matrix-core results in accumulation registers the allocator copies them
+# between register files every iteration, with vector-register results the
+# loop is the matrix instructions alone (the slice GEMM's inner loops carry
+# no such copies in either form).
+EXTRA = {"probe.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 # rocBLAS serves the DGEMMs of the FP64 form
@@ -31,7 +37,7 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(BUILD, src + ".o")
         objs.append(obj)
-        cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

@@ -213,6 +213,8 @@ struct RoundArgs {
   const struct PartsMerge* parts;
 };
 hipError_t launch_round(const RoundArgs& a, hipStream_t stream);
+// Matrix-core rate probe: kind 0 INT8 16x16x64, 1 FP64 16x16x4; 256-thread blocks.
+hipError_t launch_mfma_probe(int kind, int blocks, int iters, int* sink, hipStream_t stream);
 
 // Separately scaled Re and Im parts (4M): the real products P_rr = Re A Re B,
 // P_ii = Im A Im B, P_ri = Re A Im B and P_ir = Im A Re B are exact digit

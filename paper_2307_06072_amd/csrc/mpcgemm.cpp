@@ -2372,6 +2372,33 @@ int mpcg_to_doubles(int rows, int cols, const mpcg_part* src, int lds, int prec_
 
 const char* mpcg_last_error(void) { return g_err.c_str(); }
 
+int mpcg_probe_mfma(int kind, int blocks, int iters, void* sink, double* ops, float* ms) {
+  g_err.clear();
+  if (kind != 0 && kind != 1) return set_err(MPCG_EINVAL, "probe kind must be 0 (INT8) or 1 (FP64)");
+  if (blocks < 1 || blocks > (1 << 20)) return set_err(MPCG_EINVAL, "probe blocks must be in [1, 2^20]");
+  if (iters < 1 || iters > (1 << 24)) return set_err(MPCG_EINVAL, "probe iterations must be in [1, 2^24]");
+  if (!sink || !ops || !ms) return set_err(MPCG_EINVAL, "NULL pointer");
+  std::lock_guard<std::mutex> lock(g_mu);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return set_err(MPCG_EHIP, "probe: hipEventCreate failed");
+  }
+  hipError_t e = hipEventRecord(e0, g_stream);
+  if (e == hipSuccess) e = launch_mfma_probe(kind, blocks, iters, static_cast<int*>(sink), g_stream);
+  if (e == hipSuccess) e = hipEventRecord(e1, g_stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return set_err(MPCG_EHIP, "probe: %s", hipGetErrorString(e));
+  *ms = t;
+  *ops = (double)blocks * 4.0 * (double)iters * 8.0 * (kind == 0 ? 32768.0 : 2048.0);
+  return MPCG_OK;
+}
+
 int mpcg_enable_timing(int on) {
   std::lock_guard<std::mutex> lock(g_mu);
   g_timing = on != 0;

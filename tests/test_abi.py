@@ -365,3 +365,20 @@ def test_auto_mode_accepted_bad_mode_rejected():
     import paper_2307_06072_amd as mp
     assert _call(mode=3) == mp.MPCG_EINVAL
     assert _call(mode=mp.MPCG_AUTO) != mp.MPCG_EINVAL  # passes validation; fails later without a GPU
+
+
+@pytest.mark.parametrize("kind,blocks,iters,null", [(2, 8, 8, None), (-1, 8, 8, None), (0, 0, 8, None),
+                                                   (0, (1 << 20) + 1, 8, None), (1, 8, 0, None),
+                                                   (1, 8, (1 << 24) + 1, None), (0, 8, 8, "sink"),
+                                                   (0, 8, 8, "ops"), (1, 8, 8, "ms")])
+def test_probe_rejects_bad_arguments(kind, blocks, iters, null):
+    """The matrix-core probe checks its arguments before any device work."""
+    import paper_2307_06072_amd as mp
+    lib = ctypes.CDLL(mp.LIB_PATH)
+    lib.mpcg_probe_mfma.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float)]
+    ops, ms = ctypes.c_double(0.0), ctypes.c_float(0.0)
+    sink = None if null == "sink" else ctypes.c_void_p(1 << 40)
+    rc = lib.mpcg_probe_mfma(kind, blocks, iters, sink, None if null == "ops" else ctypes.byref(ops),
+                             None if null == "ms" else ctypes.byref(ms))
+    assert rc == mp.MPCG_EINVAL
