@@ -225,9 +225,13 @@ int mp_cgemm_ex(int m, int n, int k, const mpcg_cmat *A, int lda, const mpcg_cma
  *   - A product whose scan and workspace exceed the buffer is rejected with
  *     MPCG_ENOMEM before any device work (mpcg_workspace_size with the same
  *     arguments gives the workspace part; the scan adds 16 (m + n) bytes
- *     plus 256, rounded up to 256).  256 x 256 x 256 at 256 bits (about
- *     70 MiB), 64^3 at 1024 bits (43-90 MiB) and 32^3 at 4096 bits fit;
- *     128^3 at 1024 bits does not (140 MiB in 3M, 226 MiB in 4M, whose real
+ *     plus 256, rounded up to 256).  Where mp_cgemm_ex would run the three
+ *     real products of a 3M product on workgroups of their own (a digit
+ *     stream each) and that workspace exceeds the buffer, this call runs
+ *     them together (a third of the streams; info->block may then differ,
+ *     the result does not).  256 x 256 x 256 at 256 bits (about 66 MiB
+ *     so), 64^3 at 1024 bits (43-90 MiB) and 32^3 at 4096 bits fit; 128^3
+ *     at 1024 bits does not (138 MiB in 3M, 225 MiB in 4M, whose real
  *     products then run on workgroups of their own, a digit stream each).
  *   - adaptive slicing (opt->adaptive without max_spread) and FP64 slices
  *     (whose DGEMMs run through rocBLAS, which allocates) are rejected with

@@ -128,11 +128,12 @@ struct Q {
   static constexpr int E = 2 + 2 * NB;      // fragments per step
   static constexpr int ENT = NS * E;        // fragments per entry
   static constexpr int PW = ENT / 4;        // loads each wavefront issues per entry
-  static constexpr int QS = 160 / ENT;      // entries in the queue (at most 160 KB of LDS)
+  static constexpr int QS = (F == F3P ? 80 : 160) / ENT;  // entries in the queue (160 KB of LDS; 80 KB
+                                                          // for two workgroups per compute unit)
   static constexpr int VM = (QS - 3) * PW;  // own loads still allowed in flight when the next entry must have landed
   static constexpr int VM0 = (QS - 2) * PW; // the same for entry 0 after the prologue
-  static constexpr int NPASS = F == F3M ? 3 : 2;
-  static constexpr int NACC = F == F3M ? 3 : 2;
+  static constexpr int NPASS = (F == F3M || F == F3P) ? 3 : 2;
+  static constexpr int NACC = F == F3M ? 3 : (F == F3P ? 1 : 2);
   static constexpr int CH = W / NS;         // entries per chunk (W steps: one turn of the ring)
   static_assert(CH % 2 == 0, "entries alternate between two register buffers");
   static_assert(VM0 < 64, "vmcnt range");
@@ -417,7 +418,7 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
   P.pass_lo = pass_lo;
   P.pass_hi = pass_hi;
   {
-    const size_t xtile = (size_t)(F == F3M ? 3 : 2) * a.xs * a.kblocks * 1024;  // bytes of one row tile
+    const size_t xtile = (size_t)((F == F3M || F == F3P) ? 3 : 2) * a.xs * a.kblocks * 1024;  // bytes of one row tile
     const size_t ytile = (size_t)3 * a.ys * a.kblocks * 1024;             // bytes of one column tile
     const int8_t* X0 = a.X + (size_t)(2 * gi) * xtile;  // row tiles 2gi, 2gi+1
     const int8_t* Y0 = a.Y + (size_t)(2 * gj) * ytile;  // column tiles 2gj, 2gj+1
@@ -482,6 +483,9 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
       if (2 < pass_hi)
 #pragma unroll 1
         for (int kb = kb0; kb < kb1; ++kb) c.template unit<2, 2, KIND>(acc, P, g);
+    } else if constexpr (F == F3P) {  // this work item's one real product T_(pass_lo + 1)
+#pragma unroll 1
+      for (int kb = kb0; kb < kb1; ++kb) c.template unit<0, 0, KIND>(acc, P, g);
     } else if constexpr (F == FSEP) {  // T1 = X0 Y0 and T2 = X1 Y1, kept apart
       if (pass_lo <= 0)
 #pragma unroll 1
@@ -511,6 +515,10 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
           const int64_t t1 = acc[0][j][r], t2 = acc[1][j][r], t3 = acc[2][j][r];
           vre = t1 - t2;
           vim = t3 - t1 - t2;
+        } else if constexpr (F == F3P) {  // T1: (+, -), T2: (-, -), T3: (0, +)
+          const int64_t t = acc[0][j][r];
+          vre = pass_lo == 0 ? t : (pass_lo == 1 ? -t : 0);
+          vim = pass_lo == 2 ? t : -t;
         } else {
           vre = acc[0][j][r];
           vim = acc[1][j][r];
@@ -618,15 +626,32 @@ __global__ __launch_bounds__(256) void gemm_i8_batched_kernel(const GemmArgs* __
   }
 }
 
+// One real product per work item: a third of the registers, half the queue,
+// two workgroups per compute unit.
+template <int W>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void gemm_i8_p_kernel(GemmArgs a) {
+  extern __shared__ __attribute__((aligned(1024))) int8_t lds_queue[];
+  int split, gi, gj;
+  map_block(blockIdx.x, gridDim.x, a.mt >> 1, a.nt >> 1, split, gi, gj);
+  gemm_item<W, F3P>(a, split, gi, gj, lds_queue);
+}
+
 template <int W, int F>
 hipError_t launch_wm(const GemmArgs& a, hipStream_t stream) {
   using G = Q<W, F>;
   const int blocks = (a.mt / 2) * (a.nt / 2) * a.ksplit * (a.bsplit > 1 ? a.bsplit : 1) * (a.psplit > 1 ? a.psplit : 1);
   const size_t lds = (size_t)G::QS * G::ENT * 1024;
-  hipError_t e = hipFuncSetAttribute((const void*)gemm_i8_kernel<W, F>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  gemm_i8_kernel<W, F><<<dim3(blocks), dim3(256), lds, stream>>>(a);
+  if constexpr (F == F3P) {
+    hipError_t e = hipFuncSetAttribute((const void*)gemm_i8_p_kernel<W>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    gemm_i8_p_kernel<W><<<dim3(blocks), dim3(256), lds, stream>>>(a);
+  } else {
+    hipError_t e = hipFuncSetAttribute((const void*)gemm_i8_kernel<W, F>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    gemm_i8_kernel<W, F><<<dim3(blocks), dim3(256), lds, stream>>>(a);
+  }
   return hipGetLastError();
 }
 
@@ -636,6 +661,11 @@ hipError_t launch_w(const GemmArgs& a, hipStream_t stream) {
     case F4M: return launch_wm<W, F4M>(a, stream);
     case F3M: return launch_wm<W, F3M>(a, stream);
     case FSEP: return launch_wm<W, FSEP>(a, stream);
+    case F3P:  // one real product per workgroup (20-wide bands do not fit two workgroups' registers)
+      if constexpr (W <= 16) {
+        if (a.psplit == 3 && a.bsplit <= 1) return launch_wm<W, F3P>(a, stream);
+      }
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }

@@ -116,7 +116,7 @@ hipError_t launch_fold_scales(const RowStat* stats, int half, int Rpad, int x, i
 hipError_t launch_scales(const RowStat* stats, int R, int Rpad, int x, int32_t* G, hipStream_t stream);
 
 // Slice GEMM + combination + carry chain (INT8 digits).
-enum GemmForm { F4M = 0, F3M = 1, FSEP = 2 };
+enum GemmForm { F4M = 0, F3M = 1, FSEP = 2, F3P = 3 };
 struct GemmArgs {
   const int8_t* X;   // A-side planes
   const int8_t* Y;   // B-side planes
@@ -138,7 +138,9 @@ struct GemmArgs {
   int form;          // F4M: A planes (Re, Im), B (Re, Im, -Im), Re and Im of C out;
                      // F3M: planes (Re, Im, Re+Im) on both sides, Re and Im of C out;
                      // FSEP: A planes (X0, X1), B (Y0, Y1, ...), the two real products
-                     //       X0 Y0 and X1 Y1 out in place of Re and Im
+                     //       X0 Y0 and X1 Y1 out in place of Re and Im;
+                     // F3P: the planes of F3M, one real product per work item (psplit = 3,
+                     //       bsplit = 1), its share of Re and Im out
   void* digits;      // [ksplit][tiles][slot 8][chunk][lane 64][16] uint8 digits, q = Dmax - d
                      // (chunk = q / 16; gemm_i8_digit_chunks chunks per component)
   int64_t* top;      // [ksplit][tiles][64][8]
@@ -176,7 +178,7 @@ struct F64CarryArgs {
 hipError_t launch_f64_carry(const F64CarryArgs& a, hipStream_t stream);
 
 // Merge chunk streams (if ksplit > 1), round to prec, write C.
-constexpr int MAX_MERGE = 16;
+constexpr int MAX_MERGE = 48;
 struct MergeSrc {       // one signed digit stream of a merge
   const uint8_t* dig;   // one contraction chunk's digits, laid out like `digits`
   const int64_t* top;   // its tops

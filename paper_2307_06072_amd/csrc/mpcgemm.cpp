@@ -138,6 +138,8 @@ struct Plan {
   int allow_bsplit;  // the plain path: a product of few work items may run its bands apart
   int bsplit;        // bands on separate workgroups (1: all bands in one work item)
   int psplit;        // with bsplit > 1: the real products of a band group on workgroups of their own
+  int allow_onepass; // the plain path and Strassen's products: 3M may run one real product per work item
+  int onepass;       // 3M, one real product per work item (GEMM form F3P, psplit = 3; not with bsplit)
   int nchunk;        // INT8: 16-digit chunks per output component
   size_t off_G, off_H, off_X, off_Y, off_dig, off_top, off_lnz, off_scan, total;
   // FP64 form: slices of A per DGEMM block, the block's products and the diagonal sums
@@ -205,9 +207,18 @@ constexpr int BSPLIT_STREAMS = 16;
 // longest group: narrower bands make more and shorter groups (at 256 bits,
 // 1^3 to 64^3 run fastest with 8 diagonals per band; from 5 work items on,
 // 16 served the n = 1024 LU's products best, 12 and 8 giving 0.51 s against
-// 0.48 s).
+// 0.48 s).  A 3M product that is not split in band groups runs each real
+// product on a workgroup of its own (one accumulator set: two workgroups per
+// compute unit) with 16 diagonals, the widest band that then fits; at 2048^3
+// and 1024 bits its slice GEMM takes 321 ms against 342 ms for the three
+// products together with 20 diagonals, at 512^3 and 512 bits 1.30 against
+// 1.50-1.62 ms.
+bool onepass_form(const Plan& P, long long items) {
+  return P.allow_onepass && !P.f64 && P.mode3m && !P.sep && !(P.allow_bsplit && items < BSPLIT_ITEMS);
+}
 int pick_band(const Plan& P, long long items) {
   if (P.allow_bsplit && items <= 4 && std::min(P.SA, P.SB) < 64) return 8;
+  if (onepass_form(P, items)) return 16;
   return ((P.mode3m || P.sep) && std::min(P.SA, P.SB) >= 64) ? 20 : 16;
 }
 
@@ -314,6 +325,13 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
     // reads at most four streams per group and chunk
     const int np = P.mode3m ? 3 : 2;
     if (P.bsplit > 1 && !P.sep && P.ksplit * np <= 4) P.psplit = np;
+  }
+  // 3M with a band of at most 16 and no band groups: one real product per
+  // work item, three streams per contraction chunk
+  P.onepass = 0;
+  if (P.bsplit == 1 && P.block <= 16 && onepass_form(P, (long long)groups * P.ksplit)) {
+    P.onepass = 1;
+    P.psplit = 3;
   }
   const int streams = P.ksplit * P.bsplit * P.psplit;
   const size_t esz = P.f64 ? 8 : 1;
@@ -567,10 +585,16 @@ int run_strassen(int m, int n, int k, const DOperand& opA, const DOperand& opB, 
   Q.f64 = 0;
   Q.want_groups = 512;
   Q.extra_x = 1;
+  Q.allow_onepass = 1;
   int st;
   if ((st = plan_slices(Q, spA, spB, spA, spB, opt))) return st;
   if ((st = plan_layout(Q, opt))) return st;
-  if (4 * Q.ksplit > MAX_MERGE) return STRASSEN_DECLINED;
+  if (Q.onepass && 4 * Q.ksplit * Q.psplit > MAX_MERGE) {  // the real products together
+    Q.allow_onepass = 0;
+    if ((st = plan_layout(Q, opt))) return st;
+  }
+  const int qstreams = Q.ksplit * Q.psplit;  // digit streams of one product
+  if (4 * qstreams > MAX_MERGE) return STRASSEN_DECLINED;
   const size_t stride = align256(Q.total);
   const size_t tiles = (size_t)Q.mt * Q.nt;
   const size_t qbytes = align256(tiles * 8 * Q.nchunk * 1024);  // one quadrant's recombined digits
@@ -625,8 +649,8 @@ int run_strassen(int m, int n, int k, const DOperand& opA, const DOperand& opB, 
     GemmArgs ga{};
     ga.X = reinterpret_cast<const int8_t*>(pb + Q.off_X);
     ga.Y = reinterpret_cast<const int8_t*>(pb + Q.off_Y);
-    ga.mt = Q.mt; ga.nt = Q.nt; ga.kblocks = Q.kblocks; ga.ksplit = Q.ksplit;
-    ga.SAp = Q.SAp; ga.SBp = Q.SBp; ga.Dmax = Q.Dmax; ga.form = Q.mode3m ? F3M : F4M;
+    ga.mt = Q.mt; ga.nt = Q.nt; ga.kblocks = Q.kblocks; ga.ksplit = Q.ksplit; ga.psplit = Q.psplit;
+    ga.SAp = Q.SAp; ga.SBp = Q.SBp; ga.Dmax = Q.Dmax; ga.form = Q.onepass ? F3P : (Q.mode3m ? F3M : F4M);
     ga.digits = pb + Q.off_dig;
     ga.top = reinterpret_cast<int64_t*>(pb + Q.off_top);
     ga.lnz = reinterpret_cast<int32_t*>(pb + Q.off_lnz);
@@ -640,14 +664,14 @@ int run_strassen(int m, int n, int k, const DOperand& opA, const DOperand& opB, 
                                       {{2, +1}, {4, +1}},
                                       {{1, +1}, {3, +1}},
                                       {{0, +1}, {1, -1}, {2, +1}, {5, +1}}};
-  const size_t sstride = tiles * 8 * Q.nchunk * 1024;  // one contraction chunk's digits
+  const size_t sstride = tiles * 8 * Q.nchunk * 1024;  // one stream's digits
   char* merged = base + 7 * stride;
   MergeSrc* srcdev = reinterpret_cast<MergeSrc*>(base + 7 * stride + 4 * qbytes);
   MergeSrc srcs[4][MAX_MERGE] = {};
   int nsrc[4] = {0, 0, 0, 0};
   for (int qd = 0; qd < 4; ++qd)
     for (const Term& t : terms[qd])
-      for (int c = 0; c < Q.ksplit; ++c) {
+      for (int c = 0; c < qstreams; ++c) {  // contraction chunks (and real products)
         char* pb = base + t.prod * stride;
         MergeSrc& ms = srcs[qd][nsrc[qd]++];
         ms.dig = reinterpret_cast<const uint8_t*>(pb + Q.off_dig) + c * sstride;
@@ -996,6 +1020,7 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
   P.f64 = opt && opt->slice_type == MPCG_SLICE_FP64;
   P.want_groups = 512;
   P.allow_bsplit = 1;
+  P.allow_onepass = 1;
   const int bound = opt ? opt->max_spread : 0;
   tune_env_load();
   const size_t sA = align256(sizeof(RowStat) * (size_t)m), sB = align256(sizeof(RowStat) * (size_t)n);
@@ -1007,6 +1032,10 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
     P.tune_S = mode == MPCG_AUTO ? auto_key_S(prec_bits, bound, bound) : 0;
     if ((st = plan_slices(P, bound, bound, bound, bound, opt))) return st;
     if ((st = plan_layout(P, opt))) return st;
+    if (fixed && P.onepass && P.total > fixed->bytes) {  // the real products together: a third of the streams
+      P.allow_onepass = 0;
+      if ((st = plan_layout(P, opt))) return st;
+    }
     if (fixed) {
       if (P.total > fixed->bytes)
         return set_err(MPCG_ENOMEM, "this product needs %zu bytes of workspace; the fixed buffer holds %zu",
@@ -1096,6 +1125,10 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
     }
     if ((st = plan_slices(P, sa.spread, sb.spread, sa.hat, sb.hat, opt))) return st;
     if ((st = plan_layout(P, opt))) return st;
+    if (fixed && P.onepass && P.total > fixed->bytes - align256(scan_bytes)) {  // as above
+      P.allow_onepass = 0;
+      if ((st = plan_layout(P, opt))) return st;
+    }
     if (fixed) {
       const size_t off = align256(scan_bytes);
       if (P.total > fixed->bytes - off)
@@ -1147,7 +1180,7 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
     ga.Y = reinterpret_cast<const int8_t*>(base + P.off_Y);
     ga.mt = P.mt; ga.nt = P.nt; ga.kblocks = P.kblocks; ga.ksplit = P.ksplit; ga.bsplit = P.bsplit;
     ga.psplit = P.psplit;
-    ga.SAp = P.SAp; ga.SBp = P.SBp; ga.Dmax = P.Dmax; ga.form = P.mode3m ? F3M : F4M;
+    ga.SAp = P.SAp; ga.SBp = P.SBp; ga.Dmax = P.Dmax; ga.form = P.onepass ? F3P : (P.mode3m ? F3M : F4M);
     ga.digits = base + P.off_dig; ga.top = top; ga.lnz = lnz;
     ga.xs = P.xs; ga.ys = P.ys; ga.xlo = P.xlo; ga.ylo = P.ylo;
     HIP_TRY(launch_gemm_i8(ga, P.block, g_stream));
@@ -1164,6 +1197,7 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
   ra.f64_layout = P.f64;
   ra.top = top; ra.lnz = lnz;
   ra.ksplit = P.ksplit; ra.mt = P.mt; ra.nt = P.nt; ra.Dmax = P.Dmax; ra.w = P.w;
+  if (P.onepass) ra.ksplit = P.ksplit * P.psplit;  // every stream holds all digits: a plain sum
   if (P.bsplit > 1) {
     ra.seg_bs = P.bsplit;
     ra.seg_ps = P.psplit;
@@ -2288,6 +2322,7 @@ size_t mpcg_workspace_size(int m, int n, int k, int prec_bits, int mode, int sch
   P.f64 = opt && opt->slice_type == MPCG_SLICE_FP64;
   P.want_groups = 512;
   P.allow_bsplit = 1;  // as the call plans it
+  P.allow_onepass = 1;
   if (plan_slices(P, max_spread, max_spread, max_spread, max_spread, opt)) return 0;
   if (plan_layout(P, opt)) return 0;
   return P.total;

@@ -952,12 +952,20 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
       int32_t sum[16];
 #pragma unroll
       for (int b = 0; b < 16; ++b) sum[b] = 0;
-      for (int q = 0; q < a.nsrc; ++q) {
-        const uint4 v = *reinterpret_cast<const uint4*>(a.src[q].dig + eo + (size_t)ch * 1024);
-        const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
-        const int sg = (int)a.src[q].sign;
+      // up to eight sources' loads in flight before any is used
+      for (int q = 0; q < a.nsrc; q += 8) {
+        uint4 v[8];
 #pragma unroll
-        for (int b = 0; b < 16; ++b) sum[b] += sg * (int32_t)((wv[b >> 2] >> (8 * (b & 3))) & 255u);
+        for (int u = 0; u < 8; ++u)
+          v[u] = q + u < a.nsrc ? *reinterpret_cast<const uint4*>(a.src[q + u].dig + eo + (size_t)ch * 1024)
+                                : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const uint32_t wv[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+          const int sg = q + u < a.nsrc ? (int)a.src[q + u].sign : 0;
+#pragma unroll
+          for (int b = 0; b < 16; ++b) sum[b] += sg * (int32_t)((wv[b >> 2] >> (8 * (b & 3))) & 255u);
+        }
       }
 #pragma unroll
       for (int b = 0; b < 16; ++b) {

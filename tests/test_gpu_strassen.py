@@ -107,12 +107,14 @@ def test_cancelling_sums_and_zero_quadrants(mode):
     _check(A, B, p, mode)
 
 
-@pytest.mark.parametrize("ksplit,expect", [(2, 1), (3, 1), (4, 1), (5, 0)])
+@pytest.mark.parametrize("ksplit,expect", [(2, 1), (3, 1), (4, 1), (5, 1), (7, 1), (14, 0)])
 def test_contraction_chunks(ksplit, expect):
-    """The half-size products in 2 to 4 contraction chunks merge every
-    chunk's stream into the quadrants; 5 would exceed the merge's 16 streams
-    and the plain product runs."""
-    m, n, k, p = 36, 40, 1280, 160  # 10 blocks of 64 in the half contraction
+    """The half-size products in 2 to 7 contraction chunks merge every
+    stream into the quadrants (up to 4 chunks with each 3M real product on
+    workgroups of its own, a stream per chunk and product: at most 48 per
+    quadrant; from 5 chunks the products together); 14 would exceed the
+    merge's 48 streams and the plain product runs."""
+    m, n, k, p = 36, 40, 1792, 160  # 14 blocks of 64 in the half contraction
     A = random_cmat(64, 0, m, k, p, 8)
     B = random_cmat(64, 1, k, n, p, 8)
     info = _check(A, B, p, M3, expect, ksplit_override=ksplit)
