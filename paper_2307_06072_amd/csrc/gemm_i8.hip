@@ -543,13 +543,15 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
         }
       }
     }
+    // (T3 adds nothing to Re: its stream's Re digits are neither written nor read)
+    const bool keep_re = F != F3P || pass_lo != 2;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
       for (int u = 0; u < W / 4; ++u) {
         const int q = W * band + 4 * u;
         const uint32_t at = (uint32_t)(q >> 4) * 1024u + (uint32_t)(q & 15) + dig_lane;
-        *reinterpret_cast<uint32_t*>(dig + ((uint32_t)r * (uint32_t)slot_stride + at)) = wre[r][u];
+        if (keep_re) *reinterpret_cast<uint32_t*>(dig + ((uint32_t)r * (uint32_t)slot_stride + at)) = wre[r][u];
         *reinterpret_cast<uint32_t*>(dig + ((uint32_t)(4 + r) * (uint32_t)slot_stride + at)) = wim[r][u];
       }
   };

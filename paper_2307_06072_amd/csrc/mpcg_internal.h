@@ -193,6 +193,9 @@ struct RoundArgs {
   const int64_t* top;
   const int32_t* lnz;
   int ksplit, mt, nt, Dmax, w;
+  // 1: the ksplit streams are (chunk, 3M real product) pairs, stream q of
+  // product q % 3; T3's (q % 3 == 2) holds no Re digits (unwritten), only its tops
+  int onepass;
   // > 1: the streams are band groups (GemmArgs.bsplit, .psplit): stream
   // (chunk c, group g, pass p) = (c seg_bs + g) seg_ps + p holds group g's
   // digits, its top the carry into digit seg_w min(nbands, (g + 1) seg_bpg)
@@ -205,9 +208,10 @@ struct RoundArgs {
   int* status;
   int acc;  // 0: C := AB; +1 / -1: C := C + AB / C - AB (INT8 layout only), rounded once
   // INT8 only, nsrc > 0: the exact integer to round is the signed sum of the
-  // nsrc (<= MAX_MERGE) streams of the device table src, formed into
-  // `digits` (ksplit must be 1): the recombination of Strassen's products
-  int nsrc;
+  // nsrc (<= MAX_MERGE) streams of the device table src for Re and the
+  // nsrc_im of src + MAX_MERGE for Im, formed into `digits` (ksplit must be
+  // 1): the recombination of Strassen's products
+  int nsrc, nsrc_im;
   const MergeSrc* src;
   // INT8 only, non-null: the four real products of separately scaled parts
   // (device pointer), merged into `digits` (nchunk chunks per component;

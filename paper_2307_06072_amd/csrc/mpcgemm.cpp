@@ -260,6 +260,9 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
     if (kb_max < 1) return set_err(MPCG_EUNSUPPORTED, "precision/spread too large for int32 slice accumulation");
     int ks = (int)((P.kblocks + kb_max - 1) / kb_max);
     int want = std::max(1, ceil_div(P.want_groups, groups));
+    // the one-product form's three real products are work items too
+    if ((P.block == 0 || P.block <= 16) && onepass_form(P, (long long)groups * std::max(ks, std::min(want, P.kblocks))))
+      want = std::max(1, ceil_div(P.want_groups, 3 * groups));
     ks = std::max(ks, std::min(want, P.kblocks));
     P.ksplit = ks;
     if (P.block == 0) P.block = pick_band(P, (long long)groups * ks);
@@ -599,7 +602,7 @@ int run_strassen(int m, int n, int k, const DOperand& opA, const DOperand& opB, 
   const size_t tiles = (size_t)Q.mt * Q.nt;
   const size_t qbytes = align256(tiles * 8 * Q.nchunk * 1024);  // one quadrant's recombined digits
   void* ws = nullptr;
-  if ((st = ensure_workspace(7 * stride + 4 * qbytes + align256(sizeof(MergeSrc) * 4 * MAX_MERGE), &ws))) {
+  if ((st = ensure_workspace(7 * stride + 4 * qbytes + align256(sizeof(MergeSrc) * 8 * MAX_MERGE), &ws))) {
     if (st != MPCG_ENOMEM) return st;
     g_err.clear();  // seven plan layouts do not fit: the plain product runs
     return STRASSEN_DECLINED;
@@ -667,17 +670,21 @@ int run_strassen(int m, int n, int k, const DOperand& opA, const DOperand& opB, 
   const size_t sstride = tiles * 8 * Q.nchunk * 1024;  // one stream's digits
   char* merged = base + 7 * stride;
   MergeSrc* srcdev = reinterpret_cast<MergeSrc*>(base + 7 * stride + 4 * qbytes);
-  MergeSrc srcs[4][MAX_MERGE] = {};
-  int nsrc[4] = {0, 0, 0, 0};
+  // per quadrant, the Re sources then the Im sources (T3's streams of the
+  // one-product form hold no Re digits)
+  MergeSrc srcs[4][2][MAX_MERGE] = {};
+  int nsrc[4][2] = {};
   for (int qd = 0; qd < 4; ++qd)
     for (const Term& t : terms[qd])
-      for (int c = 0; c < qstreams; ++c) {  // contraction chunks (and real products)
-        char* pb = base + t.prod * stride;
-        MergeSrc& ms = srcs[qd][nsrc[qd]++];
-        ms.dig = reinterpret_cast<const uint8_t*>(pb + Q.off_dig) + c * sstride;
-        ms.top = reinterpret_cast<const int64_t*>(pb + Q.off_top) + (size_t)c * tiles * 512;
-        ms.sign = t.sign;
-      }
+      for (int c = 0; c < qstreams; ++c)  // contraction chunks (and real products)
+        for (int comp = 0; comp < 2; ++comp) {
+          if (comp == 0 && Q.onepass && c % 3 == 2) continue;
+          char* pb = base + t.prod * stride;
+          MergeSrc& ms = srcs[qd][comp][nsrc[qd][comp]++];
+          ms.dig = reinterpret_cast<const uint8_t*>(pb + Q.off_dig) + c * sstride;
+          ms.top = reinterpret_cast<const int64_t*>(pb + Q.off_top) + (size_t)c * tiles * 512;
+          ms.sign = t.sign;
+        }
   HIP_TRY(launch_store_words(srcdev, srcs, sizeof(srcs), g_stream));
   for (int qd = 0; qd < 4; ++qd) {
     const int qr = qd >> 1, qc = qd & 1;
@@ -694,9 +701,10 @@ int run_strassen(int m, int n, int k, const DOperand& opA, const DOperand& opB, 
     ra.ldc = ldc;
     ra.status = g_status;
     ra.acc = 0;
-    ra.nsrc = nsrc[qd];
-    ra.src = srcdev + qd * MAX_MERGE;
-    ra.top = srcs[qd][0].top;  // not read when nsrc > 0
+    ra.nsrc = nsrc[qd][0];
+    ra.nsrc_im = nsrc[qd][1];
+    ra.src = srcdev + qd * 2 * MAX_MERGE;
+    ra.top = srcs[qd][0][0].top;  // not read when nsrc > 0
     ra.lnz = reinterpret_cast<const int32_t*>(base + Q.off_lnz);
     HIP_TRY(launch_round(ra, g_stream));
   }
@@ -1197,7 +1205,10 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
   ra.f64_layout = P.f64;
   ra.top = top; ra.lnz = lnz;
   ra.ksplit = P.ksplit; ra.mt = P.mt; ra.nt = P.nt; ra.Dmax = P.Dmax; ra.w = P.w;
-  if (P.onepass) ra.ksplit = P.ksplit * P.psplit;  // every stream holds all digits: a plain sum
+  if (P.onepass) {  // every stream holds all digits (T3's: Im only): a plain sum
+    ra.ksplit = P.ksplit * P.psplit;
+    ra.onepass = 1;
+  }
   if (P.bsplit > 1) {
     ra.seg_bs = P.bsplit;
     ra.seg_ps = P.psplit;

@@ -944,6 +944,8 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
     // the signed sum of the source streams, least significant digit first, 16
     // digits at a time, written to this element's digits
     const size_t eo = ((size_t)tile * 8 + slot) * a.nchunk * 1024 + (size_t)lane * 16;
+    const int ns = comp ? a.nsrc_im : a.nsrc;  // this component's sources
+    const MergeSrc* __restrict__ sl = a.src + (comp ? MAX_MERGE : 0);
     int64_t c = 0;
     int qz = -1;
     const int nq = Dmax + 1;
@@ -953,16 +955,16 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
 #pragma unroll
       for (int b = 0; b < 16; ++b) sum[b] = 0;
       // up to eight sources' loads in flight before any is used
-      for (int q = 0; q < a.nsrc; q += 8) {
+      for (int q = 0; q < ns; q += 8) {
         uint4 v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-          v[u] = q + u < a.nsrc ? *reinterpret_cast<const uint4*>(a.src[q + u].dig + eo + (size_t)ch * 1024)
-                                : make_uint4(0u, 0u, 0u, 0u);
+          v[u] = q + u < ns ? *reinterpret_cast<const uint4*>(sl[q + u].dig + eo + (size_t)ch * 1024)
+                            : make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const uint32_t wv[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
-          const int sg = q + u < a.nsrc ? (int)a.src[q + u].sign : 0;
+          const int sg = q + u < ns ? (int)sl[q + u].sign : 0;
 #pragma unroll
           for (int b = 0; b < 16; ++b) sum[b] += sg * (int32_t)((wv[b >> 2] >> (8 * (b & 3))) & 255u);
         }
@@ -989,7 +991,7 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
     }
     z = qz < 0 ? -1 : Dmax - qz;
     T = c;
-    for (int q = 0; q < a.nsrc; ++q) T += a.src[q].sign * a.src[q].top[tb0];
+    for (int q = 0; q < ns; ++q) T += sl[q].sign * sl[q].top[tb0];
   } else if (a.seg_bs > 1) {
     // band-group streams: group g's stream holds its own digits (zero to the
     // ends of its chunks) and its top the carry into group g + 1's first
@@ -1089,8 +1091,9 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
         uint4 v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-          v[u] = q + u < a.ksplit ? *reinterpret_cast<const uint4*>(g0 + (q + u) * sstride + (size_t)ch * 1024)
-                                  : make_uint4(0u, 0u, 0u, 0u);
+          v[u] = q + u < a.ksplit && !(a.onepass && comp == 0 && (q + u) % 3 == 2)
+                     ? *reinterpret_cast<const uint4*>(g0 + (q + u) * sstride + (size_t)ch * 1024)
+                     : make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const uint32_t wv[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
