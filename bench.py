@@ -100,11 +100,13 @@ def stage_bytes(m, n, k, p, info, mode3m, slice_fp64):
     return split, rnd
 
 
-def mfma_probe(kind: int, target_ms: float = 30.0):
+def mfma_probe(kind: int, target_ms: float = 300.0):
     """Register-only rate of a slice product's matrix instruction (kind 0:
     INT8 v_mfma_i32_16x16x64_i8, 1: FP64 v_mfma_f64_16x16x4_f64), 8
     workgroups of 4 wavefronts per compute unit: the best of three runs of
-    about target_ms, in TOP/s (TFLOP/s for FP64), and the run's shape."""
+    about target_ms (long enough for the clock to settle under the load, as
+    it does under the slice GEMM), in TOP/s (TFLOP/s for FP64), and the
+    run's shape."""
     import torch
     import paper_2307_06072_amd as mp
     sink = torch.zeros(4, dtype=torch.int32, device="cuda")
@@ -796,8 +798,10 @@ def main() -> int:
     roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
             "traffic": (traffic_record(src, "strassen1" if info["strassen"] else "plain")
                         if args.slice == "int8" else None),
-            "kernel": "gemm_i8_kernel (slice-pair GEMM + carry chain)" if args.slice == "int8"
-            else "rocblas_dgemm + f64_accumulate_kernel", "launches_per_step": launches,
+            "kernel": ((f"gemm_i8_p_kernel<{info['block']}> (one 3M real product per workgroup; slice-pair GEMM + carry chain)"
+                        if info["apart"] else "gemm_i8_kernel (slice-pair GEMM + carry chain)")
+                       if args.slice == "int8" else "rocblas_dgemm + f64_accumulate_kernel"),
+            "launches_per_step": launches,
             "algo_ops_per_launch": info["algo_ops"] / launches, "avg_launch_us": gemm_us / launches}
     # the same instruction's rate with no memory traffic, beside the published peak
     meas, probe_shape = mfma_probe(0 if args.slice == "int8" else 1)

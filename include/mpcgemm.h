@@ -202,6 +202,8 @@ typedef struct {
     double bound_bits;    /* truncated: error bound exponent (error <= 2^-bound_bits * sum|a||b|) */
     int part_scales;      /* 1 if the Re and Im parts were scaled separately (S_A, S_B then cover
                              each part's own spread) */
+    int apart;            /* 1 if each 3M real product ran on workgroups of its own (a digit
+                             stream per product and contraction chunk) */
 } mpcg_info;
 
 /* mp_cgemm with options; info (may be NULL) receives the plan. */

@@ -62,7 +62,7 @@ class mpcg_info(ctypes.Structure):
     _fields_ = [("S_A", ctypes.c_int), ("S_B", ctypes.c_int), ("w", ctypes.c_int), ("cutoff", ctypes.c_int),
                 ("nprod", ctypes.c_int), ("ksplit", ctypes.c_int), ("block", ctypes.c_int),
                 ("strassen", ctypes.c_int), ("pairs", ctypes.c_longlong), ("algo_ops", ctypes.c_double),
-                ("bound_bits", ctypes.c_double), ("part_scales", ctypes.c_int)]
+                ("bound_bits", ctypes.c_double), ("part_scales", ctypes.c_int), ("apart", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

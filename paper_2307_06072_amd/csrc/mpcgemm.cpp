@@ -139,6 +139,7 @@ struct Plan {
   int bsplit;        // bands on separate workgroups (1: all bands in one work item)
   int psplit;        // with bsplit > 1: the real products of a band group on workgroups of their own
   int allow_onepass; // the plain path and Strassen's products: 3M may run one real product per work item
+  int onepass_pays;  // ... and that form is expected to be faster for this product (onepass_pays())
   int onepass;       // 3M, one real product per work item (GEMM form F3P, psplit = 3; not with bsplit)
   int nchunk;        // INT8: 16-digit chunks per output component
   size_t off_G, off_H, off_X, off_Y, off_dig, off_top, off_lnz, off_scan, total;
@@ -214,7 +215,18 @@ constexpr int BSPLIT_STREAMS = 16;
 // products together with 20 diagonals, at 512^3 and 512 bits 1.30 against
 // 1.50-1.62 ms.
 bool onepass_form(const Plan& P, long long items) {
-  return P.allow_onepass && !P.f64 && P.mode3m && !P.sep && !(P.allow_bsplit && items < BSPLIT_ITEMS);
+  return P.allow_onepass && P.onepass_pays && !P.f64 && P.mode3m && !P.sep &&
+         !(P.allow_bsplit && items < BSPLIT_ITEMS);
+}
+// The form saves slice-GEMM time in proportion to k S per output entry and
+// costs the rounding kernel about two more digit streams per contraction
+// chunk (and a merge where one chunk needed none), in proportion to S (ks + 1):
+// it pays when k S >= 2^14 (ks + 1).  (The 31 trailing updates of the order-
+// 4096 LU, k = 128 at 256 bits, lose with it: 97 against 102 ms of GEMM, 36
+// against 15 ms of rounding per pass; 512^3 at 512 bits gains, 1.47 against
+// 1.65 ms.)
+bool onepass_pays(const Plan& P, int ks) {
+  return (long long)P.k * std::max(P.SA, P.SB) >= (1ll << 14) * (ks + 1);
 }
 int pick_band(const Plan& P, long long items) {
   if (P.allow_bsplit && items <= 4 && std::min(P.SA, P.SB) < 64) return 8;
@@ -261,6 +273,10 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
     int ks = (int)((P.kblocks + kb_max - 1) / kb_max);
     int want = std::max(1, ceil_div(P.want_groups, groups));
     // the one-product form's three real products are work items too
+    {
+      const int ks_one = std::max(ks, std::min(std::max(1, ceil_div(P.want_groups, 3 * groups)), P.kblocks));
+      P.onepass_pays = onepass_pays(P, ks_one);
+    }
     if ((P.block == 0 || P.block <= 16) && onepass_form(P, (long long)groups * std::max(ks, std::min(want, P.kblocks))))
       want = std::max(1, ceil_div(P.want_groups, 3 * groups));
     ks = std::max(ks, std::min(want, P.kblocks));
@@ -332,7 +348,7 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
   // 3M with a band of at most 16 and no band groups: one real product per
   // work item, three streams per contraction chunk
   P.onepass = 0;
-  if (P.bsplit == 1 && P.block <= 16 && onepass_form(P, (long long)groups * P.ksplit)) {
+  if (P.bsplit == 1 && P.block <= 16 && onepass_form(P, (long long)groups * P.ksplit) && onepass_pays(P, P.ksplit)) {
     P.onepass = 1;
     P.psplit = 3;
   }
@@ -711,7 +727,7 @@ int run_strassen(int m, int n, int k, const DOperand& opA, const DOperand& opB, 
   if ((st = record(4))) return st;
   if (info) {
     info->S_A = Q.SA; info->S_B = Q.SB; info->w = Q.w; info->cutoff = Q.cutoff;
-    info->nprod = Q.mode3m ? 3 : 4; info->ksplit = Q.ksplit; info->block = Q.block;
+    info->nprod = Q.mode3m ? 3 : 4; info->ksplit = Q.ksplit; info->block = Q.block; info->apart = Q.onepass;
     info->pairs = Q.pairs; info->algo_ops = 7 * Q.algo_ops; info->bound_bits = 0;
     info->strassen = 1;
   }
@@ -1149,7 +1165,7 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
   }
   if (info) {
     info->S_A = P.SA; info->S_B = P.SB; info->w = P.w; info->cutoff = P.cutoff;
-    info->nprod = P.mode3m ? 3 : 4; info->ksplit = P.ksplit; info->block = P.block;
+    info->nprod = P.mode3m ? 3 : 4; info->ksplit = P.ksplit; info->block = P.block; info->apart = P.onepass;
     info->pairs = P.pairs; info->algo_ops = P.algo_ops; info->bound_bits = P.bound_bits;
   }
   char* base = static_cast<char*>(ws);

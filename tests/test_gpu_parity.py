@@ -66,6 +66,57 @@ def test_tiling_independent(block, ksplit):
     _check_exact(A, B, p, M4, I8, block_override=block, ksplit_override=ksplit)
 
 
+_APART_REF = {}
+
+
+def _apart_ref():
+    """512^3 at 512 bits: the inputs, sampled oracle entries (corners
+    included) and the fused 3M kernel's whole result (band 20)."""
+    if "ref" not in _APART_REF:
+        m, n, k, p, A, B = workload_inputs("cgemm512_p512")
+        rng = np.random.default_rng(7)
+        rows = np.concatenate([rng.integers(0, m, 300), [0, m - 1, 0, m - 1]])
+        cols = np.concatenate([rng.integers(0, n, 300), [0, 0, n - 1, n - 1]])
+        ent = oracle.cgemm_entries(A, B, rows, cols, p)
+        C20, info = run_device(A, B, p, M3, EXACT, I8, block_override=20)
+        assert info["apart"] == 0, info
+        _APART_REF["ref"] = (m, n, k, p, A, B, rows, cols, ent, C20)
+    return _APART_REF["ref"]
+
+
+@pytest.mark.parametrize("mode,block,apart", [(M3, 0, 1), (M3, 8, 1), (M3, 12, 1), (M3, 16, 1), (M4, 0, 0)])
+def test_products_apart(mode, block, apart):
+    """A 3M product whose contraction is long enough for it (k S >= 2^14 (ks +
+    1): here 512 x 67 in one contraction chunk) runs each real product on
+    workgroups of its own with bands of at most 16 diagonals: a digit stream
+    per product, T3's holding Im digits only, added up by the rounding.  4M
+    and bands of 20 keep the products together.  Every form gives the
+    oracle's bits on the sampled entries and the fused kernel's everywhere."""
+    m, n, k, p, A, B, rows, cols, (s, e, mm), C20 = _apart_ref()
+    _say(f"case m={m} n={n} k={k} p={p} mode={mode} block={block}")
+    C, info = run_device(A, B, p, mode, EXACT, I8, block_override=block)
+    assert info["apart"] == apart, info
+    if apart:
+        assert info["block"] <= 16 and info["ksplit"] == 1, info
+    bad, first = mismatches(C, C20, m, n)
+    assert bad == 0, f"{bad} components differ from the fused kernel's, first {first}, info {info}"
+    for t, (i, j) in enumerate(zip(rows, cols)):
+        for comp, part in enumerate((C.re, C.im)):
+            assert part.exp[j, i] == e[t, comp], (i, j, comp)
+            if e[t, comp] != EXP_ZERO:
+                assert part.sign[j, i] == s[t, comp]
+                assert np.array_equal(part.mant[:, j, i], mm[t, comp])
+
+
+def test_short_contraction_keeps_products_together():
+    """k S below 2^14 (ks + 1) (a rank-128 update at 256 bits): the fused form."""
+    m, n, k, p = 256, 224, 128, 256
+    A = random_cmat(22, 0, m, k, p, 4)
+    B = random_cmat(22, 1, k, n, p, 4)
+    info = _check_exact(A, B, p, M3, I8)
+    assert info["apart"] == 0, info
+
+
 @pytest.mark.parametrize("mode", [M3, M4])
 @pytest.mark.parametrize("shape", [(1, 1, 320), (3, 5, 448), (17, 9, 500)])
 def test_band_groups_many_chunks(mode, shape):
