@@ -231,8 +231,8 @@ int mp_cgemm_ex(int m, int n, int k, const mpcg_cmat *A, int lda, const mpcg_cma
  *     real products of a 3M product on workgroups of their own (a digit
  *     stream each) and that workspace exceeds the buffer, this call runs
  *     them together (a third of the streams; info->block may then differ,
- *     the result does not).  256 x 256 x 256 at 256 bits (about 66 MiB
- *     so), 64^3 at 1024 bits (43-90 MiB) and 32^3 at 4096 bits fit; 128^3
+ *     the result does not).  256 x 256 x 256 at 256 bits (about 89 MiB
+ *     with its real products apart), 64^3 at 1024 bits (43-90 MiB) and 32^3 at 4096 bits fit; 128^3
  *     at 1024 bits does not (138 MiB in 3M, 225 MiB in 4M, whose real
  *     products then run on workgroups of their own, a digit stream each).
  *   - adaptive slicing (opt->adaptive without max_spread) and FP64 slices

@@ -140,6 +140,7 @@ struct Plan {
   int psplit;        // with bsplit > 1: the real products of a band group on workgroups of their own
   int allow_onepass; // the plain path and Strassen's products: 3M may run one real product per work item
   int onepass_pays;  // ... and that form is expected to be faster for this product (onepass_pays())
+  long long fused_items;  // work items of the products together (tile groups x contraction chunks)
   int onepass;       // 3M, one real product per work item (GEMM form F3P, psplit = 3; not with bsplit)
   int nchunk;        // INT8: 16-digit chunks per output component
   size_t off_G, off_H, off_X, off_Y, off_dig, off_top, off_lnz, off_scan, total;
@@ -224,9 +225,13 @@ bool onepass_form(const Plan& P, long long items) {
 // it pays when k S >= 2^14 (ks + 1).  (The 31 trailing updates of the order-
 // 4096 LU, k = 128 at 256 bits, lose with it: 97 against 102 ms of GEMM, 36
 // against 15 ms of rounding per pass; 512^3 at 512 bits gains, 1.47 against
-// 1.65 ms.)
-bool onepass_pays(const Plan& P, int ks) {
-  return (long long)P.k * std::max(P.SA, P.SB) >= (1ll << 14) * (ks + 1);
+// 1.65 ms.)  It also pays when the products together would make fewer than
+// ONEPASS_FILL_ITEMS work items, two rounds of one workgroup per compute
+// unit: apart they fill the chip three times over (256 products of shapes on
+// [16, 768]^3 at 256 bits, one call each: 109 against 137 ms).
+constexpr long long ONEPASS_FILL_ITEMS = 1024;
+bool onepass_pays(const Plan& P, int ks, long long fused_items) {
+  return fused_items < ONEPASS_FILL_ITEMS || (long long)P.k * std::max(P.SA, P.SB) >= (1ll << 14) * (ks + 1);
 }
 int pick_band(const Plan& P, long long items) {
   if (P.allow_bsplit && items <= 4 && std::min(P.SA, P.SB) < 64) return 8;
@@ -275,7 +280,8 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
     // the one-product form's three real products are work items too
     {
       const int ks_one = std::max(ks, std::min(std::max(1, ceil_div(P.want_groups, 3 * groups)), P.kblocks));
-      P.onepass_pays = onepass_pays(P, ks_one);
+      P.fused_items = (long long)groups * std::max(ks, std::min(want, P.kblocks));
+      P.onepass_pays = onepass_pays(P, ks_one, P.fused_items);
     }
     if ((P.block == 0 || P.block <= 16) && onepass_form(P, (long long)groups * std::max(ks, std::min(want, P.kblocks))))
       want = std::max(1, ceil_div(P.want_groups, 3 * groups));
@@ -348,7 +354,8 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
   // 3M with a band of at most 16 and no band groups: one real product per
   // work item, three streams per contraction chunk
   P.onepass = 0;
-  if (P.bsplit == 1 && P.block <= 16 && onepass_form(P, (long long)groups * P.ksplit) && onepass_pays(P, P.ksplit)) {
+  if (P.bsplit == 1 && P.block <= 16 && onepass_form(P, (long long)groups * P.ksplit) &&
+      onepass_pays(P, P.ksplit, P.fused_items)) {
     P.onepass = 1;
     P.psplit = 3;
   }

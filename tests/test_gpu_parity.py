@@ -108,13 +108,28 @@ def test_products_apart(mode, block, apart):
                 assert np.array_equal(part.mant[:, j, i], mm[t, comp])
 
 
-def test_short_contraction_keeps_products_together():
-    """k S below 2^14 (ks + 1) (a rank-128 update at 256 bits): the fused form."""
-    m, n, k, p = 256, 224, 128, 256
+@pytest.mark.parametrize("m,k,apart", [(1024, 128, 0), (256, 256, 1)])
+def test_short_contraction(m, k, apart):
+    """At 256 bits k S stays below 2^14 (ks + 1): a product whose products
+    together fill the chip (1024 tile groups x 1 chunk, a rank-128 update)
+    keeps them together; one of fewer work items (64 tile groups x 4 chunks)
+    runs them apart.  Sampled oracle entries, corners included."""
+    n, p = m, 256
     A = random_cmat(22, 0, m, k, p, 4)
     B = random_cmat(22, 1, k, n, p, 4)
-    info = _check_exact(A, B, p, M3, I8)
-    assert info["apart"] == 0, info
+    _say(f"case m={m} n={n} k={k} p={p}")
+    C, info = run_device(A, B, p, M3, EXACT, I8)
+    assert info["apart"] == apart, info
+    rng = np.random.default_rng(3)
+    rows = np.concatenate([rng.integers(0, m, 400), [0, m - 1, 0, m - 1]])
+    cols = np.concatenate([rng.integers(0, n, 400), [0, 0, n - 1, n - 1]])
+    s, e, mm = oracle.cgemm_entries(A, B, rows, cols, p)
+    for t, (i, j) in enumerate(zip(rows, cols)):
+        for comp, part in enumerate((C.re, C.im)):
+            assert part.exp[j, i] == e[t, comp], (i, j, comp)
+            if e[t, comp] != EXP_ZERO:
+                assert part.sign[j, i] == s[t, comp]
+                assert np.array_equal(part.mant[:, j, i], mm[t, comp])
 
 
 @pytest.mark.parametrize("mode", [M3, M4])
