@@ -9,7 +9,7 @@ import sys
 import pytest
 
 import oracle
-from mpgen import random_cmat
+from mpgen import EXP_ZERO, random_cmat
 from tests.gpu_util import device_result_to_host, mismatches
 
 pytestmark = pytest.mark.gpu
@@ -122,3 +122,42 @@ def test_too_large_is_rejected():
     assert int((C.re.exp != 5).sum()) == 0
     got, ex, _, _ = _both(20, 20, 20, 64, 3, 85, M3, EXACT)
     assert mismatches(got, ex, 20, 20)[0] == 0
+
+
+def test_products_apart_fall_back_to_fused():
+    """A 3M product that mp_cgemm_ex runs with its real products apart (three
+    digit streams per contraction chunk, about 153 MiB of workspace here)
+    while its fused plan fits the buffer: this entry point runs the products
+    together and gives the same bits, which the oracle confirms on samples."""
+    import numpy as np
+    import torch
+    import paper_2307_06072_amd as mp
+    m = n = 256
+    k, p = 640, 256
+    _say(f"noalloc fallback m={m} n={n} k={k} p={p}")
+    A = random_cmat([93, m, k], 0, m, k, p, 2)
+    B = random_cmat([93, m, k], 1, k, n, p, 2)
+    dA, dB = mp.to_device(A), mp.to_device(B)
+    mp.mpcg_set_stream()
+    C1 = mp.device_empty(m, n, p)
+    info1 = mp.mp_cgemm_ex_noalloc(m, n, k, dA, m, dB, k, C1, m, p, M3, EXACT)
+    torch.cuda.synchronize()
+    assert mp.mpcg_stream_status() == 0, mp.mpcg_last_error()
+    C2 = mp.device_empty(m, n, p)
+    info2 = mp.mp_cgemm_ex(m, n, k, dA, m, dB, k, C2, m, p, M3, EXACT)
+    torch.cuda.synchronize()
+    assert mp.mpcg_stream_status() == 0, mp.mpcg_last_error()
+    assert info2["apart"] == 1 and info1["apart"] == 0, (info1, info2)
+    got, ex = device_result_to_host(C1, p), device_result_to_host(C2, p)
+    bad, first = mismatches(got, ex, m, n)
+    assert bad == 0, (first,)
+    rng = np.random.default_rng(5)
+    rows = np.concatenate([rng.integers(0, m, 200), [0, m - 1]])
+    cols = np.concatenate([rng.integers(0, n, 200), [n - 1, 0]])
+    s, e, mm = oracle.cgemm_entries(A, B, rows, cols, p)
+    for t, (i, j) in enumerate(zip(rows, cols)):
+        for comp, part in enumerate((got.re, got.im)):
+            assert part.exp[j, i] == e[t, comp], (i, j, comp)
+            if e[t, comp] != EXP_ZERO:
+                assert part.sign[j, i] == s[t, comp]
+                assert np.array_equal(part.mant[:, j, i], mm[t, comp])
