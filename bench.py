@@ -798,7 +798,7 @@ def main() -> int:
     roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
             "traffic": (traffic_record(src, "strassen1" if info["strassen"] else "plain")
                         if args.slice == "int8" else None),
-            "kernel": ((f"gemm_i8_p_kernel<{info['block']}> (one 3M real product per workgroup; slice-pair GEMM + carry chain)"
+            "kernel": ((f"gemm_i8_p_kernel<{info['block']}, {info['nprod']}> (one real product per workgroup; slice-pair GEMM + carry chain)"
                         if info["apart"] else "gemm_i8_kernel (slice-pair GEMM + carry chain)")
                        if args.slice == "int8" else "rocblas_dgemm + f64_accumulate_kernel"),
             "launches_per_step": launches,

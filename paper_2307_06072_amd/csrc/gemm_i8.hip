@@ -137,12 +137,12 @@ struct Q {
   static constexpr int E = 2 + 2 * NB;      // fragments per step
   static constexpr int ENT = NS * E;        // fragments per entry
   static constexpr int PW = ENT / 4;        // loads each wavefront issues per entry
-  static constexpr int QS = (F == F3P ? 80 : 160) / ENT;  // entries in the queue (160 KB of LDS; 80 KB
+  static constexpr int QS = ((F == F3P || F == F4P) ? 80 : 160) / ENT;  // entries in the queue (160 KB of LDS; 80 KB
                                                           // for two workgroups per compute unit)
   static constexpr int VM = (QS - 3) * PW;  // own loads still allowed in flight when the next entry must have landed
   static constexpr int VM0 = (QS - 2) * PW; // the same for entry 0 after the prologue
-  static constexpr int NPASS = (F == F3M || F == F3P) ? 3 : 2;
-  static constexpr int NACC = F == F3M ? 3 : (F == F3P ? 1 : 2);
+  static constexpr int NPASS = (F == F3M || F == F3P) ? 3 : (F == F4P ? 4 : 2);
+  static constexpr int NACC = F == F3M ? 3 : ((F == F3P || F == F4P) ? 1 : 2);
   static constexpr int CH = W / NS;         // entries per chunk (W steps: one turn of the ring)
   static_assert(CH % 2 == 0, "entries alternate between two register buffers");
   static_assert(VM0 < 64, "vmcnt range");
@@ -223,7 +223,9 @@ struct Producer {
     const int s0 = g.down ? g.s_hi : (g.s_lo > 0 ? g.s_lo : g.s_lo - W);
     const int t0 = g.down ? g.d0 + W - 1 - g.s_hi : g.d0 - s0;
     int pa, pb0, pb1;
-    if (F != F4M) {  // X plane p with Y plane p
+    if (F == F4P) {  // Re Re, Im (-Im) into Re; Re Im, Im Re into Im
+      pa = pass & 1; pb0 = pass == 1 ? 2 : (pass == 2 ? 1 : 0); pb1 = 0;
+    } else if (F != F4M) {  // X plane p with Y plane p
       pa = pass; pb0 = pass; pb1 = 0;
     } else {  // Re A with (Re B, Im B); Im A with (-Im B, Re B)
       pa = pass; pb0 = pass == 0 ? 0 : 2; pb1 = pass == 0 ? 1 : 0;
@@ -492,7 +494,7 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
       if (2 < pass_hi)
 #pragma unroll 1
         for (int kb = kb0; kb < kb1; ++kb) c.template unit<2, 2, KIND>(acc, P, g);
-    } else if constexpr (F == F3P) {  // this work item's one real product T_(pass_lo + 1)
+    } else if constexpr (F == F3P || F == F4P) {  // this work item's one real product
 #pragma unroll 1
       for (int kb = kb0; kb < kb1; ++kb) c.template unit<0, 0, KIND>(acc, P, g);
     } else if constexpr (F == FSEP) {  // T1 = X0 Y0 and T2 = X1 Y1, kept apart
@@ -528,6 +530,10 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
           const int64_t t = acc[0][j][r];
           vre = pass_lo == 0 ? t : (pass_lo == 1 ? -t : 0);
           vim = pass_lo == 2 ? t : -t;
+        } else if constexpr (F == F4P) {  // Re: products 0, 1; Im: 2, 3
+          const int64_t t = acc[0][j][r];
+          vre = pass_lo < 2 ? t : 0;
+          vim = pass_lo < 2 ? 0 : t;
         } else {
           vre = acc[0][j][r];
           vim = acc[1][j][r];
@@ -552,8 +558,10 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
         }
       }
     }
-    // (T3 adds nothing to Re: its stream's Re digits are neither written nor read)
-    const bool keep_re = F != F3P || pass_lo != 2;
+    // (T3 adds nothing to Re, a 4M product to one component only: the other
+    // digits of its stream are neither written nor read)
+    const bool keep_re = F == F3P ? pass_lo != 2 : (F == F4P ? pass_lo < 2 : true);
+    const bool keep_im = F == F4P ? pass_lo >= 2 : true;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -561,7 +569,7 @@ __device__ __attribute__((always_inline)) inline void gemm_item(const GemmArgs& 
         const int q = W * band + 4 * u;
         const uint32_t at = (uint32_t)(q >> 4) * 1024u + (uint32_t)(q & 15) + dig_lane;
         if (keep_re) *reinterpret_cast<uint32_t*>(dig + ((uint32_t)r * (uint32_t)slot_stride + at)) = wre[r][u];
-        *reinterpret_cast<uint32_t*>(dig + ((uint32_t)(4 + r) * (uint32_t)slot_stride + at)) = wim[r][u];
+        if (keep_im) *reinterpret_cast<uint32_t*>(dig + ((uint32_t)(4 + r) * (uint32_t)slot_stride + at)) = wim[r][u];
       }
   };
   // least significant first: upward bands with s_lo > 0, the upward band(s)
@@ -639,12 +647,12 @@ __global__ __launch_bounds__(256) void gemm_i8_batched_kernel(const GemmArgs* __
 
 // One real product per work item: a third of the registers, half the queue,
 // two workgroups per compute unit.
-template <int W>
+template <int W, int F>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void gemm_i8_p_kernel(GemmArgs a) {
   extern __shared__ __attribute__((aligned(1024))) int8_t lds_queue[];
   int split, gi, gj;
   map_block(blockIdx.x, gridDim.x, a.mt >> 1, a.nt >> 1, split, gi, gj);
-  gemm_item<W, F3P>(a, split, gi, gj, lds_queue);
+  gemm_item<W, F>(a, split, gi, gj, lds_queue);
 }
 
 template <int W, int F>
@@ -652,11 +660,11 @@ hipError_t launch_wm(const GemmArgs& a, hipStream_t stream) {
   using G = Q<W, F>;
   const int blocks = (a.mt / 2) * (a.nt / 2) * a.ksplit * (a.bsplit > 1 ? a.bsplit : 1) * (a.psplit > 1 ? a.psplit : 1);
   const size_t lds = (size_t)G::QS * G::ENT * 1024;
-  if constexpr (F == F3P) {
-    hipError_t e = hipFuncSetAttribute((const void*)gemm_i8_p_kernel<W>,
+  if constexpr (F == F3P || F == F4P) {
+    hipError_t e = hipFuncSetAttribute((const void*)gemm_i8_p_kernel<W, F>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    gemm_i8_p_kernel<W><<<dim3(blocks), dim3(256), lds, stream>>>(a);
+    gemm_i8_p_kernel<W, F><<<dim3(blocks), dim3(256), lds, stream>>>(a);
   } else {
     hipError_t e = hipFuncSetAttribute((const void*)gemm_i8_kernel<W, F>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -675,6 +683,11 @@ hipError_t launch_w(const GemmArgs& a, hipStream_t stream) {
     case F3P:  // one real product per workgroup (20-wide bands do not fit two workgroups' registers)
       if constexpr (W <= 16) {
         if (a.psplit == 3 && a.bsplit <= 1) return launch_wm<W, F3P>(a, stream);
+      }
+      return hipErrorInvalidValue;
+    case F4P:
+      if constexpr (W <= 16) {
+        if (a.psplit == 4 && a.bsplit <= 1) return launch_wm<W, F4P>(a, stream);
       }
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;

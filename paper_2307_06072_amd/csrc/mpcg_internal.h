@@ -116,7 +116,7 @@ hipError_t launch_fold_scales(const RowStat* stats, int half, int Rpad, int x, i
 hipError_t launch_scales(const RowStat* stats, int R, int Rpad, int x, int32_t* G, hipStream_t stream);
 
 // Slice GEMM + combination + carry chain (INT8 digits).
-enum GemmForm { F4M = 0, F3M = 1, FSEP = 2, F3P = 3 };
+enum GemmForm { F4M = 0, F3M = 1, FSEP = 2, F3P = 3, F4P = 4 };
 struct GemmArgs {
   const int8_t* X;   // A-side planes
   const int8_t* Y;   // B-side planes
@@ -140,7 +140,10 @@ struct GemmArgs {
                      // FSEP: A planes (X0, X1), B (Y0, Y1, ...), the two real products
                      //       X0 Y0 and X1 Y1 out in place of Re and Im;
                      // F3P: the planes of F3M, one real product per work item (psplit = 3,
-                     //       bsplit = 1), its share of Re and Im out
+                     //       bsplit = 1), its share of Re and Im out;
+                     // F4P: the planes of F4M, one real product per work item (psplit = 4,
+                     //       bsplit = 1: Re A Re B and Im A (-Im B) into Re, Re A Im B
+                     //       and Im A Re B into Im), that component out
   void* digits;      // [ksplit][tiles][slot 8][chunk][lane 64][16] uint8 digits, q = Dmax - d
                      // (chunk = q / 16; gemm_i8_digit_chunks chunks per component)
   int64_t* top;      // [ksplit][tiles][64][8]
@@ -193,8 +196,10 @@ struct RoundArgs {
   const int64_t* top;
   const int32_t* lnz;
   int ksplit, mt, nt, Dmax, w;
-  // 1: the ksplit streams are (chunk, 3M real product) pairs, stream q of
-  // product q % 3; T3's (q % 3 == 2) holds no Re digits (unwritten), only its tops
+  // 3 (4): the ksplit streams are (chunk, real product) pairs, stream q of
+  // product q % 3 (q % 4); a 3M T3 stream (q % 3 == 2) holds no Re digits, a
+  // 4M stream only Re (q % 4 < 2) or only Im digits (the others unwritten;
+  // the tops of all are written)
   int onepass;
   // > 1: the streams are band groups (GemmArgs.bsplit, .psplit): stream
   // (chunk c, group g, pass p) = (c seg_bs + g) seg_ps + p holds group g's

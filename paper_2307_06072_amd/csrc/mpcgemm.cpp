@@ -138,10 +138,11 @@ struct Plan {
   int allow_bsplit;  // the plain path: a product of few work items may run its bands apart
   int bsplit;        // bands on separate workgroups (1: all bands in one work item)
   int psplit;        // with bsplit > 1: the real products of a band group on workgroups of their own
-  int allow_onepass; // the plain path and Strassen's products: 3M may run one real product per work item
+  int allow_onepass; // the plain path and Strassen's products may run one real product per work item
   int onepass_pays;  // ... and that form is expected to be faster for this product (onepass_pays())
   long long fused_items;  // work items of the products together (tile groups x contraction chunks)
-  int onepass;       // 3M, one real product per work item (GEMM form F3P, psplit = 3; not with bsplit)
+  int onepass;       // one real product per work item (GEMM form F3P, psplit = 3, or F4P, psplit = 4;
+                     // not with bsplit)
   int nchunk;        // INT8: 16-digit chunks per output component
   size_t off_G, off_H, off_X, off_Y, off_dig, off_top, off_lnz, off_scan, total;
   // FP64 form: slices of A per DGEMM block, the block's products and the diagonal sums
@@ -209,15 +210,14 @@ constexpr int BSPLIT_STREAMS = 16;
 // longest group: narrower bands make more and shorter groups (at 256 bits,
 // 1^3 to 64^3 run fastest with 8 diagonals per band; from 5 work items on,
 // 16 served the n = 1024 LU's products best, 12 and 8 giving 0.51 s against
-// 0.48 s).  A 3M product that is not split in band groups runs each real
-// product on a workgroup of its own (one accumulator set: two workgroups per
+// 0.48 s).  A product that is not split in band groups runs each real
+// product (3M: 3, 4M: 4) on a workgroup of its own (one accumulator set: two workgroups per
 // compute unit) with 16 diagonals, the widest band that then fits; at 2048^3
 // and 1024 bits its slice GEMM takes 321 ms against 342 ms for the three
 // products together with 20 diagonals, at 512^3 and 512 bits 1.30 against
 // 1.50-1.62 ms.
 bool onepass_form(const Plan& P, long long items) {
-  return P.allow_onepass && P.onepass_pays && !P.f64 && P.mode3m && !P.sep &&
-         !(P.allow_bsplit && items < BSPLIT_ITEMS);
+  return P.allow_onepass && P.onepass_pays && !P.f64 && !P.sep && !(P.allow_bsplit && items < BSPLIT_ITEMS);
 }
 // The form saves slice-GEMM time in proportion to k S per output entry and
 // costs the rounding kernel about two more digit streams per contraction
@@ -228,10 +228,15 @@ bool onepass_form(const Plan& P, long long items) {
 // 1.65 ms.)  It also pays when the products together would make fewer than
 // ONEPASS_FILL_ITEMS work items, two rounds of one workgroup per compute
 // unit: apart they fill the chip three times over (256 products of shapes on
-// [16, 768]^3 at 256 bits, one call each: 109 against 137 ms).
+// [16, 768]^3 at 256 bits, one call each: 109 against 137 ms).  For 4M only
+// the latter holds: its fused kernel already issues two MFMAs per pair of
+// fragments, and apart its slice GEMM at 2048^3 / 1024 bits gains 1.4%
+// (431 against 437 ms), about what the doubled streams cost the rounding;
+// 512^3 at 512 bits, which fills the chip poorly, 1.69 against 1.79 ms.
 constexpr long long ONEPASS_FILL_ITEMS = 1024;
 bool onepass_pays(const Plan& P, int ks, long long fused_items) {
-  return fused_items < ONEPASS_FILL_ITEMS || (long long)P.k * std::max(P.SA, P.SB) >= (1ll << 14) * (ks + 1);
+  return fused_items < ONEPASS_FILL_ITEMS ||
+         (P.mode3m && (long long)P.k * std::max(P.SA, P.SB) >= (1ll << 14) * (ks + 1));
 }
 int pick_band(const Plan& P, long long items) {
   if (P.allow_bsplit && items <= 4 && std::min(P.SA, P.SB) < 64) return 8;
@@ -279,12 +284,13 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
     int want = std::max(1, ceil_div(P.want_groups, groups));
     // the one-product form's three real products are work items too
     {
-      const int ks_one = std::max(ks, std::min(std::max(1, ceil_div(P.want_groups, 3 * groups)), P.kblocks));
+      const int np = P.mode3m ? 3 : 4;  // real products
+      const int ks_one = std::max(ks, std::min(std::max(1, ceil_div(P.want_groups, np * groups)), P.kblocks));
       P.fused_items = (long long)groups * std::max(ks, std::min(want, P.kblocks));
       P.onepass_pays = onepass_pays(P, ks_one, P.fused_items);
     }
     if ((P.block == 0 || P.block <= 16) && onepass_form(P, (long long)groups * std::max(ks, std::min(want, P.kblocks))))
-      want = std::max(1, ceil_div(P.want_groups, 3 * groups));
+      want = std::max(1, ceil_div(P.want_groups, (P.mode3m ? 3 : 4) * groups));
     ks = std::max(ks, std::min(want, P.kblocks));
     P.ksplit = ks;
     if (P.block == 0) P.block = pick_band(P, (long long)groups * ks);
@@ -357,7 +363,7 @@ int plan_layout(Plan& P, const mpcg_options* opt) {
   if (P.bsplit == 1 && P.block <= 16 && onepass_form(P, (long long)groups * P.ksplit) &&
       onepass_pays(P, P.ksplit, P.fused_items)) {
     P.onepass = 1;
-    P.psplit = 3;
+    P.psplit = P.mode3m ? 3 : 4;
   }
   const int streams = P.ksplit * P.bsplit * P.psplit;
   const size_t esz = P.f64 ? 8 : 1;
@@ -676,7 +682,8 @@ int run_strassen(int m, int n, int k, const DOperand& opA, const DOperand& opB, 
     ga.X = reinterpret_cast<const int8_t*>(pb + Q.off_X);
     ga.Y = reinterpret_cast<const int8_t*>(pb + Q.off_Y);
     ga.mt = Q.mt; ga.nt = Q.nt; ga.kblocks = Q.kblocks; ga.ksplit = Q.ksplit; ga.psplit = Q.psplit;
-    ga.SAp = Q.SAp; ga.SBp = Q.SBp; ga.Dmax = Q.Dmax; ga.form = Q.onepass ? F3P : (Q.mode3m ? F3M : F4M);
+    ga.SAp = Q.SAp; ga.SBp = Q.SBp; ga.Dmax = Q.Dmax;
+    ga.form = Q.onepass ? (Q.mode3m ? F3P : F4P) : (Q.mode3m ? F3M : F4M);
     ga.digits = pb + Q.off_dig;
     ga.top = reinterpret_cast<int64_t*>(pb + Q.off_top);
     ga.lnz = reinterpret_cast<int32_t*>(pb + Q.off_lnz);
@@ -693,15 +700,15 @@ int run_strassen(int m, int n, int k, const DOperand& opA, const DOperand& opB, 
   const size_t sstride = tiles * 8 * Q.nchunk * 1024;  // one stream's digits
   char* merged = base + 7 * stride;
   MergeSrc* srcdev = reinterpret_cast<MergeSrc*>(base + 7 * stride + 4 * qbytes);
-  // per quadrant, the Re sources then the Im sources (T3's streams of the
-  // one-product form hold no Re digits)
+  // per quadrant, the Re sources then the Im sources (in the one-product
+  // form T3's streams hold no Re digits, a 4M product's only one component)
   MergeSrc srcs[4][2][MAX_MERGE] = {};
   int nsrc[4][2] = {};
   for (int qd = 0; qd < 4; ++qd)
     for (const Term& t : terms[qd])
       for (int c = 0; c < qstreams; ++c)  // contraction chunks (and real products)
         for (int comp = 0; comp < 2; ++comp) {
-          if (comp == 0 && Q.onepass && c % 3 == 2) continue;
+          if (Q.onepass && (Q.mode3m ? (comp == 0 && c % 3 == 2) : ((c % 4 < 2) != (comp == 0)))) continue;
           char* pb = base + t.prod * stride;
           MergeSrc& ms = srcs[qd][comp][nsrc[qd][comp]++];
           ms.dig = reinterpret_cast<const uint8_t*>(pb + Q.off_dig) + c * sstride;
@@ -1211,7 +1218,8 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
     ga.Y = reinterpret_cast<const int8_t*>(base + P.off_Y);
     ga.mt = P.mt; ga.nt = P.nt; ga.kblocks = P.kblocks; ga.ksplit = P.ksplit; ga.bsplit = P.bsplit;
     ga.psplit = P.psplit;
-    ga.SAp = P.SAp; ga.SBp = P.SBp; ga.Dmax = P.Dmax; ga.form = P.onepass ? F3P : (P.mode3m ? F3M : F4M);
+    ga.SAp = P.SAp; ga.SBp = P.SBp; ga.Dmax = P.Dmax;
+    ga.form = P.onepass ? (P.mode3m ? F3P : F4P) : (P.mode3m ? F3M : F4M);
     ga.digits = base + P.off_dig; ga.top = top; ga.lnz = lnz;
     ga.xs = P.xs; ga.ys = P.ys; ga.xlo = P.xlo; ga.ylo = P.ylo;
     HIP_TRY(launch_gemm_i8(ga, P.block, g_stream));
@@ -1228,9 +1236,9 @@ int run(int m, int n, int k, const mpcg_cmat* A, int lda, const mpcg_cmat* B, in
   ra.f64_layout = P.f64;
   ra.top = top; ra.lnz = lnz;
   ra.ksplit = P.ksplit; ra.mt = P.mt; ra.nt = P.nt; ra.Dmax = P.Dmax; ra.w = P.w;
-  if (P.onepass) {  // every stream holds all digits (T3's: Im only): a plain sum
+  if (P.onepass) {  // every stream holds all digits of what it touches: a plain sum
     ra.ksplit = P.ksplit * P.psplit;
-    ra.onepass = 1;
+    ra.onepass = P.psplit;
   }
   if (P.bsplit > 1) {
     ra.seg_bs = P.bsplit;

@@ -1091,7 +1091,8 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
         uint4 v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-          v[u] = q + u < a.ksplit && !(a.onepass && comp == 0 && (q + u) % 3 == 2)
+          v[u] = q + u < a.ksplit && !(a.onepass == 3 ? comp == 0 && (q + u) % 3 == 2
+                                                       : a.onepass == 4 && ((q + u) % 4 < 2) != (comp == 0))
                      ? *reinterpret_cast<const uint4*>(g0 + (q + u) * sstride + (size_t)ch * 1024)
                      : make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll

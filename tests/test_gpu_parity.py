@@ -84,14 +84,15 @@ def _apart_ref():
     return _APART_REF["ref"]
 
 
-@pytest.mark.parametrize("mode,block,apart", [(M3, 0, 1), (M3, 8, 1), (M3, 12, 1), (M3, 16, 1), (M4, 0, 0)])
+@pytest.mark.parametrize("mode,block,apart", [(M3, 0, 1), (M3, 8, 1), (M3, 12, 1), (M3, 16, 1), (M4, 0, 1),
+                                              (M4, 12, 1)])
 def test_products_apart(mode, block, apart):
-    """A 3M product whose contraction is long enough for it (k S >= 2^14 (ks +
+    """A product whose contraction is long enough for it (k S >= 2^14 (ks +
     1): here 512 x 67 in one contraction chunk) runs each real product on
     workgroups of its own with bands of at most 16 diagonals: a digit stream
-    per product, T3's holding Im digits only, added up by the rounding.  4M
-    and bands of 20 keep the products together.  Every form gives the
-    oracle's bits on the sampled entries and the fused kernel's everywhere."""
+    per product (3M: T3's holding Im digits only; 4M: each product's one
+    component), added up by the rounding.  Every form gives the oracle's bits
+    on the sampled entries and the fused 3M kernel's (band 20) everywhere."""
     m, n, k, p, A, B, rows, cols, (s, e, mm), C20 = _apart_ref()
     _say(f"case m={m} n={n} k={k} p={p} mode={mode} block={block}")
     C, info = run_device(A, B, p, mode, EXACT, I8, block_override=block)
