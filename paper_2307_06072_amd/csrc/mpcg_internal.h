@@ -130,7 +130,8 @@ struct GemmArgs {
                      // digits in `top`
   int psplit;        // > 1 (with bsplit > 1; 3M: 3, 4M: 2): each real product (pass) of a band
                      // group on a workgroup of its own, a stream each; stream
-                     // (chunk c, group g, pass p) is (c bsplit + g) psplit + p
+                     // (chunk c, group g, pass p) is (c bsplit + g) psplit + p.  Forms F3P
+                     // and F4P (bsplit = 1): 3 or 4, stream c psplit + p
   int SAp, SBp;      // slice counts of the A and B operands
   int xs, ys;        // slices per A / B plane including the zero pads
   int xlo, ylo;      // zero slices below slice 0 of an A / B plane
