@@ -48,14 +48,15 @@
 // resident on one XCD cover a compact block of the output and share operand
 // panels in that XCD's L2.
 //
-// One real product per workgroup (form F3P, gemm_i8_p_kernel): the three 3M
-// products T1, T2, T3 of a tile group run as separate work items, each with
-// one accumulator set and half the LDS queue, so that two workgroups share a
+// One real product per workgroup (forms F3P and F4P, gemm_i8_p_kernel): the
+// real products of a tile group run as separate work items, each with one
+// accumulator set and half the LDS queue, so that two workgroups share a
 // compute unit and one SIMD's second wavefront issues MFMAs while the first
 // waits.  Each item's carry chain emits its product's share of Re and Im
-// (T1: Re + T1, Im - T1; T2: Re - T2, Im - T2; T3: Im + T3, whose zero Re
-// digits are not stored) into a digit stream of its own; the rounding kernel
-// adds the streams.
+// into a digit stream of its own (3M: T1 to Re and -Im, T2 to -Re and -Im,
+// T3 to Im; 4M: Re A Re B and Im A (-Im B) to Re, Re A Im B and Im A Re B to
+// Im; the digits of a component a product does not touch are not stored);
+// the rounding kernel adds the streams.
 #include "mpcg_internal.h"
 
 #include <type_traits>
