@@ -1095,11 +1095,24 @@ __device__ inline void round_i8_block(const RoundArgs& a, int blk, uint8_t* lds_
                                                        : a.onepass == 4 && ((q + u) % 4 < 2) != (comp == 0))
                      ? *reinterpret_cast<const uint4*>(g0 + (q + u) * sstride + (size_t)ch * 1024)
                      : make_uint4(0u, 0u, 0u, 0u);
+        // two digits per 32-bit add: even and odd bytes in 16-bit lanes (8
+        // sources of at most 255 fit a lane), then into the 32-bit sums
+        uint32_t ev[4] = {0u, 0u, 0u, 0u}, od[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const uint32_t wv[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
 #pragma unroll
-          for (int b = 0; b < 16; ++b) sum[b] += (int32_t)((wv[b >> 2] >> (8 * (b & 3))) & 255u);
+          for (int w = 0; w < 4; ++w) {
+            ev[w] += wv[w] & 0x00FF00FFu;
+            od[w] += (wv[w] >> 8) & 0x00FF00FFu;
+          }
+        }
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          sum[4 * w] += (int32_t)(ev[w] & 0xFFFFu);
+          sum[4 * w + 1] += (int32_t)(od[w] & 0xFFFFu);
+          sum[4 * w + 2] += (int32_t)(ev[w] >> 16);
+          sum[4 * w + 3] += (int32_t)(od[w] >> 16);
         }
       }
 #pragma unroll
